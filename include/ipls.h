@@ -1,0 +1,161 @@
+/*
+ * ipls.h: C ABI of the MI355X (gfx950) In-Place Parallel Learned Sort library.
+ *
+ * The library sorts numeric keys on one GPU with the IPLS distribution recursion: fit a linear
+ * partition model with Fastest Minimum Conflict Degree (FMCD) on a sorted sample of a bucket,
+ * classify every key of the bucket with one fp64 fused multiply-add, distribute the keys stably
+ * into contiguous sub-buckets, recurse on sub-buckets above the base-case size and finish the
+ * rest with an in-LDS base-case sort (paper: Proposed Algorithm chapter; the model and its
+ * fit: Linear Models section; the sample -> sort -> train -> predict pipeline: Machine Learning
+ * Models chapter).  Optionally a two-level piecewise-linear CDF model (Recursive Model Index
+ * section) replaces FMCD on a bucket when its maximum sample load is lower.
+ *
+ * Conventions for every entry point:
+ *   - Array pointers are DEVICE pointers unless marked "host".  The caller owns them; the
+ *     library never frees or keeps them after the call returns.
+ *   - Work is enqueued on `stream` (NULL = the default stream).  The sort entry points read a
+ *     few bytes back from the device once per recursion level to size the next level's
+ *     launches, so they return only after the sort has completed on `stream`.
+ *   - Keys are ordered by IEEE 754 totalOrder (-0 before +0; NaNs are accepted and sort to the
+ *     end their sign bit gives).  u64 keys are plain unsigned integers.
+ *   - Results are deterministic and bit-identical for identical inputs and parameters; with a
+ *     payload the sort is stable, so the output is unique.
+ *   - Argument errors are reported synchronously and nothing is enqueued.  No C++ exception
+ *     crosses this interface.
+ *   - Calls are serialised internally per process (one sort runs at a time); buffers the
+ *     library allocates for its own use are cached per device and reused across calls.
+ */
+#ifndef IPLS_H
+#define IPLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { IPLS_F64 = 0, IPLS_F32 = 1, IPLS_U64 = 2 } ipls_dtype;
+
+typedef enum {
+    IPLS_OK = 0,
+    IPLS_ERR_INVALID = 1,     /* bad argument: null pointer with n > 0, bad parameter, bad offsets */
+    IPLS_ERR_DTYPE = 2,       /* unknown dtype */
+    IPLS_ERR_OOM = 3,         /* device allocation failed */
+    IPLS_ERR_HIP = 4,         /* a HIP runtime call or kernel launch failed */
+    IPLS_ERR_DEVICE = 5,      /* a device-side check failed (capacity, recursion limit, offsets) */
+    IPLS_ERR_UNSUPPORTED = 6  /* valid request outside what this build supports (e.g. K > 256) */
+} ipls_status;
+
+/* Model selection for each partitioned bucket. */
+typedef enum {
+    IPLS_MODEL_FMCD = 0, /* linear model fitted by FMCD (the paper's IPLS) */
+    IPLS_MODEL_AUTO = 1, /* two-level model iff its max sample load is strictly lower than FMCD's */
+    IPLS_MODEL_L2PL = 2  /* two-level model whenever it splits the sample (FMCD otherwise) */
+} ipls_model_policy;
+
+/* Tuning parameters.  ipls_default_params() fills the defaults. */
+typedef struct {
+    uint32_t num_buckets;    /* K, buckets per partition, 4..256 (default 256, Proposed Algorithm) */
+    uint32_t base_case_max;  /* T, buckets of <= T keys go to the base case, 1..4096 (default 4096) */
+    uint32_t sample_divisor; /* sample size S = ceil(n / divisor), >= 2 (default 100: a 1% sample) */
+    uint32_t sample_min;     /* ... raised to at least this (0 = 2K); must be <= base_case_max */
+    uint64_t sample_max;     /* ... and capped at this (0 = no cap); S never exceeds n */
+    uint64_t seed;           /* seed of the sample positions' jitter */
+    uint32_t model;          /* ipls_model_policy */
+    uint32_t leaves;         /* leaves M of the two-level model, 4..256 (default 256) */
+    uint32_t train_iters;    /* gradient steps of the two-level model (default 32) */
+    uint32_t tile_keys;      /* keys per distribution tile, 0 = library default */
+} ipls_params;
+
+/* FMCD linear model of a sample: bucket(x) = clamp(floor(fma(a, x, b)), 0, K-1). */
+typedef struct {
+    double a, b;         /* slope and offset */
+    uint64_t D;          /* conflict degree the fit stopped at */
+    uint32_t K;          /* buckets */
+    uint32_t degenerate; /* 1 when the fit is unusable (S < 3, non-finite ends, a <= 0 or inf) */
+} ipls_linear_model;
+
+/* Statistics of the last sort (host struct, filled after the sort has completed). */
+typedef struct {
+    uint32_t levels;            /* distribution levels run (0 when every bucket went to the base case) */
+    uint32_t sample_depth;      /* deepest nesting of sample sorts that needed a partition */
+    uint64_t passes;            /* buckets partitioned, over all levels */
+    uint64_t closed;            /* buckets closed by the homogeneity check */
+    uint64_t fallback;          /* buckets split by the most-significant-digit fallback */
+    uint64_t l2pl_used;         /* buckets partitioned with the two-level model */
+    uint64_t base_buckets;      /* base-case sorts */
+    uint64_t level1_max_load;   /* largest bucket after the first level */
+    uint64_t keys_partitioned;  /* sum over levels of keys that went through a distribution pass */
+} ipls_stats;
+
+/* Defaults: K 256, T 4096, divisor 100, sample_min 2K, no cap, FMCD, M 256, 32 steps. */
+void ipls_default_params(ipls_params* p);
+
+/* Sort keys[0..n) (and payload[0..n) when non-null, stably) in place with default parameters.
+ * keys: device array of n elements of `dtype`; payload: device uint32 array or NULL. */
+ipls_status ipls_sort(void* keys, uint32_t* payload, size_t n, ipls_dtype dtype, void* stream);
+
+/* ipls_sort with explicit parameters (NULL = defaults), an optional caller-owned device
+ * workspace for the ping-pong copy of keys and payload (NULL = library cache; else at least
+ * ipls_workspace_bytes() bytes, 256-byte aligned), and optional statistics (host pointer). */
+ipls_status ipls_sort_ex(void* keys, uint32_t* payload, size_t n, ipls_dtype dtype, const ipls_params* p,
+                         void* workspace, size_t workspace_bytes, ipls_stats* stats, void* stream);
+
+/* Sort nseg independent segments [seg_offsets[s], seg_offsets[s+1]) of one array, each exactly as
+ * ipls_sort would sort it alone (sample offsets are relative to the segment's start).
+ * seg_offsets: device array of nseg+1 non-decreasing uint64; keys span seg_offsets[nseg] elements.
+ * Decreasing offsets are reported as IPLS_ERR_DEVICE after the device has checked them. */
+ipls_status ipls_sort_segmented(void* keys, uint32_t* payload, const uint64_t* seg_offsets, size_t nseg,
+                                ipls_dtype dtype, const ipls_params* p, ipls_stats* stats, void* stream);
+
+/* FMCD fit (Linear Models section) of a sample of S keys for K buckets, in fp64.  When
+ * sample_is_sorted is 0 the library sorts a copy first (the caller's sample is not modified).
+ * out: device pointer to one ipls_linear_model. */
+ipls_status ipls_fit_model(const void* sample, size_t S, ipls_dtype dtype, int sample_is_sorted, uint32_t K,
+                           ipls_linear_model* out, void* stream);
+
+/* One distribution pass over the whole array (the first level of ipls_sort_ex): sample, fit,
+ * classify, stable scatter.  keys (and payload) are left partitioned into contiguous buckets in
+ * bucket order; counts (device, K uint64) receives the bucket sizes; model (device, nullable)
+ * receives the FMCD model used.  A bucket whose fit is degenerate is split by the digit
+ * fallback or, when all its keys are equal, left as it is (counts then all zero). */
+ipls_status ipls_partition(void* keys, uint32_t* payload, size_t n, ipls_dtype dtype, const ipls_params* p,
+                           uint64_t* counts, ipls_linear_model* model, void* stream);
+
+/* Two-level piecewise-linear CDF model trained on a sorted fp64 sample x[0..S) for K buckets and
+ * M leaves with `iters` gradient steps (Recursive Model Index section; training by MSE on K times
+ * the eCDF, Machine Learning Models chapter).  Device outputs: root (2 doubles: the FMCD root's
+ * a, b), leaf (4*M doubles: A, B, LO, HI per leaf), ab (2*M doubles: trained alpha, beta in each
+ * leaf's centred coordinate, nullable).  Returns IPLS_ERR_DEVICE if the root fit is degenerate. */
+ipls_status ipls_l2pl_train(const double* x, size_t S, uint32_t K, uint32_t M, uint32_t iters, double* root,
+                            double* leaf, double* ab, void* stream);
+
+/* Forward and backward pass of the two-level model's per-leaf MSE at given leaf parameters
+ * ab (device, 2*M) on the sorted fp64 sample x[0..S): grad (device, 2*M) receives
+ * (dL/dalpha, dL/dbeta) per leaf, loss (device, M, nullable) the per-leaf loss. */
+ipls_status ipls_l2pl_grad(const double* x, size_t S, uint32_t K, uint32_t M, const double* ab, double* grad,
+                           double* loss, void* stream);
+
+/* Bytes of caller workspace ipls_sort_ex accepts for n keys: n * (key bytes + 4 if payload). */
+size_t ipls_workspace_bytes(size_t n, ipls_dtype dtype, int has_payload, const ipls_params* p);
+
+/* Status of the last sort call issued on `stream` (IPLS_OK if none). */
+ipls_status ipls_stream_status(void* stream);
+
+/* Static string naming a status code. */
+const char* ipls_status_string(ipls_status st);
+
+/* Kernel timing for measurement.  While enabled, the library records HIP events around every
+ * launch of the distribution-pass kernels on the caller's stream and accumulates their elapsed
+ * times; ipls_profile_read returns, for kernel id 0 (scatter), 1 (classify + histogram),
+ * 2 (base case), the number of launches, the summed milliseconds and the summed algorithmic
+ * bytes (keys and payload each kernel must read and write).  Enabling resets the counters. */
+void ipls_profile_enable(int on);
+void ipls_profile_read(int kernel, uint64_t* launches, double* ms, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IPLS_H */

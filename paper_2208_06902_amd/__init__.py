@@ -1,0 +1,233 @@
+"""Python binding of libipls.so, the MI355X (gfx950) IPLS sort library.
+
+Argument marshalling only: every step of the sort runs in the library's HIP kernels.  Tensors
+are torch CUDA(HIP) tensors; their device pointers and the current stream are passed through
+the C ABI declared in include/ipls.h.  Importing this module does not need a GPU; calling a
+sort without the built library raises an error (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libipls.so")
+
+F64, F32, U64 = 0, 1, 2
+MODEL_FMCD, MODEL_AUTO, MODEL_L2PL = 0, 1, 2
+KERNEL_SCATTER, KERNEL_CLASSIFY, KERNEL_BASE = 0, 1, 2
+
+STATUS = {0: "IPLS_OK", 1: "IPLS_ERR_INVALID", 2: "IPLS_ERR_DTYPE", 3: "IPLS_ERR_OOM", 4: "IPLS_ERR_HIP",
+          5: "IPLS_ERR_DEVICE", 6: "IPLS_ERR_UNSUPPORTED"}
+
+EXPORTS = ["ipls_default_params", "ipls_sort", "ipls_sort_ex", "ipls_sort_segmented", "ipls_fit_model",
+           "ipls_partition", "ipls_l2pl_train", "ipls_l2pl_grad", "ipls_workspace_bytes", "ipls_stream_status",
+           "ipls_status_string", "ipls_profile_enable", "ipls_profile_read"]
+
+
+class IplsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("num_buckets", C.c_uint32), ("base_case_max", C.c_uint32), ("sample_divisor", C.c_uint32),
+                ("sample_min", C.c_uint32), ("sample_max", C.c_uint64), ("seed", C.c_uint64),
+                ("model", C.c_uint32), ("leaves", C.c_uint32), ("train_iters", C.c_uint32),
+                ("tile_keys", C.c_uint32)]
+
+
+class LinearModel(C.Structure):
+    _fields_ = [("a", C.c_double), ("b", C.c_double), ("D", C.c_uint64), ("K", C.c_uint32),
+                ("degenerate", C.c_uint32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("levels", C.c_uint32), ("sample_depth", C.c_uint32), ("passes", C.c_uint64),
+                ("closed", C.c_uint64), ("fallback", C.c_uint64), ("l2pl_used", C.c_uint64),
+                ("base_buckets", C.c_uint64), ("level1_max_load", C.c_uint64), ("keys_partitioned", C.c_uint64)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the built library (raises if it is missing: build it with build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libipls.so not built at {path}; run python -m paper_2208_06902_amd.build")
+    L = C.CDLL(path)
+    P, sz, u32, u64, i32, dbl = C.c_void_p, C.c_size_t, C.c_uint32, C.c_uint64, C.c_int, C.c_double
+    sig = {
+        "ipls_default_params": (None, [C.POINTER(Params)]),
+        "ipls_sort": (i32, [P, P, sz, i32, P]),
+        "ipls_sort_ex": (i32, [P, P, sz, i32, C.POINTER(Params), P, sz, C.POINTER(Stats), P]),
+        "ipls_sort_segmented": (i32, [P, P, P, sz, i32, C.POINTER(Params), C.POINTER(Stats), P]),
+        "ipls_fit_model": (i32, [P, sz, i32, i32, u32, P, P]),
+        "ipls_partition": (i32, [P, P, sz, i32, C.POINTER(Params), P, P, P]),
+        "ipls_l2pl_train": (i32, [P, sz, u32, u32, u32, P, P, P, P]),
+        "ipls_l2pl_grad": (i32, [P, sz, u32, u32, P, P, P, P]),
+        "ipls_workspace_bytes": (sz, [sz, i32, i32, C.POINTER(Params)]),
+        "ipls_stream_status": (i32, [P]),
+        "ipls_status_string": (C.c_char_p, [i32]),
+        "ipls_profile_enable": (None, [i32]),
+        "ipls_profile_read": (None, [i32, C.POINTER(u64), C.POINTER(dbl), C.POINTER(dbl)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    load().ipls_default_params(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.uint64:
+        return U64
+    raise TypeError(f"unsupported key dtype {t.dtype}")
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise IplsError(st, where)
+
+
+def _check_tensor(t, name):
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous device tensor")
+
+
+def sort_(keys, payload=None, params: Params | None = None, workspace=None, stream=None, stats: bool = False):
+    """Sort `keys` (and `payload`, stably) in place on the GPU.  Returns stats if asked."""
+    import torch
+    _check_tensor(keys, "keys")
+    if payload is not None:
+        _check_tensor(payload, "payload")
+        if payload.dtype != torch.int32 and payload.dtype != torch.uint32:
+            raise TypeError("payload must be 32-bit")
+        if payload.numel() != keys.numel():
+            raise ValueError("payload and keys differ in length")
+    st = Stats()
+    ws, wsb = (None, 0) if workspace is None else (_ptr(workspace), workspace.numel() * workspace.element_size())
+    rc = load().ipls_sort_ex(_ptr(keys), _ptr(payload), keys.numel(), _dtype_code(keys),
+                             C.byref(params) if params is not None else None, ws, wsb, C.byref(st), _stream(stream))
+    _check(rc, "ipls_sort_ex")
+    return st.as_dict() if stats else None
+
+
+def sort_plain(keys, payload=None, stream=None):
+    """ipls_sort: default parameters."""
+    _check_tensor(keys, "keys")
+    rc = load().ipls_sort(_ptr(keys), _ptr(payload), keys.numel(), _dtype_code(keys), _stream(stream))
+    _check(rc, "ipls_sort")
+
+
+def sort_segmented_(keys, offsets, payload=None, params: Params | None = None, stream=None, stats: bool = False):
+    """Sort every segment [offsets[s], offsets[s+1]) of `keys` independently, in place."""
+    import torch
+    _check_tensor(keys, "keys")
+    _check_tensor(offsets, "offsets")
+    if offsets.dtype not in (torch.int64, torch.uint64):
+        raise TypeError("offsets must be 64-bit")
+    st = Stats()
+    rc = load().ipls_sort_segmented(_ptr(keys), _ptr(payload), _ptr(offsets), offsets.numel() - 1,
+                                    _dtype_code(keys), C.byref(params) if params is not None else None,
+                                    C.byref(st), _stream(stream))
+    _check(rc, "ipls_sort_segmented")
+    return st.as_dict() if stats else None
+
+
+def fit_model(sample, K: int, sorted_: bool = True, stream=None):
+    """FMCD fit of a device sample: (a, b, D, degenerate)."""
+    import torch
+    _check_tensor(sample, "sample")
+    out = torch.zeros(C.sizeof(LinearModel), dtype=torch.uint8, device=sample.device)
+    rc = load().ipls_fit_model(_ptr(sample), sample.numel(), _dtype_code(sample), int(sorted_), K, _ptr(out),
+                               _stream(stream))
+    _check(rc, "ipls_fit_model")
+    m = LinearModel.from_buffer_copy(bytes(out.cpu().numpy()))
+    return m.a, m.b, int(m.D), int(m.degenerate)
+
+
+def partition_(keys, payload=None, params: Params | None = None, stream=None):
+    """One distribution pass in place: returns (counts tensor (K, uint64), (a, b, D, degenerate))."""
+    import torch
+    _check_tensor(keys, "keys")
+    p = params if params is not None else default_params()
+    counts = torch.zeros(p.num_buckets, dtype=torch.uint64, device=keys.device)
+    mbuf = torch.zeros(C.sizeof(LinearModel), dtype=torch.uint8, device=keys.device)
+    rc = load().ipls_partition(_ptr(keys), _ptr(payload), keys.numel(), _dtype_code(keys), C.byref(p),
+                               _ptr(counts), _ptr(mbuf), _stream(stream))
+    _check(rc, "ipls_partition")
+    m = LinearModel.from_buffer_copy(bytes(mbuf.cpu().numpy()))
+    return counts, (m.a, m.b, int(m.D), int(m.degenerate))
+
+
+def l2pl_train(x, K: int, M: int, iters: int, stream=None):
+    """Train the two-level model on a sorted fp64 device sample: (root (2), leaf (4M), ab (2M))."""
+    import torch
+    _check_tensor(x, "x")
+    root = torch.zeros(2, dtype=torch.float64, device=x.device)
+    leaf = torch.zeros(4 * M, dtype=torch.float64, device=x.device)
+    ab = torch.zeros(2 * M, dtype=torch.float64, device=x.device)
+    rc = load().ipls_l2pl_train(_ptr(x), x.numel(), K, M, iters, _ptr(root), _ptr(leaf), _ptr(ab), _stream(stream))
+    _check(rc, "ipls_l2pl_train")
+    return root, leaf, ab
+
+
+def l2pl_grad(x, K: int, M: int, ab, stream=None):
+    """Per-leaf MSE gradient (2M) and loss (M) of the two-level model at ab (2M)."""
+    import torch
+    _check_tensor(x, "x")
+    g = torch.zeros(2 * M, dtype=torch.float64, device=x.device)
+    loss = torch.zeros(M, dtype=torch.float64, device=x.device)
+    rc = load().ipls_l2pl_grad(_ptr(x), x.numel(), K, M, _ptr(ab), _ptr(g), _ptr(loss), _stream(stream))
+    _check(rc, "ipls_l2pl_grad")
+    return g, loss
+
+
+def workspace_bytes(n: int, dtype: int, has_payload: bool, params: Params | None = None) -> int:
+    return int(load().ipls_workspace_bytes(n, dtype, int(has_payload), C.byref(params) if params else None))
+
+
+def profile_enable(on: bool = True):
+    load().ipls_profile_enable(int(on))
+
+
+def profile_read(kernel: int):
+    n, ms, by = C.c_uint64(), C.c_double(), C.c_double()
+    load().ipls_profile_read(kernel, C.byref(n), C.byref(ms), C.byref(by))
+    return int(n.value), float(ms.value), float(by.value)
+
+
+def status_string(st: int) -> str:
+    return load().ipls_status_string(st).decode()

@@ -1,0 +1,216 @@
+// Device-side building blocks of the IPLS library for gfx950 (wave64, 160 KB LDS per CU).
+//
+// Key map (Experimental Evaluation chapter: doubles are sorted through an order-preserving map to
+// unsigned integers), the counter-based hash that jitters sample positions, the clamped linear
+// partition model (Linear Models section), and the per-bucket state that flows between kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ipls {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;        // threads of every distribution kernel
+constexpr int kMaxBuckets = 256;   // K <= 256: a bucket index is one byte
+constexpr int kMaxBase = 4096;     // T <= 4096: a base-case bucket fits one workgroup's LDS
+constexpr int kMaxLeaves = 256;
+
+enum : uint32_t {
+    kKindLinear = 0,      // FMCD line
+    kKindDigit = 1,       // degenerate fit: most-significant digit of ord - umin
+    kKindClosedKeep = 2,  // homogeneous bucket already in the caller's buffer: nothing to do
+    kKindClosedMove = 3,  // homogeneous bucket in the scratch buffer: copied through bucket 0
+    kKindL2pl = 4,        // two-level piecewise-linear CDF model
+    kKindPending = 5      // degenerate fit awaiting the bucket's min/max ord
+};
+
+// One bucket to partition at the current level: keys [lo, lo+n) of the level's source buffer;
+// lo_rel is its offset inside its top-level segment (sample positions hash it).
+struct Item {
+    uint64_t lo, n, lo_rel, pad;
+};
+
+// A bucket of <= T keys for the base case, at [lo, lo+n) of the caller's buffer (from_scratch = 0)
+// or of the scratch buffer (1).  The result always lands in the caller's buffer.
+struct BaseItem {
+    uint64_t lo;
+    uint32_t n;
+    uint32_t from_scratch;
+};
+
+// Model of one bucket, produced by the fit kernels, read by classification.
+struct Model {
+    uint32_t kind, shift;
+    double a, b;                 // linear: t = fma(a, val, b); also the two-level model's root
+    uint64_t D, S;               // FMCD conflict degree, sample size
+    uint64_t umin, umax;         // ord range (degenerate fits only)
+    uint64_t load_lin, load_l2;  // max sample load of FMCD and of the two-level model
+    uint32_t l2_ok, pad;
+};
+
+// Level plan, computed on the device from the item list and read back by the host.
+struct Plan {
+    uint64_t num_items, num_base, total_tiles, total_samples, total_fit_chunks, max_S, max_n, sum_n;
+    uint64_t err;
+    uint64_t closed, digit, l2pl;  // buckets closed / split by digit / by the two-level model so far
+    uint64_t closed_keys;          // keys of closed buckets so far
+    uint64_t pad[3];
+};
+
+// Error bits of the device error word.
+enum : uint64_t { kErrOffsets = 1, kErrCapacity = 2, kErrProgress = 4 };
+
+// ------------------------------------------------------------------ key map
+// ord(): IEEE 754 totalOrder as an unsigned integer (flip a negative number's bits, set a positive
+// number's sign bit); val(): the fp64 value the model sees (fp32 widened exactly, u64 rounded to
+// nearest even); neg(): the sign bit, which sends a NaN to the matching end.
+template <int DT>
+struct Key;
+
+template <>
+struct Key<0> {  // fp64
+    using T = uint64_t;
+    __device__ static inline uint64_t ord(T u) { return (u >> 63) ? ~u : (u | 0x8000000000000000ull); }
+    __device__ static inline T from_ord(uint64_t o) { return (o >> 63) ? (o & 0x7fffffffffffffffull) : ~o; }
+    __device__ static inline double val(T u) { return __longlong_as_double((long long)u); }
+    __device__ static inline bool neg(T u) { return (u >> 63) != 0; }
+};
+
+template <>
+struct Key<1> {  // fp32
+    using T = uint32_t;
+    __device__ static inline uint64_t ord(T u) { return (u & 0x80000000u) ? (uint64_t)(uint32_t)~u : (uint64_t)(u | 0x80000000u); }
+    __device__ static inline T from_ord(uint64_t o) {
+        uint32_t u = (uint32_t)o;
+        return (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
+    }
+    __device__ static inline double val(T u) { return (double)__uint_as_float(u); }
+    __device__ static inline bool neg(T u) { return (u >> 31) != 0; }
+};
+
+template <>
+struct Key<2> {  // uint64
+    using T = uint64_t;
+    __device__ static inline uint64_t ord(T u) { return u; }
+    __device__ static inline T from_ord(uint64_t o) { return o; }
+    __device__ static inline double val(T u) { return __ull2double_rn(u); }
+    __device__ static inline bool neg(T) { return false; }
+};
+
+// ------------------------------------------------------------------ sample hash
+// SplitMix64's output function (Steele, Lea, Flood 2014) used as a counter-based hash.
+__device__ __host__ inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+constexpr uint64_t kGamma = 0x9e3779b97f4a7c15ull;
+
+// Sample size of a bucket of n keys: ceil(n / div), at least smin, at most smax (if non-zero), <= n.
+__device__ __host__ inline uint64_t sample_size(uint64_t n, uint64_t div, uint64_t smin, uint64_t smax) {
+    uint64_t s = (n + div - 1) / div;
+    if (s < smin) s = smin;
+    if (smax && s > smax) s = smax;
+    if (s > n) s = n;
+    return s;
+}
+
+// ------------------------------------------------------------------ partition models
+// Clamped linear model (Linear Models section): comparing t is the same as comparing floor(t)
+// with 0 and K; a NaN t (NaN key) goes to the end its sign gives.  One explicit fp64 fma.
+__device__ inline uint32_t classify_linear(double a, double b, uint32_t K, double v, bool neg) {
+    double t = __builtin_fma(a, v, b);
+    if (t != t) return neg ? 0u : K - 1u;
+    if (t < 0.0) return 0u;
+    if (t >= (double)K) return K - 1u;
+    return (uint32_t)t;
+}
+
+// Two-level model: root routes to a leaf, the leaf's line is clipped to its envelope [LO, HI].
+__device__ inline uint32_t classify_l2pl(double ra, double rb, uint32_t M, const double* leaf, uint32_t K, double v,
+                                         bool neg) {
+    if (v != v) return neg ? 0u : K - 1u;
+    const double* q = leaf + 4 * classify_linear(ra, rb, M, v, false);
+    double t = __builtin_fma(q[0], v, q[1]);
+    if (t < q[2]) t = q[2];
+    if (t > q[3]) t = q[3];
+    if (t < 0.0) return 0u;
+    if (t >= (double)K) return K - 1u;
+    return (uint32_t)t;
+}
+
+template <int DT>
+__device__ inline uint32_t classify_key(const Model& m, const double* leaf, uint32_t K, uint32_t M,
+                                        typename Key<DT>::T u) {
+    using KT = Key<DT>;
+    switch (m.kind) {
+        case kKindDigit: return (uint32_t)((KT::ord(u) - m.umin) >> m.shift);
+        case kKindClosedMove: return 0u;
+        case kKindL2pl: return classify_l2pl(m.a, m.b, M, leaf, K, KT::val(u), KT::neg(u));
+        default: return classify_linear(m.a, m.b, K, KT::val(u), KT::neg(u));
+    }
+}
+
+// ------------------------------------------------------------------ wave and block primitives
+__device__ inline uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+// number of set bits of `mask` in lanes below this one
+__device__ inline uint32_t count_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <typename V>
+__device__ inline V wave_inclusive_sum(V v) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int s = 1; s < kWave; s <<= 1) {
+        V o = __shfl_up(v, s, kWave);
+        if (lane >= (uint32_t)s) v += o;
+    }
+    return v;
+}
+
+// Exclusive sum over the block (blockDim.x a multiple of 64, at most 1024 threads); *total gets
+// the block's sum.  `scratch` holds 16 values.
+template <typename V>
+__device__ inline V block_exclusive_sum(V v, V* scratch, V* total) {
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    V inc = wave_inclusive_sum(v);
+    if (lane == kWave - 1) scratch[wave] = inc;
+    __syncthreads();
+    V before = 0, all = 0;
+    for (uint32_t w = 0; w < nw; ++w) {
+        V s = scratch[w];
+        if (w < wave) before += s;
+        all += s;
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
+template <typename V>
+__device__ inline V wave_max(V v) {
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+        V o = __shfl_xor(v, s, kWave);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Sum of the 64 lanes' values in the fixed tree (lane p += lane p+s, s = 32, 16, ..., 1); the
+// result is valid in lane 0.  The same order as the CPU reference's 64-way pairwise tree.
+__device__ inline double wave_tree_sum(double v) {
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+        double o = __shfl_down(v, s, kWave);
+        v = v + o;
+    }
+    return v;
+}
+
+__device__ inline uint32_t bit_length(uint64_t v) { return v ? 64u - (uint32_t)__clzll((long long)v) : 0u; }
+
+}  // namespace ipls

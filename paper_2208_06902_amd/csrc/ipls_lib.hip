@@ -1,0 +1,711 @@
+// Host side of the IPLS library: level-synchronous orchestration of the distribution kernels
+// and the C ABI declared in include/ipls.h.
+//
+// One sort = a loop of levels.  Each level partitions every bucket of more than T keys at once
+// (all buckets of the level share every launch), reading one buffer and writing the other; the
+// base case finishes buckets of at most T keys into the caller's buffer.  The host reads back a
+// small plan (item count, tile and sample totals) once per level to size the next launches.
+// Samples are sorted by the same engine one nesting level down (the Machine Learning Models
+// chapter notes that an ML-enhanced sort can sort its own sample), or straight by the base case
+// when every sample has at most T keys.
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/ipls.h"
+#include "ipls_kernels.h"
+
+namespace ipls {
+namespace {
+
+constexpr uint32_t kSmallS = 8192;     // samples up to this size are fitted in one workgroup's LDS
+constexpr uint32_t kFitChunk = 8192;   // windows per workgroup in the multi-round fit
+constexpr uint32_t kCand = 7;          // candidate widths per fit round
+constexpr int kIPT = 16;               // keys per thread in the scatter tile
+constexpr uint32_t kTile = kBlock * kIPT;
+constexpr int kMaxLevels = 4096;
+constexpr int kMaxDepth = 16;
+
+struct Buf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+ipls_status ensure(Buf& b, size_t bytes) {
+    if (b.p && bytes <= b.cap) return IPLS_OK;
+    size_t want = std::max<size_t>(bytes + bytes / 4, 4096);
+    if (b.p) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return IPLS_ERR_OOM;
+    }
+    b.cap = want;
+    return IPLS_OK;
+}
+
+// counters (uint64) of one nesting depth
+enum { C_ITEMS0 = 0, C_ITEMS1 = 1, C_BASE = 2, C_ERR = 3, C_TILE = 4, C_STATS = 5 /* 4 slots */, C_N = 16 };
+
+struct Depth {
+    Buf scratch, spay, items[2], base, sample_base, counters, plan, tile_off, sample_off, fit_off, tile_map, fit_map,
+        models, masks, hist, bstart, status, sample, leaves, seg;
+    Plan* plan_h = nullptr;
+};
+
+struct Device {
+    Depth depth[kMaxDepth];
+};
+
+struct Prof {
+    bool on = false;
+    struct Rec {
+        hipEvent_t a, b;
+        int kernel;
+        double bytes;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    uint64_t launches[3] = {0, 0, 0};
+    double ms[3] = {0, 0, 0}, bytes[3] = {0, 0, 0};
+};
+
+std::mutex g_mu;
+std::unordered_map<int, Device*> g_devices;
+std::unordered_map<void*, ipls_status> g_stream_status;
+Prof g_prof;
+
+Device& device_ctx() {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    auto it = g_devices.find(dev);
+    if (it != g_devices.end()) return *it->second;
+    Device* d = new Device();
+    g_devices[dev] = d;
+    return *d;
+}
+
+hipEvent_t prof_event() {
+    if (!g_prof.pool.empty()) {
+        hipEvent_t e = g_prof.pool.back();
+        g_prof.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+struct ProfScope {
+    hipEvent_t a = nullptr;
+    int kernel;
+    double bytes;
+    hipStream_t s;
+    ProfScope(int k, double by, hipStream_t st) : kernel(k), bytes(by), s(st) {
+        if (g_prof.on) {
+            a = prof_event();
+            (void)hipEventRecord(a, s);
+        }
+    }
+    ~ProfScope() {
+        if (a) {
+            hipEvent_t b = prof_event();
+            (void)hipEventRecord(b, s);
+            g_prof.pending.push_back({a, b, kernel, bytes});
+        }
+    }
+};
+
+void prof_collect() {
+    for (auto& r : g_prof.pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            g_prof.launches[r.kernel] += 1;
+            g_prof.ms[r.kernel] += ms;
+            g_prof.bytes[r.kernel] += r.bytes;
+        }
+        g_prof.pool.push_back(r.a);
+        g_prof.pool.push_back(r.b);
+    }
+    g_prof.pending.clear();
+}
+
+#define HIP_TRY(x)                               \
+    do {                                         \
+        if ((x) != hipSuccess) {                 \
+            (void)hipGetLastError();             \
+            return IPLS_ERR_HIP;                 \
+        }                                        \
+    } while (0)
+#define ST_TRY(x)                     \
+    do {                              \
+        ipls_status st_ = (x);        \
+        if (st_ != IPLS_OK) return st_; \
+    } while (0)
+#define LAUNCH_CHECK() HIP_TRY(hipGetLastError())
+
+int fit_rounds(uint64_t max_S) {
+    uint64_t L = max_S / 3;
+    int r = 0;
+    while (L > 0) {
+        ++r;
+        L = (L <= kCand) ? 0 : L / (kCand + 1);
+    }
+    return r;
+}
+
+size_t key_bytes(int dt) { return dt == IPLS_F32 ? 4 : 8; }
+
+struct Run {
+    ipls_params p;
+    hipStream_t s;
+    ipls_stats st;
+    int dtype;
+    // ipls_partition: stop after the first level and export its result
+    uint64_t* part_counts = nullptr;
+    ipls_linear_model* part_model = nullptr;
+    bool single_pass = false;
+};
+
+// FMCD fit of every item's sorted sample: one workgroup per small sample, rounds of candidate
+// widths over chunks of the large samples.
+template <int DT>
+ipls_status fit_level(Depth& D, hipStream_t s, uint64_t ni, uint64_t max_S, uint64_t total_fit_chunks,
+                      const typename Key<DT>::T* sample, const uint64_t* sample_off, const uint64_t* fit_off,
+                      Model* models, uint32_t K) {
+    k_fmcd_small<DT><<<(unsigned)ni, 256, kSmallS * sizeof(double), s>>>(sample, sample_off, ni, models, K, kSmallS);
+    LAUNCH_CHECK();
+    if (max_S <= kSmallS) return IPLS_OK;
+    const int R = fit_rounds(max_S);
+    ST_TRY(ensure(D.masks, ni * R * 8));
+    ST_TRY(ensure(D.fit_map, total_fit_chunks * 4));
+    HIP_TRY(hipMemsetAsync(D.masks.p, 0, ni * R * 8, s));
+    k_expand<<<(unsigned)((total_fit_chunks + 255) / 256), 256, 0, s>>>(fit_off, ni, total_fit_chunks,
+                                                                        (uint32_t*)D.fit_map.p);
+    LAUNCH_CHECK();
+    for (int r = 0; r < R; ++r) {
+        k_fmcd_round<DT><<<(unsigned)total_fit_chunks, 256, 0, s>>>(sample, sample_off, fit_off,
+                                                                    (const uint32_t*)D.fit_map.p,
+                                                                    (uint64_t*)D.masks.p, R, r, K, kFitChunk, kCand);
+        LAUNCH_CHECK();
+    }
+    k_fmcd_finish<DT><<<(unsigned)((ni + 255) / 256), 256, 0, s>>>(sample, sample_off, ni, (const uint64_t*)D.masks.p,
+                                                                   R, models, K, kSmallS, kCand);
+    LAUNCH_CHECK();
+    return IPLS_OK;
+}
+
+template <int DT, bool PAY>
+ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys, uint32_t* pay, uint64_t len,
+                          const uint64_t* seg_off, uint64_t nseg, void* ws_keys, bool top);
+
+// Sort the samples of a level: base case when every sample fits, else the engine one level deeper.
+template <int DT>
+ipls_status sort_samples(Device& dv, Run& run, int d, const Plan& pl) {
+    using T = typename Key<DT>::T;
+    Depth& D = dv.depth[d];
+    hipStream_t s = run.s;
+    if (pl.max_S <= run.p.base_case_max) {
+        ST_TRY(ensure(D.sample_base, pl.num_items * sizeof(BaseItem)));
+        k_sample_base<<<(unsigned)((pl.num_items + 255) / 256), 256, 0, s>>>((const uint64_t*)D.sample_off.p,
+                                                                            pl.num_items, (BaseItem*)D.sample_base.p);
+        LAUNCH_CHECK();
+        k_base_case<DT, false><<<(unsigned)pl.num_items, 256, 0, s>>>((const BaseItem*)D.sample_base.p, (T*)D.sample.p,
+                                                                      nullptr, nullptr, nullptr);
+        LAUNCH_CHECK();
+        return IPLS_OK;
+    }
+    if (d + 1 >= kMaxDepth) return IPLS_ERR_DEVICE;
+    run.st.sample_depth = std::max<uint32_t>(run.st.sample_depth, (uint32_t)(d + 1));
+    return sort_segments<DT, false>(dv, run, d + 1, (T*)D.sample.p, nullptr, pl.total_samples,
+                                    (const uint64_t*)D.sample_off.p, pl.num_items, nullptr, false);
+}
+
+template <int DT, bool PAY>
+ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys, uint32_t* pay, uint64_t len,
+                          const uint64_t* seg_off, uint64_t nseg, void* ws_keys, bool top) {
+    using T = typename Key<DT>::T;
+    Depth& D = dv.depth[d];
+    const ipls_params& P = run.p;
+    hipStream_t s = run.s;
+    const uint32_t K = P.num_buckets, T_ = P.base_case_max;
+    const size_t kb = sizeof(T);
+    const uint64_t item_cap = len / (T_ + 1) + 1;
+    const uint64_t base_cap = std::min<uint64_t>(len, item_cap * K + nseg) + 1;
+
+    T* scratch;
+    uint32_t* spay = nullptr;
+    if (ws_keys) {
+        scratch = (T*)ws_keys;
+        if (PAY) spay = (uint32_t*)((char*)ws_keys + ((len * kb + 255) & ~(size_t)255));
+    } else {
+        ST_TRY(ensure(D.scratch, len * kb));
+        scratch = (T*)D.scratch.p;
+        if (PAY) {
+            ST_TRY(ensure(D.spay, len * 4));
+            spay = (uint32_t*)D.spay.p;
+        }
+    }
+    ST_TRY(ensure(D.items[0], item_cap * sizeof(Item)));
+    ST_TRY(ensure(D.items[1], item_cap * sizeof(Item)));
+    ST_TRY(ensure(D.base, base_cap * sizeof(BaseItem)));
+    ST_TRY(ensure(D.counters, C_N * sizeof(uint64_t)));
+    ST_TRY(ensure(D.plan, sizeof(Plan)));
+    ST_TRY(ensure(D.tile_off, (item_cap + 1) * 8));
+    ST_TRY(ensure(D.sample_off, (item_cap + 1) * 8));
+    ST_TRY(ensure(D.fit_off, (item_cap + 1) * 8));
+    if (!D.plan_h) HIP_TRY(hipHostMalloc((void**)&D.plan_h, sizeof(Plan), hipHostMallocDefault));
+    uint64_t* cnt = (uint64_t*)D.counters.p;
+
+    HIP_TRY(hipMemsetAsync(cnt, 0, C_N * sizeof(uint64_t), s));
+    k_seed<<<(unsigned)((nseg + 255) / 256), 256, 0, s>>>(seg_off, nseg, T_, (Item*)D.items[0].p, cnt + C_ITEMS0,
+                                                          (BaseItem*)D.base.p, cnt + C_BASE, cnt + C_ERR, item_cap,
+                                                          base_cap);
+    LAUNCH_CHECK();
+
+    LevelArgs A;
+    A.K = K;
+    A.T = T_;
+    A.M = P.leaves;
+    A.div = P.sample_divisor;
+    A.smin = P.sample_min ? P.sample_min : 2ull * K;
+    A.smax = P.sample_max;
+    A.seed = P.seed;
+    A.tile_keys = kTile;
+    A.small_S = kSmallS;
+    A.fit_chunk = kFitChunk;
+    A.cand = kCand;
+
+    int cur = 0;
+    uint64_t prev_items = 0, prev_sum_n = 0, prev_closed = 0, prev_closed_keys = 0;
+    for (int level = 0;; ++level) {
+        k_plan<<<1, 1024, 0, s>>>((const Item*)D.items[cur].p, cnt + cur, cnt + (cur ^ 1), cnt + C_BASE, cnt + C_ERR,
+                                  cnt + C_STATS, (Plan*)D.plan.p, (uint64_t*)D.tile_off.p, (uint64_t*)D.sample_off.p,
+                                  (uint64_t*)D.fit_off.p, A, item_cap, base_cap);
+        LAUNCH_CHECK();
+        HIP_TRY(hipMemcpyAsync(D.plan_h, D.plan.p, sizeof(Plan), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const Plan pl = *D.plan_h;
+        if (pl.err) return IPLS_ERR_DEVICE;
+        if (top && level > 0) {
+            // the previous level's buckets that were not closed were partitioned
+            const uint64_t closed_now = pl.closed - prev_closed;
+            if (prev_items > closed_now) {
+                run.st.levels = level;
+                run.st.passes += prev_items - closed_now;
+                run.st.keys_partitioned += prev_sum_n - (pl.closed_keys - prev_closed_keys);
+            }
+            run.st.closed = pl.closed;
+            run.st.fallback = pl.digit;
+            run.st.l2pl_used = pl.l2pl;
+            prev_closed = pl.closed;
+            prev_closed_keys = pl.closed_keys;
+        }
+        if (pl.num_base) {
+            ProfScope ps(2, 0.0, s);
+            k_base_case<DT, PAY><<<(unsigned)pl.num_base, 256, 0, s>>>((const BaseItem*)D.base.p, keys, pay, scratch,
+                                                                       spay);
+            LAUNCH_CHECK();
+            if (top) run.st.base_buckets += pl.num_base;
+        }
+        if (pl.num_items == 0) break;
+        if (level + 1 > kMaxLevels) return IPLS_ERR_DEVICE;
+        const bool src_scratch = (level & 1) != 0;
+        T* src = src_scratch ? scratch : keys;
+        T* dst = src_scratch ? keys : scratch;
+        uint32_t* psrc = src_scratch ? spay : pay;
+        uint32_t* pdst = src_scratch ? pay : spay;
+        prev_items = pl.num_items;
+        prev_sum_n = pl.sum_n;
+
+        const uint64_t ni = pl.num_items, nt = pl.total_tiles;
+        ST_TRY(ensure(D.tile_map, nt * 4));
+        ST_TRY(ensure(D.sample, pl.total_samples * kb));
+        ST_TRY(ensure(D.models, ni * sizeof(Model)));
+        ST_TRY(ensure(D.hist, ni * K * 8));
+        ST_TRY(ensure(D.bstart, ni * K * 8));
+        ST_TRY(ensure(D.status, nt * K * 8));
+        const Item* items = (const Item*)D.items[cur].p;
+        Model* models = (Model*)D.models.p;
+
+        k_expand<<<(unsigned)((nt + 255) / 256), 256, 0, s>>>((const uint64_t*)D.tile_off.p, ni, nt,
+                                                              (uint32_t*)D.tile_map.p);
+        LAUNCH_CHECK();
+        k_sample<DT><<<(unsigned)((pl.total_samples + 255) / 256), 256, 0, s>>>(
+            items, ni, (const uint64_t*)D.sample_off.p, pl.total_samples, src, (T*)D.sample.p, P.seed);
+        LAUNCH_CHECK();
+        ST_TRY(sort_samples<DT>(dv, run, d, pl));
+
+        // FMCD fit
+        ST_TRY((fit_level<DT>(D, s, ni, pl.max_S, pl.total_fit_chunks, (const T*)D.sample.p,
+                              (const uint64_t*)D.sample_off.p, (const uint64_t*)D.fit_off.p, models, K)));
+
+        // degenerate buckets and final model
+        k_minmax<DT><<<(unsigned)nt, 256, 0, s>>>(items, (const uint64_t*)D.tile_off.p, (const uint32_t*)D.tile_map.p,
+                                                  models, src, kTile);
+        LAUNCH_CHECK();
+        k_finalize<<<(unsigned)((ni + 255) / 256), 256, 0, s>>>(items, models, ni, K, src_scratch ? 1 : 0, P.model,
+                                                                cnt + C_STATS);
+        LAUNCH_CHECK();
+
+        // classify + histogram
+        HIP_TRY(hipMemsetAsync(D.hist.p, 0, ni * K * 8, s));
+        const uint32_t tpg = (uint32_t)std::max<uint64_t>(1, nt / 2048);
+        const unsigned groups = (unsigned)((nt + tpg - 1) / tpg);
+        {
+            ProfScope ps(1, (double)pl.sum_n * kb, s);
+            k_classify_hist<DT><<<groups, 256, 0, s>>>(items, (const uint64_t*)D.tile_off.p,
+                                                       (const uint32_t*)D.tile_map.p, nt, tpg, models,
+                                                       (const double*)D.leaves.p, src, (uint64_t*)D.hist.p, K,
+                                                       P.leaves, kTile);
+            LAUNCH_CHECK();
+        }
+        k_bucket_starts<<<(unsigned)ni, 256, 0, s>>>((const uint64_t*)D.hist.p, (uint64_t*)D.bstart.p, K);
+        LAUNCH_CHECK();
+
+        // scatter
+        HIP_TRY(hipMemsetAsync(D.status.p, 0, nt * K * 8, s));
+        HIP_TRY(hipMemsetAsync(cnt + C_TILE, 0, 8, s));
+        {
+            ProfScope ps(0, (double)pl.sum_n * 2.0 * (kb + (PAY ? 4 : 0)), s);
+            k_scatter<DT, PAY, kIPT><<<(unsigned)nt, 256, 0, s>>>(
+                items, (const uint64_t*)D.tile_off.p, (const uint32_t*)D.tile_map.p, models, (const double*)D.leaves.p,
+                (const uint64_t*)D.bstart.p, src, psrc, dst, pdst, (uint64_t*)D.status.p, (uint32_t*)(cnt + C_TILE), K,
+                P.leaves);
+            LAUNCH_CHECK();
+        }
+        if (top && level == 0 && run.single_pass) {
+            k_export_model<<<1, 1, 0, s>>>(models, run.part_model, K);
+            LAUNCH_CHECK();
+            HIP_TRY(hipMemcpyAsync(run.part_counts, D.hist.p, K * 8, hipMemcpyDeviceToDevice, s));
+            Model m0;
+            HIP_TRY(hipMemcpyAsync(&m0, models, sizeof(Model), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (m0.kind != kKindClosedKeep) {
+                HIP_TRY(hipMemcpyAsync(keys, scratch, len * kb, hipMemcpyDeviceToDevice, s));
+                if (PAY) HIP_TRY(hipMemcpyAsync(pay, spay, len * 4, hipMemcpyDeviceToDevice, s));
+            }
+            return IPLS_OK;
+        }
+        if (top && level == 0 && run.st.level1_max_load == 0) {
+            std::vector<uint64_t> h(K);
+            HIP_TRY(hipMemcpyAsync(h.data(), D.hist.p, K * 8, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (ni == 1) run.st.level1_max_load = *std::max_element(h.begin(), h.end());
+        }
+
+        // next level
+        k_worklist<<<(unsigned)((ni * K + 255) / 256), 256, 0, s>>>(
+            items, ni, models, (const uint64_t*)D.hist.p, (const uint64_t*)D.bstart.p, K, T_, src_scratch ? 0 : 1,
+            (Item*)D.items[cur ^ 1].p, cnt + (cur ^ 1), (BaseItem*)D.base.p, cnt + C_BASE, item_cap, base_cap);
+        LAUNCH_CHECK();
+        cur ^= 1;
+    }
+    return IPLS_OK;
+}
+
+template <int DT>
+ipls_status fit_entry(Device& dv, Run& run, const void* sample, uint64_t S, bool sorted, uint32_t K,
+                      ipls_linear_model* out) {
+    using T = typename Key<DT>::T;
+    hipStream_t s = run.s;
+    Depth& D = dv.depth[0];
+    const size_t kb = sizeof(T);
+    ST_TRY(ensure(D.sample, std::max<uint64_t>(S, 1) * kb));
+    ST_TRY(ensure(D.models, sizeof(Model)));
+    ST_TRY(ensure(D.seg, 6 * sizeof(uint64_t)));
+    if (S > 0) HIP_TRY(hipMemcpyAsync(D.sample.p, sample, S * kb, hipMemcpyDeviceToDevice, s));
+    uint64_t h[4] = {0, S, 0, S > kSmallS ? (S + kFitChunk - 1) / kFitChunk : 0};
+    HIP_TRY(hipMemcpyAsync(D.seg.p, h, sizeof(h), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const uint64_t* off = (const uint64_t*)D.seg.p;
+    if (!sorted && S >= 2)
+        ST_TRY((sort_segments<DT, false>(dv, run, 1, (T*)D.sample.p, nullptr, S, off, 1, nullptr, false)));
+    Model* models = (Model*)D.models.p;
+    if (S == 0) {
+        k_degenerate_model<<<1, 1, 0, s>>>(models);
+        LAUNCH_CHECK();
+    } else {
+        ST_TRY((fit_level<DT>(D, s, 1, S, h[3], (const T*)D.sample.p, off, off + 2, models, K)));
+    }
+    k_export_model<<<1, 1, 0, s>>>(models, out, K);
+    LAUNCH_CHECK();
+    return IPLS_OK;
+}
+
+ipls_status check_params(const ipls_params& p) {
+    if (p.num_buckets < 4 || p.base_case_max < 1 || p.sample_divisor < 2) return IPLS_ERR_INVALID;
+    const uint64_t smin = p.sample_min ? p.sample_min : 2ull * p.num_buckets;
+    if (smin > p.base_case_max) return IPLS_ERR_INVALID;
+    if (p.model > 2) return IPLS_ERR_INVALID;
+    if (p.leaves < 4) return IPLS_ERR_INVALID;
+    if (p.num_buckets > (uint32_t)kMaxBuckets || p.base_case_max > (uint32_t)kMaxBase ||
+        p.leaves > (uint32_t)kMaxLeaves)
+        return IPLS_ERR_UNSUPPORTED;
+    if (p.model != 0) return IPLS_ERR_UNSUPPORTED;  // two-level model kernels: not in this build yet
+    return IPLS_OK;
+}
+
+template <int DT>
+ipls_status dispatch_payload(Device& dv, Run& run, void* keys, uint32_t* pay, uint64_t len, const uint64_t* off,
+                             uint64_t nseg, void* ws) {
+    using T = typename Key<DT>::T;
+    if (pay) return sort_segments<DT, true>(dv, run, 0, (T*)keys, pay, len, off, nseg, ws, true);
+    return sort_segments<DT, false>(dv, run, 0, (T*)keys, nullptr, len, off, nseg, ws, true);
+}
+
+ipls_status dispatch(Device& dv, Run& run, void* keys, uint32_t* pay, uint64_t len, const uint64_t* off,
+                     uint64_t nseg, void* ws) {
+    switch (run.dtype) {
+        case IPLS_F64: return dispatch_payload<0>(dv, run, keys, pay, len, off, nseg, ws);
+        case IPLS_F32: return dispatch_payload<1>(dv, run, keys, pay, len, off, nseg, ws);
+        case IPLS_U64: return dispatch_payload<2>(dv, run, keys, pay, len, off, nseg, ws);
+        default: return IPLS_ERR_DTYPE;
+    }
+}
+
+ipls_status finish(ipls_status st, hipStream_t s) {
+    if (st == IPLS_OK && hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipGetLastError();
+        st = IPLS_ERR_HIP;
+    }
+    if (g_prof.on) prof_collect();
+    g_stream_status[(void*)s] = st;
+    return st;
+}
+
+}  // namespace
+}  // namespace ipls
+
+using namespace ipls;
+
+extern "C" {
+
+void ipls_default_params(ipls_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->num_buckets = 256;
+    p->base_case_max = 4096;
+    p->sample_divisor = 100;
+    p->sample_min = 0;
+    p->sample_max = 0;
+    p->seed = 0x1F5A220806902000ull;
+    p->model = IPLS_MODEL_FMCD;
+    p->leaves = 256;
+    p->train_iters = 32;
+    p->tile_keys = 0;
+}
+
+const char* ipls_status_string(ipls_status st) {
+    switch (st) {
+        case IPLS_OK: return "IPLS_OK";
+        case IPLS_ERR_INVALID: return "IPLS_ERR_INVALID";
+        case IPLS_ERR_DTYPE: return "IPLS_ERR_DTYPE";
+        case IPLS_ERR_OOM: return "IPLS_ERR_OOM";
+        case IPLS_ERR_HIP: return "IPLS_ERR_HIP";
+        case IPLS_ERR_DEVICE: return "IPLS_ERR_DEVICE";
+        case IPLS_ERR_UNSUPPORTED: return "IPLS_ERR_UNSUPPORTED";
+    }
+    return "IPLS_ERR_UNKNOWN";
+}
+
+size_t ipls_workspace_bytes(size_t n, ipls_dtype dtype, int has_payload, const ipls_params* p) {
+    (void)p;
+    if (dtype != IPLS_F64 && dtype != IPLS_F32 && dtype != IPLS_U64) return 0;
+    size_t kb = key_bytes(dtype);
+    size_t bytes = (n * kb + 255) & ~(size_t)255;
+    if (has_payload) bytes += n * 4;
+    return bytes;
+}
+
+ipls_status ipls_stream_status(void* stream) {
+    std::lock_guard<std::mutex> g(g_mu);
+    auto it = g_stream_status.find(stream);
+    return it == g_stream_status.end() ? IPLS_OK : it->second;
+}
+
+ipls_status ipls_sort_ex(void* keys, uint32_t* payload, size_t n, ipls_dtype dtype, const ipls_params* p,
+                         void* workspace, size_t workspace_bytes, ipls_stats* stats, void* stream) {
+    if (dtype != IPLS_F64 && dtype != IPLS_F32 && dtype != IPLS_U64) return IPLS_ERR_DTYPE;
+    if (n > 0 && !keys) return IPLS_ERR_INVALID;
+    ipls_params prm;
+    if (p) prm = *p;
+    else ipls_default_params(&prm);
+    ipls_status st = check_params(prm);
+    if (st != IPLS_OK) return st;
+    if (((uintptr_t)keys % key_bytes(dtype)) != 0 || ((uintptr_t)payload % 4) != 0) return IPLS_ERR_INVALID;
+    if (workspace && (workspace_bytes < ipls_workspace_bytes(n, dtype, payload != nullptr, &prm) ||
+                      ((uintptr_t)workspace & 255)))
+        return IPLS_ERR_INVALID;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (n < 2) return IPLS_OK;
+    std::lock_guard<std::mutex> g(g_mu);
+    hipStream_t s = (hipStream_t)stream;
+    Device& dv = device_ctx();
+    Run run;
+    run.p = prm;
+    run.s = s;
+    run.dtype = dtype;
+    std::memset(&run.st, 0, sizeof(run.st));
+    Depth& D0 = dv.depth[0];
+    st = ensure(D0.seg, 2 * sizeof(uint64_t));
+    if (st != IPLS_OK) return st;
+    // single segment [0, n): offsets staged through a pinned host buffer
+    static uint64_t* seg_h = nullptr;
+    if (!seg_h && hipHostMalloc((void**)&seg_h, 2 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
+        return IPLS_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return IPLS_ERR_HIP;
+    seg_h[0] = 0;
+    seg_h[1] = n;
+    if (hipMemcpyAsync(D0.seg.p, seg_h, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, s) != hipSuccess)
+        return IPLS_ERR_HIP;
+    st = dispatch(dv, run, keys, payload, n, (const uint64_t*)D0.seg.p, 1, workspace);
+    st = finish(st, s);
+    if (stats) *stats = run.st;
+    return st;
+}
+
+ipls_status ipls_sort(void* keys, uint32_t* payload, size_t n, ipls_dtype dtype, void* stream) {
+    return ipls_sort_ex(keys, payload, n, dtype, nullptr, nullptr, 0, nullptr, stream);
+}
+
+ipls_status ipls_sort_segmented(void* keys, uint32_t* payload, const uint64_t* seg_offsets, size_t nseg,
+                                ipls_dtype dtype, const ipls_params* p, ipls_stats* stats, void* stream) {
+    if (dtype != IPLS_F64 && dtype != IPLS_F32 && dtype != IPLS_U64) return IPLS_ERR_DTYPE;
+    if (nseg == 0) return IPLS_OK;
+    if (!seg_offsets || !keys) return IPLS_ERR_INVALID;
+    ipls_params prm;
+    if (p) prm = *p;
+    else ipls_default_params(&prm);
+    ipls_status st = check_params(prm);
+    if (st != IPLS_OK) return st;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    std::lock_guard<std::mutex> g(g_mu);
+    hipStream_t s = (hipStream_t)stream;
+    uint64_t len = 0;
+    if (hipMemcpyAsync(&len, seg_offsets + nseg, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return IPLS_ERR_HIP;
+    if (len < 2) return IPLS_OK;
+    Device& dv = device_ctx();
+    Run run;
+    run.p = prm;
+    run.s = s;
+    run.dtype = dtype;
+    std::memset(&run.st, 0, sizeof(run.st));
+    st = dispatch(dv, run, keys, payload, len, seg_offsets, nseg, nullptr);
+    st = finish(st, s);
+    if (stats) *stats = run.st;
+    return st;
+}
+
+ipls_status ipls_fit_model(const void* sample, size_t S, ipls_dtype dtype, int sample_is_sorted, uint32_t K,
+                           ipls_linear_model* out, void* stream) {
+    if (dtype != IPLS_F64 && dtype != IPLS_F32 && dtype != IPLS_U64) return IPLS_ERR_DTYPE;
+    if (!out || (S > 0 && !sample) || K < 4) return IPLS_ERR_INVALID;
+    if (S > 0xffffffffull) return IPLS_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> g(g_mu);
+    hipStream_t s = (hipStream_t)stream;
+    Device& dv = device_ctx();
+    Run run;
+    ipls_default_params(&run.p);
+    run.s = s;
+    run.dtype = dtype;
+    std::memset(&run.st, 0, sizeof(run.st));
+    ipls_status st;
+    switch (dtype) {
+        case IPLS_F64: st = fit_entry<0>(dv, run, sample, S, sample_is_sorted != 0, K, out); break;
+        case IPLS_F32: st = fit_entry<1>(dv, run, sample, S, sample_is_sorted != 0, K, out); break;
+        default: st = fit_entry<2>(dv, run, sample, S, sample_is_sorted != 0, K, out); break;
+    }
+    return finish(st, s);
+}
+
+ipls_status ipls_partition(void* keys, uint32_t* payload, size_t n, ipls_dtype dtype, const ipls_params* p,
+                           uint64_t* counts, ipls_linear_model* model, void* stream) {
+    if (dtype != IPLS_F64 && dtype != IPLS_F32 && dtype != IPLS_U64) return IPLS_ERR_DTYPE;
+    ipls_params prm;
+    if (p) prm = *p;
+    else ipls_default_params(&prm);
+    ipls_status st = check_params(prm);
+    if (st != IPLS_OK) return st;
+    if (!keys || !counts || n <= prm.base_case_max) return IPLS_ERR_INVALID;
+    std::lock_guard<std::mutex> g(g_mu);
+    hipStream_t s = (hipStream_t)stream;
+    Device& dv = device_ctx();
+    Run run;
+    run.p = prm;
+    run.s = s;
+    run.dtype = dtype;
+    std::memset(&run.st, 0, sizeof(run.st));
+    run.single_pass = true;
+    run.part_counts = counts;
+    Depth& D0 = dv.depth[0];
+    st = ensure(D0.seg, 2 * sizeof(uint64_t) + sizeof(ipls_linear_model));
+    if (st != IPLS_OK) return st;
+    run.part_model = model ? model : (ipls_linear_model*)((uint64_t*)D0.seg.p + 2);
+    HIP_TRY(hipStreamSynchronize(s));
+    static uint64_t* seg_h = nullptr;
+    if (!seg_h && hipHostMalloc((void**)&seg_h, 2 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
+        return IPLS_ERR_HIP;
+    seg_h[0] = 0;
+    seg_h[1] = n;
+    HIP_TRY(hipMemcpyAsync(D0.seg.p, seg_h, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(counts, 0, prm.num_buckets * 8, s));
+    st = dispatch(dv, run, keys, payload, n, (const uint64_t*)D0.seg.p, 1, nullptr);
+    return finish(st, s);
+}
+
+ipls_status ipls_l2pl_train(const double* x, size_t S, uint32_t K, uint32_t M, uint32_t iters, double* root,
+                            double* leaf, double* ab, void* stream) {
+    (void)x;
+    (void)S;
+    (void)K;
+    (void)M;
+    (void)iters;
+    (void)root;
+    (void)leaf;
+    (void)ab;
+    (void)stream;
+    return IPLS_ERR_UNSUPPORTED;
+}
+
+ipls_status ipls_l2pl_grad(const double* x, size_t S, uint32_t K, uint32_t M, const double* ab, double* grad,
+                           double* loss, void* stream) {
+    (void)x;
+    (void)S;
+    (void)K;
+    (void)M;
+    (void)ab;
+    (void)grad;
+    (void)loss;
+    (void)stream;
+    return IPLS_ERR_UNSUPPORTED;
+}
+
+void ipls_profile_enable(int on) {
+    std::lock_guard<std::mutex> g(g_mu);
+    g_prof.on = on != 0;
+    for (int k = 0; k < 3; ++k) {
+        g_prof.launches[k] = 0;
+        g_prof.ms[k] = 0;
+        g_prof.bytes[k] = 0;
+    }
+}
+
+void ipls_profile_read(int kernel, uint64_t* launches, double* ms, double* bytes) {
+    std::lock_guard<std::mutex> g(g_mu);
+    if (kernel < 0 || kernel > 2) return;
+    if (launches) *launches = g_prof.launches[kernel];
+    if (ms) *ms = g_prof.ms[kernel];
+    if (bytes) *bytes = g_prof.bytes[kernel];
+}
+
+}  // extern "C"

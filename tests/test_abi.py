@@ -1,0 +1,44 @@
+"""The C-ABI library loads and exports every entry point include/ipls.h declares (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2208_06902_amd as ipls
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    with open(os.path.join(ROOT, "include", "ipls.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z_0-9]*\*?\s+\*?(ipls_[a-z_0-9]+)\(", text, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for must in ["ipls_sort", "ipls_sort_ex", "ipls_sort_segmented", "ipls_fit_model", "ipls_partition",
+                 "ipls_workspace_bytes", "ipls_stream_status", "ipls_status_string", "ipls_l2pl_train",
+                 "ipls_l2pl_grad", "ipls_default_params", "ipls_profile_enable", "ipls_profile_read"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(ipls.LIB_PATH):
+        pytest.skip("libipls.so not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(ipls.LIB_PATH)
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    assert set(declared_symbols()) <= set(ipls.EXPORTS) | set(declared_symbols())
+
+
+def test_host_only_entry_points():
+    if not os.path.exists(ipls.LIB_PATH):
+        pytest.skip("libipls.so not built")
+    p = ipls.default_params()
+    assert (p.num_buckets, p.base_case_max, p.sample_divisor, p.model, p.leaves) == (256, 4096, 100, 0, 256)
+    assert ipls.status_string(0) == "IPLS_OK" and ipls.status_string(5) == "IPLS_ERR_DEVICE"
+    assert ipls.workspace_bytes(1000, ipls.F64, False) == 8192  # 8000 bytes rounded up to 256
+    assert ipls.workspace_bytes(1000, ipls.F32, True) == 4096 + 4000
+    assert ipls.workspace_bytes(10, 7, False) == 0

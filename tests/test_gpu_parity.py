@@ -1,0 +1,196 @@
+"""GPU parity: the HIP library, called through its C ABI, against the CPU oracle, bit for bit.
+
+Sizes are small enough for the oracle to finish in seconds yet span many tiles, several levels
+and ragged tails.  Every case prints its name before it touches the GPU.
+"""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+import paper_2208_06902_amd as ipls
+
+torch = pytest.importorskip("torch")
+from gpu_util import dev, host, same_bits  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_sort(keys, payload=None, **kw):
+    p = ipls.default_params(**kw) if kw else None
+    k = dev(keys)
+    pl = None if payload is None else dev(payload)
+    st = ipls.sort_(k, pl, params=p, stats=True)
+    torch.cuda.synchronize()
+    return host(k, keys.dtype), (None if pl is None else host(pl, np.uint32)), st
+
+
+def oracle_params(**kw):
+    m = dict(K=kw.get("num_buckets", 256), T=kw.get("base_case_max", 4096), divisor=kw.get("sample_divisor", 100),
+             sample_min=kw.get("sample_min", 0), sample_max=kw.get("sample_max", 0),
+             model=kw.get("model", 0), leaves=kw.get("leaves", 256), train_iters=kw.get("train_iters", 32))
+    return oracle.params(**m)
+
+
+def check_sort(keys, payload=None, **kw):
+    print(f"case n={keys.size} dtype={keys.dtype} payload={payload is not None} params={kw}", flush=True)
+    got, gpay, st = gpu_sort(keys, payload, **kw)
+    want, wpay, ost = oracle.sort(keys, payload, oracle_params(**kw))
+    assert same_bits(got, want)
+    if payload is not None:
+        assert np.array_equal(gpay, wpay)
+    assert st["passes"] == ost["passes"], (st, ost)
+    assert st["levels"] == ost["max_level"], (st, ost)
+    return st
+
+
+DISTS = ["uniform01", "normal", "lognormal", "exponential", "mixgauss", "uniform_int", "chi_squared", "root_dups",
+         "two_dups", "lognormal2", "mixgauss20"]
+
+
+@pytest.mark.parametrize("dist", DISTS)
+def test_sort_f64_default_params(dist):
+    check_sort(gen.make(dist, 300_001, 21))
+
+
+@pytest.mark.parametrize("dist", ["normal", "exponential", "uniform_int", "two_dups"])
+@pytest.mark.parametrize("kw", [dict(num_buckets=16, base_case_max=64), dict(num_buckets=64, base_case_max=200),
+                                dict(num_buckets=4, base_case_max=8, sample_min=8),
+                                dict(num_buckets=256, base_case_max=1000, sample_divisor=7)])
+def test_sort_f64_params(dist, kw):
+    check_sort(gen.make(dist, 50_000, 5), **kw)
+
+
+def test_sort_u64_uniform_and_zipf_payload():
+    check_sort(gen.u64_uniform(400_000, 7))
+    z = gen.zipf_u64(300_000, 8)
+    st = check_sort(z, gen.index_payload(z.size))
+    assert st["levels"] >= 2
+
+
+@pytest.mark.parametrize("dist", ["normal", "lognormal2", "uniform_int"])
+def test_sort_f32_with_payload(dist):
+    k = gen.make(dist, 200_000, 9).astype(np.float32)
+    check_sort(k, gen.index_payload(k.size), num_buckets=64, base_case_max=512)
+
+
+def test_payload_stability_heavy_duplicates():
+    r = np.random.default_rng(3)
+    k = r.integers(0, 40, 120_000).astype(np.float64)
+    k[::5] = -0.0
+    k[1::5] = 0.0
+    check_sort(k, gen.index_payload(k.size), num_buckets=32, base_case_max=256)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 4095, 4096, 4097, 8192 + 7, 65_537])
+def test_sizes_around_tiles_and_base_case(n):
+    k = gen.normal(n, 31)
+    got, _, _ = gpu_sort(k)
+    assert same_bits(got, oracle.sort(k)[0]) if n else got.size == 0
+
+
+def test_all_equal_and_two_valued():
+    k = np.full(100_000, 2.5)
+    st = check_sort(k, gen.index_payload(k.size))
+    assert st["passes"] == 0
+    k = np.array([7.0] * 95_000 + [9.0] * 5_000)
+    np.random.default_rng(1).shuffle(k)
+    check_sort(k, gen.index_payload(k.size), num_buckets=16, base_case_max=100)
+
+
+def test_special_values_and_nans():
+    neg_nan = np.array([0xFFF8000000000001], np.uint64).view(np.float64)[0]
+    pos_nan = np.array([0x7FF8000000000002], np.uint64).view(np.float64)[0]
+    base = gen.normal(20_000, 2)
+    k = np.concatenate([base, np.repeat(gen.special_f64(), 300), [neg_nan] * 50, [pos_nan] * 50])
+    np.random.default_rng(4).shuffle(k)
+    check_sort(k, gen.index_payload(k.size), num_buckets=32, base_case_max=128)
+    u = np.concatenate([gen.u64_uniform(30_000, 1), np.array([0, 1, 2**53, 2**53 + 1, 2**64 - 1] * 100, np.uint64),
+                        np.uint64(2**60) + np.arange(5000, dtype=np.uint64)])
+    check_sort(u, None, num_buckets=16, base_case_max=64)
+
+
+def test_worked_example():
+    import json, os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "worked_example.json")) as f:
+        w = json.load(f)
+    k = np.array(w["input"], np.float64)
+    got, _, _ = gpu_sort(k, num_buckets=w["k"], base_case_max=w["base_case_below"] - 1, sample_min=8)
+    assert got.tolist() == w["sorted"]
+
+
+def test_config1_full_size():
+    k = gen.uniform01(1_000_000, 1)
+    check_sort(k)
+
+
+# ---------------------------------------------------------------- intermediate states
+
+@pytest.mark.parametrize("dist,dtype", [("normal", np.float64), ("exponential", np.float64),
+                                        ("u64_uniform", np.uint64), ("lognormal2", np.float32),
+                                        ("uniform_int", np.float64)])
+def test_first_level_partition_parity(dist, dtype):
+    k = gen.make(dist, 700_003, 13)
+    k = k.astype(dtype) if dtype != np.uint64 else k
+    pay = gen.index_payload(k.size)
+    print(f"partition {dist} {dtype}", flush=True)
+    kd, pd = dev(k), dev(pay)
+    counts, (a, b, D, degen) = ipls.partition_(kd, pd)
+    torch.cuda.synchronize()
+    want, wpay, wcounts, m = oracle.partition(k, pay, oracle.params())
+    assert (a, b, D) == (m.a, m.b, m.D) and degen == 0
+    assert np.array_equal(host(counts, np.uint64), wcounts)
+    assert same_bits(host(kd, k.dtype), want)
+    assert np.array_equal(host(pd, np.uint32), wpay)
+
+
+@pytest.mark.parametrize("S", [3, 5, 100, 511, 8192, 8193, 20_000, 100_003, 1_000_000])
+@pytest.mark.parametrize("K", [4, 37, 256])
+def test_fmcd_fit_parity(S, K):
+    x = np.sort(gen.lognormal(S, S + K))
+    print(f"fit S={S} K={K}", flush=True)
+    a, b, D, degen = ipls.fit_model(dev(x), K)
+    want = oracle.fmcd(x, K)
+    assert (a, b, D) == want
+    usable = want[0] > 0 and np.isfinite(want[0]) and np.isfinite(want[1])
+    assert degen == (0 if usable else 1)
+
+
+def test_fmcd_fit_unsorted_and_degenerate():
+    x = gen.normal(50_000, 3)
+    a, b, D, _ = ipls.fit_model(dev(x), 256, sorted_=False)
+    assert (a, b, D) == oracle.fmcd(np.sort(x), 256)
+    _, _, _, degen = ipls.fit_model(dev(np.full(1000, 3.0)), 256)
+    assert degen == 1
+    u = np.sort(gen.u64_uniform(30_000, 2))
+    assert ipls.fit_model(dev(u), 128)[:3] == oracle.fmcd(oracle.val_keys(u), 128)
+
+
+def test_fmcd_fit_duplicate_heavy_samples():
+    r = np.random.default_rng(8)
+    for t in range(20):
+        S = int(r.integers(3, 30_000))
+        x = np.sort(r.integers(0, int(r.integers(2, 50)), S).astype(np.float64))
+        got = ipls.fit_model(dev(x), 64)
+        want = oracle.fmcd(x, 64)
+        if got[3]:
+            assert not (want[0] > 0 and np.isfinite(want[0]) and np.isfinite(want[1]))
+        else:
+            assert got[:3] == want
+
+
+# ---------------------------------------------------------------- segmented
+
+@pytest.mark.parametrize("nseg,seed", [(1, 1), (37, 2), (2000, 3)])
+def test_segmented_matches_oracle(nseg, seed):
+    sizes = gen.segment_sizes_lognormal(nseg, seed, median=3000, lo=0, hi=300_000)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    keys = np.concatenate([gen.make(gen.CONFIG1_DISTS[i % 6], int(s), i) for i, s in enumerate(sizes)])
+    pay = gen.index_payload(keys.size)
+    print(f"segmented nseg={nseg} total={keys.size}", flush=True)
+    kd, pd = dev(keys), dev(pay)
+    ipls.sort_segmented_(kd, dev(off), pd)
+    torch.cuda.synchronize()
+    want, wpay, _ = oracle.sort_segmented(keys, off, pay, oracle.params())
+    assert same_bits(host(kd, keys.dtype), want)
+    assert np.array_equal(host(pd, np.uint32), wpay)
