@@ -50,13 +50,45 @@ struct Model {
 };
 
 // Level plan, computed on the device from the item list and read back by the host.
+constexpr int kBaseClasses = 7;  // base-case size classes: n <= 64 * 2^c keys, c = 0..6
+
 struct Plan {
     uint64_t num_items, num_base, total_tiles, total_samples, total_fit_chunks, max_S, max_n, sum_n;
     uint64_t err;
     uint64_t closed, digit, l2pl;  // buckets closed / split by digit / by the two-level model so far
     uint64_t closed_keys;          // keys of closed buckets so far
-    uint64_t pad[3];
+    uint64_t base_keys;            // keys in this level's base-case buckets
+    uint64_t cls_count[kBaseClasses];
+    uint64_t total_chunks;
 };
+
+// counters of one nesting depth (uint64 slots)
+enum : int {
+    C_ITEMS0 = 0, C_ITEMS1 = 1, C_BASE = 2, C_ERR = 3, C_TILE = 4,
+    C_STATS = 5,      // 4 slots: closed buckets, digit splits, two-level models, closed keys
+    C_BASEKEYS = 9,   // keys appended to the base-case list
+    C_CLS = 10,       // 7 slots: base-case buckets per size class
+    C_N = 32
+};
+
+// Base-case buckets are appended to one list split into a fixed region per size class.  A bucket
+// of class c >= 1 holds more than 32 * 2^c keys, so at most len / (32 * 2^c) of them exist;
+// class 0 gets the general bound.
+struct BaseLayout {
+    uint64_t off[kBaseClasses + 1];
+    uint64_t cap[kBaseClasses];
+};
+
+// size class of a base-case bucket: the smallest c with n <= 64 * 2^c
+__device__ __host__ inline int base_class(uint32_t n) {
+    int c = 0;
+    uint32_t cap = 64;
+    while (cap < n && c < kBaseClasses - 1) {
+        cap <<= 1;
+        ++c;
+    }
+    return c;
+}
 
 // Error bits of the device error word.
 enum : uint64_t { kErrOffsets = 1, kErrCapacity = 2, kErrProgress = 4 };
@@ -71,6 +103,7 @@ struct Key;
 template <>
 struct Key<0> {  // fp64
     using T = uint64_t;
+    using O = uint64_t;  // ord type
     __device__ static inline uint64_t ord(T u) { return (u >> 63) ? ~u : (u | 0x8000000000000000ull); }
     __device__ static inline T from_ord(uint64_t o) { return (o >> 63) ? (o & 0x7fffffffffffffffull) : ~o; }
     __device__ static inline double val(T u) { return __longlong_as_double((long long)u); }
@@ -80,6 +113,7 @@ struct Key<0> {  // fp64
 template <>
 struct Key<1> {  // fp32
     using T = uint32_t;
+    using O = uint32_t;
     __device__ static inline uint64_t ord(T u) { return (u & 0x80000000u) ? (uint64_t)(uint32_t)~u : (uint64_t)(u | 0x80000000u); }
     __device__ static inline T from_ord(uint64_t o) {
         uint32_t u = (uint32_t)o;
@@ -92,6 +126,7 @@ struct Key<1> {  // fp32
 template <>
 struct Key<2> {  // uint64
     using T = uint64_t;
+    using O = uint64_t;
     __device__ static inline uint64_t ord(T u) { return u; }
     __device__ static inline T from_ord(uint64_t o) { return o; }
     __device__ static inline double val(T u) { return __ull2double_rn(u); }
@@ -209,6 +244,58 @@ __device__ inline double wave_tree_sum(double v) {
         v = v + o;
     }
     return v;
+}
+
+// Wave-aggregated append: every lane with `want` gets a distinct slot of `counter`, with one atomic
+// per wave.  All active lanes of the wave must call it.
+__device__ inline uint64_t wave_append(bool want, uint64_t* counter) {
+    const uint64_t m = __ballot(want);
+    if (m == 0) return 0;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    uint64_t base = 0;
+    if ((int)lane_id() == leader) base = atomicAdd((unsigned long long*)counter, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader, kWave);
+    return base + count_below(m);
+}
+
+// Block-aggregated append for the worklist and the seeds.  Every thread of the block calls it with
+// a channel: -1 (nothing), 0 (a next-level item) or 1 + c (a base-case bucket of size class c);
+// it returns the thread's slot in its channel and adds `keys` of base-case buckets to the key
+// counter.  One global atomic per channel per block.
+struct AppendScratch {
+    uint32_t wc[kBaseClasses + 1][kBlock / kWave];
+    uint64_t gbase[kBaseClasses + 1];
+    unsigned long long keys;
+};
+
+__device__ inline uint64_t block_append(int ch, uint64_t keys, AppendScratch& sc, uint64_t* item_counter,
+                                        uint64_t* cls_counter, uint64_t* key_counter) {
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
+    uint32_t local = 0;
+    if (threadIdx.x == 0) sc.keys = 0;
+    for (int c = 0; c <= kBaseClasses; ++c) {
+        const uint64_t m = __ballot(ch == c);
+        if (lane == 0) sc.wc[c][wave] = (uint32_t)__popcll(m);
+        if (ch == c) local = count_below(m);
+    }
+    uint64_t v = ch > 0 ? keys : 0;
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, kWave);
+    __syncthreads();
+    if (lane == 0 && v) atomicAdd(&sc.keys, (unsigned long long)v);
+    if (threadIdx.x <= (uint32_t)kBaseClasses) {
+        const int c = threadIdx.x;
+        uint32_t tot = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) tot += sc.wc[c][w];
+        uint64_t* ctr = c == 0 ? item_counter : &cls_counter[c - 1];
+        sc.gbase[c] = tot ? atomicAdd((unsigned long long*)ctr, (unsigned long long)tot) : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && sc.keys) atomicAdd((unsigned long long*)key_counter, sc.keys);
+    if (ch < 0) return 0;
+    uint32_t woff = 0;
+    for (uint32_t w = 0; w < wave; ++w) woff += sc.wc[ch][w];
+    return sc.gbase[ch] + woff + local;
 }
 
 __device__ inline uint32_t bit_length(uint64_t v) { return v ? 64u - (uint32_t)__clzll((long long)v) : 0u; }

@@ -19,39 +19,44 @@ namespace ipls {
 struct LevelArgs {
     uint32_t K, T, M;
     uint64_t div, smin, smax, seed;
-    uint32_t tile_keys, small_S, fit_chunk, cand;
+    uint32_t tile_keys, small_S, fit_chunk, cand, chunk;
 };
 
 // ------------------------------------------------------------------ plan
 // One workgroup of 1024 threads: per-item prefix sums of tiles, samples and large-sample fit
 // chunks; totals and maxima for the host.  Consumes the item and base-case counters of the
 // previous level and resets the counters the coming level appends to.
-__global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* item_count_cur, uint64_t* item_count_next,
-                                               uint64_t* base_count, uint64_t* err_word, const uint64_t* stat_counts,
-                                               Plan* plan, uint64_t* tile_off,
-                                               uint64_t* sample_off, uint64_t* fit_off, LevelArgs A, uint64_t item_cap,
-                                               uint64_t base_cap) {
+__global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* cnt, int cur, Plan* plan, uint64_t* tile_off,
+                                               uint64_t* sample_off, uint64_t* fit_off, uint64_t* chunk_off,
+                                               LevelArgs A, uint64_t item_cap, BaseLayout bl) {
     __shared__ uint64_t sc[16];
     __shared__ uint64_t s_max[3];
-    const uint64_t num = *item_count_cur;
-    const uint64_t nb = *base_count;
+    const uint64_t num = cnt[C_ITEMS0 + cur];
+    uint64_t nb = 0;
+    bool base_over = false;
+    for (int c = 0; c < kBaseClasses; ++c) {
+        nb += cnt[C_CLS + c];
+        base_over |= cnt[C_CLS + c] > bl.cap[c];
+    }
     if (threadIdx.x == 0) { s_max[0] = s_max[1] = s_max[2] = 0; }
     __syncthreads();
-    uint64_t run_t = 0, run_s = 0, run_f = 0;
+    uint64_t run_t = 0, run_s = 0, run_f = 0, run_c = 0;
     const uint64_t use = num < item_cap ? num : item_cap;
     for (uint64_t base = 0; base < use; base += blockDim.x) {
         uint64_t i = base + threadIdx.x;
-        uint64_t nt = 0, ns = 0, nf = 0, n = 0;
+        uint64_t nt = 0, ns = 0, nf = 0, nc = 0, n = 0;
         if (i < use) {
             n = items[i].n;
             nt = (n + A.tile_keys - 1) / A.tile_keys;
+            nc = (nt + A.chunk - 1) / A.chunk;
             ns = sample_size(n, A.div, A.smin, A.smax);
             nf = ns > A.small_S ? (ns + A.fit_chunk - 1) / A.fit_chunk : 0;
             atomicMax((unsigned long long*)&s_max[0], (unsigned long long)ns);
             atomicMax((unsigned long long*)&s_max[1], (unsigned long long)n);
             atomicAdd((unsigned long long*)&s_max[2], (unsigned long long)n);
         }
-        uint64_t tt, ts, tf;
+        uint64_t tt, ts, tf, tc;
+        uint64_t ec = block_exclusive_sum<uint64_t>(nc, sc, &tc);
         uint64_t et = block_exclusive_sum<uint64_t>(nt, sc, &tt);
         uint64_t es = block_exclusive_sum<uint64_t>(ns, sc, &ts);
         uint64_t ef = block_exclusive_sum<uint64_t>(nf, sc, &tf);
@@ -59,7 +64,9 @@ __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* item
             tile_off[i] = run_t + et;
             sample_off[i] = run_s + es;
             fit_off[i] = run_f + ef;
+            chunk_off[i] = run_c + ec;
         }
+        run_c += tc;
         run_t += tt;
         run_s += ts;
         run_f += tf;
@@ -69,11 +76,13 @@ __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* item
         tile_off[use] = run_t;
         sample_off[use] = run_s;
         fit_off[use] = run_f;
-        uint64_t e = *err_word;
-        if (num > item_cap || nb > base_cap) e |= kErrCapacity;
-        *err_word = e;
+        chunk_off[use] = run_c;
+        plan->total_chunks = run_c;
+        uint64_t e = cnt[C_ERR];
+        if (num > item_cap || base_over) e |= kErrCapacity;
+        cnt[C_ERR] = e;
         plan->num_items = use;
-        plan->num_base = nb < base_cap ? nb : base_cap;
+        plan->num_base = nb;
         plan->total_tiles = run_t;
         plan->total_samples = run_s;
         plan->total_fit_chunks = run_f;
@@ -81,13 +90,20 @@ __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* item
         plan->max_n = s_max[1];
         plan->sum_n = s_max[2];
         plan->err = e;
-        plan->closed = stat_counts[0];
-        plan->digit = stat_counts[1];
-        plan->l2pl = stat_counts[2];
-        plan->closed_keys = stat_counts[3];
-        *item_count_cur = 0;  // this level's list is consumed
-        *item_count_next = 0;
-        *base_count = 0;
+        plan->closed = cnt[C_STATS + 0];
+        plan->digit = cnt[C_STATS + 1];
+        plan->l2pl = cnt[C_STATS + 2];
+        plan->closed_keys = cnt[C_STATS + 3];
+        plan->base_keys = cnt[C_BASEKEYS];
+        for (int c = 0; c < kBaseClasses; ++c) {
+            const uint64_t k = cnt[C_CLS + c];
+            plan->cls_count[c] = k < bl.cap[c] ? k : bl.cap[c];
+            cnt[C_CLS + c] = 0;
+        }
+        cnt[C_BASEKEYS] = 0;
+        cnt[C_ITEMS0 + cur] = 0;  // this level's list is consumed
+        cnt[C_ITEMS0 + (cur ^ 1)] = 0;
+        cnt[C_BASE] = 0;
     }
 }
 
@@ -107,24 +123,22 @@ __global__ void k_expand(const uint64_t* off, uint64_t num_items, uint64_t total
 // ------------------------------------------------------------------ seeds
 // Segments of an array (or of the sample buffer) become level-1 items (> T keys) or base-case
 // buckets (2..T keys, sorted in place).
-__global__ void k_seed(const uint64_t* off, uint64_t nseg, uint32_t T, Item* items, uint64_t* item_count,
-                       BaseItem* base, uint64_t* base_count, uint64_t* err_word, uint64_t item_cap,
-                       uint64_t base_cap) {
-    uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nseg) return;
-    uint64_t a = off[s], b = off[s + 1];
-    if (b < a) {
-        atomicOr((unsigned long long*)err_word, (unsigned long long)kErrOffsets);
-        return;
+__global__ __launch_bounds__(256) void k_seed(const uint64_t* off, uint64_t nseg, uint32_t T, Item* items,
+                                              BaseItem* base, BaseLayout bl, uint64_t* cnt, uint64_t item_cap) {
+    __shared__ AppendScratch sc;
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t a = 0, n = 0;
+    if (s < nseg) {
+        a = off[s];
+        const uint64_t b = off[s + 1];
+        if (b < a) atomicOr((unsigned long long*)&cnt[C_ERR], (unsigned long long)kErrOffsets);
+        else n = b - a;
     }
-    uint64_t n = b - a;
-    if (n > T) {
-        uint64_t i = atomicAdd((unsigned long long*)item_count, 1ull);
-        if (i < item_cap) items[i] = Item{a, n, 0, 0};
-    } else if (n >= 2) {
-        uint64_t i = atomicAdd((unsigned long long*)base_count, 1ull);
-        if (i < base_cap) base[i] = BaseItem{a, (uint32_t)n, 0};
-    }
+    const int cls = base_class((uint32_t)(n <= T ? n : 1));
+    const int ch = n > T ? 0 : (n >= 2 ? 1 + cls : -1);
+    const uint64_t q = block_append(ch, n, sc, &cnt[C_ITEMS0], &cnt[C_CLS], &cnt[C_BASEKEYS]);
+    if (ch == 0 && q < item_cap) items[q] = Item{a, n, 0, 0};
+    if (ch > 0 && q < bl.cap[cls]) base[bl.off[cls] + q] = BaseItem{a, (uint32_t)n, 0};
 }
 
 // ------------------------------------------------------------------ sample gather
@@ -185,11 +199,14 @@ __device__ inline void model_degenerate(Model& m) {
     m.umax = 0ull;
 }
 
-// Small samples (S <= small_S): one workgroup per item, the sample in LDS as fp64, binary search.
+// Small samples (S <= small_S <= kFitLds): one workgroup per item, the sample in LDS as fp64,
+// binary search.
+constexpr int kFitLds = 16384;
+
 template <int DT>
 __global__ __launch_bounds__(256) void k_fmcd_small(const typename Key<DT>::T* sample, const uint64_t* sample_off,
                                                     uint64_t num_items, Model* models, uint32_t K, uint32_t small_S) {
-    extern __shared__ double sx[];
+    __shared__ double sx[kFitLds];
     using KT = Key<DT>;
     const uint64_t i = blockIdx.x;
     if (i >= num_items) return;
@@ -391,55 +408,175 @@ __global__ void k_finalize(const Item* items, Model* models, uint64_t num_items,
     models[i] = m;
 }
 
+// ------------------------------------------------------------------ tiles and chunks
+// A level's keys are cut into tiles of 256 * kIPT keys (tiles never cross items); kChunk
+// consecutive tiles of an item form a chunk.  Counting, the prefix scan and the scatter all use
+// this layout:
+//   k_classify_hist: per chunk, the count of every (tile, bucket) -> the tile's exclusive prefix
+//                    inside its chunk, and the chunk's totals;
+//   k_scan_chunks:   per (item, bucket), the exclusive prefix of the chunk totals, and the item's
+//                    bucket sizes (its histogram);
+//   k_bucket_starts: per item, bucket starts (exclusive prefix over buckets);
+//   k_scatter:       per tile, destination = item start + bucket start + chunk prefix + tile
+//                    prefix + rank inside the tile.
+// Nothing waits on another workgroup: on MI355X a decoupled look-back chain between tiles pays a
+// cross-XCD round trip per step, which measured at half the pass time.
+constexpr int kIPT = 16;
+constexpr int kTileKeys = kBlock * kIPT;
+constexpr int kChunk = 16;
+
+// Wave-level counting of one tile's keys: wave w owns keys [w * 64 * IPT, (w+1) * 64 * IPT) of the
+// tile, row r = 64 consecutive keys.  Lanes of a row holding the same bucket are found with 8
+// ballots on the bucket bits; the row's leader lane adds their number to the wave's LDS counter of
+// that bucket.  rk (when RANKS) receives each key's rank among the wave's earlier keys of its bucket,
+// i.e. its stable position.  wc holds the wave's 256 counters (zero on entry).
+template <int IPT, bool RANKS>
+__device__ inline void wave_count(const uint32_t (&bk)[IPT], uint32_t tn, uint32_t wbase, volatile uint32_t* wc,
+                                  uint32_t (&rk)[IPT]) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const bool valid = wbase + r * kWave + lane < tn;
+        const uint32_t b = bk[r];
+        uint64_t same = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const uint64_t ones = __ballot((b >> bit) & 1u);
+            same &= ((b >> bit) & 1u) ? ones : ~ones;
+        }
+        const uint32_t below = count_below(same);
+        const uint32_t prev = valid ? wc[b] : 0u;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && below == 0) wc[b] = prev + (uint32_t)__popcll(same);
+        __builtin_amdgcn_wave_barrier();
+        if (RANKS) rk[r] = prev + below;
+    }
+}
+
+// Issues the loads of one tile (wave w owns keys [w * 64 * IPT, (w+1) * 64 * IPT), row r = 64
+// consecutive keys), all before any use.
+template <int DT, bool PAY, int IPT>
+__device__ inline void load_tile(const typename Key<DT>::T* src, const uint32_t* src_pay, uint64_t base, uint32_t tn,
+                                 uint32_t wbase, typename Key<DT>::T (&k)[IPT], uint32_t (&p)[PAY ? IPT : 1]) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint32_t idx = wbase + r * kWave + lane;
+        if (idx < tn) {
+            k[r] = src[base + idx];
+            if (PAY) p[r] = src_pay[base + idx];
+        }
+    }
+}
+
+template <int DT, int IPT>
+__device__ inline void classify_tile(uint32_t tn, uint32_t wbase, const Model& m, const double* leaf, uint32_t K,
+                                     uint32_t M, const typename Key<DT>::T (&k)[IPT], uint32_t (&bk)[IPT]) {
+    const uint32_t lane = lane_id();
+    if (m.kind == kKindClosedMove) {
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) bk[r] = 0u;
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint32_t idx = wbase + r * kWave + lane;
+        bk[r] = idx < tn ? classify_key<DT>(m, leaf, K, M, k[r]) : 0u;
+    }
+}
+
 // ------------------------------------------------------------------ classify + histogram
-// Every workgroup classifies a run of `tiles_per_group` consecutive tiles with per-wave LDS
-// histograms and adds them to the item's global counts when the run leaves an item.
+// One workgroup per chunk.  For every tile of the chunk: classify, count per bucket, write the
+// tile's exclusive prefix inside the chunk (tile_pref[t][b]); at the end the chunk's totals
+// (chunk_sum[b][c], bucket-major so the scan reads it coalesced).
 template <int DT>
 __global__ __launch_bounds__(256) void k_classify_hist(const Item* items, const uint64_t* tile_off,
-                                                       const uint32_t* tile_map, uint64_t total_tiles,
-                                                       uint32_t tiles_per_group, const Model* models,
+                                                       const uint64_t* chunk_off, const uint32_t* chunk_map,
+                                                       uint64_t total_chunks, const Model* models,
                                                        const double* leaves, const typename Key<DT>::T* src,
-                                                       uint64_t* hist, uint32_t K, uint32_t M, uint32_t tile_keys) {
+                                                       uint32_t* tile_pref, uint32_t* chunk_sum, uint32_t K,
+                                                       uint32_t M) {
+    using T = typename Key<DT>::T;
     __shared__ uint32_t h[4][kMaxBuckets];
     __shared__ double s_leaf[4 * kMaxLeaves];
-    const uint32_t wave = threadIdx.x / kWave;
-    const uint64_t t0 = (uint64_t)blockIdx.x * tiles_per_group;
-    if (t0 >= total_tiles) return;
-    const uint64_t t1 = (t0 + tiles_per_group < total_tiles) ? t0 + tiles_per_group : total_tiles;
-    for (uint32_t b = threadIdx.x; b < 4 * kMaxBuckets; b += blockDim.x) (&h[0][0])[b] = 0;
-    uint64_t t = t0;
-    while (t < t1) {
-        const uint32_t i = tile_map[t];
-        const Item it = items[i];
-        const Model m = models[i];
-        const uint64_t tend_item = tile_off[i + 1];
-        const uint64_t te = tend_item < t1 ? tend_item : t1;
-        if (m.kind == kKindL2pl) {
-            __syncthreads();
-            for (uint32_t q = threadIdx.x; q < 4 * M; q += blockDim.x) s_leaf[q] = leaves[(uint64_t)i * 4 * kMaxLeaves + q];
+    const uint32_t tid = threadIdx.x, wave = tid / kWave;
+    const uint64_t c = blockIdx.x;
+    const uint32_t i = chunk_map[c];
+    const Item it = items[i];
+    const Model m = models[i];
+    const uint64_t t0 = tile_off[i];
+    const uint64_t t_first = t0 + (c - chunk_off[i]) * kChunk;
+    const uint64_t t_end = (t_first + kChunk < tile_off[i + 1]) ? t_first + kChunk : tile_off[i + 1];
+    const uint32_t wbase = wave * kWave * kIPT;
+    auto tile_n = [&](uint64_t t) -> uint32_t {
+        const uint64_t rem = it.n - (t - t0) * kTileKeys;
+        return rem < (uint64_t)kTileKeys ? (uint32_t)rem : (uint32_t)kTileKeys;
+    };
+    const bool counting = m.kind != kKindClosedKeep && m.kind != kKindClosedMove;
+    T cur[kIPT], nxt[kIPT];
+    uint32_t nop[1];
+    if (counting) load_tile<DT, false, kIPT>(src, nullptr, it.lo + (t_first - t0) * kTileKeys, tile_n(t_first), wbase, cur, nop);
+    if (m.kind == kKindL2pl)
+        for (uint32_t q = tid; q < 4 * M; q += kBlock) s_leaf[q] = leaves[(uint64_t)i * 4 * kMaxLeaves + q];
+    for (uint32_t b = tid; b < 4 * kMaxBuckets; b += kBlock) (&h[0][0])[b] = 0;
+    __syncthreads();
+    uint32_t run = 0;  // thread b's running count of bucket b over the chunk's tiles
+    for (uint64_t t = t_first; t < t_end; ++t) {
+        const uint32_t tn = tile_n(t);
+        // prefetch the next tile while this one is counted
+        if (counting && t + 1 < t_end)
+            load_tile<DT, false, kIPT>(src, nullptr, it.lo + (t + 1 - t0) * kTileKeys, tile_n(t + 1), wbase, nxt, nop);
+        if (counting) {
+#pragma unroll
+            for (int r = 0; r < kIPT; ++r)
+                if (wbase + r * kWave + lane_id() < tn)
+                    atomicAdd(&h[wave][classify_key<DT>(m, s_leaf, K, M, cur[r])], 1u);
+        } else if (m.kind == kKindClosedMove && tid == 0) {
+            h[0][0] = tn;
         }
         __syncthreads();
-        if (m.kind != kKindClosedKeep) {
-            const uint64_t k0 = (t - tile_off[i]) * tile_keys;
-            uint64_t k1 = (te - tile_off[i]) * tile_keys;
-            if (k1 > it.n) k1 = it.n;
-            if (m.kind == kKindClosedMove) {
-                if (threadIdx.x == 0) h[0][0] += (uint32_t)(k1 - k0);
-            } else {
-                for (uint64_t j = k0 + threadIdx.x; j < k1; j += blockDim.x) {
-                    const uint32_t c = classify_key<DT>(m, s_leaf, K, M, src[it.lo + j]);
-                    atomicAdd(&h[wave][c], 1u);
-                }
-            }
+        if (tid < K) {
+            tile_pref[t * K + tid] = run;
+            run += h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
+            h[0][tid] = h[1][tid] = h[2][tid] = h[3][tid] = 0;
         }
         __syncthreads();
-        for (uint32_t b = threadIdx.x; b < K; b += blockDim.x) {
-            const uint32_t v = h[0][b] + h[1][b] + h[2][b] + h[3][b];
-            h[0][b] = h[1][b] = h[2][b] = h[3][b] = 0;
-            if (v) atomicAdd((unsigned long long*)&hist[(uint64_t)i * K + b], (unsigned long long)v);
-        }
-        t = te;
+#pragma unroll
+        for (int r = 0; r < kIPT; ++r) cur[r] = nxt[r];
     }
+    if (tid < K) chunk_sum[(uint64_t)tid * total_chunks + c] = run;
+}
+
+// One wave per (item, bucket): exclusive prefix of the item's chunk totals (64 chunks per step,
+// a wave-wide inclusive scan plus the running carry); the total is the item's bucket size.
+__global__ __launch_bounds__(256) void k_scan_chunks(const uint64_t* chunk_off, uint64_t num_items, uint32_t K,
+                                                     uint64_t total_chunks, const uint32_t* chunk_sum,
+                                                     uint64_t* chunk_pref, uint64_t* hist) {
+    const uint64_t w = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    if (w >= num_items * K) return;
+    const uint64_t i = w / K;
+    const uint32_t b = (uint32_t)(w % K), lane = lane_id();
+    const uint64_t c0 = chunk_off[i], c1 = chunk_off[i + 1];
+    const uint32_t* in = chunk_sum + (uint64_t)b * total_chunks;
+    uint64_t* out = chunk_pref + (uint64_t)b * total_chunks;
+    uint64_t carry = 0;
+    constexpr int U = 4;  // rounds of 64 chunks whose loads are issued together
+    for (uint64_t c = c0; c < c1; c += U * kWave) {
+        uint64_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t j = c + u * kWave + lane;
+            v[u] = j < c1 ? in[j] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t j = c + u * kWave + lane;
+            const uint64_t inc = wave_inclusive_sum<uint64_t>(v[u]);
+            if (j < c1) out[j] = carry + inc - v[u];
+            carry += __shfl(inc, kWave - 1, kWave);
+        }
+    }
+    if (lane == 0) hist[i * K + b] = carry;
 }
 
 // Bucket starts of every item: exclusive prefix of its K counts.
@@ -453,30 +590,27 @@ __global__ __launch_bounds__(256) void k_bucket_starts(const uint64_t* hist, uin
 }
 
 // ------------------------------------------------------------------ scatter
-// Stable distribution of one tile of 256 * IPT keys (Proposed Algorithm; the Worked Example's
-// contiguous layout is the stable one).  Steps:
-//   1. dynamic tile id (tiles only wait on tiles that started earlier, so the look-back always
-//      makes progress);
-//   2. classify in registers; wave w ranks its 64 * IPT keys row by row: lanes with the same
-//      bucket are found with 8 ballots on the bucket bits, the running per-wave bucket count
-//      lives in LDS;
-//   3. per-bucket tile counts are published and a decoupled look-back over the item's earlier
-//      tiles (one bucket per thread, flag and count packed in one 64-bit word) gives the tile's
-//      offset inside each bucket;
-//   4. keys are staged in LDS in bucket order and written out in runs, so each bucket's keys of
-//      the tile land in one contiguous, coalesced span.
-constexpr uint64_t kFlagAgg = 1ull << 62, kFlagInc = 2ull << 62, kCountMask = (1ull << 62) - 1;
+// Stable distribution of one tile (Proposed Algorithm; the Worked Example's contiguous layout is
+// the stable one): classify and rank the keys in registers, stage them in LDS in bucket order,
+// then write each bucket's run of the tile to one contiguous, coalesced span of the destination.
+// Workgroups are mapped to tiles so that each of the 8 XCDs (workgroups are dealt to XCDs round
+// robin) walks one contiguous range of tiles: neighbouring tiles, whose runs of a bucket are
+// adjacent in the destination, then write through the same L2.
+__device__ inline uint64_t xcd_tile(uint64_t g, uint64_t nt) {
+    const uint64_t q = nt / 8, r = nt % 8, x = g % 8;
+    return x * q + (x < r ? x : r) + g / 8;
+}
 
-template <int DT, bool PAY, int IPT>
+template <int DT, bool PAY>
 __global__ __launch_bounds__(256) void k_scatter(const Item* items, const uint64_t* tile_off, const uint32_t* tile_map,
-                                                 const Model* models, const double* leaves, const uint64_t* bstart,
-                                                 const typename Key<DT>::T* src, const uint32_t* src_pay,
-                                                 typename Key<DT>::T* dst, uint32_t* dst_pay, uint64_t* status,
-                                                 uint32_t* tile_counter, uint32_t K, uint32_t M) {
-    using KT = Key<DT>;
-    using T = typename KT::T;
-    constexpr int TILE = kBlock * IPT;
-    __shared__ uint32_t s_tile;
+                                                 uint64_t total_tiles, const uint64_t* chunk_off,
+                                                 uint64_t total_chunks, const Model* models, const double* leaves,
+                                                 const uint64_t* bstart, const uint64_t* chunk_pref,
+                                                 const uint32_t* tile_pref, const typename Key<DT>::T* src,
+                                                 const uint32_t* src_pay, typename Key<DT>::T* dst, uint32_t* dst_pay,
+                                                 uint32_t K, uint32_t M) {
+    using T = typename Key<DT>::T;
+    constexpr int IPT = kIPT, TILE = kTileKeys;
     __shared__ uint32_t s_wcnt[4][kMaxBuckets];
     __shared__ uint32_t s_loc[kMaxBuckets];
     __shared__ uint64_t s_base[kMaxBuckets];
@@ -486,58 +620,37 @@ __global__ __launch_bounds__(256) void k_scatter(const Item* items, const uint64
     __shared__ uint32_t s_pay[PAY ? TILE : 1];
     __shared__ double s_leaf[4 * kMaxLeaves];
 
-    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-    if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
-    for (uint32_t b = tid; b < 4 * kMaxBuckets; b += kBlock) (&s_wcnt[0][0])[b] = 0;
-    __syncthreads();
-    const uint32_t t = s_tile;
+    const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
+    const uint64_t t = xcd_tile(blockIdx.x, total_tiles);
     const uint32_t i = tile_map[t];
     const Model m = models[i];
     if (m.kind == kKindClosedKeep) return;
     const Item it = items[i];
     const uint64_t tau = t - tile_off[i];
+    const uint64_t c = chunk_off[i] + tau / kChunk;
     const uint64_t base = it.lo + tau * TILE;
     const uint64_t rem = it.n - tau * TILE;
     const uint32_t tn = rem < (uint64_t)TILE ? (uint32_t)rem : (uint32_t)TILE;
-    if (m.kind == kKindL2pl) {
-        for (uint32_t q = tid; q < 4 * M; q += kBlock) s_leaf[q] = leaves[(uint64_t)i * 4 * kMaxLeaves + q];
-        __syncthreads();
-    }
-
-    // 1-2: load, classify, rank within the wave
+    // issue the tile's loads and the destination bases together, then one barrier
     T k[IPT];
     uint32_t p[PAY ? IPT : 1];
     uint32_t bk[IPT], rk[IPT];
     const uint32_t wbase = wave * kWave * IPT;
-    volatile uint32_t* wc = s_wcnt[wave];
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const uint32_t idx = wbase + r * kWave + lane;
-        const bool valid = idx < tn;
-        uint32_t b = 0;
-        if (valid) {
-            k[r] = src[base + idx];
-            if (PAY) p[r] = src_pay[base + idx];
-            b = classify_key<DT>(m, s_leaf, K, M, k[r]);
-        }
-        uint64_t same = __ballot(valid);
-#pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
-            const uint64_t ones = __ballot((b >> bit) & 1u);
-            same &= ((b >> bit) & 1u) ? ones : ~ones;
-        }
-        const uint32_t below = count_below(same);
-        const uint32_t prev = valid ? wc[b] : 0u;
-        __builtin_amdgcn_wave_barrier();
-        if (valid && below == 0) wc[b] = prev + (uint32_t)__popcll(same);
-        __builtin_amdgcn_wave_barrier();
-        bk[r] = b;
-        rk[r] = prev + below;
-    }
+    load_tile<DT, PAY, IPT>(src, src_pay, base, tn, wbase, k, p);
+    uint64_t dbase = 0;
+    if (tid < K)
+        dbase = it.lo + bstart[(uint64_t)i * K + tid] + chunk_pref[(uint64_t)tid * total_chunks + c] +
+                tile_pref[t * K + tid];
+    if (m.kind == kKindL2pl)
+        for (uint32_t q = tid; q < 4 * M; q += kBlock) s_leaf[q] = leaves[(uint64_t)i * 4 * kMaxLeaves + q];
+    for (uint32_t b = tid; b < 4 * kMaxBuckets; b += kBlock) (&s_wcnt[0][0])[b] = 0;
+    __syncthreads();
+    classify_tile<DT, IPT>(tn, wbase, m, s_leaf, K, M, k, bk);
+    wave_count<IPT, true>(bk, tn, wbase, s_wcnt[wave], rk);
     __syncthreads();
 
-    // 3: tile counts, per-wave offsets, tile-local bucket offsets, look-back
-    const uint32_t b = tid;  // one bucket per thread (K <= 256)
+    // per-wave offsets and tile-local bucket offsets (bucket order)
+    const uint32_t b = tid;
     uint32_t cnt = 0;
     if (b < K) {
         const uint32_t c0 = s_wcnt[0][b], c1 = s_wcnt[1][b], c2 = s_wcnt[2][b], c3 = s_wcnt[3][b];
@@ -551,29 +664,10 @@ __global__ __launch_bounds__(256) void k_scatter(const Item* items, const uint64
     const uint32_t loc = (uint32_t)block_exclusive_sum<uint64_t>(cnt, s_scan, &tot);
     if (b < K) {
         s_loc[b] = loc;
-        uint64_t* st = status + (uint64_t)t * K + b;
-        uint64_t excl = 0;
-        if (tau == 0) {
-            __hip_atomic_store(st, kFlagInc | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(st, kFlagAgg | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            uint64_t pt = t - 1;
-            for (;;) {
-                uint64_t v;
-                do {
-                    v = __hip_atomic_load(status + pt * K + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                } while ((v & ~kCountMask) == 0);
-                excl += v & kCountMask;
-                if (v & kFlagInc) break;
-                --pt;
-            }
-            __hip_atomic_store(st, kFlagInc | (excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        s_base[b] = it.lo + bstart[(uint64_t)i * K + b] + excl - loc;
+        s_base[b] = dbase - loc;
     }
     __syncthreads();
 
-    // 4: stage in bucket order, write runs
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
         const uint32_t idx = wbase + r * kWave + lane;
@@ -585,99 +679,168 @@ __global__ __launch_bounds__(256) void k_scatter(const Item* items, const uint64
         }
     }
     __syncthreads();
-    for (uint32_t j = tid; j < tn; j += kBlock) {
-        const uint64_t d = s_base[s_bkt[j]] + j;
-        dst[d] = s_keys[j];
-        if (PAY) dst_pay[d] = s_pay[j];
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint32_t j = tid + r * kBlock;
+        if (j < tn) {
+            const uint64_t d = s_base[s_bkt[j]] + j;
+            dst[d] = s_keys[j];
+            if (PAY) dst_pay[d] = s_pay[j];
+        }
     }
 }
 
 // ------------------------------------------------------------------ worklist
 // Children of every item: > T keys -> next level's items; otherwise -> base case (a single key
 // needs the base case only to move out of the scratch buffer).  Closed buckets have no children.
-__global__ void k_worklist(const Item* items, uint64_t num_items, const Model* models, const uint64_t* hist,
-                           const uint64_t* bstart, uint32_t K, uint32_t T, int dst_is_scratch, Item* next,
-                           uint64_t* next_count, BaseItem* base, uint64_t* base_count, uint64_t next_cap,
-                           uint64_t base_cap) {
+__global__ __launch_bounds__(256) void k_worklist(const Item* items, uint64_t num_items, const Model* models,
+                                                  const uint64_t* hist, const uint64_t* bstart, uint32_t K, uint32_t T,
+                                                  int dst_is_scratch, Item* next, BaseItem* base, BaseLayout bl,
+                                                  uint64_t* cnt, int next_slot, uint64_t next_cap) {
+    __shared__ AppendScratch sc;
     const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= num_items * K) return;
-    const uint64_t i = g / K;
-    const uint32_t kind = models[i].kind;
-    if (kind == kKindClosedKeep || kind == kKindClosedMove) return;
-    const uint64_t c = hist[g];
-    if (c == 0) return;
-    const Item it = items[i];
-    const uint64_t start = bstart[g];
-    if (c > T) {
-        const uint64_t q = atomicAdd((unsigned long long*)next_count, 1ull);
-        if (q < next_cap) next[q] = Item{it.lo + start, c, it.lo_rel + start, 0};
-    } else if (c >= 2 || dst_is_scratch) {
-        const uint64_t q = atomicAdd((unsigned long long*)base_count, 1ull);
-        if (q < base_cap) base[q] = BaseItem{it.lo + start, (uint32_t)c, (uint32_t)dst_is_scratch};
+    uint64_t c = 0, lo = 0, lo_rel = 0;
+    if (g < num_items * K) {
+        const uint64_t i = g / K;
+        const uint32_t kind = models[i].kind;
+        if (kind != kKindClosedKeep && kind != kKindClosedMove) {
+            c = hist[g];
+            const Item it = items[i];
+            const uint64_t start = bstart[g];
+            lo = it.lo + start;
+            lo_rel = it.lo_rel + start;
+        }
     }
+    const bool small = c >= 2 ? c <= T : (c == 1 && dst_is_scratch);
+    const int cls = base_class((uint32_t)(c <= T ? c : 1));
+    const int ch = c > T ? 0 : (small ? 1 + cls : -1);
+    const uint64_t q = block_append(ch, c, sc, &cnt[next_slot], &cnt[C_CLS], &cnt[C_BASEKEYS]);
+    if (ch == 0 && q < next_cap) next[q] = Item{lo, c, lo_rel, 0};
+    if (ch > 0 && q < bl.cap[cls]) base[bl.off[cls] + q] = BaseItem{lo, (uint32_t)c, (uint32_t)dst_is_scratch};
 }
 
 // ------------------------------------------------------------------ base case
-// Buckets of <= T keys (Proposed Algorithm: a radix sort below 2^12 keys in the paper; here an
-// LDS bitonic sort) sorted by ord and written into the caller's buffer.  With a payload the sort
-// key is (ord, position), which makes it stable.
-template <int DT, bool PAY>
-__global__ __launch_bounds__(256) void k_base_case(const BaseItem* list, typename Key<DT>::T* keys, uint32_t* pay,
-                                                   const typename Key<DT>::T* skeys, const uint32_t* spay) {
+// Buckets of <= T keys are sorted by ord and written into the caller's buffer (the paper's base
+// case below 2^12 keys, Proposed Algorithm).  A group of NT threads sorts one bucket of up to
+// 16 NT keys: every thread sorts 16 keys in registers with odd-even transposition (stable), then
+// log2(NT) rounds merge pairs of sorted runs through LDS; each thread finds where its 16 outputs
+// start with a merge-path search and merges them serially, taking the left run on ties.  Both
+// steps are stable, so with a payload equal keys keep their input order.  256 / NT buckets share
+// a workgroup.
+// LDS index with one pad slot every 16 elements: a thread's 16 consecutive elements then start in
+// different banks, so the blocked reads and writes of a wave do not all hit one bank.
+__device__ inline int pad16(int j) { return j + (j >> 4); }
+
+template <int DT, bool PAY, int NT>
+__global__ __launch_bounds__(256) void k_base_sort(const BaseItem* list, uint64_t count, typename Key<DT>::T* keys,
+                                                   uint32_t* pay, const typename Key<DT>::T* skeys,
+                                                   const uint32_t* spay) {
     using KT = Key<DT>;
-    __shared__ uint64_t so[kMaxBase];
-    __shared__ uint16_t si[PAY ? kMaxBase : 1];
-    __shared__ uint32_t sp[PAY ? kMaxBase : 1];
-    const BaseItem bi = list[blockIdx.x];
+    using O = typename KT::O;
+    constexpr int IPT = 16, G = kBlock / NT, CAP = NT * IPT, PCAP = CAP + CAP / 16;
+    constexpr O kPad = (O)~(O)0;
+    __shared__ O s_k[G * PCAP];
+    __shared__ uint32_t s_p[PAY ? G * PCAP : 1];
+    const int g = threadIdx.x / NT, t = threadIdx.x % NT;
+    const uint64_t bidx = (uint64_t)blockIdx.x * G + g;
+    BaseItem bi = {0, 0, 0};
+    if (bidx < count) bi = list[bidx];
+    const uint32_t n = bi.n;
     const typename KT::T* src = bi.from_scratch ? skeys : keys;
     const uint32_t* psrc = bi.from_scratch ? spay : pay;
-    const uint32_t n = bi.n;
-    if (n == 1) {
-        if (threadIdx.x == 0) {
-            keys[bi.lo] = src[bi.lo];
-            if (PAY) pay[bi.lo] = psrc[bi.lo];
+    O* sk = s_k + g * PCAP;
+    uint32_t* sp = s_p + (PAY ? g * PCAP : 0);
+
+    {
+        typename KT::T v[IPT];
+        uint32_t pv[PAY ? IPT : 1];
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const int j = t + r * NT;
+            if (j < (int)n) {
+                v[r] = src[bi.lo + j];
+                if (PAY) pv[r] = psrc[bi.lo + j];
+            }
         }
-        return;
-    }
-    uint32_t P = 2;
-    while (P < n) P <<= 1;
-    for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) {
-        so[j] = j < n ? KT::ord(src[bi.lo + j]) : ~0ull;
-        if (PAY) {
-            si[j] = (uint16_t)j;
-            if (j < n) sp[j] = psrc[bi.lo + j];
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const int j = t + r * NT;
+            sk[pad16(j)] = j < (int)n ? (O)KT::ord(v[r]) : kPad;
+            if (PAY) sp[pad16(j)] = j < (int)n ? pv[r] : 0u;
         }
     }
     __syncthreads();
-    for (uint32_t k = 2; k <= P; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t q = threadIdx.x; q < (P >> 1); q += blockDim.x) {
-                const uint32_t a = (q / j) * 2 * j + (q % j), c = a + j;
-                const bool up = (a & k) == 0;
-                const uint64_t oa = so[a], oc = so[c];
-                bool swap;
-                if (PAY) {
-                    const uint16_t ia = si[a], ic = si[c];
-                    const bool gt = oa > oc || (oa == oc && ia > ic);
-                    swap = gt == up;
-                    if (swap) {
-                        si[a] = ic;
-                        si[c] = ia;
-                    }
-                } else {
-                    swap = (oa > oc) == up && oa != oc;
-                }
-                if (swap) {
-                    so[a] = oc;
-                    so[c] = oa;
-                }
+    O k[IPT];
+    uint32_t p[PAY ? IPT : 1];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        k[i] = sk[pad16(t * IPT + i)];
+        if (PAY) p[i] = sp[pad16(t * IPT + i)];
+    }
+    // stable sort of the thread's 16 keys: odd-even transposition (adjacent swaps only)
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+#pragma unroll
+        for (int i = r & 1; i + 1 < IPT; i += 2) {
+            const bool sw = k[i + 1] < k[i];
+            const O lo = sw ? k[i + 1] : k[i], hi = sw ? k[i] : k[i + 1];
+            k[i] = lo;
+            k[i + 1] = hi;
+            if (PAY) {
+                const uint32_t pl = sw ? p[i + 1] : p[i], ph = sw ? p[i] : p[i + 1];
+                p[i] = pl;
+                p[i + 1] = ph;
             }
-            __syncthreads();
         }
     }
-    for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
-        keys[bi.lo + j] = KT::from_ord(so[j]);
-        if (PAY) pay[bi.lo + j] = sp[si[j]];
+    // merge rounds: runs of L keys -> 2L
+#pragma unroll 1
+    for (int L = IPT; L < CAP; L <<= 1) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            sk[pad16(t * IPT + i)] = k[i];
+            if (PAY) sp[pad16(t * IPT + i)] = p[i];
+        }
+        __syncthreads();
+        const int q = (t * IPT) / (2 * L), d = t * IPT - q * 2 * L;
+        const int a0 = q * 2 * L, b0 = a0 + L;  // unpadded starts of the two runs
+        int lo = d > L ? d - L : 0, hi = d < L ? d : L;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (sk[pad16(a0 + mid)] <= sk[pad16(b0 + d - 1 - mid)]) lo = mid + 1;
+            else hi = mid;
+        }
+        int ia = lo, ib = d - lo;
+        O a = ia < L ? sk[pad16(a0 + ia)] : kPad, b = ib < L ? sk[pad16(b0 + ib)] : kPad;
+#pragma unroll
+        for (int o = 0; o < IPT; ++o) {
+            const bool takeB = ib < L && (ia >= L || b < a);
+            k[o] = takeB ? b : a;
+            if (PAY) p[o] = sp[pad16(takeB ? b0 + ib : a0 + ia)];
+            if (takeB) {
+                ++ib;
+                b = ib < L ? sk[pad16(b0 + ib)] : kPad;
+            } else {
+                ++ia;
+                a = ia < L ? sk[pad16(a0 + ia)] : kPad;
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        sk[pad16(t * IPT + i)] = k[i];
+        if (PAY) sp[pad16(t * IPT + i)] = p[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const int j = t + r * NT;
+        if (j < (int)n) {
+            keys[bi.lo + j] = KT::from_ord((uint64_t)sk[pad16(j)]);
+            if (PAY) pay[bi.lo + j] = sp[pad16(j)];
+        }
     }
 }
 

@@ -20,11 +20,10 @@
 namespace ipls {
 namespace {
 
-constexpr uint32_t kSmallS = 8192;     // samples up to this size are fitted in one workgroup's LDS
-constexpr uint32_t kFitChunk = 8192;   // windows per workgroup in the multi-round fit
-constexpr uint32_t kCand = 7;          // candidate widths per fit round
-constexpr int kIPT = 16;               // keys per thread in the scatter tile
-constexpr uint32_t kTile = kBlock * kIPT;
+constexpr uint32_t kSmallS = kFitLds;  // samples up to this size are fitted in one workgroup's LDS
+constexpr uint32_t kFitChunk = 2048;   // windows per workgroup in the multi-round fit
+constexpr uint32_t kCand = 15;         // candidate widths per fit round
+constexpr uint32_t kTile = kTileKeys;
 constexpr int kMaxLevels = 4096;
 constexpr int kMaxDepth = 16;
 
@@ -51,12 +50,10 @@ ipls_status ensure(Buf& b, size_t bytes) {
     return IPLS_OK;
 }
 
-// counters (uint64) of one nesting depth
-enum { C_ITEMS0 = 0, C_ITEMS1 = 1, C_BASE = 2, C_ERR = 3, C_TILE = 4, C_STATS = 5 /* 4 slots */, C_N = 16 };
 
 struct Depth {
-    Buf scratch, spay, items[2], base, sample_base, counters, plan, tile_off, sample_off, fit_off, tile_map, fit_map,
-        models, masks, hist, bstart, status, sample, leaves, seg;
+    Buf scratch, spay, items[2], base, sample_base, counters, plan, tile_off, sample_off, fit_off, chunk_off, tile_map,
+        fit_map, chunk_map, models, masks, hist, bstart, tile_pref, chunk_sum, chunk_pref, sample, leaves, seg;
     Plan* plan_h = nullptr;
 };
 
@@ -180,7 +177,7 @@ template <int DT>
 ipls_status fit_level(Depth& D, hipStream_t s, uint64_t ni, uint64_t max_S, uint64_t total_fit_chunks,
                       const typename Key<DT>::T* sample, const uint64_t* sample_off, const uint64_t* fit_off,
                       Model* models, uint32_t K) {
-    k_fmcd_small<DT><<<(unsigned)ni, 256, kSmallS * sizeof(double), s>>>(sample, sample_off, ni, models, K, kSmallS);
+    k_fmcd_small<DT><<<(unsigned)ni, 256, 0, s>>>(sample, sample_off, ni, models, K, kSmallS);
     LAUNCH_CHECK();
     if (max_S <= kSmallS) return IPLS_OK;
     const int R = fit_rounds(max_S);
@@ -206,6 +203,32 @@ template <int DT, bool PAY>
 ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys, uint32_t* pay, uint64_t len,
                           const uint64_t* seg_off, uint64_t nseg, void* ws_keys, bool top);
 
+// Base-case sort of `count` buckets of size class cls (<= 64 * 2^cls keys): 16 keys per thread,
+// NT = 4 * 2^cls threads per bucket, 256 / NT buckets per workgroup.
+template <int DT, bool PAY, int NT>
+ipls_status launch_base_nt(hipStream_t s, const BaseItem* list, uint64_t count, typename Key<DT>::T* keys,
+                           uint32_t* pay, const typename Key<DT>::T* sk, const uint32_t* sp) {
+    constexpr uint64_t G = kBlock / NT;
+    k_base_sort<DT, PAY, NT><<<(unsigned)((count + G - 1) / G), kBlock, 0, s>>>(list, count, keys, pay, sk, sp);
+    LAUNCH_CHECK();
+    return IPLS_OK;
+}
+
+template <int DT, bool PAY>
+ipls_status launch_base(hipStream_t s, int cls, const BaseItem* list, uint64_t count, typename Key<DT>::T* keys,
+                        uint32_t* pay, const typename Key<DT>::T* sk, const uint32_t* sp) {
+    if (count == 0) return IPLS_OK;
+    switch (cls) {
+        case 0: return launch_base_nt<DT, PAY, 4>(s, list, count, keys, pay, sk, sp);
+        case 1: return launch_base_nt<DT, PAY, 8>(s, list, count, keys, pay, sk, sp);
+        case 2: return launch_base_nt<DT, PAY, 16>(s, list, count, keys, pay, sk, sp);
+        case 3: return launch_base_nt<DT, PAY, 32>(s, list, count, keys, pay, sk, sp);
+        case 4: return launch_base_nt<DT, PAY, 64>(s, list, count, keys, pay, sk, sp);
+        case 5: return launch_base_nt<DT, PAY, 128>(s, list, count, keys, pay, sk, sp);
+        default: return launch_base_nt<DT, PAY, 256>(s, list, count, keys, pay, sk, sp);
+    }
+}
+
 // Sort the samples of a level: base case when every sample fits, else the engine one level deeper.
 template <int DT>
 ipls_status sort_samples(Device& dv, Run& run, int d, const Plan& pl) {
@@ -217,10 +240,8 @@ ipls_status sort_samples(Device& dv, Run& run, int d, const Plan& pl) {
         k_sample_base<<<(unsigned)((pl.num_items + 255) / 256), 256, 0, s>>>((const uint64_t*)D.sample_off.p,
                                                                             pl.num_items, (BaseItem*)D.sample_base.p);
         LAUNCH_CHECK();
-        k_base_case<DT, false><<<(unsigned)pl.num_items, 256, 0, s>>>((const BaseItem*)D.sample_base.p, (T*)D.sample.p,
-                                                                      nullptr, nullptr, nullptr);
-        LAUNCH_CHECK();
-        return IPLS_OK;
+        return launch_base<DT, false>(s, base_class((uint32_t)pl.max_S), (const BaseItem*)D.sample_base.p,
+                                      pl.num_items, (T*)D.sample.p, nullptr, nullptr, nullptr);
     }
     if (d + 1 >= kMaxDepth) return IPLS_ERR_DEVICE;
     run.st.sample_depth = std::max<uint32_t>(run.st.sample_depth, (uint32_t)(d + 1));
@@ -238,7 +259,13 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     const uint32_t K = P.num_buckets, T_ = P.base_case_max;
     const size_t kb = sizeof(T);
     const uint64_t item_cap = len / (T_ + 1) + 1;
-    const uint64_t base_cap = std::min<uint64_t>(len, item_cap * K + nseg) + 1;
+    BaseLayout bl;
+    bl.off[0] = 0;
+    for (int c = 0; c < kBaseClasses; ++c) {
+        bl.cap[c] = c == 0 ? std::min<uint64_t>(len, item_cap * K + nseg) + 1 : len / (32ull << c) + 1;
+        bl.off[c + 1] = bl.off[c] + bl.cap[c];
+    }
+    const uint64_t base_cap = bl.off[kBaseClasses];
 
     T* scratch;
     uint32_t* spay = nullptr;
@@ -261,13 +288,13 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     ST_TRY(ensure(D.tile_off, (item_cap + 1) * 8));
     ST_TRY(ensure(D.sample_off, (item_cap + 1) * 8));
     ST_TRY(ensure(D.fit_off, (item_cap + 1) * 8));
+    ST_TRY(ensure(D.chunk_off, (item_cap + 1) * 8));
     if (!D.plan_h) HIP_TRY(hipHostMalloc((void**)&D.plan_h, sizeof(Plan), hipHostMallocDefault));
     uint64_t* cnt = (uint64_t*)D.counters.p;
 
     HIP_TRY(hipMemsetAsync(cnt, 0, C_N * sizeof(uint64_t), s));
-    k_seed<<<(unsigned)((nseg + 255) / 256), 256, 0, s>>>(seg_off, nseg, T_, (Item*)D.items[0].p, cnt + C_ITEMS0,
-                                                          (BaseItem*)D.base.p, cnt + C_BASE, cnt + C_ERR, item_cap,
-                                                          base_cap);
+    k_seed<<<(unsigned)((nseg + 255) / 256), 256, 0, s>>>(seg_off, nseg, T_, (Item*)D.items[0].p,
+                                                          (BaseItem*)D.base.p, bl, cnt, item_cap);
     LAUNCH_CHECK();
 
     LevelArgs A;
@@ -282,13 +309,13 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     A.small_S = kSmallS;
     A.fit_chunk = kFitChunk;
     A.cand = kCand;
+    A.chunk = kChunk;
 
     int cur = 0;
     uint64_t prev_items = 0, prev_sum_n = 0, prev_closed = 0, prev_closed_keys = 0;
     for (int level = 0;; ++level) {
-        k_plan<<<1, 1024, 0, s>>>((const Item*)D.items[cur].p, cnt + cur, cnt + (cur ^ 1), cnt + C_BASE, cnt + C_ERR,
-                                  cnt + C_STATS, (Plan*)D.plan.p, (uint64_t*)D.tile_off.p, (uint64_t*)D.sample_off.p,
-                                  (uint64_t*)D.fit_off.p, A, item_cap, base_cap);
+        k_plan<<<1, 1024, 0, s>>>((const Item*)D.items[cur].p, cnt, cur, (Plan*)D.plan.p, (uint64_t*)D.tile_off.p, (uint64_t*)D.sample_off.p,
+                                  (uint64_t*)D.fit_off.p, (uint64_t*)D.chunk_off.p, A, item_cap, bl);
         LAUNCH_CHECK();
         HIP_TRY(hipMemcpyAsync(D.plan_h, D.plan.p, sizeof(Plan), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
@@ -309,10 +336,10 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             prev_closed_keys = pl.closed_keys;
         }
         if (pl.num_base) {
-            ProfScope ps(2, 0.0, s);
-            k_base_case<DT, PAY><<<(unsigned)pl.num_base, 256, 0, s>>>((const BaseItem*)D.base.p, keys, pay, scratch,
-                                                                       spay);
-            LAUNCH_CHECK();
+            ProfScope ps(2, (double)pl.base_keys * 2.0 * (kb + (PAY ? 4 : 0)), s);
+            for (int c = 0; c < kBaseClasses; ++c)
+                ST_TRY((launch_base<DT, PAY>(s, c, (const BaseItem*)D.base.p + bl.off[c], pl.cls_count[c], keys, pay,
+                                             scratch, spay)));
             if (top) run.st.base_buckets += pl.num_base;
         }
         if (pl.num_items == 0) break;
@@ -331,7 +358,11 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         ST_TRY(ensure(D.models, ni * sizeof(Model)));
         ST_TRY(ensure(D.hist, ni * K * 8));
         ST_TRY(ensure(D.bstart, ni * K * 8));
-        ST_TRY(ensure(D.status, nt * K * 8));
+        const uint64_t nc = pl.total_chunks;
+        ST_TRY(ensure(D.chunk_map, nc * 4));
+        ST_TRY(ensure(D.tile_pref, nt * K * 4));
+        ST_TRY(ensure(D.chunk_sum, nc * K * 4));
+        ST_TRY(ensure(D.chunk_pref, nc * K * 8));
         const Item* items = (const Item*)D.items[cur].p;
         Model* models = (Model*)D.models.p;
 
@@ -355,30 +386,32 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                                                                 cnt + C_STATS);
         LAUNCH_CHECK();
 
-        // classify + histogram
-        HIP_TRY(hipMemsetAsync(D.hist.p, 0, ni * K * 8, s));
-        const uint32_t tpg = (uint32_t)std::max<uint64_t>(1, nt / 2048);
-        const unsigned groups = (unsigned)((nt + tpg - 1) / tpg);
+        // classify + per-tile counts, scan of the counts, bucket starts
+        k_expand<<<(unsigned)((nc + 255) / 256), 256, 0, s>>>((const uint64_t*)D.chunk_off.p, ni, nc,
+                                                              (uint32_t*)D.chunk_map.p);
+        LAUNCH_CHECK();
         {
             ProfScope ps(1, (double)pl.sum_n * kb, s);
-            k_classify_hist<DT><<<groups, 256, 0, s>>>(items, (const uint64_t*)D.tile_off.p,
-                                                       (const uint32_t*)D.tile_map.p, nt, tpg, models,
-                                                       (const double*)D.leaves.p, src, (uint64_t*)D.hist.p, K,
-                                                       P.leaves, kTile);
+            k_classify_hist<DT><<<(unsigned)nc, 256, 0, s>>>(
+                items, (const uint64_t*)D.tile_off.p, (const uint64_t*)D.chunk_off.p, (const uint32_t*)D.chunk_map.p,
+                nc, models, (const double*)D.leaves.p, src, (uint32_t*)D.tile_pref.p, (uint32_t*)D.chunk_sum.p, K,
+                P.leaves);
             LAUNCH_CHECK();
         }
+        k_scan_chunks<<<(unsigned)((ni * K + 3) / 4), 256, 0, s>>>((const uint64_t*)D.chunk_off.p, ni, K, nc,
+                                                                   (const uint32_t*)D.chunk_sum.p,
+                                                                   (uint64_t*)D.chunk_pref.p, (uint64_t*)D.hist.p);
+        LAUNCH_CHECK();
         k_bucket_starts<<<(unsigned)ni, 256, 0, s>>>((const uint64_t*)D.hist.p, (uint64_t*)D.bstart.p, K);
         LAUNCH_CHECK();
 
         // scatter
-        HIP_TRY(hipMemsetAsync(D.status.p, 0, nt * K * 8, s));
-        HIP_TRY(hipMemsetAsync(cnt + C_TILE, 0, 8, s));
         {
             ProfScope ps(0, (double)pl.sum_n * 2.0 * (kb + (PAY ? 4 : 0)), s);
-            k_scatter<DT, PAY, kIPT><<<(unsigned)nt, 256, 0, s>>>(
-                items, (const uint64_t*)D.tile_off.p, (const uint32_t*)D.tile_map.p, models, (const double*)D.leaves.p,
-                (const uint64_t*)D.bstart.p, src, psrc, dst, pdst, (uint64_t*)D.status.p, (uint32_t*)(cnt + C_TILE), K,
-                P.leaves);
+            k_scatter<DT, PAY><<<(unsigned)nt, 256, 0, s>>>(
+                items, (const uint64_t*)D.tile_off.p, (const uint32_t*)D.tile_map.p, nt, (const uint64_t*)D.chunk_off.p,
+                nc, models, (const double*)D.leaves.p, (const uint64_t*)D.bstart.p, (const uint64_t*)D.chunk_pref.p,
+                (const uint32_t*)D.tile_pref.p, src, psrc, dst, pdst, K, P.leaves);
             LAUNCH_CHECK();
         }
         if (top && level == 0 && run.single_pass) {
@@ -404,7 +437,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         // next level
         k_worklist<<<(unsigned)((ni * K + 255) / 256), 256, 0, s>>>(
             items, ni, models, (const uint64_t*)D.hist.p, (const uint64_t*)D.bstart.p, K, T_, src_scratch ? 0 : 1,
-            (Item*)D.items[cur ^ 1].p, cnt + (cur ^ 1), (BaseItem*)D.base.p, cnt + C_BASE, item_cap, base_cap);
+            (Item*)D.items[cur ^ 1].p, (BaseItem*)D.base.p, bl, cnt, C_ITEMS0 + (cur ^ 1), item_cap);
         LAUNCH_CHECK();
         cur ^= 1;
     }

@@ -144,7 +144,7 @@ def test_first_level_partition_parity(dist, dtype):
     assert np.array_equal(host(pd, np.uint32), wpay)
 
 
-@pytest.mark.parametrize("S", [3, 5, 100, 511, 8192, 8193, 20_000, 100_003, 1_000_000])
+@pytest.mark.parametrize("S", [3, 5, 100, 511, 8192, 16384, 16385, 20_000, 100_003, 1_000_000])
 @pytest.mark.parametrize("K", [4, 37, 256])
 def test_fmcd_fit_parity(S, K):
     x = np.sort(gen.lognormal(S, S + K))
