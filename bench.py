@@ -1,7 +1,9 @@
 """Benchmark of the IPLS sort on one MI355X.
 
 A step is one complete sort (every distribution level, the sample sorts, fits, and the base case)
-of 1e8 fp64 keys, keys only, 256 buckets, base case at <= 4096 keys, FMCD fit on a 1% sample.
+of 1e8 fp64 keys, keys only, 256 buckets, base case at <= 4096 keys, FMCD fit on a 1% sample
+capped at 4096 keys per bucket (the paper's IPLS samples alpha k - 1, about 1330 keys, at this
+size; the cap keeps every sample inside one base-case sort).
 Steps cycle through the five distributions of this workload: normal(0,1), lognormal(0,0.5),
 exponential(2), an equal-weight mixture of 5 N(mu_i, 1) with mu_i ~ U[-100,100], and integers
 uniform in [0, 1e6) cast to fp64.  Inputs are synthetic (seeded), generated on the host and staged
@@ -68,6 +70,7 @@ def main():
     ap.add_argument("--n", type=int, default=100_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dists", default=",".join(DISTS))
+    ap.add_argument("--sample-max", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU form is not built",
@@ -90,7 +93,7 @@ def main():
     total = args.warmup + args.steps
     order = [dists[i % len(dists)] for i in range(total)]
 
-    params = ipls.default_params()
+    params = ipls.default_params(sample_max=args.sample_max)
     stream = torch.cuda.current_stream()
 
     # warmup: also checks parity of each distribution's output against numpy's sort
@@ -127,7 +130,6 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ipls.profile_enable(False) if False else None
     sc_n, sc_ms, sc_bytes = ipls.profile_read(ipls.KERNEL_SCATTER)
     cl_n, cl_ms, cl_bytes = ipls.profile_read(ipls.KERNEL_CLASSIFY)
     bc_n, bc_ms, bc_bytes = ipls.profile_read(ipls.KERNEL_BASE)
@@ -137,13 +139,17 @@ def main():
     ms_per_step = gpu_ms / args.steps
     value = n * args.steps / (gpu_ms / 1e3)
 
-    # output check of the timed steps: sorted and the same multiset as the input (by checksum)
+    # output check of the timed steps: ascending, and the same multiset of bit patterns as the input
+    def multiset_hash(a):
+        u = np.ascontiguousarray(a).view(np.uint64)
+        h = (u ^ (u >> np.uint64(31))) * np.uint64(0x9E3779B97F4A7C15)
+        return int(np.sum(h, dtype=np.uint64)), int(np.bitwise_xor.reduce(h))
+
     timed_ok = True
     for i in range(min(args.steps, len(dists))):
         out = bufs[i].cpu().numpy()
         src = host_inputs[order[args.warmup + i]]
-        timed_ok &= bool(np.all(out[1:] >= out[:-1])) and np.array_equal(np.sort(src[:1000]), np.sort(src[:1000]))
-        timed_ok &= float(np.sum(out)) == float(np.sum(np.sort(src)))
+        timed_ok &= bool(np.all(out[1:] >= out[:-1])) and multiset_hash(out) == multiset_hash(src)
     del bufs
 
     by_dist = {}
@@ -153,7 +159,7 @@ def main():
     sc_gbs = sc_bytes / (sc_ms / 1e3) / 1e9 if sc_ms > 0 else None
     traffic = traffic_per_launch()
     roofline = {
-        "kernel": "k_scatter (classify, stable rank, decoupled look-back, LDS-staged write)",
+        "kernel": "k_scatter (classify, stable wave rank, LDS-staged bucket-ordered write)",
         "bound": "hbm",
         "achieved": round(sc_gbs, 1) if sc_gbs else None,
         "peak": HBM_PEAK_GBS,
@@ -172,7 +178,7 @@ def main():
         d0 = dists[0]
         print(f"# cpu baseline: oracle on one full step ({d0}, {n} keys)", file=sys.stderr, flush=True)
         t = time.perf_counter()
-        want, _, _ = oracle.sort(host_inputs[d0], None, oracle.params())
+        want, _, _ = oracle.sort(host_inputs[d0], None, oracle.params(sample_max=args.sample_max))
         dt = time.perf_counter() - t
         # parity of the GPU result for this step against the oracle
         g = pristine[d0].clone()
@@ -198,7 +204,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"plain single-array sort, {n} fp64 keys per step, keys only, cycling "
                                + "/".join(dists), "n": n, "num_buckets": 256, "base_case_max": 4096,
-                   "sample": "1% jittered stratified", "model": "FMCD", "parallelism": "single GPU"},
+                   "sample": f"1% jittered stratified, capped at {args.sample_max} keys", "model": "FMCD",
+                   "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu_baseline,
         "pass_gbs": round(pass_gbs, 1) if pass_gbs else None,

@@ -37,7 +37,7 @@ class Model(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("passes", C.c_uint64), ("max_level", C.c_uint64), ("closed", C.c_uint64),
                 ("fallback", C.c_uint64), ("base_cases", C.c_uint64), ("l2pl_used", C.c_uint64),
-                ("level1_max_load", C.c_uint64)]
+                ("level1_max_load", C.c_uint64), ("keys_partitioned", C.c_uint64)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

@@ -77,6 +77,7 @@ typedef struct {
     uint64_t base_cases; /* base-case sorts of more than one key */
     uint64_t l2pl_used;  /* partitions that used the two-level model */
     uint64_t level1_max_load;
+    uint64_t keys_partitioned; /* sum of the sizes of the partitioned buckets */
 } oracle_stats;
 
 /* ---------------------------------------------------------------- key map */
@@ -640,6 +641,7 @@ static void ipls(ctx_t* cx, char* keys, uint32_t* pay, uint64_t n, uint64_t lo_r
     if (m.kind == MODEL_MSD) cx->st->fallback += 1;
     if (m.kind == MODEL_L2PL) cx->st->l2pl_used += 1;
     cx->st->passes += 1;
+    cx->st->keys_partitioned += n;
     if (level > cx->st->max_level) cx->st->max_level = level;
     uint32_t K = p->num_buckets;
     uint64_t* counts = (uint64_t*)malloc(K * sizeof(uint64_t));
@@ -717,6 +719,7 @@ int oracle_sort_segmented(void* keys, uint32_t* payload, const uint64_t* off, ui
         acc.fallback += one.fallback;
         acc.base_cases += one.base_cases;
         acc.l2pl_used += one.l2pl_used;
+        acc.keys_partitioned += one.keys_partitioned;
         if (one.max_level > acc.max_level) acc.max_level = one.max_level;
         if (one.level1_max_load > acc.level1_max_load) acc.level1_max_load = one.level1_max_load;
     }

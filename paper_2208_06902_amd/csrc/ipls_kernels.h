@@ -428,12 +428,16 @@ constexpr int kChunk = 16;
 // Wave-level counting of one tile's keys: wave w owns keys [w * 64 * IPT, (w+1) * 64 * IPT) of the
 // tile, row r = 64 consecutive keys.  Lanes of a row holding the same bucket are found with 8
 // ballots on the bucket bits; the row's leader lane adds their number to the wave's LDS counter of
-// that bucket.  rk (when RANKS) receives each key's rank among the wave's earlier keys of its bucket,
-// i.e. its stable position.  wc holds the wave's 256 counters (zero on entry).
+// that bucket with an atomic that returns the previous count.  LDS executes a wave's operations in
+// order, so the 16 rows' atomics are issued back to back and each returns the count of the wave's
+// earlier rows; the leaders' values are then broadcast to their lanes.  rk (when RANKS) receives
+// each key's rank among the wave's earlier keys of its bucket, i.e. its stable position.  wc holds
+// the wave's 256 counters (zero on entry).
 template <int IPT, bool RANKS>
-__device__ inline void wave_count(const uint32_t (&bk)[IPT], uint32_t tn, uint32_t wbase, volatile uint32_t* wc,
+__device__ inline void wave_count(const uint32_t (&bk)[IPT], uint32_t tn, uint32_t wbase, uint32_t* wc,
                                   uint32_t (&rk)[IPT]) {
     const uint32_t lane = lane_id();
+    uint32_t prev[IPT], lead[IPT], below[IPT];
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
         const bool valid = wbase + r * kWave + lane < tn;
@@ -444,12 +448,17 @@ __device__ inline void wave_count(const uint32_t (&bk)[IPT], uint32_t tn, uint32
             const uint64_t ones = __ballot((b >> bit) & 1u);
             same &= ((b >> bit) & 1u) ? ones : ~ones;
         }
-        const uint32_t below = count_below(same);
-        const uint32_t prev = valid ? wc[b] : 0u;
-        __builtin_amdgcn_wave_barrier();
-        if (valid && below == 0) wc[b] = prev + (uint32_t)__popcll(same);
-        __builtin_amdgcn_wave_barrier();
-        if (RANKS) rk[r] = prev + below;
+        below[r] = count_below(same);
+        lead[r] = valid ? (uint32_t)(__ffsll((unsigned long long)same) - 1) : lane;
+        prev[r] = 0;
+        if (valid && below[r] == 0) {
+            if (RANKS) prev[r] = atomicAdd(&wc[b], (uint32_t)__popcll(same));
+            else atomicAdd(&wc[b], (uint32_t)__popcll(same));
+        }
+    }
+    if (RANKS) {
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) rk[r] = (uint32_t)__shfl((int)prev[r], (int)lead[r], kWave) + below[r];
     }
 }
 
@@ -488,7 +497,7 @@ __device__ inline void classify_tile(uint32_t tn, uint32_t wbase, const Model& m
 // ------------------------------------------------------------------ classify + histogram
 // One workgroup per chunk.  For every tile of the chunk: classify, count per bucket, write the
 // tile's exclusive prefix inside the chunk (tile_pref[t][b]); at the end the chunk's totals
-// (chunk_sum[b][c], bucket-major so the scan reads it coalesced).
+// (chunk_sum[c][b]).
 template <int DT>
 __global__ __launch_bounds__(256) void k_classify_hist(const Item* items, const uint64_t* tile_off,
                                                        const uint64_t* chunk_off, const uint32_t* chunk_map,
@@ -544,21 +553,42 @@ __global__ __launch_bounds__(256) void k_classify_hist(const Item* items, const 
 #pragma unroll
         for (int r = 0; r < kIPT; ++r) cur[r] = nxt[r];
     }
-    if (tid < K) chunk_sum[(uint64_t)tid * total_chunks + c] = run;
+    if (tid < K) chunk_sum[c * K + tid] = run;
 }
 
-// One wave per (item, bucket): exclusive prefix of the item's chunk totals (64 chunks per step,
-// a wave-wide inclusive scan plus the running carry); the total is the item's bucket size.
+// Exclusive prefix of every item's chunk totals, per bucket (chunk_pref[c][b]); the total is the
+// item's bucket size hist[i][b].  Items of at most kScanSerial chunks: one thread per (item, bucket)
+// walks the chunks (neighbouring threads read neighbouring buckets).  Larger items (only at the
+// first levels of big arrays): one wave per (item, bucket), 64 chunks per step, a wave-wide
+// inclusive scan plus the running carry.
+constexpr uint64_t kScanSerial = 64;
+
 __global__ __launch_bounds__(256) void k_scan_chunks(const uint64_t* chunk_off, uint64_t num_items, uint32_t K,
-                                                     uint64_t total_chunks, const uint32_t* chunk_sum,
-                                                     uint64_t* chunk_pref, uint64_t* hist) {
+                                                     const uint32_t* chunk_sum, uint64_t* chunk_pref,
+                                                     uint64_t* hist) {
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= num_items * K) return;
+    const uint64_t i = g / K, b = g % K;
+    const uint64_t c0 = chunk_off[i], c1 = chunk_off[i + 1];
+    if (c1 - c0 > kScanSerial) return;
+    uint64_t run = 0;
+    for (uint64_t c = c0; c < c1; ++c) {
+        const uint64_t v = chunk_sum[c * K + b];
+        chunk_pref[c * K + b] = run;
+        run += v;
+    }
+    hist[i * K + b] = run;
+}
+
+__global__ __launch_bounds__(256) void k_scan_chunks_wide(const uint64_t* chunk_off, uint64_t num_items, uint32_t K,
+                                                          const uint32_t* chunk_sum, uint64_t* chunk_pref,
+                                                          uint64_t* hist) {
     const uint64_t w = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     if (w >= num_items * K) return;
-    const uint64_t i = w / K;
-    const uint32_t b = (uint32_t)(w % K), lane = lane_id();
+    const uint64_t i = w / K, b = w % K;
+    const uint32_t lane = lane_id();
     const uint64_t c0 = chunk_off[i], c1 = chunk_off[i + 1];
-    const uint32_t* in = chunk_sum + (uint64_t)b * total_chunks;
-    uint64_t* out = chunk_pref + (uint64_t)b * total_chunks;
+    if (c1 - c0 <= kScanSerial) return;
     uint64_t carry = 0;
     constexpr int U = 4;  // rounds of 64 chunks whose loads are issued together
     for (uint64_t c = c0; c < c1; c += U * kWave) {
@@ -566,13 +596,13 @@ __global__ __launch_bounds__(256) void k_scan_chunks(const uint64_t* chunk_off, 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint64_t j = c + u * kWave + lane;
-            v[u] = j < c1 ? in[j] : 0;
+            v[u] = j < c1 ? chunk_sum[j * K + b] : 0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint64_t j = c + u * kWave + lane;
             const uint64_t inc = wave_inclusive_sum<uint64_t>(v[u]);
-            if (j < c1) out[j] = carry + inc - v[u];
+            if (j < c1) chunk_pref[j * K + b] = carry + inc - v[u];
             carry += __shfl(inc, kWave - 1, kWave);
         }
     }
@@ -639,7 +669,7 @@ __global__ __launch_bounds__(256) void k_scatter(const Item* items, const uint64
     load_tile<DT, PAY, IPT>(src, src_pay, base, tn, wbase, k, p);
     uint64_t dbase = 0;
     if (tid < K)
-        dbase = it.lo + bstart[(uint64_t)i * K + tid] + chunk_pref[(uint64_t)tid * total_chunks + c] +
+        dbase = it.lo + bstart[(uint64_t)i * K + tid] + chunk_pref[c * K + tid] +
                 tile_pref[t * K + tid];
     if (m.kind == kKindL2pl)
         for (uint32_t q = tid; q < 4 * M; q += kBlock) s_leaf[q] = leaves[(uint64_t)i * 4 * kMaxLeaves + q];
@@ -722,14 +752,38 @@ __global__ __launch_bounds__(256) void k_worklist(const Item* items, uint64_t nu
 // ------------------------------------------------------------------ base case
 // Buckets of <= T keys are sorted by ord and written into the caller's buffer (the paper's base
 // case below 2^12 keys, Proposed Algorithm).  A group of NT threads sorts one bucket of up to
-// 16 NT keys: every thread sorts 16 keys in registers with odd-even transposition (stable), then
-// log2(NT) rounds merge pairs of sorted runs through LDS; each thread finds where its 16 outputs
-// start with a merge-path search and merges them serially, taking the left run on ties.  Both
-// steps are stable, so with a payload equal keys keep their input order.  256 / NT buckets share
-// a workgroup.
-// LDS index with one pad slot every 16 elements: a thread's 16 consecutive elements then start in
-// different banks, so the blocked reads and writes of a wave do not all hit one bank.
+// 16 NT keys; 256 / NT buckets share a workgroup.
+//   1. every thread sorts 16 keys in registers with a bitonic network;
+//   2. log2(NT) rounds merge pairs of sorted runs through LDS.  A thread finds where its 16
+//      outputs start in the two runs with a merge-path search, loads the next 16 keys of each
+//      run (independent loads), keeps the 16 smallest with one compare-exchange stage (their
+//      sequence is bitonic) and sorts them with a 4-stage bitonic merge.
+// With a payload every key carries its current position and compares as (ord, position); the
+// left run's keys come first on ties, which is exactly the stable order.
+// LDS index with one pad slot every 16 elements, so that a thread's 16 consecutive elements start
+// in different banks.
 __device__ inline int pad16(int j) { return j + (j >> 4); }
+
+template <bool PAY, typename O>
+__device__ inline bool key_less(O ka, uint32_t ia, O kb, uint32_t ib) {
+    return PAY ? (ka < kb || (ka == kb && ia < ib)) : (ka < kb);
+}
+
+// compare-exchange: afterwards (a, b) is in ascending (up) or descending order
+template <bool PAY, typename O>
+__device__ inline void cex(O& ka, O& kb, uint32_t& ia, uint32_t& ib, uint32_t& pa, uint32_t& pb, bool up) {
+    const bool sw = up ? key_less<PAY>(kb, ib, ka, ia) : key_less<PAY>(ka, ia, kb, ib);
+    const O k0 = sw ? kb : ka, k1 = sw ? ka : kb;
+    ka = k0;
+    kb = k1;
+    if (PAY) {
+        const uint32_t i0 = sw ? ib : ia, i1 = sw ? ia : ib, p0 = sw ? pb : pa, p1 = sw ? pa : pb;
+        ia = i0;
+        ib = i1;
+        pa = p0;
+        pb = p1;
+    }
+}
 
 template <int DT, bool PAY, int NT>
 __global__ __launch_bounds__(256) void k_base_sort(const BaseItem* list, uint64_t count, typename Key<DT>::T* keys,
@@ -771,29 +825,24 @@ __global__ __launch_bounds__(256) void k_base_sort(const BaseItem* list, uint64_
     }
     __syncthreads();
     O k[IPT];
-    uint32_t p[PAY ? IPT : 1];
+    uint32_t id[IPT], p[IPT];  // id: current position (payload sorts only)
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         k[i] = sk[pad16(t * IPT + i)];
-        if (PAY) p[i] = sp[pad16(t * IPT + i)];
+        id[i] = t * IPT + i;
+        p[i] = PAY ? sp[pad16(t * IPT + i)] : 0u;
     }
-    // stable sort of the thread's 16 keys: odd-even transposition (adjacent swaps only)
+    // 1: bitonic sort of the thread's 16 keys
 #pragma unroll
-    for (int r = 0; r < IPT; ++r) {
+    for (int kk = 2; kk <= IPT; kk <<= 1)
 #pragma unroll
-        for (int i = r & 1; i + 1 < IPT; i += 2) {
-            const bool sw = k[i + 1] < k[i];
-            const O lo = sw ? k[i + 1] : k[i], hi = sw ? k[i] : k[i + 1];
-            k[i] = lo;
-            k[i + 1] = hi;
-            if (PAY) {
-                const uint32_t pl = sw ? p[i + 1] : p[i], ph = sw ? p[i] : p[i + 1];
-                p[i] = pl;
-                p[i + 1] = ph;
+        for (int j = kk >> 1; j > 0; j >>= 1)
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                const int l = i ^ j;
+                if (l > i) cex<PAY>(k[i], k[l], id[i], id[l], p[i], p[l], (i & kk) == 0);
             }
-        }
-    }
-    // merge rounds: runs of L keys -> 2L
+    // 2: merge rounds, runs of L keys -> 2L
 #pragma unroll 1
     for (int L = IPT; L < CAP; L <<= 1) {
         __syncthreads();
@@ -811,21 +860,38 @@ __global__ __launch_bounds__(256) void k_base_sort(const BaseItem* list, uint64_
             if (sk[pad16(a0 + mid)] <= sk[pad16(b0 + d - 1 - mid)]) lo = mid + 1;
             else hi = mid;
         }
-        int ia = lo, ib = d - lo;
-        O a = ia < L ? sk[pad16(a0 + ia)] : kPad, b = ib < L ? sk[pad16(b0 + ib)] : kPad;
+        const int ia = lo, ib = d - lo;
+        O xa[IPT], xb[IPT];
+        uint32_t pa[IPT], pb[IPT];
 #pragma unroll
-        for (int o = 0; o < IPT; ++o) {
-            const bool takeB = ib < L && (ia >= L || b < a);
-            k[o] = takeB ? b : a;
-            if (PAY) p[o] = sp[pad16(takeB ? b0 + ib : a0 + ia)];
-            if (takeB) {
-                ++ib;
-                b = ib < L ? sk[pad16(b0 + ib)] : kPad;
-            } else {
-                ++ia;
-                a = ia < L ? sk[pad16(a0 + ia)] : kPad;
+        for (int j = 0; j < IPT; ++j) {
+            xa[j] = ia + j < L ? sk[pad16(a0 + ia + j)] : kPad;
+            xb[j] = ib + j < L ? sk[pad16(b0 + ib + j)] : kPad;
+            if (PAY) {
+                pa[j] = ia + j < L ? sp[pad16(a0 + ia + j)] : 0u;
+                pb[j] = ib + j < L ? sp[pad16(b0 + ib + j)] : 0u;
             }
         }
+        // the 16 smallest of the two sorted windows: min(xa[j], xb[15-j]) is bitonic
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            // positions: past-the-end slots get positions past both runs, so real keys win ties
+            const uint32_t qa = ia + j < L ? (uint32_t)(a0 + ia + j) : (uint32_t)(2 * CAP + j);
+            const uint32_t qb = ib + IPT - 1 - j < L ? (uint32_t)(b0 + ib + IPT - 1 - j) : (uint32_t)(3 * CAP + j);
+            const bool takeB = key_less<PAY>(xb[IPT - 1 - j], qb, xa[j], qa);
+            k[j] = takeB ? xb[IPT - 1 - j] : xa[j];
+            id[j] = takeB ? qb : qa;
+            p[j] = PAY ? (takeB ? pb[IPT - 1 - j] : pa[j]) : 0u;
+        }
+#pragma unroll
+        for (int j = IPT >> 1; j > 0; j >>= 1)
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                const int l = i ^ j;
+                if (l > i) cex<PAY>(k[i], k[l], id[i], id[l], p[i], p[l], true);
+            }
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) id[i] = t * IPT + i;  // positions in the merged run
     }
     __syncthreads();
 #pragma unroll
@@ -840,6 +906,142 @@ __global__ __launch_bounds__(256) void k_base_sort(const BaseItem* list, uint64_
         if (j < (int)n) {
             keys[bi.lo + j] = KT::from_ord((uint64_t)sk[pad16(j)]);
             if (PAY) pay[bi.lo + j] = sp[pad16(j)];
+        }
+    }
+}
+
+// Radix base case for buckets of 1025 .. 64 * NW keys (NW waves, one bucket per workgroup).  Keys
+// are ranked on x = (ord - min) >> z, where min is the bucket's smallest ord and z the number of low
+// bits that are zero in every ord - min; only the bits where the bucket's keys differ are sorted,
+// 8 per pass, least significant digit first.  Each pass is a stable counting sort in LDS: wave w
+// owns positions [w * 64 * IPT, (w+1) * 64 * IPT), keys are ranked with the same ballot counting as
+// the scatter, and written to their new positions.  Stable, so a payload keeps its input order.
+template <int DT, bool PAY, int NW>
+__global__ __launch_bounds__(64 * NW) void k_base_radix(const BaseItem* list, uint64_t count,
+                                                       typename Key<DT>::T* keys, uint32_t* pay,
+                                                       const typename Key<DT>::T* skeys, const uint32_t* spay) {
+    using KT = Key<DT>;
+    using O = typename KT::O;
+    constexpr int IPT = 16, NT = 64 * NW, CAP = NT * IPT;
+    __shared__ O s_k[CAP];
+    __shared__ uint32_t s_p[PAY ? CAP : 1];
+    __shared__ uint32_t s_wcnt[NW][kMaxBuckets];
+    __shared__ uint32_t s_loc[kMaxBuckets];
+    __shared__ uint64_t s_scan[16];
+    __shared__ O s_red[2][NW];
+    const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
+    if (blockIdx.x >= count) return;
+    const BaseItem bi = list[blockIdx.x];
+    const uint32_t n = bi.n;
+    const typename KT::T* src = bi.from_scratch ? skeys : keys;
+    const uint32_t* psrc = bi.from_scratch ? spay : pay;
+    const uint32_t wbase = wave * kWave * IPT;
+    O o[IPT];
+    uint32_t p[IPT];
+    {
+        typename KT::T v[IPT];
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const uint32_t j = wbase + r * kWave + lane;
+            if (j < n) {
+                v[r] = src[bi.lo + j];
+                p[r] = PAY ? psrc[bi.lo + j] : 0u;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) o[r] = wbase + r * kWave + lane < n ? (O)KT::ord(v[r]) : (O)0;
+    }
+    // min over the bucket, then the OR of ord - min (its trailing zeros and bit length)
+    O mn = (O)~(O)0;
+#pragma unroll
+    for (int r = 0; r < IPT; ++r)
+        if (wbase + r * kWave + lane < n) mn = o[r] < mn ? o[r] : mn;
+    mn = (O)~wave_max((O)~mn);
+    if (lane == 0) s_red[0][wave] = mn;
+    __syncthreads();
+    mn = s_red[0][0];
+    for (int w = 1; w < NW; ++w) mn = s_red[0][w] < mn ? s_red[0][w] : mn;
+    O orv = 0;
+#pragma unroll
+    for (int r = 0; r < IPT; ++r)
+        if (wbase + r * kWave + lane < n) orv |= (O)(o[r] - mn);
+#pragma unroll
+    for (int sft = 32; sft >= 1; sft >>= 1) orv |= (O)__shfl_xor(orv, sft, kWave);
+    if (lane == 0) s_red[1][wave] = orv;
+    __syncthreads();
+    orv = 0;
+    for (int w = 0; w < NW; ++w) orv |= s_red[1][w];
+    const int z = orv ? __builtin_ctzll((unsigned long long)orv) : 0;
+    const int nbits = orv ? (int)bit_length((uint64_t)(orv >> z)) : 0;
+    const int passes = (nbits + 7) / 8;
+
+    for (int d = 0; d < passes; ++d) {
+        const int shift = z + 8 * d;
+        uint32_t bk[IPT], rk[IPT];
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) bk[r] = (uint32_t)(((uint64_t)(o[r] - mn) >> shift) & 255u);
+        for (uint32_t b = tid; b < NW * kMaxBuckets; b += NT) (&s_wcnt[0][0])[b] = 0;
+        __syncthreads();
+        wave_count<IPT, true>(bk, n, wbase, s_wcnt[wave], rk);
+        __syncthreads();
+        // digit offsets: exclusive over waves, then over digits
+        uint32_t tot_lo = 0, tot_hi = 0;
+        {
+            const uint32_t dg = tid;  // digits tid and tid + NT (NT >= 128)
+            uint32_t run = 0;
+            for (int w = 0; w < NW; ++w) {
+                const uint32_t cw = s_wcnt[w][dg];
+                s_wcnt[w][dg] = run;
+                run += cw;
+            }
+            tot_lo = run;
+            if (NT < kMaxBuckets) {
+                uint32_t run2 = 0;
+                for (int w = 0; w < NW; ++w) {
+                    const uint32_t cw = s_wcnt[w][dg + NT];
+                    s_wcnt[w][dg + NT] = run2;
+                    run2 += cw;
+                }
+                tot_hi = run2;
+            }
+        }
+        uint64_t all;
+        if (NT >= kMaxBuckets) {
+            s_loc[tid] = (uint32_t)block_exclusive_sum<uint64_t>(tot_lo, s_scan, &all);
+        } else {
+            // two digits per thread: tid (low half) and tid + NT (high half)
+            const uint64_t e_lo = block_exclusive_sum<uint64_t>(tot_lo, s_scan, &all);
+            uint64_t all_hi;
+            const uint64_t e_hi = block_exclusive_sum<uint64_t>(tot_hi, s_scan, &all_hi);
+            s_loc[tid] = (uint32_t)e_lo;
+            s_loc[tid + NT] = (uint32_t)(all + e_hi);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            if (wbase + r * kWave + lane < n) {
+                const uint32_t pos = s_loc[bk[r]] + s_wcnt[wave][bk[r]] + rk[r];
+                s_k[pos] = o[r];
+                if (PAY) s_p[pos] = p[r];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const uint32_t j = wbase + r * kWave + lane;
+            if (j < n) {
+                o[r] = s_k[j];
+                if (PAY) p[r] = s_p[j];
+            }
+        }
+    }
+    // keys are in sorted order at their positions: write out (coalesced)
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint32_t j = wbase + r * kWave + lane;
+        if (j < n) {
+            keys[bi.lo + j] = KT::from_ord((uint64_t)o[r]);
+            if (PAY) pay[bi.lo + j] = p[r];
         }
     }
 }

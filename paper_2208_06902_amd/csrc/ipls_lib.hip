@@ -224,8 +224,14 @@ ipls_status launch_base(hipStream_t s, int cls, const BaseItem* list, uint64_t c
         case 2: return launch_base_nt<DT, PAY, 16>(s, list, count, keys, pay, sk, sp);
         case 3: return launch_base_nt<DT, PAY, 32>(s, list, count, keys, pay, sk, sp);
         case 4: return launch_base_nt<DT, PAY, 64>(s, list, count, keys, pay, sk, sp);
-        case 5: return launch_base_nt<DT, PAY, 128>(s, list, count, keys, pay, sk, sp);
-        default: return launch_base_nt<DT, PAY, 256>(s, list, count, keys, pay, sk, sp);
+        case 5:
+            k_base_radix<DT, PAY, 2><<<(unsigned)count, 128, 0, s>>>(list, count, keys, pay, sk, sp);
+            LAUNCH_CHECK();
+            return IPLS_OK;
+        default:
+            k_base_radix<DT, PAY, 4><<<(unsigned)count, 256, 0, s>>>(list, count, keys, pay, sk, sp);
+            LAUNCH_CHECK();
+            return IPLS_OK;
     }
 }
 
@@ -398,10 +404,17 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                 P.leaves);
             LAUNCH_CHECK();
         }
-        k_scan_chunks<<<(unsigned)((ni * K + 3) / 4), 256, 0, s>>>((const uint64_t*)D.chunk_off.p, ni, K, nc,
-                                                                   (const uint32_t*)D.chunk_sum.p,
-                                                                   (uint64_t*)D.chunk_pref.p, (uint64_t*)D.hist.p);
+        k_scan_chunks<<<(unsigned)((ni * K + 255) / 256), 256, 0, s>>>((const uint64_t*)D.chunk_off.p, ni, K,
+                                                                       (const uint32_t*)D.chunk_sum.p,
+                                                                       (uint64_t*)D.chunk_pref.p, (uint64_t*)D.hist.p);
         LAUNCH_CHECK();
+        if ((pl.max_n + (uint64_t)kTileKeys * kChunk - 1) / ((uint64_t)kTileKeys * kChunk) > kScanSerial) {
+            k_scan_chunks_wide<<<(unsigned)((ni * K + 3) / 4), 256, 0, s>>>((const uint64_t*)D.chunk_off.p, ni, K,
+                                                                            (const uint32_t*)D.chunk_sum.p,
+                                                                            (uint64_t*)D.chunk_pref.p,
+                                                                            (uint64_t*)D.hist.p);
+            LAUNCH_CHECK();
+        }
         k_bucket_starts<<<(unsigned)ni, 256, 0, s>>>((const uint64_t*)D.hist.p, (uint64_t*)D.bstart.p, K);
         LAUNCH_CHECK();
 
