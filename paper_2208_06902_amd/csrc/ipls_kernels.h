@@ -442,12 +442,17 @@ __device__ inline void wave_count(const uint32_t (&bk)[IPT], uint32_t tn, uint32
     for (int r = 0; r < IPT; ++r) {
         const bool valid = wbase + r * kWave + lane < tn;
         const uint32_t b = bk[r];
-        uint64_t same = __ballot(valid);
+        const uint64_t vm = __ballot(valid);
+        uint32_t same_lo = (uint32_t)vm, same_hi = (uint32_t)(vm >> 32);
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
-            const uint64_t ones = __ballot((b >> bit) & 1u);
-            same &= ((b >> bit) & 1u) ? ones : ~ones;
+            // m = 0 or ~0 from this lane's bit; lanes agreeing with it: ~(ballot ^ m)
+            const uint32_t m = (uint32_t)(((int32_t)(b << (31 - bit))) >> 31);
+            const uint64_t ones = __ballot(m != 0u);
+            same_lo &= ~((uint32_t)ones ^ m);
+            same_hi &= ~((uint32_t)(ones >> 32) ^ m);
         }
+        const uint64_t same = ((uint64_t)same_hi << 32) | same_lo;
         below[r] = count_below(same);
         lead[r] = valid ? (uint32_t)(__ffsll((unsigned long long)same) - 1) : lane;
         prev[r] = 0;
@@ -785,45 +790,12 @@ __device__ inline void cex(O& ka, O& kb, uint32_t& ia, uint32_t& ib, uint32_t& p
     }
 }
 
-template <int DT, bool PAY, int NT>
-__global__ __launch_bounds__(256) void k_base_sort(const BaseItem* list, uint64_t count, typename Key<DT>::T* keys,
-                                                   uint32_t* pay, const typename Key<DT>::T* skeys,
-                                                   const uint32_t* spay) {
-    using KT = Key<DT>;
-    using O = typename KT::O;
-    constexpr int IPT = 16, G = kBlock / NT, CAP = NT * IPT, PCAP = CAP + CAP / 16;
+// Merge sort of CAP = 16 NT keys held in LDS (pad16 layout, positions 0 .. CAP-1, padding keys
+// are kPad at the end) by NT threads t = 0 .. NT-1 of one group; the sorted keys are left in LDS.
+template <typename O, bool PAY, int NT>
+__device__ inline void merge_sort_lds(O* sk, uint32_t* sp, int t) {
+    constexpr int IPT = 16, CAP = NT * IPT;
     constexpr O kPad = (O)~(O)0;
-    __shared__ O s_k[G * PCAP];
-    __shared__ uint32_t s_p[PAY ? G * PCAP : 1];
-    const int g = threadIdx.x / NT, t = threadIdx.x % NT;
-    const uint64_t bidx = (uint64_t)blockIdx.x * G + g;
-    BaseItem bi = {0, 0, 0};
-    if (bidx < count) bi = list[bidx];
-    const uint32_t n = bi.n;
-    const typename KT::T* src = bi.from_scratch ? skeys : keys;
-    const uint32_t* psrc = bi.from_scratch ? spay : pay;
-    O* sk = s_k + g * PCAP;
-    uint32_t* sp = s_p + (PAY ? g * PCAP : 0);
-
-    {
-        typename KT::T v[IPT];
-        uint32_t pv[PAY ? IPT : 1];
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            const int j = t + r * NT;
-            if (j < (int)n) {
-                v[r] = src[bi.lo + j];
-                if (PAY) pv[r] = psrc[bi.lo + j];
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            const int j = t + r * NT;
-            sk[pad16(j)] = j < (int)n ? (O)KT::ord(v[r]) : kPad;
-            if (PAY) sp[pad16(j)] = j < (int)n ? pv[r] : 0u;
-        }
-    }
-    __syncthreads();
     O k[IPT];
     uint32_t id[IPT], p[IPT];  // id: current position (payload sorts only)
 #pragma unroll
@@ -875,7 +847,7 @@ __global__ __launch_bounds__(256) void k_base_sort(const BaseItem* list, uint64_
         // the 16 smallest of the two sorted windows: min(xa[j], xb[15-j]) is bitonic
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
-            // positions: past-the-end slots get positions past both runs, so real keys win ties
+            // past-the-end slots get positions past both runs, so real keys win ties
             const uint32_t qa = ia + j < L ? (uint32_t)(a0 + ia + j) : (uint32_t)(2 * CAP + j);
             const uint32_t qb = ib + IPT - 1 - j < L ? (uint32_t)(b0 + ib + IPT - 1 - j) : (uint32_t)(3 * CAP + j);
             const bool takeB = key_less<PAY>(xb[IPT - 1 - j], qb, xa[j], qa);
@@ -890,8 +862,6 @@ __global__ __launch_bounds__(256) void k_base_sort(const BaseItem* list, uint64_
                 const int l = i ^ j;
                 if (l > i) cex<PAY>(k[i], k[l], id[i], id[l], p[i], p[l], true);
             }
-#pragma unroll
-        for (int i = 0; i < IPT; ++i) id[i] = t * IPT + i;  // positions in the merged run
     }
     __syncthreads();
 #pragma unroll
@@ -900,6 +870,47 @@ __global__ __launch_bounds__(256) void k_base_sort(const BaseItem* list, uint64_
         if (PAY) sp[pad16(t * IPT + i)] = p[i];
     }
     __syncthreads();
+}
+
+template <int DT, bool PAY, int NT>
+__global__ __launch_bounds__(256) void k_base_sort(const BaseItem* list, uint64_t count, typename Key<DT>::T* keys,
+                                                   uint32_t* pay, const typename Key<DT>::T* skeys,
+                                                   const uint32_t* spay) {
+    using KT = Key<DT>;
+    using O = typename KT::O;
+    constexpr int IPT = 16, G = kBlock / NT, CAP = NT * IPT, PCAP = CAP + CAP / 16;
+    constexpr O kPad = (O)~(O)0;
+    __shared__ O s_k[G * PCAP];
+    __shared__ uint32_t s_p[PAY ? G * PCAP : 1];
+    const int g = threadIdx.x / NT, t = threadIdx.x % NT;
+    const uint64_t bidx = (uint64_t)blockIdx.x * G + g;
+    BaseItem bi = {0, 0, 0};
+    if (bidx < count) bi = list[bidx];
+    const uint32_t n = bi.n;
+    const typename KT::T* src = bi.from_scratch ? skeys : keys;
+    const uint32_t* psrc = bi.from_scratch ? spay : pay;
+    O* sk = s_k + g * PCAP;
+    uint32_t* sp = s_p + (PAY ? g * PCAP : 0);
+    {
+        typename KT::T v[IPT];
+        uint32_t pv[PAY ? IPT : 1];
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const int j = t + r * NT;
+            if (j < (int)n) {
+                v[r] = src[bi.lo + j];
+                if (PAY) pv[r] = psrc[bi.lo + j];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const int j = t + r * NT;
+            sk[pad16(j)] = j < (int)n ? (O)KT::ord(v[r]) : kPad;
+            if (PAY) sp[pad16(j)] = j < (int)n ? pv[r] : 0u;
+        }
+    }
+    __syncthreads();
+    merge_sort_lds<O, PAY, NT>(sk, sp, t);
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
         const int j = t + r * NT;
@@ -910,21 +921,24 @@ __global__ __launch_bounds__(256) void k_base_sort(const BaseItem* list, uint64_
     }
 }
 
-// Radix base case for buckets of 1025 .. 64 * NW keys (NW waves, one bucket per workgroup).  Keys
-// are ranked on x = (ord - min) >> z, where min is the bucket's smallest ord and z the number of low
-// bits that are zero in every ord - min; only the bits where the bucket's keys differ are sorted,
-// 8 per pass, least significant digit first.  Each pass is a stable counting sort in LDS: wave w
-// owns positions [w * 64 * IPT, (w+1) * 64 * IPT), keys are ranked with the same ballot counting as
-// the scatter, and written to their new positions.  Stable, so a payload keeps its input order.
+// Base case for buckets of 1025 .. 1024 NW keys (NW waves, one bucket per workgroup).  The bucket's
+// smallest ord (min) and the number of low bits z that are zero in every ord - min are found
+// first; x = (ord - min) >> z then has only the bits where the bucket's keys differ.  When x needs
+// at most kRadixPasses 8-bit digits (few distinct values or a narrow range) the bucket is sorted
+// by LSD radix passes: each a stable counting sort in LDS that ranks keys with the same ballot
+// counting as the scatter.  Otherwise it goes to the merge sort.  Both are stable.
+constexpr int kRadixPasses = 3;
+
 template <int DT, bool PAY, int NW>
-__global__ __launch_bounds__(64 * NW) void k_base_radix(const BaseItem* list, uint64_t count,
+__global__ __launch_bounds__(64 * NW) void k_base_large(const BaseItem* list, uint64_t count,
                                                        typename Key<DT>::T* keys, uint32_t* pay,
                                                        const typename Key<DT>::T* skeys, const uint32_t* spay) {
     using KT = Key<DT>;
     using O = typename KT::O;
-    constexpr int IPT = 16, NT = 64 * NW, CAP = NT * IPT;
-    __shared__ O s_k[CAP];
-    __shared__ uint32_t s_p[PAY ? CAP : 1];
+    constexpr int IPT = 16, NT = 64 * NW, CAP = NT * IPT, PCAP = CAP + CAP / 16;
+    constexpr O kPad = (O)~(O)0;
+    __shared__ O s_k[PCAP];
+    __shared__ uint32_t s_p[PAY ? PCAP : 1];
     __shared__ uint32_t s_wcnt[NW][kMaxBuckets];
     __shared__ uint32_t s_loc[kMaxBuckets];
     __shared__ uint64_t s_scan[16];
@@ -949,13 +963,12 @@ __global__ __launch_bounds__(64 * NW) void k_base_radix(const BaseItem* list, ui
             }
         }
 #pragma unroll
-        for (int r = 0; r < IPT; ++r) o[r] = wbase + r * kWave + lane < n ? (O)KT::ord(v[r]) : (O)0;
+        for (int r = 0; r < IPT; ++r) o[r] = wbase + r * kWave + lane < n ? (O)KT::ord(v[r]) : kPad;
     }
     // min over the bucket, then the OR of ord - min (its trailing zeros and bit length)
-    O mn = (O)~(O)0;
+    O mn = kPad;
 #pragma unroll
-    for (int r = 0; r < IPT; ++r)
-        if (wbase + r * kWave + lane < n) mn = o[r] < mn ? o[r] : mn;
+    for (int r = 0; r < IPT; ++r) mn = o[r] < mn ? o[r] : mn;
     mn = (O)~wave_max((O)~mn);
     if (lane == 0) s_red[0][wave] = mn;
     __syncthreads();
@@ -974,6 +987,27 @@ __global__ __launch_bounds__(64 * NW) void k_base_radix(const BaseItem* list, ui
     const int z = orv ? __builtin_ctzll((unsigned long long)orv) : 0;
     const int nbits = orv ? (int)bit_length((uint64_t)(orv >> z)) : 0;
     const int passes = (nbits + 7) / 8;
+
+    if (passes > kRadixPasses) {
+        // merge sort: keys to LDS at their positions (padding keys at the end), then sort
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const uint32_t j = wbase + r * kWave + lane;
+            s_k[pad16(j)] = o[r];
+            if (PAY) s_p[pad16(j)] = j < n ? p[r] : 0u;
+        }
+        __syncthreads();
+        merge_sort_lds<O, PAY, NT>(s_k, s_p, (int)tid);
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const uint32_t j = wbase + r * kWave + lane;
+            if (j < n) {
+                keys[bi.lo + j] = KT::from_ord((uint64_t)s_k[pad16(j)]);
+                if (PAY) pay[bi.lo + j] = s_p[pad16(j)];
+            }
+        }
+        return;
+    }
 
     for (int d = 0; d < passes; ++d) {
         const int shift = z + 8 * d;

@@ -225,11 +225,11 @@ ipls_status launch_base(hipStream_t s, int cls, const BaseItem* list, uint64_t c
         case 3: return launch_base_nt<DT, PAY, 32>(s, list, count, keys, pay, sk, sp);
         case 4: return launch_base_nt<DT, PAY, 64>(s, list, count, keys, pay, sk, sp);
         case 5:
-            k_base_radix<DT, PAY, 2><<<(unsigned)count, 128, 0, s>>>(list, count, keys, pay, sk, sp);
+            k_base_large<DT, PAY, 2><<<(unsigned)count, 128, 0, s>>>(list, count, keys, pay, sk, sp);
             LAUNCH_CHECK();
             return IPLS_OK;
         default:
-            k_base_radix<DT, PAY, 4><<<(unsigned)count, 256, 0, s>>>(list, count, keys, pay, sk, sp);
+            k_base_large<DT, PAY, 4><<<(unsigned)count, 256, 0, s>>>(list, count, keys, pay, sk, sp);
             LAUNCH_CHECK();
             return IPLS_OK;
     }
