@@ -51,6 +51,86 @@ def traffic_per_launch():
     return t.get("bytes_per_launch")
 
 
+def summarize_profiles(ktrace_dir: str, fetch_dir: str, write_dir: str, bench_json: str, out_dir: str) -> None:
+    """Write the committed profile summaries from rocprofv3 CSV output of this bench.
+
+    ktrace_dir: `rocprofv3 --kernel-trace --stats -f csv` run of the bench; fetch_dir / write_dir:
+    `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs.  The counters are calibrated on the
+    bench's own device-to-device copies of one 1e8 fp64 input (800,000,000 bytes each way)."""
+    import csv
+    import glob
+    import re
+
+    def one(d, pat):
+        f = glob.glob(os.path.join(d, "**", pat), recursive=True)
+        if not f:
+            raise FileNotFoundError(f"{pat} under {d}")
+        return f[0]
+
+    def short(name):
+        return re.sub(r"\(.*", "", name).replace("void ", "")
+
+    stats = list(csv.DictReader(open(one(ktrace_dir, "*kernel_stats.csv"))))
+    bench = json.load(open(bench_json))
+    lines = ["# Kernel time of the 1e8 fp64 sort bench (rocprofv3 --kernel-trace --stats)", "",
+             "Command (from the repository root, GPU box):", "",
+             "    rocprofv3 --kernel-trace --stats -f csv -d <dir> -o bench -- \\",
+             "        python3 -u bench.py --steps 5 --warmup 5 --no-cpu-baseline", "",
+             f"Bench line of the same run: {bench['value']:.4g} keys/s, {bench['ms_per_step']} ms per step; "
+             f"k_scatter average launch by HIP events in bench.py: {bench['roofline']['avg_launch_ms']} ms over "
+             f"{bench['roofline']['launches']} timed launches.", "",
+             "10 sorts (5 warmup + 5 timed, all five distributions).  `__amd_rocclr_copyBuffer` is the bench's "
+             "own staging of inputs, outside the timed steps.", "",
+             "| kernel | calls | avg us | total ms | % |", "|---|---:|---:|---:|---:|"]
+    for r in stats[:28]:
+        lines.append(f"| {short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} |")
+    sc = [r for r in stats if "k_scatter" in r["Name"]]
+    if sc:
+        lines += ["", f"k_scatter average by rocprofv3: {float(sc[0]['AverageNs']) / 1e6:.4f} ms "
+                      f"(bench.py HIP events: {bench['roofline']['avg_launch_ms']} ms)."]
+    open(os.path.join(out_dir, "sort_1e8_fp64_kernel_stats.md"), "w").write("\n".join(lines) + "\n")
+
+    def counters(d):
+        rows = list(csv.DictReader(open(one(d, "*counter_collection.csv"))))
+        return [(short(r["Kernel_Name"]), int(r["Grid_Size"]) // int(r["Workgroup_Size"]),
+                 float(r["Counter_Value"]) * 1024.0) for r in rows]
+
+    fetch, write = counters(fetch_dir), counters(write_dir)
+    copy_bytes = 8.0 * 100_000_000
+    cf = [b for k, g, b in fetch if "copyBuffer" in k and b > 0.25 * copy_bytes]
+    cw = [b for k, g, b in write if "copyBuffer" in k and b > 0.5 * copy_bytes]
+    f_scale = copy_bytes / (sum(cf) / len(cf))
+    w_scale = copy_bytes / (sum(cw) / len(cw))
+    sf = [b * f_scale for k, g, b in fetch if "k_scatter" in k]
+    sw = [b * w_scale for k, g, b in write if "k_scatter" in k]
+    n_launch = min(len(sf), len(sw))
+    per_launch = (sum(sf[:n_launch]) + sum(sw[:n_launch])) / n_launch
+    big = [(f, w) for f, w in zip(sf, sw) if f > 1e8]
+    t = {"kernel": "k_scatter", "kernel_sha": kernel_hash(), "bytes_per_launch": round(per_launch),
+         "launches": n_launch, "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+         "workload": "bench.py --steps 2 --warmup 1 --no-cpu-baseline --dists normal (3 sorts of 1e8 normal fp64)",
+         "large_launches_bytes": [[round(f), round(w)] for f, w in big[:6]],
+         "algorithmic_bytes_large_launch": 1_600_000_000}
+    json.dump(t, open(os.path.join(out_dir, "scatter_traffic.json"), "w"), indent=1)
+    md = ["# HBM traffic of k_scatter (rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE, separate runs)", "",
+          "Commands (from the repository root, GPU box), one counter per run:", "",
+          "    rocprofv3 --pmc FETCH_SIZE -f csv -d <dir> -o bench -- \\",
+          "        python3 -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --dists normal",
+          "    rocprofv3 --pmc WRITE_SIZE -f csv -d <dir> -o bench -- \\",
+          "        python3 -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --dists normal", "",
+          f"Calibration: the bench's device-to-device copies of one 800,000,000-byte input read as "
+          f"FETCH_SIZE x {f_scale:.3f} and WRITE_SIZE x {w_scale:.3f}; every k_scatter value below is scaled "
+          f"by those factors.", "",
+          "| scatter launch (level) | fetch MB | write MB | algorithmic MB (read + write) |",
+          "|---|---:|---:|---:|"]
+    for i, (f, w) in enumerate(big[:6]):
+        md.append(f"| {i} | {f / 1e6:.1f} | {w / 1e6:.1f} | 1600.0 |")
+    md += ["", f"Mean over all {n_launch} scatter launches of the run: {per_launch / 1e6:.1f} MB per launch "
+               f"(bench.py reports it as roofline.traffic while the kernel source is unchanged, sha {t['kernel_sha']})."]
+    open(os.path.join(out_dir, "scatter_traffic.md"), "w").write("\n".join(md) + "\n")
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -71,7 +151,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dists", default=",".join(DISTS))
     ap.add_argument("--sample-max", type=int, default=4096)
+    ap.add_argument("--summarize-profiles", nargs=4, metavar=("KTRACE_DIR", "FETCH_DIR", "WRITE_DIR", "BENCH_JSON"),
+                    help="write profiles/ summaries from rocprofv3 CSV output and exit")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(*args.summarize_profiles, out_dir=os.path.join(ROOT, "profiles"))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU form is not built",
               file=sys.stderr, flush=True)
