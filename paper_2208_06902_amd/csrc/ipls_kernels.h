@@ -347,10 +347,230 @@ __global__ void k_export_model(const Model* m, ipls_linear_model* out, uint32_t 
     *out = r;
 }
 
+__global__ void k_linear_placeholder(Model* m) {
+    Model x = {};
+    x.kind = kKindLinear;
+    m[0] = x;
+}
+
 __global__ void k_degenerate_model(Model* m) {
     Model x = {};
     model_degenerate(x);
     m[0] = x;
+}
+
+// ------------------------------------------------------------------ two-level model (RMI section)
+// A two-level piecewise-linear CDF model: the root is FMCD onto M leaves (a linear model, routed
+// like classify_linear); each leaf is a line predicting K times the eCDF of the sorted sample,
+// y_j = K (j + 1/2) / S (the Machine Learning Models chapter: an eCDF model becomes a partition
+// model through floor(k F(x))).  Because the root is monotone, each leaf owns a contiguous range
+// of the sorted sample.  A leaf is trained in its centred coordinate u = (v - c) / h (c the mean
+// of its samples, h their largest distance to it) by gradient steps on its mean-squared error;
+// the steps are scaled per coordinate by the inverse Hessian diagonal halved (alpha by 1/(4 m2),
+// m2 = mean u^2; beta by 1/4).  Sums use 64 strided partials (lane p takes samples p, p+64, ...
+// of the leaf in increasing order) and the fixed 64-way tree of wave_tree_sum, so results are
+// reproducible bit for bit.  Export: A = alpha / h, B = beta - A c, and a monotone envelope
+// [LO, HI] per leaf (LO = HI of the previous leaf, HI = max(LO, min(K, prediction at the leaf's
+// last sample))).
+
+__device__ inline double l2pl_target(uint64_t j, uint64_t S, uint32_t K) {
+    return (double)K * ((double)j + 0.5) / (double)S;
+}
+
+// first[i][l] = first sample of leaf l of item i (M + 1 entries; empty leaves get zero-length ranges)
+template <int DT>
+__global__ __launch_bounds__(256) void k_l2pl_bounds(const typename Key<DT>::T* sample, const uint64_t* sample_off,
+                                                     uint64_t num_items, const Model* models, const Model* roots,
+                                                     uint32_t M, uint32_t* first) {
+    using KT = Key<DT>;
+    const uint64_t i = blockIdx.x;
+    if (i >= num_items || models[i].kind != kKindLinear || roots[i].kind != kKindLinear) return;
+    const double ra = roots[i].a, rb = roots[i].b;
+    const uint64_t off = sample_off[i], S = sample_off[i + 1] - off;
+    uint32_t* f = first + i * (M + 1);
+    for (uint64_t j = threadIdx.x; j <= S; j += blockDim.x) {
+        const int lp = j == 0 ? -1 : (int)classify_linear(ra, rb, M, KT::val(sample[off + j - 1]), false);
+        const int lc = j == S ? (int)M : (int)classify_linear(ra, rb, M, KT::val(sample[off + j]), false);
+        for (int l = lp + 1; l <= lc; ++l) f[l] = (uint32_t)j;
+    }
+}
+
+// One wave per (item, leaf): geometry, interpolation start, `iters` gradient steps, export.
+// grad mode (ab_in != nullptr): evaluate the loss and its gradient at ab_in instead of training.
+template <int DT>
+__global__ __launch_bounds__(256) void k_l2pl_train(const typename Key<DT>::T* sample, const uint64_t* sample_off,
+                                                    uint64_t num_items, const Model* models, const Model* roots,
+                                                    const uint32_t* first, uint32_t K, uint32_t M, uint32_t iters,
+                                                    double* leaves, double* lastp, const double* ab_in,
+                                                    double* grad_out, double* loss_out, double* ab_out) {
+    using KT = Key<DT>;
+    const uint64_t w = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint32_t lane = lane_id();
+    const uint64_t i = w / M;
+    const uint32_t l = (uint32_t)(w % M);
+    if (i >= num_items || models[i].kind != kKindLinear || roots[i].kind != kKindLinear) return;
+    const uint64_t off = sample_off[i], S = sample_off[i + 1] - off;
+    const typename KT::T* xs = sample + off;
+    const uint32_t* f = first + i * (M + 1);
+    const uint64_t j0 = f[l], j1 = f[l + 1];
+    double* lv = leaves + i * 4 * kMaxLeaves + 4 * l;
+    if (j1 == j0) {
+        if (lane == 0) {
+            lv[0] = 0.0;
+            lv[1] = 0.0;
+            lastp[i * kMaxLeaves + l] = 0.0;
+            if (ab_out) ab_out[2 * l] = ab_out[2 * l + 1] = 0.0;
+            if (grad_out) grad_out[2 * l] = grad_out[2 * l + 1] = 0.0;
+            if (loss_out) loss_out[l] = 0.0;
+        }
+        return;
+    }
+    const double cnt = (double)(j1 - j0);
+    double acc = 0.0;
+    for (uint64_t j = j0 + lane; j < j1; j += kWave) acc = acc + KT::val(xs[j]);
+    const double mean = __shfl(wave_tree_sum(acc), 0, kWave) / cnt;
+    const double x0 = KT::val(xs[j0]), x1 = KT::val(xs[j1 - 1]);
+    const double d0 = fabs(x0 - mean), d1 = fabs(x1 - mean);
+    double h = d0 > d1 ? d0 : d1;
+    if (!(h > 0.0)) h = 1.0;
+    acc = 0.0;
+    for (uint64_t j = j0 + lane; j < j1; j += kWave) {
+        const double u = (KT::val(xs[j]) - mean) / h;
+        acc = __builtin_fma(u, u, acc);
+    }
+    const double m2 = __shfl(wave_tree_sum(acc), 0, kWave) / cnt;
+    double alpha = 0.0, beta;
+    {
+        const double y0 = l2pl_target(j0, S, K), y1 = l2pl_target(j1 - 1, S, K);
+        const double u0 = (x0 - mean) / h, u1 = (x1 - mean) / h;
+        if (u1 > u0) alpha = (y1 - y0) / (u1 - u0);
+        beta = y0 - alpha * u0;
+    }
+    const double inv = 2.0 / cnt;
+    if (ab_in) {
+        alpha = ab_in[2 * l];
+        beta = ab_in[2 * l + 1];
+        double pa = 0.0, pb = 0.0, pl = 0.0;
+        for (uint64_t j = j0 + lane; j < j1; j += kWave) {
+            const double u = (KT::val(xs[j]) - mean) / h;
+            const double r = __builtin_fma(alpha, u, beta) - l2pl_target(j, S, K);
+            pa = __builtin_fma(r, u, pa);
+            pb = pb + r;
+            pl = __builtin_fma(r, r, pl);
+        }
+        const double ga = wave_tree_sum(pa) * inv, gb = wave_tree_sum(pb) * inv, ls = wave_tree_sum(pl) / cnt;
+        if (lane == 0) {
+            grad_out[2 * l] = ga;
+            grad_out[2 * l + 1] = gb;
+            if (loss_out) loss_out[l] = ls;
+        }
+        return;
+    }
+    for (uint32_t it = 0; it < iters; ++it) {
+        double pa = 0.0, pb = 0.0;
+        for (uint64_t j = j0 + lane; j < j1; j += kWave) {
+            const double u = (KT::val(xs[j]) - mean) / h;
+            const double r = __builtin_fma(alpha, u, beta) - l2pl_target(j, S, K);
+            pa = __builtin_fma(r, u, pa);
+            pb = pb + r;
+        }
+        const double ga = __shfl(wave_tree_sum(pa), 0, kWave) * inv;
+        const double gb = __shfl(wave_tree_sum(pb), 0, kWave) * inv;
+        double na = 0.0;
+        if (m2 > 0.0) {
+            const double q = 0.25 / m2;
+            na = alpha - q * ga;
+            if (!(na > 0.0)) na = 0.0;
+        }
+        alpha = na;
+        beta = beta - 0.25 * gb;
+    }
+    if (lane == 0) {
+        const double A = alpha / h;
+        const double B = beta - A * mean;
+        double last = __builtin_fma(A, x1, B);
+        if (last > (double)K) last = (double)K;
+        lv[0] = A;
+        lv[1] = B;
+        lastp[i * kMaxLeaves + l] = last;
+        if (ab_out) {
+            ab_out[2 * l] = alpha;
+            ab_out[2 * l + 1] = beta;
+        }
+    }
+}
+
+// Monotone envelope of every item's leaves (one thread per item, leaves in order) and the check
+// that every coefficient is finite; an empty leaf is the constant LO (A = 0, B = LO = HI).
+__global__ void k_l2pl_envelope(uint64_t num_items, Model* models, const Model* roots, const uint32_t* first,
+                                uint32_t M, double* leaves, const double* lastp) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= num_items) return;
+    Model m = models[i];
+    m.l2_ok = 0;
+    if (m.kind != kKindLinear || roots[i].kind != kKindLinear) {
+        models[i] = m;
+        return;
+    }
+    const uint32_t* f = first + i * (M + 1);
+    double* lv = leaves + i * 4 * kMaxLeaves;
+    double prev = 0.0;
+    bool ok = true;
+    for (uint32_t l = 0; l < M; ++l) {
+        double A = 0.0, B = prev, lo = prev, hi = prev;
+        if (f[l + 1] > f[l]) {
+            A = lv[4 * l];
+            B = lv[4 * l + 1];
+            const double last = lastp[i * kMaxLeaves + l];
+            hi = last > lo ? last : lo;
+        }
+        ok = ok && isfinite(A) && isfinite(B) && isfinite(hi);
+        lv[4 * l] = A;
+        lv[4 * l + 1] = B;
+        lv[4 * l + 2] = lo;
+        lv[4 * l + 3] = hi;
+        prev = hi;
+    }
+    m.l2_ok = ok ? 1u : 0u;
+    models[i] = m;
+}
+
+// Max sample load of every item under FMCD and under the two-level model (one workgroup per item).
+// The FMCD line stays in the model's (a, b) until k_finalize picks the two-level model and moves
+// the root there, where classification reads it.
+template <int DT>
+__global__ __launch_bounds__(256) void k_l2pl_load(const typename Key<DT>::T* sample, const uint64_t* sample_off,
+                                                   uint64_t num_items, Model* models, const Model* roots,
+                                                   const double* leaves, uint32_t K, uint32_t M) {
+    using KT = Key<DT>;
+    __shared__ uint32_t h1[kMaxBuckets], h2[kMaxBuckets];
+    __shared__ double s_leaf[4 * kMaxLeaves];
+    __shared__ uint32_t s_max[2];
+    const uint64_t i = blockIdx.x;
+    if (i >= num_items) return;
+    const Model m = models[i];
+    if (m.kind != kKindLinear || !m.l2_ok) return;
+    const double ra = roots[i].a, rb = roots[i].b;
+    for (uint32_t q = threadIdx.x; q < 4 * M; q += blockDim.x) s_leaf[q] = leaves[i * 4 * kMaxLeaves + q];
+    for (uint32_t b = threadIdx.x; b < kMaxBuckets; b += blockDim.x) h1[b] = h2[b] = 0;
+    if (threadIdx.x < 2) s_max[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t off = sample_off[i], S = sample_off[i + 1] - off;
+    for (uint64_t j = threadIdx.x; j < S; j += blockDim.x) {
+        const double v = KT::val(sample[off + j]);
+        atomicAdd(&h1[classify_linear(m.a, m.b, K, v, false)], 1u);
+        atomicAdd(&h2[classify_l2pl(ra, rb, M, s_leaf, K, v, false)], 1u);
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < K; b += blockDim.x) {
+        atomicMax(&s_max[0], h1[b]);
+        atomicMax(&s_max[1], h2[b]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        models[i].load_lin = s_max[0];
+        models[i].load_l2 = s_max[1];
+    }
 }
 
 // ------------------------------------------------------------------ degenerate buckets
@@ -382,8 +602,8 @@ __global__ __launch_bounds__(256) void k_minmax(const Item* items, const uint64_
 // Final model of every item: closes homogeneous buckets, sets the digit fallback, and picks the
 // two-level model when the policy and the sample loads ask for it.
 // stat_counts: [0] closed buckets, [1] digit splits, [2] two-level models, [3] keys in closed buckets
-__global__ void k_finalize(const Item* items, Model* models, uint64_t num_items, uint32_t K, int src_is_scratch,
-                           uint32_t policy, uint64_t* stat_counts) {
+__global__ void k_finalize(const Item* items, Model* models, const Model* roots, uint64_t num_items, uint32_t K,
+                           int src_is_scratch, uint32_t policy, uint64_t* stat_counts) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= num_items) return;
     Model m = models[i];
@@ -402,6 +622,8 @@ __global__ void k_finalize(const Item* items, Model* models, uint64_t num_items,
         const bool splits = m.load_l2 < m.S;
         if (splits && (policy == 2 || m.load_l2 < m.load_lin)) {
             m.kind = kKindL2pl;
+            m.a = roots[i].a;  // classification reads the root from (a, b)
+            m.b = roots[i].b;
             atomicAdd((unsigned long long*)&stat_counts[2], 1ull);
         }
     }

@@ -53,7 +53,8 @@ ipls_status ensure(Buf& b, size_t bytes) {
 
 struct Depth {
     Buf scratch, spay, items[2], base, sample_base, counters, plan, tile_off, sample_off, fit_off, chunk_off, tile_map,
-        fit_map, chunk_map, models, masks, hist, bstart, tile_pref, chunk_sum, chunk_pref, sample, leaves, seg;
+        fit_map, chunk_map, models, masks, hist, bstart, tile_pref, chunk_sum, chunk_pref, sample, leaves, seg, roots,
+        leaf_first, leaf_last;
     Plan* plan_h = nullptr;
 };
 
@@ -195,6 +196,37 @@ ipls_status fit_level(Depth& D, hipStream_t s, uint64_t ni, uint64_t max_S, uint
     }
     k_fmcd_finish<DT><<<(unsigned)((ni + 255) / 256), 256, 0, s>>>(sample, sample_off, ni, (const uint64_t*)D.masks.p,
                                                                    R, models, K, kSmallS, kCand);
+    LAUNCH_CHECK();
+    return IPLS_OK;
+}
+
+// Two-level model of every item whose FMCD fit is usable: root fit onto M leaves, leaf ranges,
+// per-leaf training (one wave per leaf), envelope, and the max sample loads of both models.
+// grad mode (ab_in set): one item, evaluate the loss gradient at ab_in instead of training.
+template <int DT>
+ipls_status train_l2pl(Depth& D, hipStream_t s, uint64_t ni, uint64_t max_S, uint64_t total_fit_chunks,
+                       const typename Key<DT>::T* sample, const uint64_t* sample_off, const uint64_t* fit_off,
+                       Model* models, uint32_t K, uint32_t M, uint32_t iters, const double* ab_in = nullptr,
+                       double* grad_out = nullptr, double* loss_out = nullptr, double* ab_out = nullptr) {
+    ST_TRY(ensure(D.roots, ni * sizeof(Model)));
+    ST_TRY(ensure(D.leaf_first, ni * (M + 1) * 4));
+    ST_TRY(ensure(D.leaves, ni * 4 * kMaxLeaves * 8));
+    ST_TRY(ensure(D.leaf_last, ni * kMaxLeaves * 8));
+    Model* roots = (Model*)D.roots.p;
+    ST_TRY((fit_level<DT>(D, s, ni, max_S, total_fit_chunks, sample, sample_off, fit_off, roots, M)));
+    k_l2pl_bounds<DT><<<(unsigned)ni, 256, 0, s>>>(sample, sample_off, ni, models, roots, M,
+                                                   (uint32_t*)D.leaf_first.p);
+    LAUNCH_CHECK();
+    k_l2pl_train<DT><<<(unsigned)((ni * M + 3) / 4), 256, 0, s>>>(
+        sample, sample_off, ni, models, roots, (const uint32_t*)D.leaf_first.p, K, M, iters, (double*)D.leaves.p,
+        (double*)D.leaf_last.p, ab_in, grad_out, loss_out, ab_out);
+    LAUNCH_CHECK();
+    if (ab_in) return IPLS_OK;
+    k_l2pl_envelope<<<(unsigned)((ni + 63) / 64), 64, 0, s>>>(ni, models, roots, (const uint32_t*)D.leaf_first.p, M,
+                                                             (double*)D.leaves.p, (const double*)D.leaf_last.p);
+    LAUNCH_CHECK();
+    k_l2pl_load<DT><<<(unsigned)ni, 256, 0, s>>>(sample, sample_off, ni, models, roots, (const double*)D.leaves.p, K,
+                                                 M);
     LAUNCH_CHECK();
     return IPLS_OK;
 }
@@ -383,12 +415,17 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         // FMCD fit
         ST_TRY((fit_level<DT>(D, s, ni, pl.max_S, pl.total_fit_chunks, (const T*)D.sample.p,
                               (const uint64_t*)D.sample_off.p, (const uint64_t*)D.fit_off.p, models, K)));
+        if (P.model != 0)
+            ST_TRY((train_l2pl<DT>(D, s, ni, pl.max_S, pl.total_fit_chunks, (const T*)D.sample.p,
+                                   (const uint64_t*)D.sample_off.p, (const uint64_t*)D.fit_off.p, models, K, P.leaves,
+                                   P.train_iters)));
 
         // degenerate buckets and final model
         k_minmax<DT><<<(unsigned)nt, 256, 0, s>>>(items, (const uint64_t*)D.tile_off.p, (const uint32_t*)D.tile_map.p,
                                                   models, src, kTile);
         LAUNCH_CHECK();
-        k_finalize<<<(unsigned)((ni + 255) / 256), 256, 0, s>>>(items, models, ni, K, src_scratch ? 1 : 0, P.model,
+        k_finalize<<<(unsigned)((ni + 255) / 256), 256, 0, s>>>(items, models, (const Model*)D.roots.p, ni, K,
+                                                                src_scratch ? 1 : 0, P.model,
                                                                 cnt + C_STATS);
         LAUNCH_CHECK();
 
@@ -486,6 +523,39 @@ ipls_status fit_entry(Device& dv, Run& run, const void* sample, uint64_t S, bool
     return IPLS_OK;
 }
 
+// One sorted fp64 sample x[0..S) as a single item at depth 0: copy it in, fit the placeholder
+// FMCD model, then train (or evaluate the gradient of) the two-level model.
+ipls_status l2pl_entry(Device& dv, hipStream_t s, const double* x, uint64_t S, uint32_t K, uint32_t M, uint32_t iters,
+                       double* root_out, double* leaf_out, double* ab_out, const double* ab_in, double* grad_out,
+                       double* loss_out) {
+    Depth& D = dv.depth[0];
+    ST_TRY(ensure(D.sample, S * 8));
+    ST_TRY(ensure(D.models, sizeof(Model)));
+    ST_TRY(ensure(D.seg, 6 * sizeof(uint64_t)));
+    HIP_TRY(hipMemcpyAsync(D.sample.p, x, S * 8, hipMemcpyDeviceToDevice, s));
+    uint64_t h[4] = {0, S, 0, S > kSmallS ? (S + kFitChunk - 1) / kFitChunk : 0};
+    HIP_TRY(hipMemcpyAsync(D.seg.p, h, sizeof(h), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const uint64_t* off = (const uint64_t*)D.seg.p;
+    Model* models = (Model*)D.models.p;
+    k_linear_placeholder<<<1, 1, 0, s>>>(models);
+    LAUNCH_CHECK();
+    ST_TRY((train_l2pl<0>(D, s, 1, S, h[3], (const uint64_t*)D.sample.p, off, off + 2, models, K, M, iters, ab_in,
+                          grad_out, loss_out, ab_out)));
+    Model root, m;
+    HIP_TRY(hipMemcpyAsync(&root, D.roots.p, sizeof(Model), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&m, models, sizeof(Model), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (root.kind != kKindLinear) return IPLS_ERR_DEVICE;  // the root fit is degenerate
+    if (ab_in) return IPLS_OK;
+    if (!m.l2_ok) return IPLS_ERR_DEVICE;  // a coefficient is not finite
+    double r[2] = {root.a, root.b};
+    HIP_TRY(hipMemcpyAsync(root_out, r, sizeof(r), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(leaf_out, D.leaves.p, 4 * (size_t)M * 8, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return IPLS_OK;
+}
+
 ipls_status check_params(const ipls_params& p) {
     if (p.num_buckets < 4 || p.base_case_max < 1 || p.sample_divisor < 2) return IPLS_ERR_INVALID;
     const uint64_t smin = p.sample_min ? p.sample_min : 2ull * p.num_buckets;
@@ -495,7 +565,6 @@ ipls_status check_params(const ipls_params& p) {
     if (p.num_buckets > (uint32_t)kMaxBuckets || p.base_case_max > (uint32_t)kMaxBase ||
         p.leaves > (uint32_t)kMaxLeaves)
         return IPLS_ERR_UNSUPPORTED;
-    if (p.model != 0) return IPLS_ERR_UNSUPPORTED;  // two-level model kernels: not in this build yet
     return IPLS_OK;
 }
 
@@ -711,29 +780,22 @@ ipls_status ipls_partition(void* keys, uint32_t* payload, size_t n, ipls_dtype d
 
 ipls_status ipls_l2pl_train(const double* x, size_t S, uint32_t K, uint32_t M, uint32_t iters, double* root,
                             double* leaf, double* ab, void* stream) {
-    (void)x;
-    (void)S;
-    (void)K;
-    (void)M;
-    (void)iters;
-    (void)root;
-    (void)leaf;
-    (void)ab;
-    (void)stream;
-    return IPLS_ERR_UNSUPPORTED;
+    if (!x || !root || !leaf || S < 3 || K < 4 || M < 4) return IPLS_ERR_INVALID;
+    if (K > (uint32_t)kMaxBuckets || M > (uint32_t)kMaxLeaves || S > 0xffffffffull) return IPLS_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> g(g_mu);
+    hipStream_t s = (hipStream_t)stream;
+    ipls_status st = l2pl_entry(device_ctx(), s, x, S, K, M, iters, root, leaf, ab, nullptr, nullptr, nullptr);
+    return finish(st, s);
 }
 
 ipls_status ipls_l2pl_grad(const double* x, size_t S, uint32_t K, uint32_t M, const double* ab, double* grad,
                            double* loss, void* stream) {
-    (void)x;
-    (void)S;
-    (void)K;
-    (void)M;
-    (void)ab;
-    (void)grad;
-    (void)loss;
-    (void)stream;
-    return IPLS_ERR_UNSUPPORTED;
+    if (!x || !ab || !grad || S < 3 || K < 4 || M < 4) return IPLS_ERR_INVALID;
+    if (K > (uint32_t)kMaxBuckets || M > (uint32_t)kMaxLeaves || S > 0xffffffffull) return IPLS_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> g(g_mu);
+    hipStream_t s = (hipStream_t)stream;
+    ipls_status st = l2pl_entry(device_ctx(), s, x, S, K, M, 0, nullptr, nullptr, nullptr, ab, grad, loss);
+    return finish(st, s);
 }
 
 void ipls_profile_enable(int on) {
