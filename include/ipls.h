@@ -58,14 +58,17 @@ typedef enum {
 typedef struct {
     uint32_t num_buckets;    /* K, buckets per partition, 4..256 (default 256, Proposed Algorithm) */
     uint32_t base_case_max;  /* T, buckets of <= T keys go to the base case, 1..4096 (default 4096) */
-    uint32_t sample_divisor; /* sample size S = ceil(n / divisor), >= 2 (default 100: a 1% sample) */
-    uint32_t sample_min;     /* ... raised to at least this (0 = 2K); must be <= base_case_max */
+    uint32_t sample_divisor; /* policy 0: sample size S = ceil(n / divisor), >= 2 (default 100: a 1% sample) */
+    uint32_t sample_min;     /* ... raised to at least this (0 = 2K, or none under policy 1); <= base_case_max */
     uint64_t sample_max;     /* ... and capped at this (0 = no cap); S never exceeds n */
     uint64_t seed;           /* seed of the sample positions' jitter */
     uint32_t model;          /* ipls_model_policy */
     uint32_t leaves;         /* leaves M of the two-level model, 4..256 (default 256) */
     uint32_t train_iters;    /* gradient steps of the two-level model (default 32) */
     uint32_t tile_keys;      /* keys per distribution tile, 0 = library default */
+    uint32_t sample_policy;  /* 0: the divisor rule above (Learned Sort's 1% sample, Background chapter);
+                              * 1: IPLS's alpha*K - 1 with alpha = 0.2 log2(n), rounded to nearest,
+                              *    at most ceil(n/2) (Proposed Algorithm chapter) */
 } ipls_params;
 
 /* FMCD linear model of a sample: bucket(x) = clamp(floor(fma(a, x, b)), 0, K-1). */
@@ -89,7 +92,7 @@ typedef struct {
     uint64_t keys_partitioned;  /* sum over levels of keys that went through a distribution pass */
 } ipls_stats;
 
-/* Defaults: K 256, T 4096, divisor 100, sample_min 2K, no cap, FMCD, M 256, 32 steps. */
+/* Defaults: K 256, T 4096, divisor 100, sample_min 2K, no cap, FMCD, M 256, 32 steps, policy 0. */
 void ipls_default_params(ipls_params* p);
 
 /* Sort keys[0..n) (and payload[0..n) when non-null, stably) in place with default parameters.

@@ -25,7 +25,7 @@ _DT = {np.dtype(np.float64): F64, np.dtype(np.float32): F32, np.dtype(np.uint64)
 class Params(C.Structure):
     _fields_ = [("num_buckets", C.c_uint32), ("base_case_max", C.c_uint32), ("sample_divisor", C.c_uint32),
                 ("sample_min", C.c_uint32), ("sample_max", C.c_uint64), ("seed", C.c_uint64),
-                ("model", C.c_uint32), ("leaves", C.c_uint32), ("train_iters", C.c_uint32), ("pad_", C.c_uint32)]
+                ("model", C.c_uint32), ("leaves", C.c_uint32), ("train_iters", C.c_uint32), ("sample_policy", C.c_uint32)]
 
 
 class Model(C.Structure):
@@ -47,8 +47,8 @@ DEFAULT_SEED = 0x1F5A_2208_0690_2000
 
 
 def params(K=256, T=4096, divisor=100, sample_min=0, sample_max=0, seed=DEFAULT_SEED, model=0, leaves=256,
-           train_iters=32) -> Params:
-    return Params(K, T, divisor, sample_min, sample_max, seed, model, leaves, train_iters, 0)
+           train_iters=32, sample_policy=0) -> Params:
+    return Params(K, T, divisor, sample_min, sample_max, seed, model, leaves, train_iters, sample_policy)
 
 
 def build(force: bool = False) -> str:
@@ -72,6 +72,7 @@ def lib():
         sig = {
             "oracle_mix64": (u64, [u64]),
             "oracle_sample_size": (u64, [u64, C.POINTER(Params)]),
+            "oracle_log2": (C.c_double, [u64]),
             "oracle_sample_positions": (None, [u64, u64, u64, u64, P]),
             "oracle_sorted_sample": (None, [P, u64, i32, u64, u64, u64, P]),
             "oracle_keymap": (None, [P, C.c_size_t, i32, P, P]),
@@ -124,6 +125,10 @@ def mix64(z: int) -> int:
 
 def sample_size(n: int, p: Params) -> int:
     return int(lib().oracle_sample_size(n, C.byref(p)))
+
+
+def log2(n: int) -> float:
+    return float(lib().oracle_log2(n))
 
 
 def sample_positions(n: int, lo_rel: int, S: int, seed: int) -> np.ndarray:

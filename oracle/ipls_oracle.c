@@ -53,7 +53,7 @@ typedef struct {
     uint32_t model;          /* 0 FMCD, 1 auto (two-level model iff lower max sample load), 2 two-level */
     uint32_t leaves;         /* M leaves of the two-level model */
     uint32_t train_iters;    /* gradient steps of the two-level model */
-    uint32_t pad_;
+    uint32_t sample_policy;  /* 0: S = ceil(n / divisor); 1: the paper's alpha*K - 1 */
 } oracle_params;
 
 typedef struct {
@@ -148,11 +148,47 @@ uint64_t oracle_mix64(uint64_t z) {
 /* Sample size of a bucket of n keys: ceil(n / divisor), raised to sample_min (2K by default),
  * capped by sample_max when given, and never more than n.  The paper's Learned Sort section
  * reports a 1% sample (divisor 100) as a good choice. */
+/* Binary logarithm of n >= 1: the exponent, plus 24 fractional bits obtained by squaring the
+ * mantissa m in [1, 2) repeatedly (each squaring that reaches 2 contributes the next bit). */
+double oracle_log2(uint64_t n) {
+    int e = 63 - __builtin_clzll(n);
+    double m = ldexp((double)n, -e);
+    if (m >= 2.0) { /* (double)n rounded up to the next power of two */
+        m = m / 2.0;
+        e = e + 1;
+    }
+    double f = 0.0, bit = 0.5;
+    for (int i = 0; i < 24; ++i) {
+        m = m * m;
+        if (m >= 2.0) {
+            m = m / 2.0;
+            f = f + bit;
+        }
+        bit = bit / 2.0;
+    }
+    return (double)e + f;
+}
+
+/* Sample size of a bucket of n keys.
+ * Policy 0 (Learned Sort's 1%, Background chapter): ceil(n / divisor), at least sample_min
+ *   (0 means 2K).
+ * Policy 1 (IPLS, Proposed Algorithm chapter): alpha*K - 1 with alpha = 0.2 log2(n), rounded
+ *   to the nearest integer (halves down), at least sample_min when that is non-zero, and at
+ *   most ceil(n/2) so that a sample is always smaller than its bucket.
+ * Both: at most sample_max when non-zero, never above n. */
 uint64_t oracle_sample_size(uint64_t n, const oracle_params* p) {
-    uint64_t div = p->sample_divisor ? p->sample_divisor : 100;
-    uint64_t smin = p->sample_min ? p->sample_min : 2ull * p->num_buckets;
-    uint64_t s = (n + div - 1) / div;
-    if (s < smin) s = smin;
+    uint64_t s;
+    if (p->sample_policy == 1) {
+        double t = 0.2 * oracle_log2(n ? n : 1) * (double)p->num_buckets - 0.5;
+        s = t > 0.0 ? (uint64_t)t : 0;
+        if (p->sample_min && s < p->sample_min) s = p->sample_min;
+        if (s > (n + 1) / 2) s = (n + 1) / 2;
+    } else {
+        uint64_t div = p->sample_divisor ? p->sample_divisor : 100;
+        uint64_t smin = p->sample_min ? p->sample_min : 2ull * p->num_buckets;
+        s = (n + div - 1) / div;
+        if (s < smin) s = smin;
+    }
     if (p->sample_max && s > p->sample_max) s = p->sample_max;
     if (s > n) s = n;
     return s;

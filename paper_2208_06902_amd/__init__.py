@@ -35,7 +35,7 @@ class Params(C.Structure):
     _fields_ = [("num_buckets", C.c_uint32), ("base_case_max", C.c_uint32), ("sample_divisor", C.c_uint32),
                 ("sample_min", C.c_uint32), ("sample_max", C.c_uint64), ("seed", C.c_uint64),
                 ("model", C.c_uint32), ("leaves", C.c_uint32), ("train_iters", C.c_uint32),
-                ("tile_keys", C.c_uint32)]
+                ("tile_keys", C.c_uint32), ("sample_policy", C.c_uint32)]
 
 
 class LinearModel(C.Structure):
@@ -90,7 +90,10 @@ def load(path: str = LIB_PATH):
 def default_params(**kw) -> Params:
     p = Params()
     load().ipls_default_params(C.byref(p))
+    names = {f for f, _ in Params._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"unknown ipls_params field {k!r}")
         setattr(p, k, v)
     return p
 

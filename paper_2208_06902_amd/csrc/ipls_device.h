@@ -142,10 +142,42 @@ __device__ __host__ inline uint64_t mix64(uint64_t z) {
 }
 constexpr uint64_t kGamma = 0x9e3779b97f4a7c15ull;
 
-// Sample size of a bucket of n keys: ceil(n / div), at least smin, at most smax (if non-zero), <= n.
-__device__ __host__ inline uint64_t sample_size(uint64_t n, uint64_t div, uint64_t smin, uint64_t smax) {
-    uint64_t s = (n + div - 1) / div;
-    if (s < smin) s = smin;
+// Binary logarithm of n >= 1: exponent plus 24 fractional bits, each bit read off by squaring
+// the mantissa in [1, 2) and halving it when it reaches 2.
+__device__ __host__ inline double log2_bits(uint64_t n) {
+    int e = 63 - __builtin_clzll(n);
+    double m = (double)n * __builtin_bit_cast(double, (uint64_t)(1023 - e) << 52);
+    if (m >= 2.0) {  // (double)n rounded up to 2^(e+1)
+        m *= 0.5;
+        e += 1;
+    }
+    double frac = 0.0, bit = 0.5;
+    for (int i = 0; i < 24; ++i) {
+        m = m * m;
+        if (m >= 2.0) {
+            m *= 0.5;
+            frac += bit;
+        }
+        bit *= 0.5;
+    }
+    return (double)e + frac;
+}
+
+// Sample size of a bucket of n keys.  Policy 0: ceil(n / div), at least smin.  Policy 1 (the
+// paper's IPLS): alpha*K - 1 with alpha = 0.2 log2(n), rounded to nearest (halves down), at
+// least smin, at most ceil(n/2).  Then at most smax (if non-zero) and never above n.
+__device__ __host__ inline uint64_t sample_size(uint64_t n, uint64_t div, uint64_t smin, uint64_t smax,
+                                                uint32_t policy, uint32_t K) {
+    uint64_t s;
+    if (policy == 1) {
+        double t = 0.2 * log2_bits(n ? n : 1) * (double)K - 0.5;
+        s = t > 0.0 ? (uint64_t)t : 0;
+        if (s < smin) s = smin;
+        if (s > (n + 1) / 2) s = (n + 1) / 2;
+    } else {
+        s = (n + div - 1) / div;
+        if (s < smin) s = smin;
+    }
     if (smax && s > smax) s = smax;
     if (s > n) s = n;
     return s;

@@ -19,6 +19,7 @@ namespace ipls {
 struct LevelArgs {
     uint32_t K, T, M;
     uint64_t div, smin, smax, seed;
+    uint32_t policy;
     uint32_t tile_keys, small_S, fit_chunk, cand, chunk;
 };
 
@@ -49,7 +50,7 @@ __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* cnt,
             n = items[i].n;
             nt = (n + A.tile_keys - 1) / A.tile_keys;
             nc = (nt + A.chunk - 1) / A.chunk;
-            ns = sample_size(n, A.div, A.smin, A.smax);
+            ns = sample_size(n, A.div, A.smin, A.smax, A.policy, A.K);
             nf = ns > A.small_S ? (ns + A.fit_chunk - 1) / A.fit_chunk : 0;
             atomicMax((unsigned long long*)&s_max[0], (unsigned long long)ns);
             atomicMax((unsigned long long*)&s_max[1], (unsigned long long)n);

@@ -340,8 +340,9 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     A.T = T_;
     A.M = P.leaves;
     A.div = P.sample_divisor;
-    A.smin = P.sample_min ? P.sample_min : 2ull * K;
+    A.smin = P.sample_min ? P.sample_min : (P.sample_policy == 1 ? 0 : 2ull * K);
     A.smax = P.sample_max;
+    A.policy = P.sample_policy;
     A.seed = P.seed;
     A.tile_keys = kTile;
     A.small_S = kSmallS;
@@ -558,7 +559,8 @@ ipls_status l2pl_entry(Device& dv, hipStream_t s, const double* x, uint64_t S, u
 
 ipls_status check_params(const ipls_params& p) {
     if (p.num_buckets < 4 || p.base_case_max < 1 || p.sample_divisor < 2) return IPLS_ERR_INVALID;
-    const uint64_t smin = p.sample_min ? p.sample_min : 2ull * p.num_buckets;
+    if (p.sample_policy > 1) return IPLS_ERR_INVALID;
+    const uint64_t smin = p.sample_min ? p.sample_min : (p.sample_policy == 1 ? 0 : 2ull * p.num_buckets);
     if (smin > p.base_case_max) return IPLS_ERR_INVALID;
     if (p.model > 2) return IPLS_ERR_INVALID;
     if (p.leaves < 4) return IPLS_ERR_INVALID;
@@ -616,6 +618,7 @@ void ipls_default_params(ipls_params* p) {
     p->leaves = 256;
     p->train_iters = 32;
     p->tile_keys = 0;
+    p->sample_policy = 0;
 }
 
 const char* ipls_status_string(ipls_status st) {

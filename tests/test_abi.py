@@ -42,3 +42,22 @@ def test_host_only_entry_points():
     assert ipls.workspace_bytes(1000, ipls.F64, False) == 8192  # 8000 bytes rounded up to 256
     assert ipls.workspace_bytes(1000, ipls.F32, True) == 4096 + 4000
     assert ipls.workspace_bytes(10, 7, False) == 0
+
+
+@pytest.mark.parametrize("field,value", [("sample_policy", 2), ("num_buckets", 3), ("sample_divisor", 1),
+                                         ("sample_min", 5000), ("model", 3), ("leaves", 2)])
+def test_invalid_params_rejected_before_any_device_work(field, value):
+    # argument errors return synchronously; the key pointer is never dereferenced
+    if not os.path.exists(ipls.LIB_PATH):
+        pytest.skip("libipls.so not built")
+    p = ipls.default_params(**{field: value})
+    lib = ipls.load()
+    st = lib.ipls_sort_ex(ctypes.c_void_p(4096), None, 100, ipls.F64, ctypes.byref(p), None, 0, None, None)
+    assert st == 1  # IPLS_ERR_INVALID
+
+
+def test_unknown_param_name_is_an_error():
+    if not os.path.exists(ipls.LIB_PATH):
+        pytest.skip("libipls.so not built")
+    with pytest.raises(TypeError):
+        ipls.default_params(sample_polciy=1)

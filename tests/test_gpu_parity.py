@@ -28,7 +28,8 @@ def gpu_sort(keys, payload=None, **kw):
 def oracle_params(**kw):
     m = dict(K=kw.get("num_buckets", 256), T=kw.get("base_case_max", 4096), divisor=kw.get("sample_divisor", 100),
              sample_min=kw.get("sample_min", 0), sample_max=kw.get("sample_max", 0),
-             model=kw.get("model", 0), leaves=kw.get("leaves", 256), train_iters=kw.get("train_iters", 32))
+             model=kw.get("model", 0), leaves=kw.get("leaves", 256), train_iters=kw.get("train_iters", 32),
+             sample_policy=kw.get("sample_policy", 0))
     return oracle.params(**m)
 
 
@@ -59,6 +60,14 @@ def test_sort_f64_default_params(dist):
                                 dict(num_buckets=256, base_case_max=1000, sample_divisor=7)])
 def test_sort_f64_params(dist, kw):
     check_sort(gen.make(dist, 50_000, 5), **kw)
+
+
+@pytest.mark.parametrize("dist", ["normal", "exponential", "two_dups", "zipf_u64"])
+@pytest.mark.parametrize("kw", [dict(sample_policy=1), dict(sample_policy=1, num_buckets=16, base_case_max=64),
+                                dict(sample_policy=1, num_buckets=64, base_case_max=32, sample_min=20)])
+def test_sort_paper_sample_policy(dist, kw):
+    k = gen.make(dist, 250_000, 17)
+    check_sort(k, gen.index_payload(k.size), **kw)
 
 
 def test_sort_u64_uniform_and_zipf_payload():

@@ -248,6 +248,41 @@ def test_sample_size_policy(n):
     assert S == min(n, max(512, -(-n // 100)))
 
 
+def test_log2_against_exact_bounds():
+    # 24 fractional bits, truncated: log2(n) - 2^-23 < L <= log2(n) + tiny, and exact at powers of two
+    import math
+    r = np.random.default_rng(11)
+    ns = [1, 2, 3, 5, 4095, 4096, 4097, 10**6, 10**8, 10**9, 2**53 - 1, 2**53 + 1, 2**64 - 1]
+    ns += [int(v) for v in r.integers(1, 2**62, 2000)]
+    for n in ns:
+        L = oracle.log2(n)
+        exact = math.log2(n) if n < 2**53 else math.log2(n >> 11) + 11
+        assert exact - 2**-22 < L <= exact + 1e-12, (n, L, exact)
+    for e in range(64):
+        assert oracle.log2(2**e) == e
+
+
+@pytest.mark.parametrize("n,S", [(10**6, 1019), (10**8, 1360), (10**9, 1530)])
+def test_paper_sample_size_vectors(n, S):
+    # alpha*K - 1 with alpha = 0.2 log2(n) and K = 256, rounded (Proposed Algorithm chapter)
+    assert oracle.sample_size(n, oracle.params(sample_policy=1)) == S
+
+
+def test_paper_sample_size_rounding_and_bounds():
+    import math
+    for K in (4, 16, 256):
+        p = oracle.params(K=K, sample_policy=1)
+        for n in list(range(1, 3000)) + [10**k + 7 for k in range(4, 12)]:
+            t = 0.2 * math.log2(n) * K - 1
+            if abs(t - math.floor(t) - 0.5) < 1e-4:
+                continue  # within the 24-bit logarithm's error of a rounding tie
+            want = max(0, math.floor(t + 0.5)) if t - math.floor(t) != 0.5 else math.floor(t)
+            want = min(want, (n + 1) // 2, n)
+            assert oracle.sample_size(n, p) == want, (K, n)
+    assert oracle.sample_size(10**8, oracle.params(sample_policy=1, sample_min=2000)) == 2000
+    assert oracle.sample_size(10**8, oracle.params(sample_policy=1, sample_max=1000)) == 1000
+
+
 @pytest.mark.parametrize("n,S,lo", [(5000, 512, 0), (10**6, 10**4, 123456), (997, 997, 5), (10**5, 1000, 7)])
 def test_sample_positions_one_per_stratum(n, S, lo):
     pos = oracle.sample_positions(n, lo, S, 42)
