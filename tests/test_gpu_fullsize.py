@@ -7,11 +7,15 @@
 * 10^9 uniform uint64 keys: too large for the oracle in a test, so checked by properties that
   hold at any size: the output is non-decreasing and is the same multiset as the input
   (compared with an independent device sort of the input).
+
+The two uint64 inputs are drawn on the GPU (gen.device); the oracle gets a host copy of the
+same bytes.
 """
 import numpy as np
 import pytest
 
 import gen
+import gen.device as gdev
 import oracle
 import paper_2208_06902_amd as ipls
 
@@ -50,9 +54,13 @@ def test_1e8_fp64_against_oracle(dist, seed):
 def test_2e8_zipf_u64_payload_against_oracle():
     n = 200_000_000
     print(f"full size zipf u64 + payload n={n}", flush=True)
-    keys = gen.zipf_u64(n, 8)
+    kd = gdev.zipf_u64(n, 8)
+    keys = kd.cpu().numpy().view(np.uint64)
     pay = gen.index_payload(n)
-    kd, pd, st = _sort_on_device(keys, pay, **BENCH)
+    kd = kd.view(torch.uint64)
+    pd = torch.from_numpy(pay.view(np.int32)).to("cuda:0")
+    st = ipls.sort_(kd, pd, params=ipls.default_params(**BENCH), stats=True)
+    torch.cuda.synchronize()
     got = kd.view(torch.int64).cpu().numpy().view(np.uint64)
     gpay = pd.cpu().numpy().view(np.uint32)
     del kd, pd
@@ -65,15 +73,16 @@ def test_2e8_zipf_u64_payload_against_oracle():
 def test_1e9_u64_sorted_permutation():
     n = 1_000_000_000
     print(f"full size u64 uniform n={n}", flush=True)
-    keys = gen.u64_uniform(n, 7)
-    kd, _, st = _sort_on_device(keys, **BENCH)
+    src = gdev.u64_uniform(n, 7)
+    kd = src.clone().view(torch.uint64)
+    st = ipls.sort_(kd, None, params=ipls.default_params(**BENCH), stats=True)
+    torch.cuda.synchronize()
     # uint64 order is the signed order of the values with the top bit flipped
     flip = torch.tensor(-(2**63), dtype=torch.int64, device="cuda:0")
     got = torch.bitwise_xor(kd.view(torch.int64), flip)
     del kd
     assert bool((got[1:] >= got[:-1]).all())
-    ref = torch.from_numpy(keys.view(np.int64)).to("cuda:0")
-    ref = torch.bitwise_xor(ref, flip)
-    ref = torch.sort(ref).values
+    ref = torch.sort(torch.bitwise_xor(src, flip)).values
+    del src
     assert torch.equal(ref, got)
     assert st["levels"] >= 3
