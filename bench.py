@@ -142,6 +142,231 @@ def cpu_model() -> str:
     return platform.processor()
 
 
+def _line(value, ms_per_step, steps, warmup, dtype, config, **extra):
+    line = {"metric": METRIC, "value": round(value, 1), "unit": "keys/s", "n_gpus": 1, "steps": steps,
+            "warmup": warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config,
+            "roofline": None, "cpu_baseline": None}
+    line.update(extra)
+    return line
+
+
+def _u64_sorted(t, torch):
+    flip = torch.tensor(-(2**63), dtype=torch.int64, device=t.device)
+    v = torch.bitwise_xor(t.view(torch.int64), flip)
+    return bool((v[1:] >= v[:-1]).all())
+
+
+def bench_batched(args):
+    """Batched form: 100,000 fp64 arrays with lognormal sizes (median 4096, sigma 1.39, clipped to
+    [64, 1e7]), each drawn from one of six distributions chosen per array by seed, sorted by one
+    segmented sort with autotuned parameters; compared with the default parameters and with one
+    plain ipls_sort launch per array (on a bounded leading subset of the arrays)."""
+    import numpy as np
+    import torch
+
+    import gen
+    import gen.device as gdev
+    import paper_2208_06902_amd as ipls
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    nseg = args.arrays
+    sizes = gen.segment_sizes_lognormal(nseg, 10, median=4096, lo=64, hi=10_000_000)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    total = int(off[-1])
+    dists6 = ("uniform01", "normal", "lognormal", "exponential", "mixgauss", "uniform_int")
+    which = np.random.default_rng(11).integers(0, 6, nseg)
+    print(f"# batched: {nseg} arrays, {total} fp64 keys", file=sys.stderr, flush=True)
+    ids = torch.repeat_interleave(torch.from_numpy(which).to(dev), torch.from_numpy(sizes.astype(np.int64)).to(dev))
+    pristine = torch.empty(total, dtype=torch.float64, device=dev)
+    for d in range(6):
+        part = gdev.fp64(dists6[d], total, 20 + d, device=dev)
+        torch.where(ids == d, part, pristine, out=pristine)
+        del part
+    del ids
+    offs = torch.from_numpy(off.view(np.int64)).to(dev)
+    work = torch.empty_like(pristine)
+    stream = torch.cuda.current_stream()
+
+    t = time.perf_counter()
+    tuned, rep = ipls.autotune_segmented(pristine, offs)
+    tune_s = time.perf_counter() - t
+    base = ipls.default_params()
+
+    def run(params, reps):
+        ms = []
+        for _ in range(reps):
+            work.copy_(pristine)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            ipls.sort_segmented_(work, offs, params=params)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        return ms
+
+    run(tuned, args.warmup)
+    tuned_ms = run(tuned, args.steps)
+    base_ms = run(base, max(1, args.steps // 2))
+    # correctness on a sample of arrays: sorted and a permutation of the input (device sort as reference)
+    work.copy_(pristine)
+    ipls.sort_segmented_(work, offs, params=tuned)
+    torch.cuda.synchronize()
+    ok = True
+    for i in np.random.default_rng(12).integers(0, nseg, 64):
+        a, b = int(off[i]), int(off[i + 1])
+        ok &= torch.equal(work[a:b], torch.sort(pristine[a:b]).values)
+    # plain launches, one per array, on the leading arrays up to args.plain_keys keys
+    m = int(np.searchsorted(off, args.plain_keys, side="right")) - 1
+    m = max(1, min(m, nseg))
+    sub_keys = int(off[m])
+    work[:sub_keys].copy_(pristine[:sub_keys])
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for i in range(m):
+        lo, hi = int(off[i]), int(off[i + 1])
+        ipls.sort_(work[lo:hi], None, base)
+    b.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = a.elapsed_time(b)
+    sub_offs = offs[: m + 1].clone()
+    work[:sub_keys].copy_(pristine[:sub_keys])
+    a.record(stream)
+    ipls.sort_segmented_(work[:sub_keys], sub_offs, params=tuned)
+    b.record(stream)
+    torch.cuda.synchronize()
+    sub_batched_ms = a.elapsed_time(b)
+    mean_ms = sum(tuned_ms) / len(tuned_ms)
+    line = _line(total / (mean_ms / 1e3), mean_ms, args.steps, args.warmup, "f64",
+                 {"workload": f"batched segmented sort: {nseg} fp64 arrays, lognormal sizes (median 4096, "
+                              f"sigma 1.39, clipped to [64, 1e7]), {total} keys, six distributions chosen per array",
+                  "arrays": nseg, "keys": total, "parallelism": "single GPU"},
+                 tuned_params={"num_buckets": tuned.num_buckets, "base_case_max": tuned.base_case_max,
+                               "tile_keys": tuned.tile_keys or 4096},
+                 autotune={"seconds": round(tune_s, 3), **{k: (round(v, 4) if isinstance(v, float) else v)
+                                                           for k, v in rep.items()}},
+                 default_params_keys_per_s=round(total / (sum(base_ms) / len(base_ms) / 1e3), 1),
+                 plain_per_array={"arrays": m, "keys": sub_keys, "plain_keys_per_s": round(sub_keys / (plain_ms / 1e3), 1),
+                                  "batched_keys_per_s": round(sub_keys / (sub_batched_ms / 1e3), 1),
+                                  "speedup": round(plain_ms / sub_batched_ms, 2)},
+                 outputs_sorted=bool(ok))
+    print(json.dumps(line), flush=True)
+
+
+def bench_served(args):
+    """Served form: Poisson arrivals at args.rate requests/s (seed 9), sizes log-uniform in
+    [1e3, 1e8], dtypes 50% fp64 / 30% uint64 / 20% fp32, distributions including lognormal(sigma=2)
+    and a 20-component Gaussian mixture, admitted under a 64 GB HBM budget, the learned model
+    chosen when its max bucket load is lower.  Inputs are generated on the device into the
+    admitted slots.  Reports latency (arrival to completion) percentiles and throughput, then the
+    same requests all at once (capacity) and as plain one-at-a-time ipls_sort launches."""
+    import numpy as np
+    import torch
+
+    import gen.device as gdev
+    import paper_2208_06902_amd as ipls
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    count = args.requests
+    r = np.random.default_rng(9)
+    arrival = np.cumsum(r.exponential(1.0 / args.rate, count))
+    sizes = np.round(10 ** r.uniform(3, 8, count)).astype(np.int64)
+    u = r.random(count)
+    dtypes = np.where(u < 0.5, 0, np.where(u < 0.8, 2, 1))
+    dnames = ("lognormal2", "mixgauss20", "normal", "exponential", "uniform01", "lognormal")
+    which = r.integers(0, len(dnames), count)
+    total = int(sizes.sum())
+    params = ipls.default_params(model=ipls.MODEL_AUTO, sample_max=args.sample_max)
+    budget = args.budget_gb << 30
+    arena = torch.empty(budget, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    print(f"# served: {count} requests, {total} keys, budget {args.budget_gb} GB", file=sys.stderr, flush=True)
+
+    srv = ipls.Server(arena, ipls.server_config(params, lanes=args.lanes))
+
+    def serve(arrivals, k):
+        done_t = {}
+        checked = [True]
+        before = srv.stats()
+        views = {}
+
+        def reap():
+            for d in srv.poll(1024):
+                i, kv = views.pop(d["req_id"])
+                if d["status"] != 0:
+                    raise RuntimeError(f"request {i} failed: {d}")
+                done_t[i] = d["t_done"]
+                if i % 97 == 0:  # spot check of the order before the slot is released
+                    checked[0] &= _u64_sorted(kv, torch) if dtypes[i] == 2 else bool((kv[1:] >= kv[:-1]).all())
+                srv.release(d["req_id"])
+
+        t0 = time.monotonic() + 0.02
+        for i in range(k):
+            while time.monotonic() < t0 + arrivals[i]:
+                reap()
+            while True:
+                got = srv.reserve(int(sizes[i]), int(dtypes[i]), False)
+                if got is not None:
+                    break
+                reap()
+                time.sleep(0.0002)
+            rid, kv, _ = got
+            gdev.request_keys(dnames[which[i]], int(sizes[i]), 50_000 + i, int(dtypes[i]), kv, device=dev)
+            srv.submit(rid, stream)
+            views[rid] = (i, kv)
+        while views:
+            reap()
+            time.sleep(0.0002)
+        after = srv.stats()
+        st = {f: after[f] - before[f] for f in ("batches_run", "singles_run", "rejected")}
+        st["max_queue_depth"] = after["max_queue_depth"]
+        st["peak_bytes_in_use"] = after["peak_bytes_in_use"]
+        lat = np.array([done_t[i] - (t0 + arrivals[i]) for i in range(k)]) * 1e3
+        span = max(done_t.values()) - t0
+        return lat, span, st, checked[0]
+
+    serve(np.zeros(count), min(count, 200))  # warm the lanes' contexts
+    lat, span, st, ok1 = serve(arrival, count)
+    lat_sat, span_sat, st_sat, ok2 = serve(np.zeros(count), count)
+    srv.close()
+    # plain: one request at a time through ipls_sort, same generation
+    bufs = {0: torch.empty(int(sizes.max()), dtype=torch.float64, device=dev),
+            1: torch.empty(int(sizes.max()), dtype=torch.float32, device=dev),
+            2: torch.empty(int(sizes.max()), dtype=torch.int64, device=dev)}
+    torch.cuda.synchronize()
+    t = time.monotonic()
+    for i in range(count):
+        n = int(sizes[i])
+        b = bufs[int(dtypes[i])][:n]
+        gdev.request_keys(dnames[which[i]], n, 50_000 + i, int(dtypes[i]), b, device=dev)
+        ipls.sort_(b.view(torch.uint64) if dtypes[i] == 2 else b, None, params)
+    torch.cuda.synchronize()
+    plain_s = time.monotonic() - t
+    achieved = total / span
+    line = _line(achieved, span * 1e3 / count, count, 0, "mixed f64/u64/f32",
+                 {"workload": f"served: {count} requests, Poisson {args.rate:g}/s, sizes log-uniform [1e3, 1e8], "
+                              f"dtypes 50/30/20 f64/u64/f32, {args.budget_gb} GB budget, learned model when lower "
+                              f"max load", "requests": count, "keys": total, "lanes": args.lanes,
+                  "parallelism": "single GPU"},
+                 latency_ms={"p50": round(float(np.percentile(lat, 50)), 3),
+                             "p99": round(float(np.percentile(lat, 99)), 3),
+                             "mean": round(float(lat.mean()), 3), "max": round(float(lat.max()), 3)},
+                 offered_keys_per_s=round(total / float(arrival[-1]), 1),
+                 saturated={"keys_per_s": round(total / span_sat, 1),
+                            "latency_p50_ms": round(float(np.percentile(lat_sat, 50)), 3),
+                            "latency_p99_ms": round(float(np.percentile(lat_sat, 99)), 3)},
+                 plain_one_at_a_time_keys_per_s=round(total / plain_s, 1),
+                 saturated_vs_plain=round(plain_s / span_sat, 2),
+                 server={"batches_run": st["batches_run"], "singles_run": st["singles_run"],
+                         "max_queue_depth": st["max_queue_depth"], "rejected_reserves": st["rejected"],
+                         "peak_bytes_in_use": st["peak_bytes_in_use"]},
+                 outputs_sorted=bool(ok1 and ok2))
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +376,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dists", default=",".join(DISTS))
     ap.add_argument("--sample-max", type=int, default=4096)
+    ap.add_argument("--workload", choices=("sort", "batched", "served"), default="sort",
+                    help="sort: the 1e8 fp64 single-array sort (default); batched; served")
+    ap.add_argument("--arrays", type=int, default=100_000, help="batched: number of arrays")
+    ap.add_argument("--plain-keys", type=int, default=50_000_000, help="batched: keys of the per-array subset")
+    ap.add_argument("--requests", type=int, default=4000, help="served: number of requests")
+    ap.add_argument("--rate", type=float, default=2000.0, help="served: arrivals per second")
+    ap.add_argument("--budget-gb", type=int, default=64, help="served: HBM budget")
+    ap.add_argument("--lanes", type=int, default=3, help="served: concurrent lanes")
     ap.add_argument("--summarize-profiles", nargs=4, metavar=("KTRACE_DIR", "FETCH_DIR", "WRITE_DIR", "BENCH_JSON"),
                     help="write profiles/ summaries from rocprofv3 CSV output and exit")
     args = ap.parse_args()
@@ -161,6 +394,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU form is not built",
               file=sys.stderr, flush=True)
         sys.exit(2)
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "served":
+        return bench_served(args)
 
     import numpy as np
     import torch

@@ -49,3 +49,53 @@ def zipf_u64(n: int, seed: int, s: float = 1.1, vmax: int = 2**32, device="cuda:
             out[todo[ok]] = k[ok].to(torch.int64)
             todo = todo[~ok]
     return out
+
+
+# ---------------------------------------------------------------- fp64 distributions on the device
+# The same recipes as the host generators (different random streams): normal(0,1),
+# lognormal(0, sigma), exponential(lam), a mixture of m N(mu_i, 1) with mu_i ~ U[-100, 100] and
+# equal weights, integers uniform in [0, hi) as fp64, and U[0, 1).
+DEVICE_DISTS = ("uniform01", "normal", "lognormal", "exponential", "mixgauss", "uniform_int", "lognormal2",
+                "mixgauss20")
+
+
+def fp64(dist: str, n: int, seed: int, device="cuda:0", out: torch.Tensor | None = None) -> torch.Tensor:
+    """n fp64 keys of a named distribution, written into `out` when given."""
+    g = _gen(seed, device)
+    x = out if out is not None else torch.empty(n, dtype=torch.float64, device=device)
+    if dist == "uniform01":
+        x.uniform_(0.0, 1.0, generator=g)
+    elif dist == "normal":
+        x.normal_(0.0, 1.0, generator=g)
+    elif dist in ("lognormal", "lognormal2"):
+        x.log_normal_(0.0, 0.5 if dist == "lognormal" else 2.0, generator=g)
+    elif dist == "exponential":
+        x.exponential_(2.0, generator=g)
+    elif dist in ("mixgauss", "mixgauss20"):
+        m = 5 if dist == "mixgauss" else 20
+        means = torch.empty(m, dtype=torch.float64, device=device).uniform_(-100.0, 100.0, generator=g)
+        comp = torch.randint(0, m, (n,), device=device, generator=g)
+        x.normal_(0.0, 1.0, generator=g)
+        x.add_(means[comp])
+    elif dist == "uniform_int":
+        x.copy_(torch.randint(0, 1_000_000, (n,), device=device, generator=g))
+    else:
+        raise ValueError(dist)
+    return x
+
+
+def request_keys(dist: str, n: int, seed: int, dtype: int, out: torch.Tensor, device="cuda:0") -> None:
+    """A served request's keys into `out`: fp64 as drawn, uint64 = floor(|x| * 2^32) (written as
+    int64 bits), fp32 = x rounded to nearest."""
+    if dtype == 0:
+        fp64(dist, n, seed, device, out=out)
+        return
+    x = fp64(dist, n, seed, device)
+    if dtype == 1:
+        out.copy_(x)
+    else:
+        y = torch.floor(torch.abs(x) * 4294967296.0)
+        # values reach 2^64 only for |x| >= 2^32, which these distributions do not draw
+        big = y >= 9223372036854775808.0
+        lo = torch.where(big, y - 18446744073709551616.0, y).to(torch.int64)
+        out.view(torch.int64).copy_(lo)

@@ -65,7 +65,7 @@ typedef struct {
     uint32_t model;          /* ipls_model_policy */
     uint32_t leaves;         /* leaves M of the two-level model, 4..256 (default 256) */
     uint32_t train_iters;    /* gradient steps of the two-level model (default 32) */
-    uint32_t tile_keys;      /* keys per distribution tile, 0 = library default */
+    uint32_t tile_keys;      /* keys per distribution tile: 0 or 4096 (default), or 2048 */
     uint32_t sample_policy;  /* 0: the divisor rule above (Learned Sort's 1% sample, Background chapter);
                               * 1: IPLS's alpha*K - 1 with alpha = 0.2 log2(n), rounded to nearest,
                               *    at most ceil(n/2) (Proposed Algorithm chapter) */
@@ -156,6 +156,87 @@ const char* ipls_status_string(ipls_status st);
  * bytes (keys and payload each kernel must read and write).  Enabling resets the counters. */
 void ipls_profile_enable(int on);
 void ipls_profile_read(int kernel, uint64_t* launches, double* ms, double* bytes);
+
+/* ---------------------------------------------------------------- batched form: autotuner
+ * Picks num_buckets (K), base_case_max (T) and tile_keys for the segmented sort of a batch shaped
+ * like the given one.  It times ipls_sort_segmented on a window of the batch's leading segments
+ * (at least 2^25 keys, or all of them), copied to a private buffer so the caller's keys are not
+ * modified, and walks the candidates one parameter at a time: tile_keys in {4096, 2048}, then T in
+ * {4096, 2048, 1024}, then K in {256, 128, 64}, keeping each best.  The result is a sort of the
+ * same keys (the output of a sort does not depend on these parameters); only its speed changes.
+ * keys, seg_offsets: device (as ipls_sort_segmented); base: the other parameters (NULL =
+ * defaults); out: host, receives the chosen parameters; report: host, nullable.  Synchronous. */
+typedef struct {
+    uint32_t trials;       /* configurations timed */
+    uint32_t window_segments;
+    uint64_t window_keys;
+    double default_ms;     /* window sort time with the base parameters */
+    double best_ms;        /* window sort time with the chosen parameters */
+} ipls_tune_report;
+
+ipls_status ipls_autotune_segmented(const void* keys, const uint64_t* seg_offsets, size_t nseg, ipls_dtype dtype,
+                                    int has_payload, const ipls_params* base, ipls_params* out,
+                                    ipls_tune_report* report, void* stream);
+
+/* ---------------------------------------------------------------- served form: request server
+ * Continuous batching of sort requests of mixed sizes and dtypes on one GPU.
+ *   Memory: the caller gives the server one device arena (the HBM budget, 256-byte aligned,
+ *   caller-owned, outlives the server).  ipls_server_reserve admits a request when its memory fits
+ *   now and never blocks: a request of more than batch_max_keys keys gets its own slot (keys,
+ *   payload) plus its sort workspace; a smaller one gets a slot at the end of the open batch
+ *   buffer of its class (dtype, payload or not), so the slots of a batch are contiguous and the
+ *   batch is sorted in place by one segmented sort.  IPLS_ERR_OOM means "not now": retry after a
+ *   release.  Engine metadata (per-level tables, about 1.5 bytes per key of the largest request a
+ *   lane has run) is allocated outside the arena.
+ *   Flow: reserve -> caller writes the input into the slot (any stream) -> submit(stream) -> the
+ *   server's sort waits for that stream's work with an event -> wait/poll -> caller reads the
+ *   sorted slot -> release.
+ *   Execution: `lanes` threads, each with its own stream and engine context, take submitted work
+ *   in order: a large request, or a whole batch (taking a batch closes it).  Lanes overlap on the
+ *   device.  A request's result is bit-identical to ipls_sort_ex of its keys alone with the same
+ *   parameters.  Timestamps are CLOCK_MONOTONIC seconds. */
+typedef struct ipls_server ipls_server;
+
+typedef struct {
+    uint32_t lanes;              /* concurrent lanes, 1..16 (default 3) */
+    uint32_t batch_max_requests; /* requests per batch (default 1024) */
+    uint64_t batch_max_keys;     /* requests of at most this many keys are batched (default 2^18) */
+    uint64_t batch_keys;         /* key capacity of one batch buffer, >= batch_max_keys (default 2^22) */
+    ipls_params params;          /* sort parameters of every request */
+} ipls_server_config;
+
+typedef struct {
+    uint64_t req_id;
+    uint64_t n;
+    ipls_status status;
+    uint32_t batch_size;         /* requests sorted together with it (1 for a large request) */
+    double t_reserve, t_submit, t_start, t_done;
+} ipls_server_done;
+
+typedef struct {
+    uint64_t admitted, completed, rejected; /* rejected: reserve calls answered IPLS_ERR_OOM */
+    uint64_t singles_run, batches_run, keys_sorted;
+    uint64_t arena_bytes, bytes_in_use, peak_bytes_in_use;
+    uint64_t queue_depth, max_queue_depth;
+} ipls_server_stats;
+
+void ipls_server_default_config(ipls_server_config* cfg);
+ipls_status ipls_server_create(void* arena, size_t arena_bytes, const ipls_server_config* cfg, ipls_server** out);
+/* keys, payload (host out-params) receive the slot's device pointers; payload may be NULL when
+ * has_payload is 0. */
+ipls_status ipls_server_reserve(ipls_server* srv, size_t n, ipls_dtype dtype, int has_payload, uint64_t* req_id,
+                                void** keys, uint32_t** payload);
+ipls_status ipls_server_submit(ipls_server* srv, uint64_t req_id, void* producer_stream);
+/* Blocks until the request is done; returns its status; info (host, nullable) its timestamps. */
+ipls_status ipls_server_wait(ipls_server* srv, uint64_t req_id, ipls_server_done* info);
+/* Up to max completions not yet reported, in completion order. */
+ipls_status ipls_server_poll(ipls_server* srv, ipls_server_done* out, size_t max, size_t* count);
+/* Frees a done request's memory; its slot must not be used afterwards. */
+ipls_status ipls_server_release(ipls_server* srv, uint64_t req_id);
+ipls_status ipls_server_stats_get(ipls_server* srv, ipls_server_stats* out);
+/* Finishes submitted work (a batch with unsubmitted slots fails with IPLS_ERR_INVALID), stops
+ * the lanes and frees the server (not the arena). */
+ipls_status ipls_server_destroy(ipls_server* srv);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,10 @@ STATUS = {0: "IPLS_OK", 1: "IPLS_ERR_INVALID", 2: "IPLS_ERR_DTYPE", 3: "IPLS_ERR
 
 EXPORTS = ["ipls_default_params", "ipls_sort", "ipls_sort_ex", "ipls_sort_segmented", "ipls_fit_model",
            "ipls_partition", "ipls_l2pl_train", "ipls_l2pl_grad", "ipls_workspace_bytes", "ipls_stream_status",
-           "ipls_status_string", "ipls_profile_enable", "ipls_profile_read"]
+           "ipls_status_string", "ipls_profile_enable", "ipls_profile_read", "ipls_autotune_segmented",
+           "ipls_server_default_config", "ipls_server_create", "ipls_server_reserve", "ipls_server_submit",
+           "ipls_server_wait", "ipls_server_poll", "ipls_server_release", "ipls_server_stats_get",
+           "ipls_server_destroy"]
 
 
 class IplsError(RuntimeError):
@@ -47,6 +50,34 @@ class Stats(C.Structure):
     _fields_ = [("levels", C.c_uint32), ("sample_depth", C.c_uint32), ("passes", C.c_uint64),
                 ("closed", C.c_uint64), ("fallback", C.c_uint64), ("l2pl_used", C.c_uint64),
                 ("base_buckets", C.c_uint64), ("level1_max_load", C.c_uint64), ("keys_partitioned", C.c_uint64)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("trials", C.c_uint32), ("window_segments", C.c_uint32), ("window_keys", C.c_uint64),
+                ("default_ms", C.c_double), ("best_ms", C.c_double)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("lanes", C.c_uint32), ("batch_max_requests", C.c_uint32), ("batch_max_keys", C.c_uint64),
+                ("batch_keys", C.c_uint64), ("params", Params)]
+
+
+class ServerDone(C.Structure):
+    _fields_ = [("req_id", C.c_uint64), ("n", C.c_uint64), ("status", C.c_int), ("batch_size", C.c_uint32),
+                ("t_reserve", C.c_double), ("t_submit", C.c_double), ("t_start", C.c_double),
+                ("t_done", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(f, C.c_uint64) for f in ("admitted", "completed", "rejected", "singles_run", "batches_run",
+                                          "keys_sorted", "arena_bytes", "bytes_in_use", "peak_bytes_in_use",
+                                          "queue_depth", "max_queue_depth")]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -78,6 +109,17 @@ def load(path: str = LIB_PATH):
         "ipls_status_string": (C.c_char_p, [i32]),
         "ipls_profile_enable": (None, [i32]),
         "ipls_profile_read": (None, [i32, C.POINTER(u64), C.POINTER(dbl), C.POINTER(dbl)]),
+        "ipls_autotune_segmented": (i32, [P, P, sz, i32, i32, C.POINTER(Params), C.POINTER(Params),
+                                          C.POINTER(TuneReport), P]),
+        "ipls_server_default_config": (None, [C.POINTER(ServerConfig)]),
+        "ipls_server_create": (i32, [P, sz, C.POINTER(ServerConfig), C.POINTER(P)]),
+        "ipls_server_reserve": (i32, [P, sz, i32, i32, C.POINTER(u64), C.POINTER(P), C.POINTER(P)]),
+        "ipls_server_submit": (i32, [P, u64, P]),
+        "ipls_server_wait": (i32, [P, u64, C.POINTER(ServerDone)]),
+        "ipls_server_poll": (i32, [P, C.POINTER(ServerDone), sz, C.POINTER(sz)]),
+        "ipls_server_release": (i32, [P, u64]),
+        "ipls_server_stats_get": (i32, [P, C.POINTER(ServerStats)]),
+        "ipls_server_destroy": (i32, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -234,3 +276,106 @@ def profile_read(kernel: int):
 
 def status_string(st: int) -> str:
     return load().ipls_status_string(st).decode()
+
+
+def autotune_segmented(keys, offsets, has_payload: bool = False, base: Params | None = None, stream=None):
+    """Pick K, T and the tile size for segmented sorts shaped like this batch: (Params, report)."""
+    _check_tensor(keys, "keys")
+    _check_tensor(offsets, "offsets")
+    out, rep = Params(), TuneReport()
+    rc = load().ipls_autotune_segmented(_ptr(keys), _ptr(offsets), offsets.numel() - 1, _dtype_code(keys),
+                                        int(has_payload), C.byref(base) if base is not None else None,
+                                        C.byref(out), C.byref(rep), _stream(stream))
+    _check(rc, "ipls_autotune_segmented")
+    return out, {f: getattr(rep, f) for f, _ in rep._fields_}
+
+
+def server_config(params: Params | None = None, **kw) -> ServerConfig:
+    c = ServerConfig()
+    load().ipls_server_default_config(C.byref(c))
+    if params is not None:
+        c.params = params
+    names = {f for f, _ in ServerConfig._fields_}
+    for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"unknown ipls_server_config field {k!r}")
+        setattr(c, k, v)
+    return c
+
+
+_TORCH_DT = {F64: "float64", F32: "float32", U64: "uint64"}
+_WIDTH = {F64: 8, F32: 4, U64: 8}
+
+
+class Server:
+    """Request server over a device arena (a torch uint8 tensor that is the HBM budget).
+
+    reserve() returns (req_id, keys_view, payload_view) -- tensors aliasing the request's slot in
+    the arena, or None when the budget is full right now.  Fill the views (on any stream), then
+    submit(); wait() or poll() for completion; read the views; release().
+    """
+
+    def __init__(self, arena, config: ServerConfig | None = None):
+        import torch
+        _check_tensor(arena, "arena")
+        if arena.dtype != torch.uint8:
+            raise TypeError("arena must be a uint8 tensor")
+        self.arena = arena
+        self._h = C.c_void_p()
+        rc = load().ipls_server_create(_ptr(arena), arena.numel(), C.byref(config) if config else None,
+                                       C.byref(self._h))
+        _check(rc, "ipls_server_create")
+
+    def reserve(self, n: int, dtype: int, payload: bool = False):
+        import torch
+        rid, kp, pp = C.c_uint64(), C.c_void_p(), C.c_void_p()
+        rc = load().ipls_server_reserve(self._h, n, dtype, int(payload), C.byref(rid), C.byref(kp), C.byref(pp))
+        if rc == 3:
+            return None
+        _check(rc, "ipls_server_reserve")
+        base = self.arena.data_ptr()
+        ko = kp.value - base
+        w = _WIDTH[dtype]
+        if dtype == U64:
+            kv = self.arena[ko:ko + n * w].view(torch.int64).view(torch.uint64)
+        else:
+            kv = self.arena[ko:ko + n * w].view(getattr(torch, _TORCH_DT[dtype]))
+        pv = None
+        if payload:
+            po = pp.value - base
+            pv = self.arena[po:po + n * 4].view(torch.int32)
+        return int(rid.value), kv, pv
+
+    def submit(self, req_id: int, stream=None):
+        _check(load().ipls_server_submit(self._h, req_id, _stream(stream)), "ipls_server_submit")
+
+    def wait(self, req_id: int) -> dict:
+        d = ServerDone()
+        rc = load().ipls_server_wait(self._h, req_id, C.byref(d))
+        _check(rc, "ipls_server_wait")
+        return d.as_dict()
+
+    def poll(self, max_items: int = 256) -> list:
+        arr = (ServerDone * max_items)()
+        cnt = C.c_size_t()
+        _check(load().ipls_server_poll(self._h, arr, max_items, C.byref(cnt)), "ipls_server_poll")
+        return [arr[i].as_dict() for i in range(cnt.value)]
+
+    def release(self, req_id: int):
+        _check(load().ipls_server_release(self._h, req_id), "ipls_server_release")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().ipls_server_stats_get(self._h, C.byref(st)), "ipls_server_stats_get")
+        return st.as_dict()
+
+    def close(self):
+        if self._h:
+            load().ipls_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

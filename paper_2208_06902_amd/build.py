@@ -8,6 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "ipls_lib.hip")
+# host-only parts of the library: the batched form's autotuner and the request server
+HOST_SRCS = [os.path.join(HERE, "csrc", "ipls_tune.cpp"), os.path.join(HERE, "csrc", "ipls_server.cpp")]
 LIB = os.path.join(HERE, "libipls.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -23,7 +25,7 @@ FLAGS = [
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, SRC, "-o", tmp]
+    cmd = [HIPCC, *FLAGS, SRC, *HOST_SRCS, "-lpthread", "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

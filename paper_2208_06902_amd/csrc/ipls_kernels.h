@@ -632,7 +632,8 @@ __global__ void k_finalize(const Item* items, Model* models, const Model* roots,
 }
 
 // ------------------------------------------------------------------ tiles and chunks
-// A level's keys are cut into tiles of 256 * kIPT keys (tiles never cross items); kChunk
+// A level's keys are cut into tiles of 256 * IPT keys (IPT = 16 by default, 8 for the small
+// tiles the batched form may pick; tiles never cross items); kChunk
 // consecutive tiles of an item form a chunk.  Counting, the prefix scan and the scatter all use
 // this layout:
 //   k_classify_hist: per chunk, the count of every (tile, bucket) -> the tile's exclusive prefix
@@ -646,6 +647,7 @@ __global__ void k_finalize(const Item* items, Model* models, const Model* roots,
 // cross-XCD round trip per step, which measured at half the pass time.
 constexpr int kIPT = 16;
 constexpr int kTileKeys = kBlock * kIPT;
+constexpr int kSmallIPT = 8;
 constexpr int kChunk = 16;
 
 // Wave-level counting of one tile's keys: wave w owns keys [w * 64 * IPT, (w+1) * 64 * IPT) of the
@@ -726,7 +728,7 @@ __device__ inline void classify_tile(uint32_t tn, uint32_t wbase, const Model& m
 // One workgroup per chunk.  For every tile of the chunk: classify, count per bucket, write the
 // tile's exclusive prefix inside the chunk (tile_pref[t][b]); at the end the chunk's totals
 // (chunk_sum[c][b]).
-template <int DT>
+template <int DT, int IPT>
 __global__ __launch_bounds__(256) void k_classify_hist(const Item* items, const uint64_t* tile_off,
                                                        const uint64_t* chunk_off, const uint32_t* chunk_map,
                                                        uint64_t total_chunks, const Model* models,
@@ -734,6 +736,7 @@ __global__ __launch_bounds__(256) void k_classify_hist(const Item* items, const 
                                                        uint32_t* tile_pref, uint32_t* chunk_sum, uint32_t K,
                                                        uint32_t M) {
     using T = typename Key<DT>::T;
+    constexpr int TILE = kBlock * IPT;
     __shared__ uint32_t h[4][kMaxBuckets];
     __shared__ double s_leaf[4 * kMaxLeaves];
     const uint32_t tid = threadIdx.x, wave = tid / kWave;
@@ -744,15 +747,15 @@ __global__ __launch_bounds__(256) void k_classify_hist(const Item* items, const 
     const uint64_t t0 = tile_off[i];
     const uint64_t t_first = t0 + (c - chunk_off[i]) * kChunk;
     const uint64_t t_end = (t_first + kChunk < tile_off[i + 1]) ? t_first + kChunk : tile_off[i + 1];
-    const uint32_t wbase = wave * kWave * kIPT;
+    const uint32_t wbase = wave * kWave * IPT;
     auto tile_n = [&](uint64_t t) -> uint32_t {
-        const uint64_t rem = it.n - (t - t0) * kTileKeys;
-        return rem < (uint64_t)kTileKeys ? (uint32_t)rem : (uint32_t)kTileKeys;
+        const uint64_t rem = it.n - (t - t0) * TILE;
+        return rem < (uint64_t)TILE ? (uint32_t)rem : (uint32_t)TILE;
     };
     const bool counting = m.kind != kKindClosedKeep && m.kind != kKindClosedMove;
-    T cur[kIPT], nxt[kIPT];
+    T cur[IPT], nxt[IPT];
     uint32_t nop[1];
-    if (counting) load_tile<DT, false, kIPT>(src, nullptr, it.lo + (t_first - t0) * kTileKeys, tile_n(t_first), wbase, cur, nop);
+    if (counting) load_tile<DT, false, IPT>(src, nullptr, it.lo + (t_first - t0) * TILE, tile_n(t_first), wbase, cur, nop);
     if (m.kind == kKindL2pl)
         for (uint32_t q = tid; q < 4 * M; q += kBlock) s_leaf[q] = leaves[(uint64_t)i * 4 * kMaxLeaves + q];
     for (uint32_t b = tid; b < 4 * kMaxBuckets; b += kBlock) (&h[0][0])[b] = 0;
@@ -762,10 +765,10 @@ __global__ __launch_bounds__(256) void k_classify_hist(const Item* items, const 
         const uint32_t tn = tile_n(t);
         // prefetch the next tile while this one is counted
         if (counting && t + 1 < t_end)
-            load_tile<DT, false, kIPT>(src, nullptr, it.lo + (t + 1 - t0) * kTileKeys, tile_n(t + 1), wbase, nxt, nop);
+            load_tile<DT, false, IPT>(src, nullptr, it.lo + (t + 1 - t0) * TILE, tile_n(t + 1), wbase, nxt, nop);
         if (counting) {
 #pragma unroll
-            for (int r = 0; r < kIPT; ++r)
+            for (int r = 0; r < IPT; ++r)
                 if (wbase + r * kWave + lane_id() < tn)
                     atomicAdd(&h[wave][classify_key<DT>(m, s_leaf, K, M, cur[r])], 1u);
         } else if (m.kind == kKindClosedMove && tid == 0) {
@@ -779,7 +782,7 @@ __global__ __launch_bounds__(256) void k_classify_hist(const Item* items, const 
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < kIPT; ++r) cur[r] = nxt[r];
+        for (int r = 0; r < IPT; ++r) cur[r] = nxt[r];
     }
     if (tid < K) chunk_sum[c * K + tid] = run;
 }
@@ -859,7 +862,7 @@ __device__ inline uint64_t xcd_tile(uint64_t g, uint64_t nt) {
     return x * q + (x < r ? x : r) + g / 8;
 }
 
-template <int DT, bool PAY>
+template <int DT, bool PAY, int IPT>
 __global__ __launch_bounds__(256) void k_scatter(const Item* items, const uint64_t* tile_off, const uint32_t* tile_map,
                                                  uint64_t total_tiles, const uint64_t* chunk_off,
                                                  uint64_t total_chunks, const Model* models, const double* leaves,
@@ -868,7 +871,7 @@ __global__ __launch_bounds__(256) void k_scatter(const Item* items, const uint64
                                                  const uint32_t* src_pay, typename Key<DT>::T* dst, uint32_t* dst_pay,
                                                  uint32_t K, uint32_t M) {
     using T = typename Key<DT>::T;
-    constexpr int IPT = kIPT, TILE = kTileKeys;
+    constexpr int TILE = kBlock * IPT;
     __shared__ uint32_t s_wcnt[4][kMaxBuckets];
     __shared__ uint32_t s_loc[kMaxBuckets];
     __shared__ uint64_t s_base[kMaxBuckets];

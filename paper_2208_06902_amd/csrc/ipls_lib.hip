@@ -9,12 +9,14 @@
 // chapter notes that an ML-enhanced sort can sort its own sample), or straight by the base case
 // when every sample has at most T keys.
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <unordered_map>
 #include <vector>
 
 #include "../../include/ipls.h"
+#include "ipls_engine.h"
 #include "ipls_kernels.h"
 
 namespace ipls {
@@ -24,6 +26,10 @@ constexpr uint32_t kSmallS = kFitLds;  // samples up to this size are fitted in 
 constexpr uint32_t kFitChunk = 2048;   // windows per workgroup in the multi-round fit
 constexpr uint32_t kCand = 15;         // candidate widths per fit round
 constexpr uint32_t kTile = kTileKeys;
+constexpr uint32_t kSmallTile = kBlock * kSmallIPT;
+
+// Keys per distribution tile: 4096 (the default) or 2048.
+inline uint32_t tile_keys_of(const ipls_params& p) { return p.tile_keys == kSmallTile ? kSmallTile : kTile; }
 constexpr int kMaxLevels = 4096;
 constexpr int kMaxDepth = 16;
 
@@ -58,12 +64,36 @@ struct Depth {
     Plan* plan_h = nullptr;
 };
 
+// One engine context: the cached buffers of every nesting depth.  Calls on one context are
+// serialised by its mutex; separate contexts (the server's lanes) run concurrently.
 struct Device {
     Depth depth[kMaxDepth];
+    std::mutex mu;
+    uint64_t* seg_h = nullptr;  // pinned staging of a single segment's offsets
 };
 
+void release(Buf& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+void release_device(Device& dv) {
+    for (Depth& D : dv.depth) {
+        for (Buf* b : {&D.scratch, &D.spay, &D.items[0], &D.items[1], &D.base, &D.sample_base, &D.counters, &D.plan,
+                       &D.tile_off, &D.sample_off, &D.fit_off, &D.chunk_off, &D.tile_map, &D.fit_map, &D.chunk_map,
+                       &D.models, &D.masks, &D.hist, &D.bstart, &D.tile_pref, &D.chunk_sum, &D.chunk_pref, &D.sample,
+                       &D.leaves, &D.seg, &D.roots, &D.leaf_first, &D.leaf_last})
+            release(*b);
+        if (D.plan_h) (void)hipHostFree(D.plan_h);
+        D.plan_h = nullptr;
+    }
+    if (dv.seg_h) (void)hipHostFree(dv.seg_h);
+    dv.seg_h = nullptr;
+}
+
 struct Prof {
-    bool on = false;
+    std::atomic<bool> on{false};
     struct Rec {
         hipEvent_t a, b;
         int kernel;
@@ -75,14 +105,18 @@ struct Prof {
     double ms[3] = {0, 0, 0}, bytes[3] = {0, 0, 0};
 };
 
-std::mutex g_mu;
+std::mutex g_mu;         // the map of default contexts
+std::mutex g_prof_mu;    // profiling records
+std::mutex g_status_mu;  // last status per stream
 std::unordered_map<int, Device*> g_devices;
 std::unordered_map<void*, ipls_status> g_stream_status;
 Prof g_prof;
 
+// The default context of the current device (used by the plain entry points).
 Device& device_ctx() {
     int dev = 0;
     (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> g(g_mu);
     auto it = g_devices.find(dev);
     if (it != g_devices.end()) return *it->second;
     Device* d = new Device();
@@ -108,21 +142,37 @@ struct ProfScope {
     hipStream_t s;
     ProfScope(int k, double by, hipStream_t st) : kernel(k), bytes(by), s(st) {
         if (g_prof.on) {
-            a = prof_event();
+            {
+                std::lock_guard<std::mutex> g(g_prof_mu);
+                a = prof_event();
+            }
             (void)hipEventRecord(a, s);
         }
     }
     ~ProfScope() {
         if (a) {
-            hipEvent_t b = prof_event();
+            hipEvent_t b;
+            {
+                std::lock_guard<std::mutex> g(g_prof_mu);
+                b = prof_event();
+            }
             (void)hipEventRecord(b, s);
+            std::lock_guard<std::mutex> g(g_prof_mu);
             g_prof.pending.push_back({a, b, kernel, bytes});
         }
     }
 };
 
+// Accumulates the finished records (the caller has synchronised the streams they were on).
 void prof_collect() {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    std::vector<Prof::Rec> keep;
     for (auto& r : g_prof.pending) {
+        if (hipEventQuery(r.b) != hipSuccess) {  // still running on another context's stream
+            (void)hipGetLastError();
+            keep.push_back(r);
+            continue;
+        }
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
             g_prof.launches[r.kernel] += 1;
@@ -132,7 +182,7 @@ void prof_collect() {
         g_prof.pool.push_back(r.a);
         g_prof.pool.push_back(r.b);
     }
-    g_prof.pending.clear();
+    g_prof.pending.swap(keep);
 }
 
 #define HIP_TRY(x)                               \
@@ -344,7 +394,8 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     A.smax = P.sample_max;
     A.policy = P.sample_policy;
     A.seed = P.seed;
-    A.tile_keys = kTile;
+    const uint32_t tile = tile_keys_of(P);
+    A.tile_keys = tile;
     A.small_S = kSmallS;
     A.fit_chunk = kFitChunk;
     A.cand = kCand;
@@ -423,7 +474,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
 
         // degenerate buckets and final model
         k_minmax<DT><<<(unsigned)nt, 256, 0, s>>>(items, (const uint64_t*)D.tile_off.p, (const uint32_t*)D.tile_map.p,
-                                                  models, src, kTile);
+                                                  models, src, tile);
         LAUNCH_CHECK();
         k_finalize<<<(unsigned)((ni + 255) / 256), 256, 0, s>>>(items, models, (const Model*)D.roots.p, ni, K,
                                                                 src_scratch ? 1 : 0, P.model,
@@ -436,7 +487,8 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         LAUNCH_CHECK();
         {
             ProfScope ps(1, (double)pl.sum_n * kb, s);
-            k_classify_hist<DT><<<(unsigned)nc, 256, 0, s>>>(
+            auto kc = tile == kTile ? k_classify_hist<DT, kIPT> : k_classify_hist<DT, kSmallIPT>;
+            kc<<<(unsigned)nc, 256, 0, s>>>(
                 items, (const uint64_t*)D.tile_off.p, (const uint64_t*)D.chunk_off.p, (const uint32_t*)D.chunk_map.p,
                 nc, models, (const double*)D.leaves.p, src, (uint32_t*)D.tile_pref.p, (uint32_t*)D.chunk_sum.p, K,
                 P.leaves);
@@ -446,7 +498,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                                                                        (const uint32_t*)D.chunk_sum.p,
                                                                        (uint64_t*)D.chunk_pref.p, (uint64_t*)D.hist.p);
         LAUNCH_CHECK();
-        if ((pl.max_n + (uint64_t)kTileKeys * kChunk - 1) / ((uint64_t)kTileKeys * kChunk) > kScanSerial) {
+        if ((pl.max_n + (uint64_t)tile * kChunk - 1) / ((uint64_t)tile * kChunk) > kScanSerial) {
             k_scan_chunks_wide<<<(unsigned)((ni * K + 3) / 4), 256, 0, s>>>((const uint64_t*)D.chunk_off.p, ni, K,
                                                                             (const uint32_t*)D.chunk_sum.p,
                                                                             (uint64_t*)D.chunk_pref.p,
@@ -459,7 +511,8 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         // scatter
         {
             ProfScope ps(0, (double)pl.sum_n * 2.0 * (kb + (PAY ? 4 : 0)), s);
-            k_scatter<DT, PAY><<<(unsigned)nt, 256, 0, s>>>(
+            auto ks = tile == kTile ? k_scatter<DT, PAY, kIPT> : k_scatter<DT, PAY, kSmallIPT>;
+            ks<<<(unsigned)nt, 256, 0, s>>>(
                 items, (const uint64_t*)D.tile_off.p, (const uint32_t*)D.tile_map.p, nt, (const uint64_t*)D.chunk_off.p,
                 nc, models, (const double*)D.leaves.p, (const uint64_t*)D.bstart.p, (const uint64_t*)D.chunk_pref.p,
                 (const uint32_t*)D.tile_pref.p, src, psrc, dst, pdst, K, P.leaves);
@@ -560,6 +613,7 @@ ipls_status l2pl_entry(Device& dv, hipStream_t s, const double* x, uint64_t S, u
 ipls_status check_params(const ipls_params& p) {
     if (p.num_buckets < 4 || p.base_case_max < 1 || p.sample_divisor < 2) return IPLS_ERR_INVALID;
     if (p.sample_policy > 1) return IPLS_ERR_INVALID;
+    if (p.tile_keys != 0 && p.tile_keys != kTile && p.tile_keys != kSmallTile) return IPLS_ERR_INVALID;
     const uint64_t smin = p.sample_min ? p.sample_min : (p.sample_policy == 1 ? 0 : 2ull * p.num_buckets);
     if (smin > p.base_case_max) return IPLS_ERR_INVALID;
     if (p.model > 2) return IPLS_ERR_INVALID;
@@ -594,11 +648,116 @@ ipls_status finish(ipls_status st, hipStream_t s) {
         st = IPLS_ERR_HIP;
     }
     if (g_prof.on) prof_collect();
+    std::lock_guard<std::mutex> g(g_status_mu);
     g_stream_status[(void*)s] = st;
     return st;
 }
 
 }  // namespace
+}  // namespace ipls
+
+extern "C" size_t ipls_workspace_bytes(size_t n, ipls_dtype dtype, int has_payload, const ipls_params* p);
+
+namespace ipls {
+
+ipls_status sort_single(Device& dv, void* keys, uint32_t* payload, size_t n, ipls_dtype dtype, const ipls_params* p,
+                        void* workspace, size_t workspace_bytes, ipls_stats* stats, hipStream_t s) {
+    if (dtype != IPLS_F64 && dtype != IPLS_F32 && dtype != IPLS_U64) return IPLS_ERR_DTYPE;
+    if (n > 0 && !keys) return IPLS_ERR_INVALID;
+    ipls_params prm;
+    if (p) prm = *p;
+    else ipls_default_params(&prm);
+    ipls_status st = check_params(prm);
+    if (st != IPLS_OK) return st;
+    if (((uintptr_t)keys % key_bytes(dtype)) != 0 || ((uintptr_t)payload % 4) != 0) return IPLS_ERR_INVALID;
+    if (workspace && (workspace_bytes < ipls_workspace_bytes(n, dtype, payload != nullptr, &prm) ||
+                      ((uintptr_t)workspace & 255)))
+        return IPLS_ERR_INVALID;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (n < 2) return IPLS_OK;
+    std::lock_guard<std::mutex> g(dv.mu);
+    Run run;
+    run.p = prm;
+    run.s = s;
+    run.dtype = dtype;
+    std::memset(&run.st, 0, sizeof(run.st));
+    Depth& D0 = dv.depth[0];
+    st = ensure(D0.seg, 2 * sizeof(uint64_t));
+    if (st != IPLS_OK) return st;
+    // single segment [0, n): offsets staged through the context's pinned host buffer
+    if (!dv.seg_h && hipHostMalloc((void**)&dv.seg_h, 2 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
+        return IPLS_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return IPLS_ERR_HIP;
+    dv.seg_h[0] = 0;
+    dv.seg_h[1] = n;
+    if (hipMemcpyAsync(D0.seg.p, dv.seg_h, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, s) != hipSuccess)
+        return IPLS_ERR_HIP;
+    st = dispatch(dv, run, keys, payload, n, (const uint64_t*)D0.seg.p, 1, workspace);
+    st = finish(st, s);
+    if (stats) *stats = run.st;
+    return st;
+}
+
+ipls_status sort_multi(Device& dv, void* keys, uint32_t* payload, const uint64_t* seg_offsets, size_t nseg,
+                                  ipls_dtype dtype, const ipls_params* p, void* workspace, size_t workspace_bytes,
+                                  ipls_stats* stats, hipStream_t s) {
+    if (dtype != IPLS_F64 && dtype != IPLS_F32 && dtype != IPLS_U64) return IPLS_ERR_DTYPE;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (nseg == 0) return IPLS_OK;
+    if (!seg_offsets || !keys) return IPLS_ERR_INVALID;
+    ipls_params prm;
+    if (p) prm = *p;
+    else ipls_default_params(&prm);
+    ipls_status st = check_params(prm);
+    if (st != IPLS_OK) return st;
+    if (((uintptr_t)keys % key_bytes(dtype)) != 0 || ((uintptr_t)payload % 4) != 0) return IPLS_ERR_INVALID;
+    std::lock_guard<std::mutex> g(dv.mu);
+    uint64_t len = 0;
+    if (hipMemcpyAsync(&len, seg_offsets + nseg, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return IPLS_ERR_HIP;
+    if (len < 2) return IPLS_OK;
+    if (workspace && (workspace_bytes < ipls_workspace_bytes(len, dtype, payload != nullptr, &prm) ||
+                      ((uintptr_t)workspace & 255)))
+        return IPLS_ERR_INVALID;
+    Run run;
+    run.p = prm;
+    run.s = s;
+    run.dtype = dtype;
+    std::memset(&run.st, 0, sizeof(run.st));
+    st = dispatch(dv, run, keys, payload, len, seg_offsets, nseg, workspace);
+    st = finish(st, s);
+    if (stats) *stats = run.st;
+    return st;
+}
+
+struct Engine {
+    Device dev;
+};
+
+Engine* engine_new() { return new Engine(); }
+
+void engine_free(Engine* e) {
+    if (!e) return;
+    {
+        std::lock_guard<std::mutex> g(e->dev.mu);
+        (void)hipDeviceSynchronize();
+        release_device(e->dev);
+    }
+    delete e;
+}
+
+ipls_status engine_sort(Engine& e, void* keys, uint32_t* payload, size_t n, ipls_dtype dtype, const ipls_params* p,
+                        void* workspace, size_t workspace_bytes, ipls_stats* stats, hipStream_t s) {
+    return sort_single(e.dev, keys, payload, n, dtype, p, workspace, workspace_bytes, stats, s);
+}
+
+ipls_status engine_sort_segmented(Engine& e, void* keys, uint32_t* payload, const uint64_t* seg_offsets, size_t nseg,
+                                  ipls_dtype dtype, const ipls_params* p, void* workspace, size_t workspace_bytes,
+                                  ipls_stats* stats, hipStream_t s) {
+    return sort_multi(e.dev, keys, payload, seg_offsets, nseg, dtype, p, workspace, workspace_bytes, stats, s);
+}
+
 }  // namespace ipls
 
 using namespace ipls;
@@ -644,50 +803,15 @@ size_t ipls_workspace_bytes(size_t n, ipls_dtype dtype, int has_payload, const i
 }
 
 ipls_status ipls_stream_status(void* stream) {
-    std::lock_guard<std::mutex> g(g_mu);
+    std::lock_guard<std::mutex> g(g_status_mu);
     auto it = g_stream_status.find(stream);
     return it == g_stream_status.end() ? IPLS_OK : it->second;
 }
 
 ipls_status ipls_sort_ex(void* keys, uint32_t* payload, size_t n, ipls_dtype dtype, const ipls_params* p,
                          void* workspace, size_t workspace_bytes, ipls_stats* stats, void* stream) {
-    if (dtype != IPLS_F64 && dtype != IPLS_F32 && dtype != IPLS_U64) return IPLS_ERR_DTYPE;
-    if (n > 0 && !keys) return IPLS_ERR_INVALID;
-    ipls_params prm;
-    if (p) prm = *p;
-    else ipls_default_params(&prm);
-    ipls_status st = check_params(prm);
-    if (st != IPLS_OK) return st;
-    if (((uintptr_t)keys % key_bytes(dtype)) != 0 || ((uintptr_t)payload % 4) != 0) return IPLS_ERR_INVALID;
-    if (workspace && (workspace_bytes < ipls_workspace_bytes(n, dtype, payload != nullptr, &prm) ||
-                      ((uintptr_t)workspace & 255)))
-        return IPLS_ERR_INVALID;
-    if (stats) std::memset(stats, 0, sizeof(*stats));
-    if (n < 2) return IPLS_OK;
-    std::lock_guard<std::mutex> g(g_mu);
-    hipStream_t s = (hipStream_t)stream;
-    Device& dv = device_ctx();
-    Run run;
-    run.p = prm;
-    run.s = s;
-    run.dtype = dtype;
-    std::memset(&run.st, 0, sizeof(run.st));
-    Depth& D0 = dv.depth[0];
-    st = ensure(D0.seg, 2 * sizeof(uint64_t));
-    if (st != IPLS_OK) return st;
-    // single segment [0, n): offsets staged through a pinned host buffer
-    static uint64_t* seg_h = nullptr;
-    if (!seg_h && hipHostMalloc((void**)&seg_h, 2 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
-        return IPLS_ERR_HIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return IPLS_ERR_HIP;
-    seg_h[0] = 0;
-    seg_h[1] = n;
-    if (hipMemcpyAsync(D0.seg.p, seg_h, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, s) != hipSuccess)
-        return IPLS_ERR_HIP;
-    st = dispatch(dv, run, keys, payload, n, (const uint64_t*)D0.seg.p, 1, workspace);
-    st = finish(st, s);
-    if (stats) *stats = run.st;
-    return st;
+    return sort_single(device_ctx(), keys, payload, n, dtype, p, workspace, workspace_bytes, stats,
+                       (hipStream_t)stream);
 }
 
 ipls_status ipls_sort(void* keys, uint32_t* payload, size_t n, ipls_dtype dtype, void* stream) {
@@ -696,32 +820,8 @@ ipls_status ipls_sort(void* keys, uint32_t* payload, size_t n, ipls_dtype dtype,
 
 ipls_status ipls_sort_segmented(void* keys, uint32_t* payload, const uint64_t* seg_offsets, size_t nseg,
                                 ipls_dtype dtype, const ipls_params* p, ipls_stats* stats, void* stream) {
-    if (dtype != IPLS_F64 && dtype != IPLS_F32 && dtype != IPLS_U64) return IPLS_ERR_DTYPE;
-    if (nseg == 0) return IPLS_OK;
-    if (!seg_offsets || !keys) return IPLS_ERR_INVALID;
-    ipls_params prm;
-    if (p) prm = *p;
-    else ipls_default_params(&prm);
-    ipls_status st = check_params(prm);
-    if (st != IPLS_OK) return st;
-    if (stats) std::memset(stats, 0, sizeof(*stats));
-    std::lock_guard<std::mutex> g(g_mu);
-    hipStream_t s = (hipStream_t)stream;
-    uint64_t len = 0;
-    if (hipMemcpyAsync(&len, seg_offsets + nseg, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return IPLS_ERR_HIP;
-    if (len < 2) return IPLS_OK;
-    Device& dv = device_ctx();
-    Run run;
-    run.p = prm;
-    run.s = s;
-    run.dtype = dtype;
-    std::memset(&run.st, 0, sizeof(run.st));
-    st = dispatch(dv, run, keys, payload, len, seg_offsets, nseg, nullptr);
-    st = finish(st, s);
-    if (stats) *stats = run.st;
-    return st;
+    return sort_multi(device_ctx(), keys, payload, seg_offsets, nseg, dtype, p, nullptr, 0, stats,
+                      (hipStream_t)stream);
 }
 
 ipls_status ipls_fit_model(const void* sample, size_t S, ipls_dtype dtype, int sample_is_sorted, uint32_t K,
@@ -729,9 +829,9 @@ ipls_status ipls_fit_model(const void* sample, size_t S, ipls_dtype dtype, int s
     if (dtype != IPLS_F64 && dtype != IPLS_F32 && dtype != IPLS_U64) return IPLS_ERR_DTYPE;
     if (!out || (S > 0 && !sample) || K < 4) return IPLS_ERR_INVALID;
     if (S > 0xffffffffull) return IPLS_ERR_UNSUPPORTED;
-    std::lock_guard<std::mutex> g(g_mu);
     hipStream_t s = (hipStream_t)stream;
     Device& dv = device_ctx();
+    std::lock_guard<std::mutex> g(dv.mu);
     Run run;
     ipls_default_params(&run.p);
     run.s = s;
@@ -755,9 +855,9 @@ ipls_status ipls_partition(void* keys, uint32_t* payload, size_t n, ipls_dtype d
     ipls_status st = check_params(prm);
     if (st != IPLS_OK) return st;
     if (!keys || !counts || n <= prm.base_case_max) return IPLS_ERR_INVALID;
-    std::lock_guard<std::mutex> g(g_mu);
     hipStream_t s = (hipStream_t)stream;
     Device& dv = device_ctx();
+    std::lock_guard<std::mutex> g(dv.mu);
     Run run;
     run.p = prm;
     run.s = s;
@@ -770,12 +870,11 @@ ipls_status ipls_partition(void* keys, uint32_t* payload, size_t n, ipls_dtype d
     if (st != IPLS_OK) return st;
     run.part_model = model ? model : (ipls_linear_model*)((uint64_t*)D0.seg.p + 2);
     HIP_TRY(hipStreamSynchronize(s));
-    static uint64_t* seg_h = nullptr;
-    if (!seg_h && hipHostMalloc((void**)&seg_h, 2 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
+    if (!dv.seg_h && hipHostMalloc((void**)&dv.seg_h, 2 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
         return IPLS_ERR_HIP;
-    seg_h[0] = 0;
-    seg_h[1] = n;
-    HIP_TRY(hipMemcpyAsync(D0.seg.p, seg_h, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    dv.seg_h[0] = 0;
+    dv.seg_h[1] = n;
+    HIP_TRY(hipMemcpyAsync(D0.seg.p, dv.seg_h, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(counts, 0, prm.num_buckets * 8, s));
     st = dispatch(dv, run, keys, payload, n, (const uint64_t*)D0.seg.p, 1, nullptr);
     return finish(st, s);
@@ -785,9 +884,10 @@ ipls_status ipls_l2pl_train(const double* x, size_t S, uint32_t K, uint32_t M, u
                             double* leaf, double* ab, void* stream) {
     if (!x || !root || !leaf || S < 3 || K < 4 || M < 4) return IPLS_ERR_INVALID;
     if (K > (uint32_t)kMaxBuckets || M > (uint32_t)kMaxLeaves || S > 0xffffffffull) return IPLS_ERR_UNSUPPORTED;
-    std::lock_guard<std::mutex> g(g_mu);
     hipStream_t s = (hipStream_t)stream;
-    ipls_status st = l2pl_entry(device_ctx(), s, x, S, K, M, iters, root, leaf, ab, nullptr, nullptr, nullptr);
+    Device& dv = device_ctx();
+    std::lock_guard<std::mutex> g(dv.mu);
+    ipls_status st = l2pl_entry(dv, s, x, S, K, M, iters, root, leaf, ab, nullptr, nullptr, nullptr);
     return finish(st, s);
 }
 
@@ -795,14 +895,15 @@ ipls_status ipls_l2pl_grad(const double* x, size_t S, uint32_t K, uint32_t M, co
                            double* loss, void* stream) {
     if (!x || !ab || !grad || S < 3 || K < 4 || M < 4) return IPLS_ERR_INVALID;
     if (K > (uint32_t)kMaxBuckets || M > (uint32_t)kMaxLeaves || S > 0xffffffffull) return IPLS_ERR_UNSUPPORTED;
-    std::lock_guard<std::mutex> g(g_mu);
     hipStream_t s = (hipStream_t)stream;
-    ipls_status st = l2pl_entry(device_ctx(), s, x, S, K, M, 0, nullptr, nullptr, nullptr, ab, grad, loss);
+    Device& dv = device_ctx();
+    std::lock_guard<std::mutex> g(dv.mu);
+    ipls_status st = l2pl_entry(dv, s, x, S, K, M, 0, nullptr, nullptr, nullptr, ab, grad, loss);
     return finish(st, s);
 }
 
 void ipls_profile_enable(int on) {
-    std::lock_guard<std::mutex> g(g_mu);
+    std::lock_guard<std::mutex> g(g_prof_mu);
     g_prof.on = on != 0;
     for (int k = 0; k < 3; ++k) {
         g_prof.launches[k] = 0;
@@ -812,7 +913,7 @@ void ipls_profile_enable(int on) {
 }
 
 void ipls_profile_read(int kernel, uint64_t* launches, double* ms, double* bytes) {
-    std::lock_guard<std::mutex> g(g_mu);
+    std::lock_guard<std::mutex> g(g_prof_mu);
     if (kernel < 0 || kernel > 2) return;
     if (launches) *launches = g_prof.launches[kernel];
     if (ms) *ms = g_prof.ms[kernel];
