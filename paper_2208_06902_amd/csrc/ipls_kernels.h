@@ -1147,13 +1147,62 @@ __global__ __launch_bounds__(256) void k_base_sort(const BaseItem* list, uint64_
     }
 }
 
-// Base case for buckets of 1025 .. 1024 NW keys (NW waves, one bucket per workgroup).  The bucket's
-// smallest ord (min) and the number of low bits z that are zero in every ord - min are found
-// first; x = (ord - min) >> z then has only the bits where the bucket's keys differ.  When x needs
-// at most kRadixPasses 8-bit digits (few distinct values or a narrow range) the bucket is sorted
-// by LSD radix passes: each a stable counting sort in LDS that ranks keys with the same ballot
-// counting as the scatter.  Otherwise it goes to the merge sort.  Both are stable.
-constexpr int kRadixPasses = 3;
+// Stable counting of one digit (0..255) per key over a workgroup of NW waves, with the same
+// ballot ranking as the scatter.  Afterwards the key of wave w with digit b and rank rk among the
+// wave's earlier keys of b belongs at s_loc[b] + s_wcnt[w][b] + rk; s_cnt[b] is digit b's count.
+// Returns the largest count.
+template <int NW, int IPT>
+__device__ inline uint32_t block_count_digits(const uint32_t (&bk)[IPT], uint32_t n, uint32_t wbase,
+                                              uint32_t (*s_wcnt)[kMaxBuckets], uint32_t* s_loc, uint32_t* s_cnt,
+                                              uint64_t* s_scan, uint32_t* s_max, uint32_t (&rk)[IPT]) {
+    constexpr int NT = kWave * NW, DPT = kMaxBuckets / NT;  // digits per thread
+    const uint32_t tid = threadIdx.x, wave = tid / kWave;
+    for (uint32_t b = tid; b < NW * kMaxBuckets; b += NT) (&s_wcnt[0][0])[b] = 0;
+    __syncthreads();
+    wave_count<IPT, true>(bk, n, wbase, s_wcnt[wave], rk);
+    __syncthreads();
+    uint32_t tot[DPT], sum = 0, mx = 0;
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+        const uint32_t dg = tid * DPT + i;
+        uint32_t run = 0;
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t c = s_wcnt[w][dg];
+            s_wcnt[w][dg] = run;
+            run += c;
+        }
+        tot[i] = run;
+        sum += run;
+        mx = run > mx ? run : mx;
+    }
+    mx = wave_max(mx);
+    if (lane_id() == 0) s_max[wave] = mx;
+    uint64_t all;
+    uint32_t e = (uint32_t)block_exclusive_sum<uint64_t>(sum, s_scan, &all);  // synchronises
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+        const uint32_t dg = tid * DPT + i;
+        s_loc[dg] = e;
+        s_cnt[dg] = tot[i];
+        e += tot[i];
+    }
+    mx = 0;
+    for (int w = 0; w < NW; ++w) mx = s_max[w] > mx ? s_max[w] : mx;
+    __syncthreads();
+    return mx;
+}
+
+// Base case for one bucket of at most 1024 NW keys per workgroup of NW waves (16 keys a thread).
+// The bucket's smallest ord (min) and the low bits z that are zero in every ord - min are found
+// first; x = (ord - min) >> z keeps only the bits where the keys differ, nbits of them.
+//  * nbits <= 8: one stable counting pass on x sorts the bucket.
+//  * otherwise a stable counting pass on the top 8 bits of x splits it into 256 ordered
+//    sub-buckets (an MSD radix step, as SkaSort starts); each key's final place is its
+//    sub-bucket's start plus the number of keys of its sub-bucket that precede it in (ord,
+//    position) order.  A sub-bucket of more than kSubMax keys (skewed buckets) sends the whole
+//    bucket to the merge sort instead.
+// All paths are stable.
+constexpr uint32_t kSubMax = 64;
 
 template <int DT, bool PAY, int NW>
 __global__ __launch_bounds__(64 * NW) void k_base_large(const BaseItem* list, uint64_t count,
@@ -1166,8 +1215,9 @@ __global__ __launch_bounds__(64 * NW) void k_base_large(const BaseItem* list, ui
     __shared__ O s_k[PCAP];
     __shared__ uint32_t s_p[PAY ? PCAP : 1];
     __shared__ uint32_t s_wcnt[NW][kMaxBuckets];
-    __shared__ uint32_t s_loc[kMaxBuckets];
+    __shared__ uint32_t s_loc[kMaxBuckets], s_cnt[kMaxBuckets];
     __shared__ uint64_t s_scan[16];
+    __shared__ uint32_t s_max[NW];
     __shared__ O s_red[2][NW];
     const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
     if (blockIdx.x >= count) return;
@@ -1212,10 +1262,15 @@ __global__ __launch_bounds__(64 * NW) void k_base_large(const BaseItem* list, ui
     for (int w = 0; w < NW; ++w) orv |= s_red[1][w];
     const int z = orv ? __builtin_ctzll((unsigned long long)orv) : 0;
     const int nbits = orv ? (int)bit_length((uint64_t)(orv >> z)) : 0;
-    const int passes = (nbits + 7) / 8;
 
-    if (passes > kRadixPasses) {
-        // merge sort: keys to LDS at their positions (padding keys at the end), then sort
+    uint32_t bk[IPT], rk[IPT];
+    const int shift = nbits <= 8 ? z : z + nbits - 8;  // the low digit, or the top 8 varying bits
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) bk[r] = (uint32_t)(((uint64_t)(o[r] - mn) >> shift) & 255u);
+    const uint32_t most = block_count_digits<NW, IPT>(bk, n, wbase, s_wcnt, s_loc, s_cnt, s_scan, s_max, rk);
+
+    if (nbits > 8 && most > kSubMax) {
+        // merge sort: keys to LDS at their input positions (padding keys at the end), then sort
 #pragma unroll
         for (int r = 0; r < IPT; ++r) {
             const uint32_t j = wbase + r * kWave + lane;
@@ -1235,73 +1290,48 @@ __global__ __launch_bounds__(64 * NW) void k_base_large(const BaseItem* list, ui
         return;
     }
 
-    for (int d = 0; d < passes; ++d) {
-        const int shift = z + 8 * d;
-        uint32_t bk[IPT], rk[IPT];
+    // keys in digit order (stable)
+    uint32_t pos[IPT];
 #pragma unroll
-        for (int r = 0; r < IPT; ++r) bk[r] = (uint32_t)(((uint64_t)(o[r] - mn) >> shift) & 255u);
-        for (uint32_t b = tid; b < NW * kMaxBuckets; b += NT) (&s_wcnt[0][0])[b] = 0;
-        __syncthreads();
-        wave_count<IPT, true>(bk, n, wbase, s_wcnt[wave], rk);
-        __syncthreads();
-        // digit offsets: exclusive over waves, then over digits
-        uint32_t tot_lo = 0, tot_hi = 0;
-        {
-            const uint32_t dg = tid;  // digits tid and tid + NT (NT >= 128)
-            uint32_t run = 0;
-            for (int w = 0; w < NW; ++w) {
-                const uint32_t cw = s_wcnt[w][dg];
-                s_wcnt[w][dg] = run;
-                run += cw;
-            }
-            tot_lo = run;
-            if (NT < kMaxBuckets) {
-                uint32_t run2 = 0;
-                for (int w = 0; w < NW; ++w) {
-                    const uint32_t cw = s_wcnt[w][dg + NT];
-                    s_wcnt[w][dg + NT] = run2;
-                    run2 += cw;
-                }
-                tot_hi = run2;
-            }
+    for (int r = 0; r < IPT; ++r) {
+        pos[r] = s_loc[bk[r]] + s_wcnt[wave][bk[r]] + rk[r];
+        if (wbase + r * kWave + lane < n) {
+            s_k[pos[r]] = o[r];
+            if (PAY) s_p[pos[r]] = p[r];
         }
-        uint64_t all;
-        if (NT >= kMaxBuckets) {
-            s_loc[tid] = (uint32_t)block_exclusive_sum<uint64_t>(tot_lo, s_scan, &all);
-        } else {
-            // two digits per thread: tid (low half) and tid + NT (high half)
-            const uint64_t e_lo = block_exclusive_sum<uint64_t>(tot_lo, s_scan, &all);
-            uint64_t all_hi;
-            const uint64_t e_hi = block_exclusive_sum<uint64_t>(tot_hi, s_scan, &all_hi);
-            s_loc[tid] = (uint32_t)e_lo;
-            s_loc[tid + NT] = (uint32_t)(all + e_hi);
+    }
+    __syncthreads();
+    if (nbits > 8) {
+        // final place inside the sub-bucket: keys of the sub-bucket before this one in (ord, position)
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            if (wbase + r * kWave + lane < n) {
+                const uint32_t start = s_loc[bk[r]], cnt = s_cnt[bk[r]];
+                uint32_t before = 0;
+                for (uint32_t q = 0; q < cnt; ++q) {
+                    const O x = s_k[start + q];
+                    before += (x < o[r] || (x == o[r] && start + q < pos[r])) ? 1u : 0u;
+                }
+                pos[r] = start + before;
+            }
         }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < IPT; ++r) {
             if (wbase + r * kWave + lane < n) {
-                const uint32_t pos = s_loc[bk[r]] + s_wcnt[wave][bk[r]] + rk[r];
-                s_k[pos] = o[r];
-                if (PAY) s_p[pos] = p[r];
+                s_k[pos[r]] = o[r];
+                if (PAY) s_p[pos[r]] = p[r];
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            const uint32_t j = wbase + r * kWave + lane;
-            if (j < n) {
-                o[r] = s_k[j];
-                if (PAY) p[r] = s_p[j];
-            }
-        }
     }
-    // keys are in sorted order at their positions: write out (coalesced)
+    // sorted keys at positions 0 .. n-1: write out (coalesced)
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
         const uint32_t j = wbase + r * kWave + lane;
         if (j < n) {
-            keys[bi.lo + j] = KT::from_ord((uint64_t)o[r]);
-            if (PAY) pay[bi.lo + j] = p[r];
+            keys[bi.lo + j] = KT::from_ord((uint64_t)s_k[j]);
+            if (PAY) pay[bi.lo + j] = s_p[j];
         }
     }
 }

@@ -285,7 +285,7 @@ template <int DT, bool PAY>
 ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys, uint32_t* pay, uint64_t len,
                           const uint64_t* seg_off, uint64_t nseg, void* ws_keys, bool top);
 
-// Base-case sort of `count` buckets of size class cls (<= 64 * 2^cls keys): 16 keys per thread,
+// Base-case sort of `count` buckets of size class cls (<= 64 * 2^cls keys).  Classes 0..3: merge sort, 16 keys per thread,
 // NT = 4 * 2^cls threads per bucket, 256 / NT buckets per workgroup.
 template <int DT, bool PAY, int NT>
 ipls_status launch_base_nt(hipStream_t s, const BaseItem* list, uint64_t count, typename Key<DT>::T* keys,
@@ -305,7 +305,10 @@ ipls_status launch_base(hipStream_t s, int cls, const BaseItem* list, uint64_t c
         case 1: return launch_base_nt<DT, PAY, 8>(s, list, count, keys, pay, sk, sp);
         case 2: return launch_base_nt<DT, PAY, 16>(s, list, count, keys, pay, sk, sp);
         case 3: return launch_base_nt<DT, PAY, 32>(s, list, count, keys, pay, sk, sp);
-        case 4: return launch_base_nt<DT, PAY, 64>(s, list, count, keys, pay, sk, sp);
+        case 4:
+            k_base_large<DT, PAY, 1><<<(unsigned)count, 64, 0, s>>>(list, count, keys, pay, sk, sp);
+            LAUNCH_CHECK();
+            return IPLS_OK;
         case 5:
             k_base_large<DT, PAY, 2><<<(unsigned)count, 128, 0, s>>>(list, count, keys, pay, sk, sp);
             LAUNCH_CHECK();
