@@ -1291,36 +1291,43 @@ __global__ __launch_bounds__(64 * NW) void k_base_large(const BaseItem* list, ui
     }
 
     // keys in digit order (stable)
-    uint32_t pos[IPT];
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
-        pos[r] = s_loc[bk[r]] + s_wcnt[wave][bk[r]] + rk[r];
         if (wbase + r * kWave + lane < n) {
-            s_k[pos[r]] = o[r];
-            if (PAY) s_p[pos[r]] = p[r];
+            const uint32_t pos = s_loc[bk[r]] + s_wcnt[wave][bk[r]] + rk[r];
+            s_k[pos] = o[r];
+            if (PAY) s_p[pos] = p[r];
         }
     }
     __syncthreads();
     if (nbits > 8) {
-        // final place inside the sub-bucket: keys of the sub-bucket before this one in (ord, position)
+        // final place inside the sub-bucket: the keys of the sub-bucket that precede this one in
+        // (ord, position) order.  Lane j takes position j of the digit order, so the lanes of a
+        // wave mostly share a sub-bucket and its LDS reads are broadcasts.
+        O xs[IPT];
+        uint32_t ps[IPT], np[IPT];
 #pragma unroll
         for (int r = 0; r < IPT; ++r) {
-            if (wbase + r * kWave + lane < n) {
-                const uint32_t start = s_loc[bk[r]], cnt = s_cnt[bk[r]];
+            const uint32_t j = wbase + r * kWave + lane;
+            if (j < n) {
+                xs[r] = s_k[j];
+                ps[r] = PAY ? s_p[j] : 0u;
+                const uint32_t d = (uint32_t)(((uint64_t)(xs[r] - mn) >> shift) & 255u);
+                const uint32_t start = s_loc[d], cnt = s_cnt[d];
                 uint32_t before = 0;
                 for (uint32_t q = 0; q < cnt; ++q) {
                     const O x = s_k[start + q];
-                    before += (x < o[r] || (x == o[r] && start + q < pos[r])) ? 1u : 0u;
+                    before += (x < xs[r] || (x == xs[r] && start + q < j)) ? 1u : 0u;
                 }
-                pos[r] = start + before;
+                np[r] = start + before;
             }
         }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < IPT; ++r) {
             if (wbase + r * kWave + lane < n) {
-                s_k[pos[r]] = o[r];
-                if (PAY) s_p[pos[r]] = p[r];
+                s_k[np[r]] = xs[r];
+                if (PAY) s_p[np[r]] = ps[r];
             }
         }
         __syncthreads();
