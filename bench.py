@@ -376,6 +376,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dists", default=",".join(DISTS))
     ap.add_argument("--sample-max", type=int, default=4096)
+    ap.add_argument("--tile-keys", type=int, default=0, help="keys per distribution tile (0 = library default)")
     ap.add_argument("--workload", choices=("sort", "batched", "served"), default="sort",
                     help="sort: the 1e8 fp64 single-array sort (default); batched; served")
     ap.add_argument("--arrays", type=int, default=100_000, help="batched: number of arrays")
@@ -415,7 +416,7 @@ def main():
     total = args.warmup + args.steps
     order = [dists[i % len(dists)] for i in range(total)]
 
-    params = ipls.default_params(sample_max=args.sample_max)
+    params = ipls.default_params(sample_max=args.sample_max, tile_keys=args.tile_keys)
     stream = torch.cuda.current_stream()
 
     # warmup: also checks parity of each distribution's output against numpy's sort

@@ -876,10 +876,14 @@ __global__ __launch_bounds__(256) void k_scatter(const Item* items, const uint64
     __shared__ uint32_t s_loc[kMaxBuckets];
     __shared__ uint64_t s_base[kMaxBuckets];
     __shared__ uint64_t s_scan[16];
-    __shared__ T s_keys[TILE];
+    // The two-level model's leaves are only read by the classification, which ends (two barriers)
+    // before the first staging write: they share memory with the staged keys.
+    constexpr int kStageBytes = TILE * (int)sizeof(T), kLeafBytes = 4 * kMaxLeaves * (int)sizeof(double);
+    __shared__ __align__(16) unsigned char s_stage[kStageBytes > kLeafBytes ? kStageBytes : kLeafBytes];
+    T* s_keys = (T*)s_stage;
+    const double* s_leaf = (const double*)s_stage;
     __shared__ uint8_t s_bkt[TILE];
     __shared__ uint32_t s_pay[PAY ? TILE : 1];
-    __shared__ double s_leaf[4 * kMaxLeaves];
 
     const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
     const uint64_t t = xcd_tile(blockIdx.x, total_tiles);
@@ -903,7 +907,8 @@ __global__ __launch_bounds__(256) void k_scatter(const Item* items, const uint64
         dbase = it.lo + bstart[(uint64_t)i * K + tid] + chunk_pref[c * K + tid] +
                 tile_pref[t * K + tid];
     if (m.kind == kKindL2pl)
-        for (uint32_t q = tid; q < 4 * M; q += kBlock) s_leaf[q] = leaves[(uint64_t)i * 4 * kMaxLeaves + q];
+        for (uint32_t q = tid; q < 4 * M; q += kBlock)
+            ((double*)s_stage)[q] = leaves[(uint64_t)i * 4 * kMaxLeaves + q];
     for (uint32_t b = tid; b < 4 * kMaxBuckets; b += kBlock) (&s_wcnt[0][0])[b] = 0;
     __syncthreads();
     classify_tile<DT, IPT>(tn, wbase, m, s_leaf, K, M, k, bk);
