@@ -1023,8 +1023,11 @@ __device__ inline void cex(O& ka, O& kb, uint32_t& ia, uint32_t& ib, uint32_t& p
 
 // Merge sort of CAP = 16 NT keys held in LDS (pad16 layout, positions 0 .. CAP-1, padding keys
 // are kPad at the end) by NT threads t = 0 .. NT-1 of one group; the sorted keys are left in LDS.
+// Threads of the workgroup that are not among the NT pass active = false: they only take part in
+// the barriers.
 template <typename O, bool PAY, int NT>
-__device__ inline void merge_sort_lds(O* sk, uint32_t* sp, int t) {
+__device__ inline void merge_sort_lds(O* sk, uint32_t* sp, int t_in, bool active = true) {
+    const int t = active ? t_in : 0;  // inactive threads read in bounds and write nothing
     constexpr int IPT = 16, CAP = NT * IPT;
     constexpr O kPad = (O)~(O)0;
     O k[IPT];
@@ -1049,10 +1052,12 @@ __device__ inline void merge_sort_lds(O* sk, uint32_t* sp, int t) {
 #pragma unroll 1
     for (int L = IPT; L < CAP; L <<= 1) {
         __syncthreads();
+        if (active) {
 #pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-            sk[pad16(t * IPT + i)] = k[i];
-            if (PAY) sp[pad16(t * IPT + i)] = p[i];
+            for (int i = 0; i < IPT; ++i) {
+                sk[pad16(t * IPT + i)] = k[i];
+                if (PAY) sp[pad16(t * IPT + i)] = p[i];
+            }
         }
         __syncthreads();
         const int q = (t * IPT) / (2 * L), d = t * IPT - q * 2 * L;
@@ -1095,10 +1100,12 @@ __device__ inline void merge_sort_lds(O* sk, uint32_t* sp, int t) {
             }
     }
     __syncthreads();
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-        sk[pad16(t * IPT + i)] = k[i];
-        if (PAY) sp[pad16(t * IPT + i)] = p[i];
+        for (int i = 0; i < IPT; ++i) {
+            sk[pad16(t * IPT + i)] = k[i];
+            if (PAY) sp[pad16(t * IPT + i)] = p[i];
+        }
     }
     __syncthreads();
 }
@@ -1160,7 +1167,7 @@ template <int NW, int IPT>
 __device__ inline uint32_t block_count_digits(const uint32_t (&bk)[IPT], uint32_t n, uint32_t wbase,
                                               uint32_t (*s_wcnt)[kMaxBuckets], uint32_t* s_loc, uint32_t* s_cnt,
                                               uint64_t* s_scan, uint32_t* s_max, uint32_t (&rk)[IPT]) {
-    constexpr int NT = kWave * NW, DPT = kMaxBuckets / NT;  // digits per thread
+    constexpr int NT = kWave * NW, DPT = NT >= kMaxBuckets ? 1 : kMaxBuckets / NT;  // digits per thread
     const uint32_t tid = threadIdx.x, wave = tid / kWave;
     for (uint32_t b = tid; b < NW * kMaxBuckets; b += NT) (&s_wcnt[0][0])[b] = 0;
     __syncthreads();
@@ -1171,10 +1178,12 @@ __device__ inline uint32_t block_count_digits(const uint32_t (&bk)[IPT], uint32_
     for (int i = 0; i < DPT; ++i) {
         const uint32_t dg = tid * DPT + i;
         uint32_t run = 0;
-        for (int w = 0; w < NW; ++w) {
-            const uint32_t c = s_wcnt[w][dg];
-            s_wcnt[w][dg] = run;
-            run += c;
+        if (dg < (uint32_t)kMaxBuckets) {
+            for (int w = 0; w < NW; ++w) {
+                const uint32_t c = s_wcnt[w][dg];
+                s_wcnt[w][dg] = run;
+                run += c;
+            }
         }
         tot[i] = run;
         sum += run;
@@ -1187,8 +1196,10 @@ __device__ inline uint32_t block_count_digits(const uint32_t (&bk)[IPT], uint32_
 #pragma unroll
     for (int i = 0; i < DPT; ++i) {
         const uint32_t dg = tid * DPT + i;
-        s_loc[dg] = e;
-        s_cnt[dg] = tot[i];
+        if (dg < (uint32_t)kMaxBuckets) {
+            s_loc[dg] = e;
+            s_cnt[dg] = tot[i];
+        }
         e += tot[i];
     }
     mx = 0;
@@ -1197,7 +1208,7 @@ __device__ inline uint32_t block_count_digits(const uint32_t (&bk)[IPT], uint32_
     return mx;
 }
 
-// Base case for one bucket of at most 1024 NW keys per workgroup of NW waves (16 keys a thread).
+// Base case for one bucket of at most 64 NW IPT keys per workgroup of NW waves (IPT keys a thread).
 // The bucket's smallest ord (min) and the low bits z that are zero in every ord - min are found
 // first; x = (ord - min) >> z keeps only the bits where the keys differ, nbits of them.
 //  * nbits <= 8: one stable counting pass on x sorts the bucket.
@@ -1209,13 +1220,14 @@ __device__ inline uint32_t block_count_digits(const uint32_t (&bk)[IPT], uint32_
 // All paths are stable.
 constexpr uint32_t kSubMax = 64;
 
-template <int DT, bool PAY, int NW>
+template <int DT, bool PAY, int NW, int IPT>
 __global__ __launch_bounds__(64 * NW) void k_base_large(const BaseItem* list, uint64_t count,
                                                        typename Key<DT>::T* keys, uint32_t* pay,
                                                        const typename Key<DT>::T* skeys, const uint32_t* spay) {
     using KT = Key<DT>;
     using O = typename KT::O;
-    constexpr int IPT = 16, NT = 64 * NW, CAP = NT * IPT, PCAP = CAP + CAP / 16;
+    constexpr int NT = 64 * NW, CAP = NT * IPT, PCAP = CAP + CAP / 16;
+    constexpr int MT = CAP / 16;  // threads of the merge-sort fallback (16 keys each)
     constexpr O kPad = (O)~(O)0;
     __shared__ O s_k[PCAP];
     __shared__ uint32_t s_p[PAY ? PCAP : 1];
@@ -1283,7 +1295,7 @@ __global__ __launch_bounds__(64 * NW) void k_base_large(const BaseItem* list, ui
             if (PAY) s_p[pad16(j)] = j < n ? p[r] : 0u;
         }
         __syncthreads();
-        merge_sort_lds<O, PAY, NT>(s_k, s_p, (int)tid);
+        merge_sort_lds<O, PAY, MT>(s_k, s_p, (int)tid, tid < (uint32_t)MT);
 #pragma unroll
         for (int r = 0; r < IPT; ++r) {
             const uint32_t j = wbase + r * kWave + lane;

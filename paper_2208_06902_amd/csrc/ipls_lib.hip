@@ -28,8 +28,8 @@ constexpr uint32_t kCand = 15;         // candidate widths per fit round
 constexpr uint32_t kTile = kTileKeys;
 constexpr uint32_t kSmallTile = kBlock * kSmallIPT;
 
-// Keys per distribution tile: 4096 (the default) or 2048.
-inline uint32_t tile_keys_of(const ipls_params& p) { return p.tile_keys == kSmallTile ? kSmallTile : kTile; }
+// Keys per distribution tile: 2048 (the default: 8 keys a thread, twice the occupancy) or 4096.
+inline uint32_t tile_keys_of(const ipls_params& p) { return p.tile_keys == kTile ? kTile : kSmallTile; }
 constexpr int kMaxLevels = 4096;
 constexpr int kMaxDepth = 16;
 
@@ -306,15 +306,15 @@ ipls_status launch_base(hipStream_t s, int cls, const BaseItem* list, uint64_t c
         case 2: return launch_base_nt<DT, PAY, 16>(s, list, count, keys, pay, sk, sp);
         case 3: return launch_base_nt<DT, PAY, 32>(s, list, count, keys, pay, sk, sp);
         case 4:
-            k_base_large<DT, PAY, 1><<<(unsigned)count, 64, 0, s>>>(list, count, keys, pay, sk, sp);
+            k_base_large<DT, PAY, 2, 8><<<(unsigned)count, 128, 0, s>>>(list, count, keys, pay, sk, sp);
             LAUNCH_CHECK();
             return IPLS_OK;
         case 5:
-            k_base_large<DT, PAY, 2><<<(unsigned)count, 128, 0, s>>>(list, count, keys, pay, sk, sp);
+            k_base_large<DT, PAY, 4, 8><<<(unsigned)count, 256, 0, s>>>(list, count, keys, pay, sk, sp);
             LAUNCH_CHECK();
             return IPLS_OK;
         default:
-            k_base_large<DT, PAY, 4><<<(unsigned)count, 256, 0, s>>>(list, count, keys, pay, sk, sp);
+            k_base_large<DT, PAY, 8, 8><<<(unsigned)count, 512, 0, s>>>(list, count, keys, pay, sk, sp);
             LAUNCH_CHECK();
             return IPLS_OK;
     }
