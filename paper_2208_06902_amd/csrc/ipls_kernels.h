@@ -1332,14 +1332,9 @@ __global__ __launch_bounds__(64 * NW) void k_base_large(const BaseItem* list, ui
                 const uint32_t d = (uint32_t)(((uint64_t)(xs[r] - mn) >> shift) & 255u);
                 const uint32_t start = s_loc[d], cnt = s_cnt[d];
                 uint32_t before = 0;
-                // eight reads in flight per step: the loop is bound by LDS latency, not bandwidth
-                for (uint32_t q = 0; q < cnt; q += 8) {
-                    O xv[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) xv[u] = q + u < cnt ? s_k[start + q + u] : (O)0;
-#pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        before += (q + u < cnt && (xv[u] < xs[r] || (xv[u] == xs[r] && start + q + u < j))) ? 1u : 0u;
+                for (uint32_t q = 0; q < cnt; ++q) {
+                    const O x = s_k[start + q];
+                    before += (x < xs[r] || (x == xs[r] && start + q < j)) ? 1u : 0u;
                 }
                 np[r] = start + before;
             }
