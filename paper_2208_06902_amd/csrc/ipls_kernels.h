@@ -1208,7 +1208,8 @@ __device__ inline uint32_t block_count_digits(const uint32_t (&bk)[IPT], uint32_
     return mx;
 }
 
-// Base case for one bucket of at most 64 NW IPT keys per workgroup of NW waves (IPT keys a thread).
+// Stable base case (used for payload sorts) for one bucket of at most 64 NW IPT keys per workgroup
+// of NW waves (IPT keys a thread).
 // The bucket's smallest ord (min) and the low bits z that are zero in every ord - min are found
 // first; x = (ord - min) >> z keeps only the bits where the keys differ, nbits of them.
 //  * nbits <= 8: one stable counting pass on x sorts the bucket.
@@ -1221,9 +1222,8 @@ __device__ inline uint32_t block_count_digits(const uint32_t (&bk)[IPT], uint32_
 constexpr uint32_t kSubMax = 64;
 
 template <int DT, bool PAY, int NW, int IPT>
-__global__ __launch_bounds__(64 * NW) void k_base_large(const BaseItem* list, uint64_t count,
-                                                       typename Key<DT>::T* keys, uint32_t* pay,
-                                                       const typename Key<DT>::T* skeys, const uint32_t* spay) {
+__device__ inline void base_large_stable(const BaseItem& bi, typename Key<DT>::T* keys, uint32_t* pay,
+                                         const typename Key<DT>::T* skeys, const uint32_t* spay) {
     using KT = Key<DT>;
     using O = typename KT::O;
     constexpr int NT = 64 * NW, CAP = NT * IPT, PCAP = CAP + CAP / 16;
@@ -1237,8 +1237,6 @@ __global__ __launch_bounds__(64 * NW) void k_base_large(const BaseItem* list, ui
     __shared__ uint32_t s_max[NW];
     __shared__ O s_red[2][NW];
     const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
-    if (blockIdx.x >= count) return;
-    const BaseItem bi = list[blockIdx.x];
     const uint32_t n = bi.n;
     const typename KT::T* src = bi.from_scratch ? skeys : keys;
     const uint32_t* psrc = bi.from_scratch ? spay : pay;
@@ -1358,6 +1356,169 @@ __global__ __launch_bounds__(64 * NW) void k_base_large(const BaseItem* list, ui
             if (PAY) pay[bi.lo + j] = s_p[j];
         }
     }
+}
+
+
+// Base case of keys-only sorts for one bucket of at most CAP = 64 NW IPT keys per workgroup.  Keys
+// with equal ord are identical, so any order among them is the sorted order and the pass need not
+// be stable.  One reduction finds the bucket's min, max and the low bits z shared by all keys
+// (the trailing zeros of every key's difference to the bucket's first key); a histogram of
+// log2(CAP)-bit digits of (ord - min) >> z, taken from the top of the varying bits, with LDS atomics,
+// places every key in its digit's range.  Digits then hold one key on average:
+//  * when the varying bits fit the digit, keys of a digit are equal and the bucket is sorted;
+//  * otherwise a key's final place is its digit's start plus the keys of the digit before it in
+//    (ord, position) order; a digit of more than kSubMax keys (skewed buckets) sends the bucket to
+//    the merge sort instead.
+template <int DT, int NW, int IPT>
+__device__ inline void base_large_keys(const BaseItem& bi, typename Key<DT>::T* keys,
+                                       const typename Key<DT>::T* skeys) {
+    using KT = Key<DT>;
+    using O = typename KT::O;
+    constexpr int NT = 64 * NW, CAP = NT * IPT, PCAP = CAP + CAP / 16, MT = CAP / 16;
+    constexpr int DB = CAP >= 4096 ? 12 : CAP >= 2048 ? 11 : CAP >= 1024 ? 10 : 9;  // digit bits
+    constexpr int ND = 1 << DB, CPT = ND / NT;                                     // digits, per thread
+    static_assert(ND == CAP && CPT == IPT, "one digit per key slot");
+    constexpr O kPad = (O)~(O)0;
+    __shared__ O s_k[PCAP];
+    __shared__ uint32_t s_c[ND + 1];
+    __shared__ uint64_t s_scan[16];
+    __shared__ O s_red[3][NW];
+    __shared__ uint32_t s_most[NW];
+    const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
+    const uint32_t n = bi.n;
+    const typename KT::T* src = bi.from_scratch ? skeys : keys;
+    const uint32_t wbase = wave * kWave * IPT;
+    O o[IPT];
+    {
+        typename KT::T v[IPT];
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const uint32_t j = wbase + r * kWave + lane;
+            if (j < n) v[r] = src[bi.lo + j];
+        }
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) o[r] = wbase + r * kWave + lane < n ? (O)KT::ord(v[r]) : kPad;
+    }
+    const O oref = (O)KT::ord(src[bi.lo]);  // n >= 1
+    O mn = kPad, mx = 0, ov = 0;
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        if (wbase + r * kWave + lane < n) {
+            mn = o[r] < mn ? o[r] : mn;
+            mx = o[r] > mx ? o[r] : mx;
+            ov |= (O)(o[r] - oref);
+        }
+    }
+    mn = (O)~wave_max((O)~mn);
+    mx = wave_max(mx);
+#pragma unroll
+    for (int sft = 32; sft >= 1; sft >>= 1) ov |= (O)__shfl_xor(ov, sft, kWave);
+    for (uint32_t d = tid; d <= (uint32_t)ND; d += NT) s_c[d] = 0;
+    if (lane == 0) {
+        s_red[0][wave] = mn;
+        s_red[1][wave] = mx;
+        s_red[2][wave] = ov;
+    }
+    __syncthreads();
+    mn = s_red[0][0];
+    mx = s_red[1][0];
+    ov = s_red[2][0];
+    for (int w = 1; w < NW; ++w) {
+        mn = s_red[0][w] < mn ? s_red[0][w] : mn;
+        mx = s_red[1][w] > mx ? s_red[1][w] : mx;
+        ov |= s_red[2][w];
+    }
+    const int z = ov ? __builtin_ctzll((unsigned long long)ov) : 0;
+    const int nbits = (int)bit_length((uint64_t)((O)(mx - mn) >> z));
+    const int shift = z + (nbits > DB ? nbits - DB : 0);
+    const bool exact = nbits <= DB;
+    uint32_t dg[IPT], sl[IPT];
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        if (wbase + r * kWave + lane < n) {
+            dg[r] = (uint32_t)((uint64_t)(o[r] - mn) >> shift);
+            sl[r] = atomicAdd(&s_c[dg[r]], 1u);
+        }
+    }
+    __syncthreads();
+    // digit starts: thread t owns digits [t CPT, (t+1) CPT)
+    uint32_t c[CPT], sum = 0, most = 0;
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+        c[i] = s_c[tid * CPT + i];
+        sum += c[i];
+        most = c[i] > most ? c[i] : most;
+    }
+    most = wave_max(most);
+    if (lane == 0) s_most[wave] = most;
+    uint64_t all;
+    uint32_t e = (uint32_t)block_exclusive_sum<uint64_t>(sum, s_scan, &all);  // synchronises
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+        s_c[tid * CPT + i] = e;
+        e += c[i];
+    }
+    if (tid == 0) s_c[ND] = n;
+    most = 0;
+    for (int w = 0; w < NW; ++w) most = s_most[w] > most ? s_most[w] : most;
+    __syncthreads();
+
+    if (!exact && most > kSubMax) {
+        // merge sort: keys to LDS at their input positions (padding keys at the end), then sort
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) s_k[pad16(wbase + r * kWave + lane)] = o[r];
+        __syncthreads();
+        merge_sort_lds<O, false, MT>(s_k, nullptr, (int)tid, tid < (uint32_t)MT);
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const uint32_t j = wbase + r * kWave + lane;
+            if (j < n) keys[bi.lo + j] = KT::from_ord((uint64_t)s_k[pad16(j)]);
+        }
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < IPT; ++r)
+        if (wbase + r * kWave + lane < n) s_k[s_c[dg[r]] + sl[r]] = o[r];
+    __syncthreads();
+    if (!exact) {
+        O xs[IPT];
+        uint32_t np[IPT];
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const uint32_t j = wbase + r * kWave + lane;
+            if (j < n) {
+                xs[r] = s_k[j];
+                const uint32_t d = (uint32_t)((uint64_t)(xs[r] - mn) >> shift);
+                const uint32_t start = s_c[d], end = s_c[d + 1];
+                uint32_t before = 0;
+                for (uint32_t q = start; q < end; ++q) {
+                    const O y = s_k[q];
+                    before += (y < xs[r] || (y == xs[r] && q < j)) ? 1u : 0u;
+                }
+                np[r] = start + before;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < IPT; ++r)
+            if (wbase + r * kWave + lane < n) s_k[np[r]] = xs[r];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint32_t j = wbase + r * kWave + lane;
+        if (j < n) keys[bi.lo + j] = KT::from_ord((uint64_t)s_k[j]);
+    }
+}
+
+template <int DT, bool PAY, int NW, int IPT>
+__global__ __launch_bounds__(64 * NW) void k_base_large(const BaseItem* list, uint64_t count,
+                                                       typename Key<DT>::T* keys, uint32_t* pay,
+                                                       const typename Key<DT>::T* skeys, const uint32_t* spay) {
+    if (blockIdx.x >= count) return;
+    const BaseItem bi = list[blockIdx.x];
+    if constexpr (PAY) base_large_stable<DT, true, NW, IPT>(bi, keys, pay, skeys, spay);
+    else base_large_keys<DT, NW, IPT>(bi, keys, skeys);
 }
 
 }  // namespace ipls
