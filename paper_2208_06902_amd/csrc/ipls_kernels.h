@@ -1110,6 +1110,55 @@ __device__ inline void merge_sort_lds(O* sk, uint32_t* sp, int t_in, bool active
     __syncthreads();
 }
 
+template <int DT, bool PAY, int NT>
+__global__ __launch_bounds__(256) void k_base_sort(const BaseItem* list, uint64_t count, typename Key<DT>::T* keys,
+                                                   uint32_t* pay, const typename Key<DT>::T* skeys,
+                                                   const uint32_t* spay) {
+    using KT = Key<DT>;
+    using O = typename KT::O;
+    constexpr int IPT = 16, G = kBlock / NT, CAP = NT * IPT, PCAP = CAP + CAP / 16;
+    constexpr O kPad = (O)~(O)0;
+    __shared__ O s_k[G * PCAP];
+    __shared__ uint32_t s_p[PAY ? G * PCAP : 1];
+    const int g = threadIdx.x / NT, t = threadIdx.x % NT;
+    const uint64_t bidx = (uint64_t)blockIdx.x * G + g;
+    BaseItem bi = {0, 0, 0};
+    if (bidx < count) bi = list[bidx];
+    const uint32_t n = bi.n;
+    const typename KT::T* src = bi.from_scratch ? skeys : keys;
+    const uint32_t* psrc = bi.from_scratch ? spay : pay;
+    O* sk = s_k + g * PCAP;
+    uint32_t* sp = s_p + (PAY ? g * PCAP : 0);
+    {
+        typename KT::T v[IPT];
+        uint32_t pv[PAY ? IPT : 1];
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const int j = t + r * NT;
+            if (j < (int)n) {
+                v[r] = src[bi.lo + j];
+                if (PAY) pv[r] = psrc[bi.lo + j];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const int j = t + r * NT;
+            sk[pad16(j)] = j < (int)n ? (O)KT::ord(v[r]) : kPad;
+            if (PAY) sp[pad16(j)] = j < (int)n ? pv[r] : 0u;
+        }
+    }
+    __syncthreads();
+    merge_sort_lds<O, PAY, NT>(sk, sp, t);
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const int j = t + r * NT;
+        if (j < (int)n) {
+            keys[bi.lo + j] = KT::from_ord((uint64_t)sk[pad16(j)]);
+            if (PAY) pay[bi.lo + j] = sp[pad16(j)];
+        }
+    }
+}
+
 // Stable counting of one digit (0..255) per key over a workgroup of NW waves, with the same
 // ballot ranking as the scatter.  Afterwards the key of wave w with digit b and rank rk among the
 // wave's earlier keys of b belongs at s_loc[b] + s_wcnt[w][b] + rk; s_cnt[b] is digit b's count.
@@ -1157,91 +1206,6 @@ __device__ inline uint32_t block_count_digits(const uint32_t (&bk)[IPT], uint32_
     for (int w = 0; w < NW; ++w) mx = s_max[w] > mx ? s_max[w] : mx;
     __syncthreads();
     return mx;
-}
-
-// Base case for buckets of at most 64 R keys (R = 1, 2, 4, 8): one wave per bucket, four buckets
-// per workgroup, no LDS and no barriers.  Key i = lane + 64 r of the bucket sits in register r of
-// its lane; a bitonic network sorts the 64 R keys, exchanging across lanes with shuffles (strides
-// below 64) and inside a lane (strides of 64 and more).  Payload sorts compare (ord, position),
-// which makes the result the stable order; padding slots hold the largest ord and the largest
-// positions, so they end up last.
-template <int DT, bool PAY, int R>
-__global__ __launch_bounds__(256) void k_base_wave(const BaseItem* list, uint64_t count, typename Key<DT>::T* keys,
-                                                   uint32_t* pay, const typename Key<DT>::T* skeys,
-                                                   const uint32_t* spay) {
-    using KT = Key<DT>;
-    using O = typename KT::O;
-    constexpr int N = 64 * R;
-    constexpr O kPad = (O)~(O)0;
-    const uint32_t lane = lane_id();
-    const uint64_t bidx = (uint64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    if (bidx >= count) return;  // the whole wave leaves together
-    const BaseItem bi = list[bidx];
-    const uint32_t n = bi.n;
-    const typename KT::T* src = bi.from_scratch ? skeys : keys;
-    const uint32_t* psrc = bi.from_scratch ? spay : pay;
-    O k[R];
-    uint32_t id[R], p[R];
-    {
-        typename KT::T v[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint32_t i = lane + kWave * r;
-            if (i < n) {
-                v[r] = src[bi.lo + i];
-                p[r] = PAY ? psrc[bi.lo + i] : 0u;
-            } else {
-                p[r] = 0u;
-            }
-            id[r] = i;
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) k[r] = lane + kWave * r < n ? (O)KT::ord(v[r]) : kPad;
-    }
-#pragma unroll
-    for (int kk = 2; kk <= N; kk <<= 1) {
-#pragma unroll
-        for (int j = kk >> 1; j > 0; j >>= 1) {
-            if (j >= kWave) {
-                const int jr = j / kWave;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    if ((r & jr) == 0) {
-                        const int l = r | jr;
-                        const bool up = (((uint32_t)(lane + kWave * r)) & (uint32_t)kk) == 0;
-                        cex<PAY>(k[r], k[l], id[r], id[l], p[r], p[l], up);
-                    }
-                }
-            } else {
-                const bool lower = (lane & (uint32_t)j) == 0;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const O ok = (O)__shfl_xor(k[r], j, kWave);
-                    const uint32_t oid = PAY ? (uint32_t)__shfl_xor((int)id[r], j, kWave) : 0u;
-                    const uint32_t op = PAY ? (uint32_t)__shfl_xor((int)p[r], j, kWave) : 0u;
-                    const bool up = (((uint32_t)(lane + kWave * r)) & (uint32_t)kk) == 0;
-                    const bool other_less = key_less<PAY>(ok, oid, k[r], id[r]);
-                    // ascending pairs: the lower slot keeps the smaller key; descending: the larger
-                    const bool take = (lower == up) ? other_less : !other_less;
-                    if (take) {
-                        k[r] = ok;
-                        if (PAY) {
-                            id[r] = oid;
-                            p[r] = op;
-                        }
-                    }
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t i = lane + kWave * r;
-        if (i < n) {
-            keys[bi.lo + i] = KT::from_ord((uint64_t)k[r]);
-            if (PAY) pay[bi.lo + i] = p[r];
-        }
-    }
 }
 
 // Stable base case (used for payload sorts) for one bucket of at most 64 NW IPT keys per workgroup

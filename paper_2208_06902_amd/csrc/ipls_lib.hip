@@ -285,13 +285,13 @@ template <int DT, bool PAY>
 ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys, uint32_t* pay, uint64_t len,
                           const uint64_t* seg_off, uint64_t nseg, void* ws_keys, bool top);
 
-// Base-case sort of `count` buckets of size class cls (<= 64 * 2^cls keys).  Classes 0..3: one
-// wave per bucket (register bitonic network); classes 4..6: one workgroup per bucket.
-template <int DT, bool PAY, int R>
-ipls_status launch_base_wave(hipStream_t s, const BaseItem* list, uint64_t count, typename Key<DT>::T* keys,
-                             uint32_t* pay, const typename Key<DT>::T* sk, const uint32_t* sp) {
-    constexpr uint64_t G = kBlock / kWave;
-    k_base_wave<DT, PAY, R><<<(unsigned)((count + G - 1) / G), kBlock, 0, s>>>(list, count, keys, pay, sk, sp);
+// Base-case sort of `count` buckets of size class cls (<= 64 * 2^cls keys).  Classes 0..3: merge sort, 16 keys per thread,
+// NT = 4 * 2^cls threads per bucket, 256 / NT buckets per workgroup.
+template <int DT, bool PAY, int NT>
+ipls_status launch_base_nt(hipStream_t s, const BaseItem* list, uint64_t count, typename Key<DT>::T* keys,
+                           uint32_t* pay, const typename Key<DT>::T* sk, const uint32_t* sp) {
+    constexpr uint64_t G = kBlock / NT;
+    k_base_sort<DT, PAY, NT><<<(unsigned)((count + G - 1) / G), kBlock, 0, s>>>(list, count, keys, pay, sk, sp);
     LAUNCH_CHECK();
     return IPLS_OK;
 }
@@ -301,10 +301,10 @@ ipls_status launch_base(hipStream_t s, int cls, const BaseItem* list, uint64_t c
                         uint32_t* pay, const typename Key<DT>::T* sk, const uint32_t* sp) {
     if (count == 0) return IPLS_OK;
     switch (cls) {
-        case 0: return launch_base_wave<DT, PAY, 1>(s, list, count, keys, pay, sk, sp);
-        case 1: return launch_base_wave<DT, PAY, 2>(s, list, count, keys, pay, sk, sp);
-        case 2: return launch_base_wave<DT, PAY, 4>(s, list, count, keys, pay, sk, sp);
-        case 3: return launch_base_wave<DT, PAY, 8>(s, list, count, keys, pay, sk, sp);
+        case 0: return launch_base_nt<DT, PAY, 4>(s, list, count, keys, pay, sk, sp);
+        case 1: return launch_base_nt<DT, PAY, 8>(s, list, count, keys, pay, sk, sp);
+        case 2: return launch_base_nt<DT, PAY, 16>(s, list, count, keys, pay, sk, sp);
+        case 3: return launch_base_nt<DT, PAY, 32>(s, list, count, keys, pay, sk, sp);
         case 4:
             k_base_large<DT, PAY, 2, 8><<<(unsigned)count, 128, 0, s>>>(list, count, keys, pay, sk, sp);
             LAUNCH_CHECK();
