@@ -279,7 +279,7 @@ def bench_served(args):
     dnames = ("lognormal2", "mixgauss20", "normal", "exponential", "uniform01", "lognormal")
     which = r.integers(0, len(dnames), count)
     total = int(sizes.sum())
-    params = ipls.default_params(model=ipls.MODEL_AUTO, sample_max=args.sample_max)
+    params = ipls.default_params(model=args.model, sample_max=args.sample_max)
     budget = args.budget_gb << 30
     arena = torch.empty(budget, dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
@@ -377,6 +377,7 @@ def main():
     ap.add_argument("--dists", default=",".join(DISTS))
     ap.add_argument("--sample-max", type=int, default=4096)
     ap.add_argument("--tile-keys", type=int, default=0, help="keys per distribution tile (0 = library default)")
+    ap.add_argument("--sort-model", type=int, default=0, help="sort: 0 FMCD (default), 1 auto, 2 learned")
     ap.add_argument("--workload", choices=("sort", "batched", "served"), default="sort",
                     help="sort: the 1e8 fp64 single-array sort (default); batched; served")
     ap.add_argument("--arrays", type=int, default=100_000, help="batched: number of arrays")
@@ -385,6 +386,7 @@ def main():
     ap.add_argument("--rate", type=float, default=2000.0, help="served: arrivals per second")
     ap.add_argument("--budget-gb", type=int, default=64, help="served: HBM budget")
     ap.add_argument("--lanes", type=int, default=3, help="served: concurrent lanes")
+    ap.add_argument("--model", type=int, default=1, help="served: 0 FMCD, 1 auto (learned model when lower max load)")
     ap.add_argument("--summarize-profiles", nargs=4, metavar=("KTRACE_DIR", "FETCH_DIR", "WRITE_DIR", "BENCH_JSON"),
                     help="write profiles/ summaries from rocprofv3 CSV output and exit")
     args = ap.parse_args()
@@ -416,7 +418,7 @@ def main():
     total = args.warmup + args.steps
     order = [dists[i % len(dists)] for i in range(total)]
 
-    params = ipls.default_params(sample_max=args.sample_max, tile_keys=args.tile_keys)
+    params = ipls.default_params(sample_max=args.sample_max, tile_keys=args.tile_keys, model=args.sort_model)
     stream = torch.cuda.current_stream()
 
     # warmup: also checks parity of each distribution's output against numpy's sort
@@ -501,7 +503,7 @@ def main():
         d0 = dists[0]
         print(f"# cpu baseline: oracle on one full step ({d0}, {n} keys)", file=sys.stderr, flush=True)
         t = time.perf_counter()
-        want, _, _ = oracle.sort(host_inputs[d0], None, oracle.params(sample_max=args.sample_max))
+        want, _, _ = oracle.sort(host_inputs[d0], None, oracle.params(sample_max=args.sample_max, model=args.sort_model))
         dt = time.perf_counter() - t
         # parity of the GPU result for this step against the oracle
         g = pristine[d0].clone()
@@ -527,7 +529,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"plain single-array sort, {n} fp64 keys per step, keys only, cycling "
                                + "/".join(dists), "n": n, "num_buckets": 256, "base_case_max": 4096,
-                   "sample": f"1% jittered stratified, capped at {args.sample_max} keys", "model": "FMCD",
+                   "sample": f"1% jittered stratified, capped at {args.sample_max} keys",
+                   "model": ("FMCD", "auto (learned model when lower max load)", "learned")[args.sort_model],
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu_baseline,

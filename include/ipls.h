@@ -64,7 +64,7 @@ typedef struct {
     uint64_t seed;           /* seed of the sample positions' jitter */
     uint32_t model;          /* ipls_model_policy */
     uint32_t leaves;         /* leaves M of the two-level model, 4..256 (default 256) */
-    uint32_t train_iters;    /* gradient steps of the two-level model (default 32) */
+    uint32_t train_iters;    /* gradient steps of the two-level model (default 4; each a Newton step) */
     uint32_t tile_keys;      /* keys per distribution tile: 2048 (0 = default) or 4096 */
     uint32_t sample_policy;  /* 0: the divisor rule above (Learned Sort's 1% sample, Background chapter);
                               * 1: IPLS's alpha*K - 1 with alpha = 0.2 log2(n), rounded to nearest,
@@ -92,7 +92,7 @@ typedef struct {
     uint64_t keys_partitioned;  /* sum over levels of keys that went through a distribution pass */
 } ipls_stats;
 
-/* Defaults: K 256, T 4096, divisor 100, sample_min 2K, no cap, FMCD, M 256, 32 steps, policy 0. */
+/* Defaults: K 256, T 4096, divisor 100, sample_min 2K, no cap, FMCD, M 256, 4 steps, tile 2048, policy 0. */
 void ipls_default_params(ipls_params* p);
 
 /* Sort keys[0..n) (and payload[0..n) when non-null, stably) in place with default parameters.

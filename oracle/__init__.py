@@ -47,7 +47,7 @@ DEFAULT_SEED = 0x1F5A_2208_0690_2000
 
 
 def params(K=256, T=4096, divisor=100, sample_min=0, sample_max=0, seed=DEFAULT_SEED, model=0, leaves=256,
-           train_iters=32, sample_policy=0) -> Params:
+           train_iters=4, sample_policy=0) -> Params:
     return Params(K, T, divisor, sample_min, sample_max, seed, model, leaves, train_iters, sample_policy)
 
 

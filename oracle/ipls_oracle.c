@@ -398,8 +398,9 @@ void oracle_l2pl_grad(const double* x, uint64_t S, uint32_t K, uint32_t M, const
 /* Training: root = FMCD onto M leaves; each leaf starts at the line through its first and last
  * sample (interpolation, the Learned Sort choice) and takes `iters` gradient steps.  With u
  * centred on the leaf mean the MSE's Hessian is diag(2 m2, 2), so the step is scaled per
- * coordinate: alpha -= (1/4 / m2) g_alpha, beta -= g_beta / 4 (half a Newton step: the error
- * halves every iteration).  The slope is kept >= 0 so the model stays monotone.  Export:
+ * coordinate by its inverse: alpha -= (1/2 / m2) g_alpha, beta -= g_beta / 2 (a Newton step,
+ * which lands on the minimiser of the quadratic loss; later steps only absorb rounding and the
+ * clamp).  The slope is kept >= 0 so the model stays monotone.  Export:
  * A = alpha / h, B = beta - A c; envelope LO_0 = 0, LO_l = HI_(l-1),
  * HI_l = max(LO_l, min(K, fma(A, last sample, B))) (an empty leaf has A = 0, B = LO_l = HI_l).
  * ab_out (2*M, nullable) receives the trained (alpha, beta).  Returns 0, or -1 when the root
@@ -435,12 +436,12 @@ int oracle_l2pl_train(const double* x, uint64_t S, uint32_t K, uint32_t M, uint3
             if (first[l + 1] == first[l]) continue;
             double alpha = 0.0;
             if (m2[l] > 0.0) {
-                double q = 0.25 / m2[l];
+                double q = 0.5 / m2[l];
                 alpha = ab[2 * l] - q * g[2 * l];
                 if (!(alpha > 0.0)) alpha = 0.0;
             }
             ab[2 * l] = alpha;
-            ab[2 * l + 1] = ab[2 * l + 1] - 0.25 * g[2 * l + 1];
+            ab[2 * l + 1] = ab[2 * l + 1] - 0.5 * g[2 * l + 1];
         }
     }
     double prev_hi = 0.0;

@@ -467,24 +467,42 @@ __global__ __launch_bounds__(256) void k_l2pl_train(const typename Key<DT>::T* s
         }
         return;
     }
+    // A leaf of at most 64 samples keeps its lane's (u, y) in registers across the steps (the
+    // same values the loop below recomputes).
+    const bool one_per_lane = j1 - j0 <= (uint64_t)kWave;
+    const bool mine = j0 + lane < j1;
+    double u1l = 0.0, y1l = 0.0;
+    if (one_per_lane && mine) {
+        u1l = (KT::val(xs[j0 + lane]) - mean) / h;
+        y1l = l2pl_target(j0 + lane, S, K);
+    }
     for (uint32_t it = 0; it < iters; ++it) {
         double pa = 0.0, pb = 0.0;
-        for (uint64_t j = j0 + lane; j < j1; j += kWave) {
-            const double u = (KT::val(xs[j]) - mean) / h;
-            const double r = __builtin_fma(alpha, u, beta) - l2pl_target(j, S, K);
-            pa = __builtin_fma(r, u, pa);
-            pb = pb + r;
+        if (one_per_lane) {
+            if (mine) {
+                const double r = __builtin_fma(alpha, u1l, beta) - y1l;
+                pa = __builtin_fma(r, u1l, pa);
+                pb = pb + r;
+            }
+        } else {
+            for (uint64_t j = j0 + lane; j < j1; j += kWave) {
+                const double u = (KT::val(xs[j]) - mean) / h;
+                const double r = __builtin_fma(alpha, u, beta) - l2pl_target(j, S, K);
+                pa = __builtin_fma(r, u, pa);
+                pb = pb + r;
+            }
         }
         const double ga = __shfl(wave_tree_sum(pa), 0, kWave) * inv;
         const double gb = __shfl(wave_tree_sum(pb), 0, kWave) * inv;
+        // Newton step: with u centred the loss's Hessian is diag(2 m2, 2)
         double na = 0.0;
         if (m2 > 0.0) {
-            const double q = 0.25 / m2;
+            const double q = 0.5 / m2;
             na = alpha - q * ga;
             if (!(na > 0.0)) na = 0.0;
         }
         alpha = na;
-        beta = beta - 0.25 * gb;
+        beta = beta - 0.5 * gb;
     }
     if (lane == 0) {
         const double A = alpha / h;
@@ -503,37 +521,73 @@ __global__ __launch_bounds__(256) void k_l2pl_train(const typename Key<DT>::T* s
 
 // Monotone envelope of every item's leaves (one thread per item, leaves in order) and the check
 // that every coefficient is finite; an empty leaf is the constant LO (A = 0, B = LO = HI).
-__global__ void k_l2pl_envelope(uint64_t num_items, Model* models, const Model* roots, const uint32_t* first,
-                                uint32_t M, double* leaves, const double* lastp) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(64) void k_l2pl_envelope(uint64_t num_items, Model* models, const Model* roots,
+                                                      const uint32_t* first, uint32_t M, double* leaves,
+                                                      const double* lastp) {
+    // One wave per item.  Leaf l's HI is the running max, from 0, of the last-sample values of the
+    // non-empty leaves up to l (a NaN never wins); LO_l = HI_(l-1).  The running max keeps the
+    // earliest of equal values, as the sequential walk does, so a parallel prefix over the lanes
+    // (4 consecutive leaves each) gives the same bits.
+    const uint64_t i = blockIdx.x;
+    const uint32_t lane = lane_id();
     if (i >= num_items) return;
     Model m = models[i];
-    m.l2_ok = 0;
     if (m.kind != kKindLinear || roots[i].kind != kKindLinear) {
-        models[i] = m;
+        if (lane == 0) {
+            m.l2_ok = 0;
+            models[i] = m;
+        }
         return;
     }
     const uint32_t* f = first + i * (M + 1);
     double* lv = leaves + i * 4 * kMaxLeaves;
-    double prev = 0.0;
-    bool ok = true;
-    for (uint32_t l = 0; l < M; ++l) {
-        double A = 0.0, B = prev, lo = prev, hi = prev;
-        if (f[l + 1] > f[l]) {
-            A = lv[4 * l];
-            B = lv[4 * l + 1];
-            const double last = lastp[i * kMaxLeaves + l];
-            hi = last > lo ? last : lo;
-        }
-        ok = ok && isfinite(A) && isfinite(B) && isfinite(hi);
-        lv[4 * l] = A;
-        lv[4 * l + 1] = B;
-        lv[4 * l + 2] = lo;
-        lv[4 * l + 3] = hi;
-        prev = hi;
+    constexpr int LPL = kMaxLeaves / kWave;  // leaves per lane
+    const double kAbsent = __builtin_nan("");
+    // combine(a, b): b follows a; b wins only if a is absent or b > a
+    auto combine = [](double a, double b) { return (a != a || b > a) ? b : a; };
+    double c[LPL], own = kAbsent;
+#pragma unroll
+    for (int q = 0; q < LPL; ++q) {
+        const uint32_t l = lane * LPL + q;
+        c[q] = kAbsent;
+        if (l < M && f[l + 1] > f[l]) c[q] = lastp[i * kMaxLeaves + l];
+        own = combine(own, c[q]);
     }
-    m.l2_ok = ok ? 1u : 0u;
-    models[i] = m;
+    // exclusive prefix over the lanes
+    double inc = own;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const double o = __shfl_up(inc, d, kWave);
+        if (lane >= (uint32_t)d) inc = combine(o, inc);
+    }
+    double ex = __shfl_up(inc, 1, kWave);
+    if (lane == 0) ex = kAbsent;
+    double prev = combine(0.0, ex);
+    bool ok = true;
+#pragma unroll
+    for (int q = 0; q < LPL; ++q) {
+        const uint32_t l = lane * LPL + q;
+        if (l < M) {
+            double A = 0.0, B = prev, lo = prev, hi = prev;
+            if (f[l + 1] > f[l]) {
+                A = lv[4 * l];
+                B = lv[4 * l + 1];
+                const double last = lastp[i * kMaxLeaves + l];
+                hi = last > lo ? last : lo;
+            }
+            ok = ok && isfinite(A) && isfinite(B) && isfinite(hi);
+            lv[4 * l] = A;
+            lv[4 * l + 1] = B;
+            lv[4 * l + 2] = lo;
+            lv[4 * l + 3] = hi;
+            prev = hi;
+        }
+    }
+    const bool all_ok = __all(ok);
+    if (lane == 0) {
+        m.l2_ok = all_ok ? 1u : 0u;
+        models[i] = m;
+    }
 }
 
 // Max sample load of every item under FMCD and under the two-level model (one workgroup per item).

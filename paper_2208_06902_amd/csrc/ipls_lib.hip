@@ -272,8 +272,8 @@ ipls_status train_l2pl(Depth& D, hipStream_t s, uint64_t ni, uint64_t max_S, uin
         (double*)D.leaf_last.p, ab_in, grad_out, loss_out, ab_out);
     LAUNCH_CHECK();
     if (ab_in) return IPLS_OK;
-    k_l2pl_envelope<<<(unsigned)((ni + 63) / 64), 64, 0, s>>>(ni, models, roots, (const uint32_t*)D.leaf_first.p, M,
-                                                             (double*)D.leaves.p, (const double*)D.leaf_last.p);
+    k_l2pl_envelope<<<(unsigned)ni, 64, 0, s>>>(ni, models, roots, (const uint32_t*)D.leaf_first.p, M,
+                                                (double*)D.leaves.p, (const double*)D.leaf_last.p);
     LAUNCH_CHECK();
     k_l2pl_load<DT><<<(unsigned)ni, 256, 0, s>>>(sample, sample_off, ni, models, roots, (const double*)D.leaves.p, K,
                                                  M);
@@ -778,7 +778,7 @@ void ipls_default_params(ipls_params* p) {
     p->seed = 0x1F5A220806902000ull;
     p->model = IPLS_MODEL_FMCD;
     p->leaves = 256;
-    p->train_iters = 32;
+    p->train_iters = 4;
     p->tile_keys = 0;
     p->sample_policy = 0;
 }

@@ -28,7 +28,7 @@ def gpu_sort(keys, payload=None, **kw):
 def oracle_params(**kw):
     m = dict(K=kw.get("num_buckets", 256), T=kw.get("base_case_max", 4096), divisor=kw.get("sample_divisor", 100),
              sample_min=kw.get("sample_min", 0), sample_max=kw.get("sample_max", 0),
-             model=kw.get("model", 0), leaves=kw.get("leaves", 256), train_iters=kw.get("train_iters", 32),
+             model=kw.get("model", 0), leaves=kw.get("leaves", 256), train_iters=kw.get("train_iters", 4),
              sample_policy=kw.get("sample_policy", 0))
     return oracle.params(**m)
 
