@@ -686,8 +686,8 @@ __global__ void k_finalize(const Item* items, Model* models, const Model* roots,
 }
 
 // ------------------------------------------------------------------ tiles and chunks
-// A level's keys are cut into tiles of 256 * IPT keys (IPT = 16 by default, 8 for the small
-// tiles the batched form may pick; tiles never cross items); kChunk
+// A level's keys are cut into tiles of 64 NW IPT keys (NW waves of 8 keys a thread: 2048 keys with
+// 4 waves, the default, or 4096 with 8; tiles never cross items); kChunk
 // consecutive tiles of an item form a chunk.  Counting, the prefix scan and the scatter all use
 // this layout:
 //   k_classify_hist: per chunk, the count of every (tile, bucket) -> the tile's exclusive prefix
@@ -699,9 +699,7 @@ __global__ void k_finalize(const Item* items, Model* models, const Model* roots,
 //                    prefix + rank inside the tile.
 // Nothing waits on another workgroup: on MI355X a decoupled look-back chain between tiles pays a
 // cross-XCD round trip per step, which measured at half the pass time.
-constexpr int kIPT = 16;
-constexpr int kTileKeys = kBlock * kIPT;
-constexpr int kSmallIPT = 8;
+constexpr int kPassIPT = 8;  // keys per thread of the counting and scatter kernels
 constexpr int kChunk = 16;
 
 // Wave-level counting of one tile's keys: wave w owns keys [w * 64 * IPT, (w+1) * 64 * IPT) of the
@@ -782,16 +780,16 @@ __device__ inline void classify_tile(uint32_t tn, uint32_t wbase, const Model& m
 // One workgroup per chunk.  For every tile of the chunk: classify, count per bucket, write the
 // tile's exclusive prefix inside the chunk (tile_pref[t][b]); at the end the chunk's totals
 // (chunk_sum[c][b]).
-template <int DT, int IPT>
-__global__ __launch_bounds__(256) void k_classify_hist(const Item* items, const uint64_t* tile_off,
+template <int DT, int NW, int IPT>
+__global__ __launch_bounds__(64 * NW) void k_classify_hist(const Item* items, const uint64_t* tile_off,
                                                        const uint64_t* chunk_off, const uint32_t* chunk_map,
                                                        uint64_t total_chunks, const Model* models,
                                                        const double* leaves, const typename Key<DT>::T* src,
                                                        uint32_t* tile_pref, uint32_t* chunk_sum, uint32_t K,
                                                        uint32_t M) {
     using T = typename Key<DT>::T;
-    constexpr int TILE = kBlock * IPT;
-    __shared__ uint32_t h[4][kMaxBuckets];
+    constexpr int NT = kWave * NW, TILE = NT * IPT;
+    __shared__ uint32_t h[NW][kMaxBuckets];
     __shared__ double s_leaf[4 * kMaxLeaves];
     const uint32_t tid = threadIdx.x, wave = tid / kWave;
     const uint64_t c = blockIdx.x;
@@ -811,8 +809,8 @@ __global__ __launch_bounds__(256) void k_classify_hist(const Item* items, const 
     uint32_t nop[1];
     if (counting) load_tile<DT, false, IPT>(src, nullptr, it.lo + (t_first - t0) * TILE, tile_n(t_first), wbase, cur, nop);
     if (m.kind == kKindL2pl)
-        for (uint32_t q = tid; q < 4 * M; q += kBlock) s_leaf[q] = leaves[(uint64_t)i * 4 * kMaxLeaves + q];
-    for (uint32_t b = tid; b < 4 * kMaxBuckets; b += kBlock) (&h[0][0])[b] = 0;
+        for (uint32_t q = tid; q < 4 * M; q += NT) s_leaf[q] = leaves[(uint64_t)i * 4 * kMaxLeaves + q];
+    for (uint32_t b = tid; b < NW * kMaxBuckets; b += NT) (&h[0][0])[b] = 0;
     __syncthreads();
     uint32_t run = 0;  // thread b's running count of bucket b over the chunk's tiles
     for (uint64_t t = t_first; t < t_end; ++t) {
@@ -831,8 +829,11 @@ __global__ __launch_bounds__(256) void k_classify_hist(const Item* items, const 
         __syncthreads();
         if (tid < K) {
             tile_pref[t * K + tid] = run;
-            run += h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
-            h[0][tid] = h[1][tid] = h[2][tid] = h[3][tid] = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                run += h[w][tid];
+                h[w][tid] = 0;
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -916,8 +917,8 @@ __device__ inline uint64_t xcd_tile(uint64_t g, uint64_t nt) {
     return x * q + (x < r ? x : r) + g / 8;
 }
 
-template <int DT, bool PAY, int IPT>
-__global__ __launch_bounds__(256) void k_scatter(const Item* items, const uint64_t* tile_off, const uint32_t* tile_map,
+template <int DT, bool PAY, int NW, int IPT>
+__global__ __launch_bounds__(64 * NW) void k_scatter(const Item* items, const uint64_t* tile_off, const uint32_t* tile_map,
                                                  uint64_t total_tiles, const uint64_t* chunk_off,
                                                  uint64_t total_chunks, const Model* models, const double* leaves,
                                                  const uint64_t* bstart, const uint64_t* chunk_pref,
@@ -925,8 +926,8 @@ __global__ __launch_bounds__(256) void k_scatter(const Item* items, const uint64
                                                  const uint32_t* src_pay, typename Key<DT>::T* dst, uint32_t* dst_pay,
                                                  uint32_t K, uint32_t M) {
     using T = typename Key<DT>::T;
-    constexpr int TILE = kBlock * IPT;
-    __shared__ uint32_t s_wcnt[4][kMaxBuckets];
+    constexpr int NT = kWave * NW, TILE = NT * IPT;
+    __shared__ uint32_t s_wcnt[NW][kMaxBuckets];
     __shared__ uint32_t s_loc[kMaxBuckets];
     __shared__ uint64_t s_base[kMaxBuckets];
     __shared__ uint64_t s_scan[16];
@@ -961,9 +962,9 @@ __global__ __launch_bounds__(256) void k_scatter(const Item* items, const uint64
         dbase = it.lo + bstart[(uint64_t)i * K + tid] + chunk_pref[c * K + tid] +
                 tile_pref[t * K + tid];
     if (m.kind == kKindL2pl)
-        for (uint32_t q = tid; q < 4 * M; q += kBlock)
+        for (uint32_t q = tid; q < 4 * M; q += NT)
             ((double*)s_stage)[q] = leaves[(uint64_t)i * 4 * kMaxLeaves + q];
-    for (uint32_t b = tid; b < 4 * kMaxBuckets; b += kBlock) (&s_wcnt[0][0])[b] = 0;
+    for (uint32_t b = tid; b < NW * kMaxBuckets; b += NT) (&s_wcnt[0][0])[b] = 0;
     __syncthreads();
     classify_tile<DT, IPT>(tn, wbase, m, s_leaf, K, M, k, bk);
     wave_count<IPT, true>(bk, tn, wbase, s_wcnt[wave], rk);
@@ -973,12 +974,12 @@ __global__ __launch_bounds__(256) void k_scatter(const Item* items, const uint64
     const uint32_t b = tid;
     uint32_t cnt = 0;
     if (b < K) {
-        const uint32_t c0 = s_wcnt[0][b], c1 = s_wcnt[1][b], c2 = s_wcnt[2][b], c3 = s_wcnt[3][b];
-        s_wcnt[0][b] = 0;
-        s_wcnt[1][b] = c0;
-        s_wcnt[2][b] = c0 + c1;
-        s_wcnt[3][b] = c0 + c1 + c2;
-        cnt = c0 + c1 + c2 + c3;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t cw = s_wcnt[w][b];
+            s_wcnt[w][b] = cnt;
+            cnt += cw;
+        }
     }
     uint64_t tot;
     const uint32_t loc = (uint32_t)block_exclusive_sum<uint64_t>(cnt, s_scan, &tot);
@@ -1001,7 +1002,7 @@ __global__ __launch_bounds__(256) void k_scatter(const Item* items, const uint64
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
-        const uint32_t j = tid + r * kBlock;
+        const uint32_t j = tid + r * NT;
         if (j < tn) {
             const uint64_t d = s_base[s_bkt[j]] + j;
             dst[d] = s_keys[j];

@@ -25,8 +25,8 @@ namespace {
 constexpr uint32_t kSmallS = kFitLds;  // samples up to this size are fitted in one workgroup's LDS
 constexpr uint32_t kFitChunk = 2048;   // windows per workgroup in the multi-round fit
 constexpr uint32_t kCand = 15;         // candidate widths per fit round
-constexpr uint32_t kTile = kTileKeys;
-constexpr uint32_t kSmallTile = kBlock * kSmallIPT;
+constexpr uint32_t kSmallTile = 4 * kWave * kPassIPT;  // 2048 keys: 4 waves
+constexpr uint32_t kTile = 8 * kWave * kPassIPT;       // 4096 keys: 8 waves
 
 // Keys per distribution tile: 2048 (the default: 8 keys a thread, twice the occupancy) or 4096.
 inline uint32_t tile_keys_of(const ipls_params& p) { return p.tile_keys == kTile ? kTile : kSmallTile; }
@@ -490,8 +490,8 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         LAUNCH_CHECK();
         {
             ProfScope ps(1, (double)pl.sum_n * kb, s);
-            auto kc = tile == kTile ? k_classify_hist<DT, kIPT> : k_classify_hist<DT, kSmallIPT>;
-            kc<<<(unsigned)nc, 256, 0, s>>>(
+            auto kc = tile == kTile ? k_classify_hist<DT, 8, kPassIPT> : k_classify_hist<DT, 4, kPassIPT>;
+            kc<<<(unsigned)nc, tile / kPassIPT, 0, s>>>(
                 items, (const uint64_t*)D.tile_off.p, (const uint64_t*)D.chunk_off.p, (const uint32_t*)D.chunk_map.p,
                 nc, models, (const double*)D.leaves.p, src, (uint32_t*)D.tile_pref.p, (uint32_t*)D.chunk_sum.p, K,
                 P.leaves);
@@ -514,8 +514,8 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         // scatter
         {
             ProfScope ps(0, (double)pl.sum_n * 2.0 * (kb + (PAY ? 4 : 0)), s);
-            auto ks = tile == kTile ? k_scatter<DT, PAY, kIPT> : k_scatter<DT, PAY, kSmallIPT>;
-            ks<<<(unsigned)nt, 256, 0, s>>>(
+            auto ks = tile == kTile ? k_scatter<DT, PAY, 8, kPassIPT> : k_scatter<DT, PAY, 4, kPassIPT>;
+            ks<<<(unsigned)nt, tile / kPassIPT, 0, s>>>(
                 items, (const uint64_t*)D.tile_off.p, (const uint32_t*)D.tile_map.p, nt, (const uint64_t*)D.chunk_off.p,
                 nc, models, (const double*)D.leaves.p, (const uint64_t*)D.bstart.p, (const uint64_t*)D.chunk_pref.p,
                 (const uint32_t*)D.tile_pref.p, src, psrc, dst, pdst, K, P.leaves);
