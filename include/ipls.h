@@ -65,7 +65,7 @@ typedef struct {
     uint32_t model;          /* ipls_model_policy */
     uint32_t leaves;         /* leaves M of the two-level model, 4..256 (default 256) */
     uint32_t train_iters;    /* gradient steps of the two-level model (default 4; each a Newton step) */
-    uint32_t tile_keys;      /* keys per distribution tile: 2048 (0 = default) or 4096 */
+    uint32_t tile_keys;      /* keys per distribution tile: 4096 (0 = default) or 2048 */
     uint32_t sample_policy;  /* 0: the divisor rule above (Learned Sort's 1% sample, Background chapter);
                               * 1: IPLS's alpha*K - 1 with alpha = 0.2 log2(n), rounded to nearest,
                               *    at most ceil(n/2) (Proposed Algorithm chapter) */
@@ -92,7 +92,7 @@ typedef struct {
     uint64_t keys_partitioned;  /* sum over levels of keys that went through a distribution pass */
 } ipls_stats;
 
-/* Defaults: K 256, T 4096, divisor 100, sample_min 2K, no cap, FMCD, M 256, 4 steps, tile 2048, policy 0. */
+/* Defaults: K 256, T 4096, divisor 100, sample_min 2K, no cap, FMCD, M 256, 4 steps, tile 4096, policy 0. */
 void ipls_default_params(ipls_params* p);
 
 /* Sort keys[0..n) (and payload[0..n) when non-null, stably) in place with default parameters.
@@ -161,7 +161,7 @@ void ipls_profile_read(int kernel, uint64_t* launches, double* ms, double* bytes
  * Picks num_buckets (K), base_case_max (T) and tile_keys for the segmented sort of a batch shaped
  * like the given one.  It times ipls_sort_segmented on a window of the batch's leading segments
  * (at least 2^25 keys, or all of them), copied to a private buffer so the caller's keys are not
- * modified, and walks the candidates one parameter at a time: tile_keys in {2048, 4096}, then T in
+ * modified, and walks the candidates one parameter at a time: tile_keys in {4096, 2048}, then T in
  * {4096, 2048, 1024}, then K in {256, 128, 64}, keeping each best.  The result is a sort of the
  * same keys (the output of a sort does not depend on these parameters); only its speed changes.
  * keys, seg_offsets: device (as ipls_sort_segmented); base: the other parameters (NULL =

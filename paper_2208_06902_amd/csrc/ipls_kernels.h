@@ -687,7 +687,7 @@ __global__ void k_finalize(const Item* items, Model* models, const Model* roots,
 
 // ------------------------------------------------------------------ tiles and chunks
 // A level's keys are cut into tiles of 64 NW IPT keys (NW waves of 8 keys a thread: 2048 keys with
-// 4 waves, the default, or 4096 with 8; tiles never cross items); kChunk
+// 4 waves, or 4096 with 8, the default; tiles never cross items); kChunk
 // consecutive tiles of an item form a chunk.  Counting, the prefix scan and the scatter all use
 // this layout:
 //   k_classify_hist: per chunk, the count of every (tile, bucket) -> the tile's exclusive prefix
@@ -787,9 +787,12 @@ __global__ __launch_bounds__(64 * NW) void k_classify_hist(const Item* items, co
                                                        const double* leaves, const typename Key<DT>::T* src,
                                                        uint32_t* tile_pref, uint32_t* chunk_sum, uint32_t K,
                                                        uint32_t M) {
+    // Every tile of the chunk has its own LDS histogram, so the waves count tile after tile (the
+    // next tile's keys are loaded while this one is counted) with no barrier in between; one
+    // barrier at the end, then thread b turns bucket b's counts into the tiles' prefixes.
     using T = typename Key<DT>::T;
     constexpr int NT = kWave * NW, TILE = NT * IPT;
-    __shared__ uint32_t h[NW][kMaxBuckets];
+    __shared__ uint32_t h[kChunk][kMaxBuckets];
     __shared__ double s_leaf[4 * kMaxLeaves];
     const uint32_t tid = threadIdx.x, wave = tid / kWave;
     const uint64_t c = blockIdx.x;
@@ -810,36 +813,32 @@ __global__ __launch_bounds__(64 * NW) void k_classify_hist(const Item* items, co
     if (counting) load_tile<DT, false, IPT>(src, nullptr, it.lo + (t_first - t0) * TILE, tile_n(t_first), wbase, cur, nop);
     if (m.kind == kKindL2pl)
         for (uint32_t q = tid; q < 4 * M; q += NT) s_leaf[q] = leaves[(uint64_t)i * 4 * kMaxLeaves + q];
-    for (uint32_t b = tid; b < NW * kMaxBuckets; b += NT) (&h[0][0])[b] = 0;
+    for (uint32_t b = tid; b < kChunk * kMaxBuckets; b += NT) (&h[0][0])[b] = 0;
     __syncthreads();
-    uint32_t run = 0;  // thread b's running count of bucket b over the chunk's tiles
     for (uint64_t t = t_first; t < t_end; ++t) {
-        const uint32_t tn = tile_n(t);
-        // prefetch the next tile while this one is counted
+        const uint32_t tn = tile_n(t), q = (uint32_t)(t - t_first);
         if (counting && t + 1 < t_end)
             load_tile<DT, false, IPT>(src, nullptr, it.lo + (t + 1 - t0) * TILE, tile_n(t + 1), wbase, nxt, nop);
         if (counting) {
 #pragma unroll
             for (int r = 0; r < IPT; ++r)
                 if (wbase + r * kWave + lane_id() < tn)
-                    atomicAdd(&h[wave][classify_key<DT>(m, s_leaf, K, M, cur[r])], 1u);
+                    atomicAdd(&h[q][classify_key<DT>(m, s_leaf, K, M, cur[r])], 1u);
         } else if (m.kind == kKindClosedMove && tid == 0) {
-            h[0][0] = tn;
+            h[q][0] = tn;
         }
-        __syncthreads();
-        if (tid < K) {
-            tile_pref[t * K + tid] = run;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                run += h[w][tid];
-                h[w][tid] = 0;
-            }
-        }
-        __syncthreads();
 #pragma unroll
         for (int r = 0; r < IPT; ++r) cur[r] = nxt[r];
     }
-    if (tid < K) chunk_sum[c * K + tid] = run;
+    __syncthreads();
+    if (tid < K) {
+        uint32_t run = 0;  // bucket tid's running count over the chunk's tiles
+        for (uint64_t t = t_first; t < t_end; ++t) {
+            tile_pref[t * K + tid] = run;
+            run += h[t - t_first][tid];
+        }
+        chunk_sum[c * K + tid] = run;
+    }
 }
 
 // Exclusive prefix of every item's chunk totals, per bucket (chunk_pref[c][b]); the total is the

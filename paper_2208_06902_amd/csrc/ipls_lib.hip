@@ -28,8 +28,8 @@ constexpr uint32_t kCand = 15;         // candidate widths per fit round
 constexpr uint32_t kSmallTile = 4 * kWave * kPassIPT;  // 2048 keys: 4 waves
 constexpr uint32_t kTile = 8 * kWave * kPassIPT;       // 4096 keys: 8 waves
 
-// Keys per distribution tile: 2048 (the default: 8 keys a thread, twice the occupancy) or 4096.
-inline uint32_t tile_keys_of(const ipls_params& p) { return p.tile_keys == kTile ? kTile : kSmallTile; }
+// Keys per distribution tile: 4096 (8 waves, the default) or 2048 (4 waves); 8 keys a thread.
+inline uint32_t tile_keys_of(const ipls_params& p) { return p.tile_keys == kSmallTile ? kSmallTile : kTile; }
 constexpr int kMaxLevels = 4096;
 constexpr int kMaxDepth = 16;
 

@@ -55,7 +55,7 @@ extern "C" ipls_status ipls_autotune_segmented(const void* keys, const uint64_t*
     ipls_params p0;
     if (base) p0 = *base;
     else ipls_default_params(&p0);
-    if (p0.tile_keys == 0) p0.tile_keys = 2048;  // the library default, named
+    if (p0.tile_keys == 0) p0.tile_keys = 4096;  // the library default, named
     hipStream_t s = (hipStream_t)stream;
     std::vector<uint64_t> off(nseg + 1);
     if (hipMemcpyAsync(off.data(), seg_offsets, (nseg + 1) * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -113,7 +113,7 @@ extern "C" ipls_status ipls_autotune_segmented(const void* keys, const uint64_t*
         trials = 1;
         if (best_ms < 0) st = IPLS_ERR_HIP;
     }
-    const uint32_t tiles[] = {2048, 4096}, thresholds[] = {4096, 2048, 1024}, buckets[] = {256, 128, 64};
+    const uint32_t tiles[] = {4096, 2048}, thresholds[] = {4096, 2048, 1024}, buckets[] = {256, 128, 64};
     for (int dim = 0; dim < 3 && st == IPLS_OK; ++dim) {
         const uint32_t* cand = dim == 0 ? tiles : dim == 1 ? thresholds : buckets;
         const int nc = dim == 0 ? 2 : 3;

@@ -58,7 +58,7 @@ def test_sort_f64_default_params(dist):
 @pytest.mark.parametrize("kw", [dict(num_buckets=16, base_case_max=64), dict(num_buckets=64, base_case_max=200),
                                 dict(num_buckets=4, base_case_max=8, sample_min=8),
                                 dict(num_buckets=256, base_case_max=1000, sample_divisor=7),
-                                dict(tile_keys=4096), dict(tile_keys=4096, num_buckets=64, base_case_max=1024)])
+                                dict(tile_keys=2048), dict(tile_keys=2048, num_buckets=64, base_case_max=1024)])
 def test_sort_f64_params(dist, kw):
     check_sort(gen.make(dist, 50_000, 5), **kw)
 
@@ -82,7 +82,7 @@ def test_sort_u64_uniform_and_zipf_payload():
 def test_sort_f32_with_payload(dist):
     k = gen.make(dist, 200_000, 9).astype(np.float32)
     check_sort(k, gen.index_payload(k.size), num_buckets=64, base_case_max=512)
-    check_sort(k, gen.index_payload(k.size), tile_keys=4096)
+    check_sort(k, gen.index_payload(k.size), tile_keys=2048)
 
 
 def test_payload_stability_heavy_duplicates():
