@@ -700,7 +700,7 @@ __global__ void k_finalize(const Item* items, Model* models, const Model* roots,
 // Nothing waits on another workgroup: on MI355X a decoupled look-back chain between tiles pays a
 // cross-XCD round trip per step, which measured at half the pass time.
 constexpr int kPassIPT = 8;  // keys per thread of the counting and scatter kernels
-constexpr int kChunk = 16;
+constexpr int kChunk = 8;
 
 // Wave-level counting of one tile's keys: wave w owns keys [w * 64 * IPT, (w+1) * 64 * IPT) of the
 // tile, row r = 64 consecutive keys.  Lanes of a row holding the same bucket are found with 8
