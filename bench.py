@@ -157,6 +157,70 @@ def _u64_sorted(t, torch):
     return bool((v[1:] >= v[:-1]).all())
 
 
+def bench_large_u64(args):
+    """Single-array sorts of uint64 keys drawn on the device: 1e9 uniform keys, keys only, or 2e8
+    Zipf(1.1) ranks over [1, 2^32] with their uint32 index as payload (stable).  Each step sorts a
+    fresh copy of the input (staged before the step); the output of the last step is checked to be
+    non-decreasing, and a permutation of the input (against a device sort), with the payload
+    pointing at equal keys."""
+    import numpy as np
+    import torch
+
+    import gen.device as gdev
+    import paper_2208_06902_amd as ipls
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    zipf = args.workload == "zipf"
+    n = 200_000_000 if zipf else 1_000_000_000
+    print(f"# {args.workload}: drawing {n} keys on the device", file=sys.stderr, flush=True)
+    src = gdev.zipf_u64(n, 8) if zipf else gdev.u64_uniform(n, 7)
+    work = torch.empty_like(src)
+    pay0 = torch.arange(n, dtype=torch.int32, device=dev) if zipf else None
+    pay = torch.empty_like(pay0) if zipf else None
+    params = ipls.default_params(sample_max=args.sample_max)
+    stream = torch.cuda.current_stream()
+    ipls.profile_enable(True)
+    ms, stats = [], None
+    for step in range(args.warmup + args.steps):
+        work.copy_(src)
+        if zipf:
+            pay.copy_(pay0)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        if step == args.warmup:
+            ipls.profile_enable(True)
+        a.record(stream)
+        stats = ipls.sort_(work.view(torch.uint64), pay, params, stats=True)
+        b.record(stream)
+        torch.cuda.synchronize()
+        if step >= args.warmup:
+            ms.append(a.elapsed_time(b))
+    sc_n, sc_ms, sc_bytes = ipls.profile_read(ipls.KERNEL_SCATTER)
+    ipls.profile_enable(False)
+    flip = torch.tensor(-(2**63), dtype=torch.int64, device=dev)
+    got = torch.bitwise_xor(work, flip)
+    ok = bool((got[1:] >= got[:-1]).all())
+    ref = torch.sort(torch.bitwise_xor(src, flip)).values
+    ok = ok and torch.equal(ref, got)
+    del ref
+    if zipf:
+        ok = ok and torch.equal(src[pay.long()], work)
+    mean_ms = sum(ms) / len(ms)
+    sc_gbs = sc_bytes / (sc_ms / 1e3) / 1e9 if sc_ms > 0 else None
+    desc = ("plain key+payload sort, 200000000 uint64 Zipf(1.1) ranks over [1, 2^32] with a uint32 index payload, stable"
+            if zipf else "plain single-array sort, 1000000000 uniform uint64 keys, keys only")
+    line = _line(n / (mean_ms / 1e3), mean_ms, args.steps, args.warmup, "u64",
+                 {"workload": desc, "n": n, "num_buckets": 256, "base_case_max": 4096,
+                  "sample": f"1% jittered stratified, capped at {args.sample_max} keys", "model": "FMCD",
+                  "parallelism": "single GPU"},
+                 roofline={"kernel": "k_scatter", "bound": "hbm",
+                           "achieved": round(sc_gbs, 1) if sc_gbs else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(sc_gbs / HBM_PEAK_GBS, 4) if sc_gbs else None, "traffic": None,
+                           "launches": sc_n},
+                 stats={k: int(v) for k, v in stats.items()}, outputs_sorted=ok)
+    print(json.dumps(line), flush=True)
+
+
 def bench_batched(args):
     """Batched form: 100,000 fp64 arrays with lognormal sizes (median 4096, sigma 1.39, clipped to
     [64, 1e7]), each drawn from one of six distributions chosen per array by seed, sorted by one
@@ -378,8 +442,9 @@ def main():
     ap.add_argument("--sample-max", type=int, default=4096)
     ap.add_argument("--tile-keys", type=int, default=0, help="keys per distribution tile (0 = library default)")
     ap.add_argument("--sort-model", type=int, default=0, help="sort: 0 FMCD (default), 1 auto, 2 learned")
-    ap.add_argument("--workload", choices=("sort", "batched", "served"), default="sort",
-                    help="sort: the 1e8 fp64 single-array sort (default); batched; served")
+    ap.add_argument("--workload", choices=("sort", "u64", "zipf", "batched", "served"), default="sort",
+                    help="sort: the 1e8 fp64 single-array sort (default); u64: 1e9 uniform uint64 keys; "
+                         "zipf: 2e8 Zipf(1.1) uint64 keys with a uint32 index payload; batched; served")
     ap.add_argument("--arrays", type=int, default=100_000, help="batched: number of arrays")
     ap.add_argument("--plain-keys", type=int, default=50_000_000, help="batched: keys of the per-array subset")
     ap.add_argument("--requests", type=int, default=4000, help="served: number of requests")
@@ -397,6 +462,8 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU form is not built",
               file=sys.stderr, flush=True)
         sys.exit(2)
+    if args.workload in ("u64", "zipf"):
+        return bench_large_u64(args)
     if args.workload == "batched":
         return bench_batched(args)
     if args.workload == "served":

@@ -754,8 +754,10 @@ __device__ inline void load_tile(const typename Key<DT>::T* src, const uint32_t*
     for (int r = 0; r < IPT; ++r) {
         const uint32_t idx = wbase + r * kWave + lane;
         if (idx < tn) {
-            k[r] = src[base + idx];
-            if (PAY) p[r] = src_pay[base + idx];
+            // streamed once: non-temporal loads (non-temporal stores measured slower: the
+            // scatter's partial-line runs need the L2 to combine them)
+            k[r] = __builtin_nontemporal_load(&src[base + idx]);
+            if (PAY) p[r] = __builtin_nontemporal_load(&src_pay[base + idx]);
         }
     }
 }
@@ -1190,8 +1192,8 @@ __global__ __launch_bounds__(256) void k_base_sort(const BaseItem* list, uint64_
         for (int r = 0; r < IPT; ++r) {
             const int j = t + r * NT;
             if (j < (int)n) {
-                v[r] = src[bi.lo + j];
-                if (PAY) pv[r] = psrc[bi.lo + j];
+                v[r] = __builtin_nontemporal_load(&src[bi.lo + j]);
+                if (PAY) pv[r] = __builtin_nontemporal_load(&psrc[bi.lo + j]);
             }
         }
 #pragma unroll
@@ -1303,8 +1305,8 @@ __device__ inline void base_large_stable(const BaseItem& bi, typename Key<DT>::T
         for (int r = 0; r < IPT; ++r) {
             const uint32_t j = wbase + r * kWave + lane;
             if (j < n) {
-                v[r] = src[bi.lo + j];
-                p[r] = PAY ? psrc[bi.lo + j] : 0u;
+                v[r] = __builtin_nontemporal_load(&src[bi.lo + j]);
+                p[r] = PAY ? __builtin_nontemporal_load(&psrc[bi.lo + j]) : 0u;
             }
         }
 #pragma unroll
@@ -1448,7 +1450,7 @@ __device__ inline void base_large_keys(const BaseItem& bi, typename Key<DT>::T* 
 #pragma unroll
         for (int r = 0; r < IPT; ++r) {
             const uint32_t j = wbase + r * kWave + lane;
-            if (j < n) v[r] = src[bi.lo + j];
+            if (j < n) v[r] = __builtin_nontemporal_load(&src[bi.lo + j]);
         }
 #pragma unroll
         for (int r = 0; r < IPT; ++r) o[r] = wbase + r * kWave + lane < n ? (O)KT::ord(v[r]) : kPad;
