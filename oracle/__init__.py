@@ -25,13 +25,15 @@ _DT = {np.dtype(np.float64): F64, np.dtype(np.float32): F32, np.dtype(np.uint64)
 class Params(C.Structure):
     _fields_ = [("num_buckets", C.c_uint32), ("base_case_max", C.c_uint32), ("sample_divisor", C.c_uint32),
                 ("sample_min", C.c_uint32), ("sample_max", C.c_uint64), ("seed", C.c_uint64),
-                ("model", C.c_uint32), ("leaves", C.c_uint32), ("train_iters", C.c_uint32), ("sample_policy", C.c_uint32)]
+                ("model", C.c_uint32), ("leaves", C.c_uint32), ("train_iters", C.c_uint32), ("sample_policy", C.c_uint32),
+                ("equality", C.c_uint32), ("pad_", C.c_uint32)]
 
 
 class Model(C.Structure):
     _fields_ = [("kind", C.c_uint32), ("K", C.c_uint32), ("a", C.c_double), ("b", C.c_double), ("D", C.c_uint64),
                 ("umin", C.c_uint64), ("shift", C.c_uint32), ("degenerate", C.c_uint32), ("S", C.c_uint64),
-                ("max_load_linear", C.c_uint64), ("max_load_l2pl", C.c_uint64)]
+                ("max_load_linear", C.c_uint64), ("max_load_l2pl", C.c_uint64), ("neq", C.c_uint32),
+                ("Km", C.c_uint32), ("const0", C.c_uint32), ("pad_", C.c_uint32), ("heavy", C.c_uint64 * 16)]
 
 
 class Stats(C.Structure):
@@ -47,8 +49,8 @@ DEFAULT_SEED = 0x1F5A_2208_0690_2000
 
 
 def params(K=256, T=4096, divisor=100, sample_min=0, sample_max=0, seed=DEFAULT_SEED, model=0, leaves=256,
-           train_iters=4, sample_policy=0) -> Params:
-    return Params(K, T, divisor, sample_min, sample_max, seed, model, leaves, train_iters, sample_policy)
+           train_iters=4, sample_policy=0, equality=0) -> Params:
+    return Params(K, T, divisor, sample_min, sample_max, seed, model, leaves, train_iters, sample_policy, equality, 0)
 
 
 def build(force: bool = False) -> str:

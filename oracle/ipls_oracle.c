@@ -54,6 +54,8 @@ typedef struct {
     uint32_t leaves;         /* M leaves of the two-level model */
     uint32_t train_iters;    /* gradient steps of the two-level model */
     uint32_t sample_policy;  /* 0: S = ceil(n / divisor); 1: the paper's alpha*K - 1 */
+    uint32_t equality;       /* 1: equality buckets for heavy sample values (IPS4o) */
+    uint32_t pad_;
 } oracle_params;
 
 typedef struct {
@@ -67,6 +69,11 @@ typedef struct {
     uint64_t S; /* sample size the model was fitted on */
     uint64_t max_load_linear; /* max sample load of the FMCD model (model=auto only) */
     uint64_t max_load_l2pl;   /* max sample load of the two-level model (model=auto only) */
+    uint32_t neq;             /* equality buckets: number of heavy sample values (0 = none) */
+    uint32_t Km;              /* buckets of the linear part when neq > 0: K - 2 neq */
+    uint32_t const0;          /* linear part unusable: every other key is in linear bucket 0 */
+    uint32_t pad_;
+    uint64_t heavy[16];       /* the heavy values' ords, ascending */
 } oracle_model;
 
 typedef struct {
@@ -229,16 +236,23 @@ static double val_from_ord(uint64_t o, int dtype) {
 }
 
 /* Sorted sample of a bucket as fp64 values x[0..S): gather, sort by ord, map to val. */
-void oracle_sorted_sample(const void* keys, uint64_t n, int dtype, uint64_t lo_rel, uint64_t S, uint64_t seed,
-                          double* x) {
-    uint64_t* pos = (uint64_t*)malloc(S * sizeof(uint64_t));
-    uint64_t* ords = (uint64_t*)malloc(S * sizeof(uint64_t));
+/* The sorted sample as ords (ords_out, nullable) and as the fp64 values the models see (x). */
+static void sorted_sample_ords(const void* keys, uint64_t n, int dtype, uint64_t lo_rel, uint64_t S, uint64_t seed,
+                               double* x, uint64_t* ords_out) {
+    uint64_t* pos = (uint64_t*)malloc((S ? S : 1) * sizeof(uint64_t));
+    uint64_t* ords = (uint64_t*)malloc((S ? S : 1) * sizeof(uint64_t));
     oracle_sample_positions(n, lo_rel, S, seed, pos);
     for (uint64_t j = 0; j < S; ++j) ords[j] = oracle_ord_one(keys, pos[j], dtype);
     qsort(ords, S, sizeof(uint64_t), cmp_u64);
     for (uint64_t j = 0; j < S; ++j) x[j] = val_from_ord(ords[j], dtype);
+    if (ords_out) memcpy(ords_out, ords, S * sizeof(uint64_t));
     free(pos);
     free(ords);
+}
+
+void oracle_sorted_sample(const void* keys, uint64_t n, int dtype, uint64_t lo_rel, uint64_t S, uint64_t seed,
+                          double* x) {
+    sorted_sample_ords(keys, n, dtype, lo_rel, S, seed, x, NULL);
 }
 
 /* ---------------------------------------------------------------- FMCD (Linear Models section) */
@@ -504,6 +518,58 @@ static uint32_t bitlen(uint64_t v) {
 
 /* Model of the bucket keys[0..n) whose first key sits at offset lo_rel of its array.
  * l2 receives the two-level model when it is chosen (its leaf array is owned by the caller). */
+/* Equality buckets (IPS4o; applied to the linear model): a value whose run in the sorted sample
+ * is longer than S/K (run * K > S) is heavy; at most min(16, (K-4)/2) of them, the smallest
+ * first.  The linear part is fitted by FMCD on the sample without the heavy runs, with K - 2E
+ * buckets; when that fit is unusable every other key goes to linear bucket 0.  A sample of one
+ * value only (E = 1 and nothing else) is left to the degenerate handling (closure or digit split),
+ * which guarantees progress.  Returns 1 when equality buckets are used (m filled). */
+static int fit_equality(const double* x, const uint64_t* o, uint64_t S, uint32_t K, oracle_model* m) {
+    uint32_t emax = (K - 4) / 2;
+    if (emax > 16) emax = 16;
+    uint32_t E = 0;
+    uint64_t heavy_keys = 0;
+    uint64_t run_lo[16], run_hi[16];
+    for (uint64_t j = 0; j < S;) {
+        uint64_t r = j;
+        while (r < S && o[r] == o[j]) ++r;
+        if ((r - j) * (uint64_t)K > S && E < emax) {
+            m->heavy[E] = o[j];
+            run_lo[E] = j;
+            run_hi[E] = r;
+            heavy_keys += r - j;
+            ++E;
+        }
+        j = r;
+    }
+    if (E == 0 || (E == 1 && heavy_keys == S)) return 0;
+    const uint64_t Sr = S - heavy_keys;
+    double* xr = (double*)malloc((Sr ? Sr : 1) * sizeof(double));
+    uint64_t q = 0;
+    for (uint64_t j = 0, e = 0; j < S; ++j) {
+        while (e < E && j >= run_hi[e]) ++e;
+        if (e < E && j >= run_lo[e]) continue;  /* inside heavy run e */
+        xr[q++] = x[j];
+    }
+    m->neq = E;
+    m->Km = K - 2 * E;
+    m->kind = MODEL_LINEAR;
+    m->degenerate = 0;
+    m->const0 = 1;
+    if (Sr >= 3 && isfinite(xr[0]) && isfinite(xr[Sr - 1])) {
+        double a, b;
+        uint64_t D;
+        if (oracle_fmcd(xr, Sr, m->Km, &a, &b, &D) == 0 && a > 0.0 && isfinite(a) && isfinite(b)) {
+            m->a = a;
+            m->b = b;
+            m->D = D;
+            m->const0 = 0;
+        }
+    }
+    free(xr);
+    return 1;
+}
+
 static void fit_bucket(const void* keys, uint64_t n, int dtype, const oracle_params* p, uint64_t lo_rel,
                        oracle_model* m, l2pl_model* l2, double* l2_leaf) {
     uint32_t K = p->num_buckets;
@@ -512,7 +578,14 @@ static void fit_bucket(const void* keys, uint64_t n, int dtype, const oracle_par
     uint64_t S = oracle_sample_size(n, p);
     m->S = S;
     double* x = (double*)malloc((S ? S : 1) * sizeof(double));
-    oracle_sorted_sample(keys, n, dtype, lo_rel, S, p->seed, x);
+    uint64_t* o = (uint64_t*)malloc((S ? S : 1) * sizeof(uint64_t));
+    sorted_sample_ords(keys, n, dtype, lo_rel, S, p->seed, x, o);
+    if (p->equality && fit_equality(x, o, S, K, m)) {
+        free(x);
+        free(o);
+        return;
+    }
+    free(o);
     int degenerate = 1;
     if (S >= 3 && isfinite(x[0]) && isfinite(x[S - 1])) {
         double a, b;
@@ -577,11 +650,27 @@ static void fit_bucket(const void* keys, uint64_t n, int dtype, const oracle_par
     free(x);
 }
 
+/* Equality buckets (IPS4o's, for keys repeated often in the sample): with heavy values
+ * h_0 < ... < h_(E-1) the linear part has K - 2E buckets, and a key goes to
+ *   linear bucket + 2 * #{e : h_e < key} + [key is some h_e],
+ * which keeps the buckets in key order: each heavy value gets a bucket of its own between the
+ * keys below it and the keys above it. */
+static uint32_t classify_equality(const oracle_model* m, uint64_t o, double v, int neg) {
+    uint32_t less = 0, eq = 0;
+    for (uint32_t e = 0; e < m->neq; ++e) {
+        less += m->heavy[e] < o ? 1u : 0u;
+        eq |= m->heavy[e] == o ? 1u : 0u;
+    }
+    uint32_t b = m->const0 ? 0u : classify_linear(m->a, m->b, m->Km, v, neg);
+    return b + 2u * less + eq;
+}
+
 static uint32_t classify_key(const void* keys, uint64_t i, int dtype, const oracle_model* m, const l2pl_model* l2) {
     if (m->kind == MODEL_MSD) return (uint32_t)((oracle_ord_one(keys, i, dtype) - m->umin) >> m->shift);
     double v = oracle_val_one(keys, i, dtype);
     int neg = key_negative(keys, i, dtype);
     if (m->kind == MODEL_L2PL) return classify_l2pl(l2, m->K, v, neg);
+    if (m->neq) return classify_equality(m, oracle_ord_one(keys, i, dtype), v, neg);
     return classify_linear(m->a, m->b, m->K, v, neg);
 }
 
