@@ -69,6 +69,10 @@ typedef struct {
     uint32_t sample_policy;  /* 0: the divisor rule above (Learned Sort's 1% sample, Background chapter);
                               * 1: IPLS's alpha*K - 1 with alpha = 0.2 log2(n), rounded to nearest,
                               *    at most ceil(n/2) (Proposed Algorithm chapter) */
+    uint32_t equality;       /* 1: equality buckets (IPS4o's, applied to the linear model): a value whose
+                              * run in the sorted sample is longer than S/K gets a bucket of its own (at
+                              * most min(16, (K-4)/2) of them); the linear part is fitted on the sample
+                              * without those runs with K - 2E buckets.  0 (default): the paper's IPLS */
 } ipls_params;
 
 /* FMCD linear model of a sample: bucket(x) = clamp(floor(fma(a, x, b)), 0, K-1). */

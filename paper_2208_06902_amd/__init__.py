@@ -38,7 +38,8 @@ class Params(C.Structure):
     _fields_ = [("num_buckets", C.c_uint32), ("base_case_max", C.c_uint32), ("sample_divisor", C.c_uint32),
                 ("sample_min", C.c_uint32), ("sample_max", C.c_uint64), ("seed", C.c_uint64),
                 ("model", C.c_uint32), ("leaves", C.c_uint32), ("train_iters", C.c_uint32),
-                ("tile_keys", C.c_uint32), ("sample_policy", C.c_uint32)]
+                ("tile_keys", C.c_uint32), ("sample_policy", C.c_uint32),
+                ("equality", C.c_uint32)]
 
 
 class LinearModel(C.Structure):

@@ -40,6 +40,8 @@ struct BaseItem {
 };
 
 // Model of one bucket, produced by the fit kernels, read by classification.
+constexpr int kMaxHeavy = 16;  // equality buckets per partitioned bucket
+
 struct Model {
     uint32_t kind, shift;
     double a, b;                 // linear: t = fma(a, val, b); also the two-level model's root
@@ -47,6 +49,17 @@ struct Model {
     uint64_t umin, umax;         // ord range (degenerate fits only)
     uint64_t load_lin, load_l2;  // max sample load of FMCD and of the two-level model
     uint32_t l2_ok, pad;
+    // equality buckets: neq heavy values (ords, ascending); the linear part has km buckets, or
+    // sends every other key to bucket 0 (const0)
+    uint32_t neq, km, const0, pad2;
+    uint64_t heavy[kMaxHeavy];
+};
+
+// Heavy values of an item's sorted sample and the length of the sample without their runs.
+struct EqInfo {
+    uint32_t neq, km;
+    uint64_t sr;
+    uint64_t heavy[kMaxHeavy];
 };
 
 // Level plan, computed on the device from the item list and read back by the host.
@@ -207,6 +220,25 @@ __device__ inline uint32_t classify_l2pl(double ra, double rb, uint32_t M, const
     return (uint32_t)t;
 }
 
+// Equality buckets (IPS4o's): with heavy values h_0 < ... < h_(E-1) a key goes to
+// linear bucket (of km) + 2 #{e : h_e < key} + [key is some h_e]; the buckets stay in key order
+// and each heavy value has one of its own.
+template <int DT>
+__device__ inline uint32_t classify_equality(const Model& m, typename Key<DT>::T u) {
+    using KT = Key<DT>;
+    const uint64_t o = KT::ord(u);
+    uint32_t less = 0, eq = 0;
+#pragma unroll
+    for (int e = 0; e < kMaxHeavy; ++e) {
+        if ((uint32_t)e < m.neq) {
+            less += m.heavy[e] < o ? 1u : 0u;
+            eq |= m.heavy[e] == o ? 1u : 0u;
+        }
+    }
+    const uint32_t b = m.const0 ? 0u : classify_linear(m.a, m.b, m.km, KT::val(u), KT::neg(u));
+    return b + 2u * less + eq;
+}
+
 template <int DT>
 __device__ inline uint32_t classify_key(const Model& m, const double* leaf, uint32_t K, uint32_t M,
                                         typename Key<DT>::T u) {
@@ -215,7 +247,9 @@ __device__ inline uint32_t classify_key(const Model& m, const double* leaf, uint
         case kKindDigit: return (uint32_t)((KT::ord(u) - m.umin) >> m.shift);
         case kKindClosedMove: return 0u;
         case kKindL2pl: return classify_l2pl(m.a, m.b, M, leaf, K, KT::val(u), KT::neg(u));
-        default: return classify_linear(m.a, m.b, K, KT::val(u), KT::neg(u));
+        default:
+            if (m.neq) return classify_equality<DT>(m, u);
+            return classify_linear(m.a, m.b, K, KT::val(u), KT::neg(u));
     }
 }
 

@@ -206,12 +206,15 @@ constexpr int kFitLds = 16384;
 
 template <int DT>
 __global__ __launch_bounds__(256) void k_fmcd_small(const typename Key<DT>::T* sample, const uint64_t* sample_off,
-                                                    uint64_t num_items, Model* models, uint32_t K, uint32_t small_S) {
+                                                    uint64_t num_items, Model* models, uint32_t K_all, uint32_t small_S,
+                                                    const EqInfo* eq) {
     __shared__ double sx[kFitLds];
     using KT = Key<DT>;
     const uint64_t i = blockIdx.x;
     if (i >= num_items) return;
-    const uint64_t off = sample_off[i], S = sample_off[i + 1] - off;
+    // with equality buckets: the sample without heavy runs, and K - 2E buckets
+    const uint64_t off = sample_off[i], S = eq ? eq[i].sr : sample_off[i + 1] - off;
+    const uint32_t K = eq ? eq[i].km : K_all;
     if (S > small_S) return;
     for (uint64_t j = threadIdx.x; j < S; j += blockDim.x) sx[j] = KT::val(sample[off + j]);
     __syncthreads();
@@ -276,13 +279,15 @@ __device__ inline void fmcd_replay(const uint64_t* masks, int rounds, uint64_t D
 template <int DT>
 __global__ __launch_bounds__(256) void k_fmcd_round(const typename Key<DT>::T* sample, const uint64_t* sample_off,
                                                     const uint64_t* fit_off, const uint32_t* fit_map, uint64_t* masks,
-                                                    int max_rounds, int round, uint32_t K, uint32_t chunk,
-                                                    uint32_t cand) {
+                                                    int max_rounds, int round, uint32_t K_all, uint32_t chunk,
+                                                    uint32_t cand, const EqInfo* eq) {
     using KT = Key<DT>;
     __shared__ uint64_t s_bits;
     const uint32_t i = fit_map[blockIdx.x];
     const uint64_t w = blockIdx.x - fit_off[i];
-    const uint64_t off = sample_off[i], S = sample_off[i + 1] - off;
+    const uint64_t off = sample_off[i], S = eq ? eq[i].sr : sample_off[i + 1] - off;
+    const uint32_t K = eq ? eq[i].km : K_all;
+    if (S < 3) return;
     const typename KT::T* xs = sample + off;
     if (!(isfinite(KT::val(xs[0])) && isfinite(KT::val(xs[S - 1])))) return;
     uint64_t* mk = masks + (uint64_t)i * max_rounds;
@@ -310,12 +315,13 @@ __global__ __launch_bounds__(256) void k_fmcd_round(const typename Key<DT>::T* s
 
 template <int DT>
 __global__ void k_fmcd_finish(const typename Key<DT>::T* sample, const uint64_t* sample_off, uint64_t num_items,
-                              const uint64_t* masks, int rounds, Model* models, uint32_t K, uint32_t small_S,
-                              uint32_t cand) {
+                              const uint64_t* masks, int rounds, Model* models, uint32_t K_all, uint32_t small_S,
+                              uint32_t cand, const EqInfo* eq) {
     using KT = Key<DT>;
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= num_items) return;
-    const uint64_t off = sample_off[i], S = sample_off[i + 1] - off;
+    const uint64_t off = sample_off[i], S = eq ? eq[i].sr : sample_off[i + 1] - off;
+    const uint32_t K = eq ? eq[i].km : K_all;
     if (S <= small_S) return;
     const typename KT::T* xs = sample + off;
     Model m = {};
@@ -657,11 +663,109 @@ __global__ __launch_bounds__(256) void k_minmax(const Item* items, const uint64_
 // Final model of every item: closes homogeneous buckets, sets the digit fallback, and picks the
 // two-level model when the policy and the sample loads ask for it.
 // stat_counts: [0] closed buckets, [1] digit splits, [2] two-level models, [3] keys in closed buckets
+// Equality buckets: the heavy values of every item's sorted sample and the sample without their
+// runs (one workgroup per item).  A value whose run is longer than S/K (run * K > S) spans at
+// least S/K + 1 positions, so it sits at one of the positions 0, m, 2m, ... with m = floor(S/K)+1;
+// each such candidate that starts a new value is measured by two binary searches.  The first
+// min(16, (K-4)/2) heavy values in ascending order are kept; the sample keeps its order with their
+// runs removed (written to rsample at the same offset).  A sample of a single value keeps E = 0
+// (the degenerate rule handles it).
+template <int DT>
+__global__ __launch_bounds__(256) void k_heavy(const typename Key<DT>::T* sample, const uint64_t* sample_off,
+                                               uint64_t num_items, uint32_t K, EqInfo* eq,
+                                               typename Key<DT>::T* rsample) {
+    using KT = Key<DT>;
+    __shared__ uint64_t s_val[kMaxHeavy], s_lo[kMaxHeavy], s_hi[kMaxHeavy];
+    __shared__ uint32_t s_cnt;
+    __shared__ uint64_t s_scan[16];
+    const uint64_t i = blockIdx.x;
+    if (i >= num_items) return;
+    const uint64_t off = sample_off[i], S = sample_off[i + 1] - off;
+    const typename KT::T* xs = sample + off;
+    uint32_t emax = (K - 4) / 2;
+    emax = emax < (uint32_t)kMaxHeavy ? emax : (uint32_t)kMaxHeavy;
+    const uint64_t step = S / K + 1;
+    const uint64_t ncand = S ? (S + step - 1) / step : 0;
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    // candidates in rounds of 256, compacted in order
+    for (uint64_t base = 0; base < ncand; base += blockDim.x) {
+        const uint64_t c = base + threadIdx.x;
+        uint32_t flag = 0;
+        uint64_t v = 0, lo = 0, hi = 0;
+        if (c < ncand) {
+            v = KT::ord(xs[c * step]);
+            const bool first = c == 0 || KT::ord(xs[(c - 1) * step]) != v;
+            if (first) {
+                uint64_t a = 0, b = S;  // lower bound of v
+                while (a < b) {
+                    const uint64_t mid = (a + b) >> 1;
+                    if (KT::ord(xs[mid]) < v) a = mid + 1;
+                    else b = mid;
+                }
+                lo = a;
+                b = S;  // upper bound of v
+                while (a < b) {
+                    const uint64_t mid = (a + b) >> 1;
+                    if (KT::ord(xs[mid]) <= v) a = mid + 1;
+                    else b = mid;
+                }
+                hi = a;
+                flag = (hi - lo) * (uint64_t)K > S ? 1u : 0u;
+            }
+        }
+        uint64_t tot;
+        const uint32_t before = (uint32_t)block_exclusive_sum<uint64_t>(flag, s_scan, &tot);
+        const uint32_t at = s_cnt + before;
+        if (flag && at < emax) {
+            s_val[at] = v;
+            s_lo[at] = lo;
+            s_hi[at] = hi;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) s_cnt = s_cnt + (uint32_t)tot;
+        __syncthreads();
+    }
+    uint32_t E = s_cnt < emax ? s_cnt : emax;
+    uint64_t heavy_keys = 0;
+    for (uint32_t e = 0; e < E; ++e) heavy_keys += s_hi[e] - s_lo[e];
+    if (E == 1 && heavy_keys == S) E = 0;  // a single value: the degenerate rule decides
+    if (E == 0) heavy_keys = 0;
+    for (uint64_t j = threadIdx.x; j < S; j += blockDim.x) {
+        uint64_t shift = 0;
+        bool drop = false;
+        for (uint32_t e = 0; e < E; ++e) {
+            if (j >= s_hi[e]) shift += s_hi[e] - s_lo[e];
+            else if (j >= s_lo[e]) drop = true;
+        }
+        if (!drop) rsample[off + j - shift] = xs[j];
+    }
+    if (threadIdx.x == 0) {
+        EqInfo q;
+        q.neq = E;
+        q.km = K - 2 * E;
+        q.sr = S - heavy_keys;
+        for (int e = 0; e < kMaxHeavy; ++e) q.heavy[e] = (uint32_t)e < E ? s_val[e] : 0;
+        eq[i] = q;
+    }
+}
+
 __global__ void k_finalize(const Item* items, Model* models, const Model* roots, uint64_t num_items, uint32_t K,
-                           int src_is_scratch, uint32_t policy, uint64_t* stat_counts) {
+                           int src_is_scratch, uint32_t policy, uint64_t* stat_counts, const EqInfo* eq) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= num_items) return;
     Model m = models[i];
+    m.neq = 0;
+    if (eq && eq[i].neq) {
+        // equality buckets: the linear part (fitted without the heavy runs) or a constant bucket 0
+        m.neq = eq[i].neq;
+        m.km = eq[i].km;
+        for (uint32_t e = 0; e < kMaxHeavy; ++e) m.heavy[e] = e < m.neq ? eq[i].heavy[e] : 0;
+        m.const0 = m.kind == kKindPending ? 1u : 0u;
+        m.kind = kKindLinear;
+        models[i] = m;
+        return;
+    }
     if (m.kind == kKindPending) {
         if (m.umin == m.umax) {
             m.kind = src_is_scratch ? kKindClosedMove : kKindClosedKeep;

@@ -60,7 +60,7 @@ ipls_status ensure(Buf& b, size_t bytes) {
 struct Depth {
     Buf scratch, spay, items[2], base, sample_base, counters, plan, tile_off, sample_off, fit_off, chunk_off, tile_map,
         fit_map, chunk_map, models, masks, hist, bstart, tile_pref, chunk_sum, chunk_pref, sample, leaves, seg, roots,
-        leaf_first, leaf_last;
+        leaf_first, leaf_last, eqinfo, rsample;
     Plan* plan_h = nullptr;
 };
 
@@ -83,7 +83,7 @@ void release_device(Device& dv) {
         for (Buf* b : {&D.scratch, &D.spay, &D.items[0], &D.items[1], &D.base, &D.sample_base, &D.counters, &D.plan,
                        &D.tile_off, &D.sample_off, &D.fit_off, &D.chunk_off, &D.tile_map, &D.fit_map, &D.chunk_map,
                        &D.models, &D.masks, &D.hist, &D.bstart, &D.tile_pref, &D.chunk_sum, &D.chunk_pref, &D.sample,
-                       &D.leaves, &D.seg, &D.roots, &D.leaf_first, &D.leaf_last})
+                       &D.leaves, &D.seg, &D.roots, &D.leaf_first, &D.leaf_last, &D.eqinfo, &D.rsample})
             release(*b);
         if (D.plan_h) (void)hipHostFree(D.plan_h);
         D.plan_h = nullptr;
@@ -227,8 +227,8 @@ struct Run {
 template <int DT>
 ipls_status fit_level(Depth& D, hipStream_t s, uint64_t ni, uint64_t max_S, uint64_t total_fit_chunks,
                       const typename Key<DT>::T* sample, const uint64_t* sample_off, const uint64_t* fit_off,
-                      Model* models, uint32_t K) {
-    k_fmcd_small<DT><<<(unsigned)ni, 256, 0, s>>>(sample, sample_off, ni, models, K, kSmallS);
+                      Model* models, uint32_t K, const EqInfo* eq = nullptr) {
+    k_fmcd_small<DT><<<(unsigned)ni, 256, 0, s>>>(sample, sample_off, ni, models, K, kSmallS, eq);
     LAUNCH_CHECK();
     if (max_S <= kSmallS) return IPLS_OK;
     const int R = fit_rounds(max_S);
@@ -241,11 +241,12 @@ ipls_status fit_level(Depth& D, hipStream_t s, uint64_t ni, uint64_t max_S, uint
     for (int r = 0; r < R; ++r) {
         k_fmcd_round<DT><<<(unsigned)total_fit_chunks, 256, 0, s>>>(sample, sample_off, fit_off,
                                                                     (const uint32_t*)D.fit_map.p,
-                                                                    (uint64_t*)D.masks.p, R, r, K, kFitChunk, kCand);
+                                                                    (uint64_t*)D.masks.p, R, r, K, kFitChunk, kCand,
+                                                                    eq);
         LAUNCH_CHECK();
     }
     k_fmcd_finish<DT><<<(unsigned)((ni + 255) / 256), 256, 0, s>>>(sample, sample_off, ni, (const uint64_t*)D.masks.p,
-                                                                   R, models, K, kSmallS, kCand);
+                                                                   R, models, K, kSmallS, kCand, eq);
     LAUNCH_CHECK();
     return IPLS_OK;
 }
@@ -467,9 +468,19 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         LAUNCH_CHECK();
         ST_TRY(sort_samples<DT>(dv, run, d, pl));
 
-        // FMCD fit
-        ST_TRY((fit_level<DT>(D, s, ni, pl.max_S, pl.total_fit_chunks, (const T*)D.sample.p,
-                              (const uint64_t*)D.sample_off.p, (const uint64_t*)D.fit_off.p, models, K)));
+        // FMCD fit (with equality buckets: on the sample without the heavy values' runs)
+        const EqInfo* eq = nullptr;
+        if (P.equality) {
+            ST_TRY(ensure(D.eqinfo, ni * sizeof(EqInfo)));
+            ST_TRY(ensure(D.rsample, pl.total_samples * kb));
+            k_heavy<DT><<<(unsigned)ni, 256, 0, s>>>((const T*)D.sample.p, (const uint64_t*)D.sample_off.p, ni, K,
+                                                     (EqInfo*)D.eqinfo.p, (T*)D.rsample.p);
+            LAUNCH_CHECK();
+            eq = (const EqInfo*)D.eqinfo.p;
+        }
+        ST_TRY((fit_level<DT>(D, s, ni, pl.max_S, pl.total_fit_chunks,
+                              eq ? (const T*)D.rsample.p : (const T*)D.sample.p, (const uint64_t*)D.sample_off.p,
+                              (const uint64_t*)D.fit_off.p, models, K, eq)));
         if (P.model != 0)
             ST_TRY((train_l2pl<DT>(D, s, ni, pl.max_S, pl.total_fit_chunks, (const T*)D.sample.p,
                                    (const uint64_t*)D.sample_off.p, (const uint64_t*)D.fit_off.p, models, K, P.leaves,
@@ -481,7 +492,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         LAUNCH_CHECK();
         k_finalize<<<(unsigned)((ni + 255) / 256), 256, 0, s>>>(items, models, (const Model*)D.roots.p, ni, K,
                                                                 src_scratch ? 1 : 0, P.model,
-                                                                cnt + C_STATS);
+                                                                cnt + C_STATS, eq);
         LAUNCH_CHECK();
 
         // classify + per-tile counts, scan of the counts, bucket starts
@@ -615,7 +626,7 @@ ipls_status l2pl_entry(Device& dv, hipStream_t s, const double* x, uint64_t S, u
 
 ipls_status check_params(const ipls_params& p) {
     if (p.num_buckets < 4 || p.base_case_max < 1 || p.sample_divisor < 2) return IPLS_ERR_INVALID;
-    if (p.sample_policy > 1) return IPLS_ERR_INVALID;
+    if (p.sample_policy > 1 || p.equality > 1) return IPLS_ERR_INVALID;
     if (p.tile_keys != 0 && p.tile_keys != kTile && p.tile_keys != kSmallTile) return IPLS_ERR_INVALID;
     const uint64_t smin = p.sample_min ? p.sample_min : (p.sample_policy == 1 ? 0 : 2ull * p.num_buckets);
     if (smin > p.base_case_max) return IPLS_ERR_INVALID;
@@ -781,6 +792,7 @@ void ipls_default_params(ipls_params* p) {
     p->train_iters = 4;
     p->tile_keys = 0;
     p->sample_policy = 0;
+    p->equality = 0;
 }
 
 const char* ipls_status_string(ipls_status st) {

@@ -51,20 +51,21 @@ def test_1e8_fp64_against_oracle(dist, seed):
     assert (st["passes"], st["levels"]) == (ost["passes"], ost["max_level"])
 
 
-def test_2e8_zipf_u64_payload_against_oracle():
+@pytest.mark.parametrize("equality", [0, 1])
+def test_2e8_zipf_u64_payload_against_oracle(equality):
     n = 200_000_000
-    print(f"full size zipf u64 + payload n={n}", flush=True)
+    print(f"full size zipf u64 + payload n={n} equality={equality}", flush=True)
     kd = gdev.zipf_u64(n, 8)
     keys = kd.cpu().numpy().view(np.uint64)
     pay = gen.index_payload(n)
     kd = kd.view(torch.uint64)
     pd = torch.from_numpy(pay.view(np.int32)).to("cuda:0")
-    st = ipls.sort_(kd, pd, params=ipls.default_params(**BENCH), stats=True)
+    st = ipls.sort_(kd, pd, params=ipls.default_params(equality=equality, **BENCH), stats=True)
     torch.cuda.synchronize()
     got = kd.view(torch.int64).cpu().numpy().view(np.uint64)
     gpay = pd.cpu().numpy().view(np.uint32)
     del kd, pd
-    want, wpay, ost = oracle.sort(keys, pay, oracle.params(sample_max=4096))
+    want, wpay, ost = oracle.sort(keys, pay, oracle.params(sample_max=4096, equality=equality))
     assert np.array_equal(got, want)
     assert np.array_equal(gpay, wpay)
     assert st["closed"] == ost["closed"] and st["passes"] == ost["passes"]

@@ -29,7 +29,7 @@ def oracle_params(**kw):
     m = dict(K=kw.get("num_buckets", 256), T=kw.get("base_case_max", 4096), divisor=kw.get("sample_divisor", 100),
              sample_min=kw.get("sample_min", 0), sample_max=kw.get("sample_max", 0),
              model=kw.get("model", 0), leaves=kw.get("leaves", 256), train_iters=kw.get("train_iters", 4),
-             sample_policy=kw.get("sample_policy", 0))
+             sample_policy=kw.get("sample_policy", 0), equality=kw.get("equality", 0))
     return oracle.params(**m)
 
 
@@ -69,6 +69,26 @@ def test_sort_f64_params(dist, kw):
 def test_sort_paper_sample_policy(dist, kw):
     k = gen.make(dist, 250_000, 17)
     check_sort(k, gen.index_payload(k.size), **kw)
+
+
+@pytest.mark.parametrize("dist", ["zipf_u64", "root_dups", "two_dups", "uniform_int", "normal", "mixgauss"])
+@pytest.mark.parametrize("kw", [dict(equality=1), dict(equality=1, num_buckets=16, base_case_max=64),
+                                dict(equality=1, num_buckets=64, base_case_max=300, tile_keys=2048)])
+def test_sort_equality_buckets(dist, kw):
+    k = gen.make(dist, 220_000, 23)
+    check_sort(k, gen.index_payload(k.size), **kw)
+
+
+def test_equality_buckets_f32_and_heavy_specials():
+    r = np.random.default_rng(5)
+    k = r.standard_normal(150_000).astype(np.float32)
+    k[::3] = np.float32(0.5)
+    k[1::7] = -np.float32(0.0)
+    k[2::11] = np.float32(np.inf)
+    check_sort(k, gen.index_payload(k.size), equality=1, num_buckets=32, base_case_max=128)
+    u = np.concatenate([gen.u64_uniform(50_000, 3), np.full(40_000, 2**63, np.uint64), np.full(30_000, 7, np.uint64)])
+    r.shuffle(u)
+    check_sort(u, None, equality=1, num_buckets=64, base_case_max=256)
 
 
 def test_sort_u64_uniform_and_zipf_payload():
