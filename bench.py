@@ -178,7 +178,7 @@ def bench_large_u64(args):
     work = torch.empty_like(src)
     pay0 = torch.arange(n, dtype=torch.int32, device=dev) if zipf else None
     pay = torch.empty_like(pay0) if zipf else None
-    params = ipls.default_params(sample_max=args.sample_max)
+    params = ipls.default_params(sample_max=args.sample_max, equality=args.equality)
     stream = torch.cuda.current_stream()
     ipls.profile_enable(True)
     ms, stats = [], None
@@ -212,7 +212,7 @@ def bench_large_u64(args):
     line = _line(n / (mean_ms / 1e3), mean_ms, args.steps, args.warmup, "u64",
                  {"workload": desc, "n": n, "num_buckets": 256, "base_case_max": 4096,
                   "sample": f"1% jittered stratified, capped at {args.sample_max} keys", "model": "FMCD",
-                  "parallelism": "single GPU"},
+                  "equality_buckets": bool(args.equality), "parallelism": "single GPU"},
                  roofline={"kernel": "k_scatter", "bound": "hbm",
                            "achieved": round(sc_gbs, 1) if sc_gbs else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(sc_gbs / HBM_PEAK_GBS, 4) if sc_gbs else None, "traffic": None,
@@ -442,6 +442,7 @@ def main():
     ap.add_argument("--sample-max", type=int, default=4096)
     ap.add_argument("--tile-keys", type=int, default=0, help="keys per distribution tile (0 = library default)")
     ap.add_argument("--sort-model", type=int, default=0, help="sort: 0 FMCD (default), 1 auto, 2 learned")
+    ap.add_argument("--equality", type=int, default=0, help="sort, u64, zipf: 1 = equality buckets for heavy values")
     ap.add_argument("--workload", choices=("sort", "u64", "zipf", "batched", "served"), default="sort",
                     help="sort: the 1e8 fp64 single-array sort (default); u64: 1e9 uniform uint64 keys; "
                          "zipf: 2e8 Zipf(1.1) uint64 keys with a uint32 index payload; batched; served")
@@ -485,7 +486,8 @@ def main():
     total = args.warmup + args.steps
     order = [dists[i % len(dists)] for i in range(total)]
 
-    params = ipls.default_params(sample_max=args.sample_max, tile_keys=args.tile_keys, model=args.sort_model)
+    params = ipls.default_params(sample_max=args.sample_max, tile_keys=args.tile_keys, model=args.sort_model,
+                                 equality=args.equality)
     stream = torch.cuda.current_stream()
 
     # warmup: also checks parity of each distribution's output against numpy's sort
@@ -570,7 +572,8 @@ def main():
         d0 = dists[0]
         print(f"# cpu baseline: oracle on one full step ({d0}, {n} keys)", file=sys.stderr, flush=True)
         t = time.perf_counter()
-        want, _, _ = oracle.sort(host_inputs[d0], None, oracle.params(sample_max=args.sample_max, model=args.sort_model))
+        want, _, _ = oracle.sort(host_inputs[d0], None, oracle.params(sample_max=args.sample_max, model=args.sort_model,
+                                                                      equality=args.equality))
         dt = time.perf_counter() - t
         # parity of the GPU result for this step against the oracle
         g = pristine[d0].clone()
