@@ -654,7 +654,8 @@ static void fit_bucket(const void* keys, uint64_t n, int dtype, const oracle_par
  * h_0 < ... < h_(E-1) the linear part has K - 2E buckets, and a key goes to
  *   linear bucket + 2 * #{e : h_e < key} + [key is some h_e],
  * which keeps the buckets in key order: each heavy value gets a bucket of its own between the
- * keys below it and the keys above it. */
+ * keys below it and the keys above it.  Such a bucket holds one value only, so the recursion
+ * closes it where it is made (it counts as closed, and is neither partitioned nor base-sorted). */
 static uint32_t classify_equality(const oracle_model* m, uint64_t o, double v, int neg) {
     uint32_t less = 0, eq = 0;
     for (uint32_t e = 0; e < m->neq; ++e) {
@@ -779,10 +780,21 @@ static void ipls(ctx_t* cx, char* keys, uint32_t* pay, uint64_t n, uint64_t lo_r
             if (counts[c] > mx) mx = counts[c];
         cx->st->level1_max_load = mx;
     }
+    /* an equality bucket holds one value only: it is closed where it is made */
+    uint32_t eqb[16];
+    const uint32_t neq = m.kind == MODEL_LINEAR ? m.neq : 0;
+    for (uint32_t e = 0; e < neq; ++e) {
+        const uint64_t o = m.heavy[e];
+        const int neg = cx->dtype == OR_U64 ? 0 : (cx->dtype == OR_F32 ? !((o >> 31) & 1u) : !(o >> 63));
+        eqb[e] = classify_equality(&m, o, val_from_ord(o, cx->dtype), neg);
+    }
     uint64_t off = 0;
     for (uint32_t c = 0; c < K; ++c) {
         uint64_t cnt = counts[c];
-        if (cnt > 0) ipls(cx, keys + off * cx->kb, pay ? pay + off : NULL, cnt, lo_rel + off, level + 1);
+        int is_eq = 0;
+        for (uint32_t e = 0; e < neq; ++e) is_eq |= eqb[e] == c;
+        if (cnt > 0 && is_eq) cx->st->closed += 1;
+        else if (cnt > 0) ipls(cx, keys + off * cx->kb, pay ? pay + off : NULL, cnt, lo_rel + off, level + 1);
         off += cnt;
     }
     free(counts);

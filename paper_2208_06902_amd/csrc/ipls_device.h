@@ -53,6 +53,12 @@ struct Model {
     // sends every other key to bucket 0 (const0)
     uint32_t neq, km, const0, pad2;
     uint64_t heavy[kMaxHeavy];
+    uint8_t eqb[kMaxHeavy];  // the bucket of each heavy value
+};
+
+// An equality bucket whose keys a level wrote to the scratch buffer: moved back as they are.
+struct CopyItem {
+    uint64_t lo, n;
 };
 
 // Heavy values of an item's sorted sample and the length of the sample without their runs.
@@ -73,7 +79,11 @@ struct Plan {
     uint64_t base_keys;            // keys in this level's base-case buckets
     uint64_t cls_count[kBaseClasses];
     uint64_t total_chunks;
+    uint64_t eq_closed;                // equality buckets closed so far
+    uint64_t copy_count, copy_tiles;   // equality buckets to move back, in tiles of kCopyTile keys
 };
+
+constexpr uint32_t kCopyTile = 4096;
 
 // counters of one nesting depth (uint64 slots)
 enum : int {
@@ -81,6 +91,9 @@ enum : int {
     C_STATS = 5,      // 4 slots: closed buckets, digit splits, two-level models, closed keys
     C_BASEKEYS = 9,   // keys appended to the base-case list
     C_CLS = 10,       // 7 slots: base-case buckets per size class
+    C_EQCLOSED = 17,  // equality buckets closed where they were made (all levels)
+    C_COPY = 18,      // equality buckets of this level to move from the scratch buffer
+    C_COPYKEYS = 19,  // ... and their keys
     C_N = 32
 };
 

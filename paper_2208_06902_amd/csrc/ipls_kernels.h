@@ -29,7 +29,8 @@ struct LevelArgs {
 // previous level and resets the counters the coming level appends to.
 __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* cnt, int cur, Plan* plan, uint64_t* tile_off,
                                                uint64_t* sample_off, uint64_t* fit_off, uint64_t* chunk_off,
-                                               LevelArgs A, uint64_t item_cap, BaseLayout bl) {
+                                               LevelArgs A, uint64_t item_cap, BaseLayout bl, const CopyItem* copy,
+                                               uint64_t* copy_off, uint64_t copy_cap) {
     __shared__ uint64_t sc[16];
     __shared__ uint64_t s_max[3];
     const uint64_t num = cnt[C_ITEMS0 + cur];
@@ -72,8 +73,26 @@ __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* cnt,
         run_s += ts;
         run_f += tf;
     }
+    // tiles of the equality buckets the previous level left in the scratch buffer
+    const uint64_t ncopy_all = cnt[C_COPY], ncopy = ncopy_all < copy_cap ? ncopy_all : copy_cap;
+    uint64_t run_k = 0;
+    for (uint64_t base = 0; base < ncopy; base += blockDim.x) {
+        const uint64_t q = base + threadIdx.x;
+        const uint64_t nt = q < ncopy ? (copy[q].n + kCopyTile - 1) / kCopyTile : 0;
+        uint64_t tk;
+        const uint64_t ek = block_exclusive_sum<uint64_t>(nt, sc, &tk);
+        if (q < ncopy) copy_off[q] = run_k + ek;
+        run_k += tk;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
+        copy_off[ncopy] = run_k;
+        plan->copy_count = ncopy;
+        plan->copy_tiles = run_k;
+        plan->eq_closed = cnt[C_EQCLOSED];
+        if (ncopy_all > copy_cap) cnt[C_ERR] |= kErrCapacity;
+        cnt[C_COPY] = 0;
+        cnt[C_COPYKEYS] = 0;
         tile_off[use] = run_t;
         sample_off[use] = run_s;
         fit_off[use] = run_f;
@@ -750,6 +769,7 @@ __global__ __launch_bounds__(256) void k_heavy(const typename Key<DT>::T* sample
     }
 }
 
+template <int DT>
 __global__ void k_finalize(const Item* items, Model* models, const Model* roots, uint64_t num_items, uint32_t K,
                            int src_is_scratch, uint32_t policy, uint64_t* stat_counts, const EqInfo* eq) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -763,6 +783,8 @@ __global__ void k_finalize(const Item* items, Model* models, const Model* roots,
         for (uint32_t e = 0; e < kMaxHeavy; ++e) m.heavy[e] = e < m.neq ? eq[i].heavy[e] : 0;
         m.const0 = m.kind == kKindPending ? 1u : 0u;
         m.kind = kKindLinear;
+        for (uint32_t e = 0; e < kMaxHeavy; ++e)
+            m.eqb[e] = e < m.neq ? (uint8_t)classify_equality<DT>(m, Key<DT>::from_ord(m.heavy[e])) : (uint8_t)0;
         models[i] = m;
         return;
     }
@@ -1122,7 +1144,8 @@ __global__ __launch_bounds__(64 * NW) void k_scatter(const Item* items, const ui
 __global__ __launch_bounds__(256) void k_worklist(const Item* items, uint64_t num_items, const Model* models,
                                                   const uint64_t* hist, const uint64_t* bstart, uint32_t K, uint32_t T,
                                                   int dst_is_scratch, Item* next, BaseItem* base, BaseLayout bl,
-                                                  uint64_t* cnt, int next_slot, uint64_t next_cap) {
+                                                  uint64_t* cnt, int next_slot, uint64_t next_cap, CopyItem* copy,
+                                                  uint64_t copy_cap) {
     __shared__ AppendScratch sc;
     const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t c = 0, lo = 0, lo_rel = 0;
@@ -1135,6 +1158,19 @@ __global__ __launch_bounds__(256) void k_worklist(const Item* items, uint64_t nu
             const uint64_t start = bstart[g];
             lo = it.lo + start;
             lo_rel = it.lo_rel + start;
+            // an equality bucket holds one value: closed here; moved back if it sits in the scratch buffer
+            const uint32_t neq = kind == kKindLinear ? models[i].neq : 0u;
+            bool is_eq = false;
+            for (uint32_t e = 0; e < neq; ++e) is_eq |= models[i].eqb[e] == (uint32_t)(g % K);
+            if (is_eq && c > 0) {
+                atomicAdd((unsigned long long*)&cnt[C_EQCLOSED], 1ull);
+                if (dst_is_scratch) {
+                    const uint64_t q = atomicAdd((unsigned long long*)&cnt[C_COPY], 1ull);
+                    if (q < copy_cap) copy[q] = CopyItem{lo, c};
+                    atomicAdd((unsigned long long*)&cnt[C_COPYKEYS], (unsigned long long)c);
+                }
+                c = 0;  // neither an item nor a base-case bucket
+            }
         }
     }
     const bool small = c >= 2 ? c <= T : (c == 1 && dst_is_scratch);
@@ -1143,6 +1179,26 @@ __global__ __launch_bounds__(256) void k_worklist(const Item* items, uint64_t nu
     const uint64_t q = block_append(ch, c, sc, &cnt[next_slot], &cnt[C_CLS], &cnt[C_BASEKEYS]);
     if (ch == 0 && q < next_cap) next[q] = Item{lo, c, lo_rel, 0};
     if (ch > 0 && q < bl.cap[cls]) base[bl.off[cls] + q] = BaseItem{lo, (uint32_t)c, (uint32_t)dst_is_scratch};
+}
+
+// Equality buckets a level wrote to the scratch buffer move back to the caller's buffer as they
+// are (their keys are equal, their payloads in stable order): one workgroup per tile of
+// kCopyTile keys, tile t of copy item map[t].
+template <int DT, bool PAY>
+__global__ __launch_bounds__(256) void k_copy(const CopyItem* copy, const uint64_t* copy_off, const uint32_t* map,
+                                              uint64_t total_tiles, typename Key<DT>::T* keys, uint32_t* pay,
+                                              const typename Key<DT>::T* skeys, const uint32_t* spay) {
+    const uint64_t t = blockIdx.x;
+    if (t >= total_tiles) return;
+    const uint32_t q = map[t];
+    const CopyItem ci = copy[q];
+    const uint64_t base = (t - copy_off[q]) * kCopyTile;
+    const uint64_t rem = ci.n - base;
+    const uint32_t n = rem < kCopyTile ? (uint32_t)rem : kCopyTile;
+    for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
+        keys[ci.lo + base + j] = __builtin_nontemporal_load(&skeys[ci.lo + base + j]);
+        if (PAY) pay[ci.lo + base + j] = __builtin_nontemporal_load(&spay[ci.lo + base + j]);
+    }
 }
 
 // ------------------------------------------------------------------ base case

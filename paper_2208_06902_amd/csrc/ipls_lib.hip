@@ -60,7 +60,7 @@ ipls_status ensure(Buf& b, size_t bytes) {
 struct Depth {
     Buf scratch, spay, items[2], base, sample_base, counters, plan, tile_off, sample_off, fit_off, chunk_off, tile_map,
         fit_map, chunk_map, models, masks, hist, bstart, tile_pref, chunk_sum, chunk_pref, sample, leaves, seg, roots,
-        leaf_first, leaf_last, eqinfo, rsample;
+        leaf_first, leaf_last, eqinfo, rsample, copy, copy_off, copy_map;
     Plan* plan_h = nullptr;
 };
 
@@ -83,7 +83,8 @@ void release_device(Device& dv) {
         for (Buf* b : {&D.scratch, &D.spay, &D.items[0], &D.items[1], &D.base, &D.sample_base, &D.counters, &D.plan,
                        &D.tile_off, &D.sample_off, &D.fit_off, &D.chunk_off, &D.tile_map, &D.fit_map, &D.chunk_map,
                        &D.models, &D.masks, &D.hist, &D.bstart, &D.tile_pref, &D.chunk_sum, &D.chunk_pref, &D.sample,
-                       &D.leaves, &D.seg, &D.roots, &D.leaf_first, &D.leaf_last, &D.eqinfo, &D.rsample})
+                       &D.leaves, &D.seg, &D.roots, &D.leaf_first, &D.leaf_last, &D.eqinfo, &D.rsample, &D.copy,
+                       &D.copy_off, &D.copy_map})
             release(*b);
         if (D.plan_h) (void)hipHostFree(D.plan_h);
         D.plan_h = nullptr;
@@ -374,6 +375,9 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     }
     ST_TRY(ensure(D.items[0], item_cap * sizeof(Item)));
     ST_TRY(ensure(D.items[1], item_cap * sizeof(Item)));
+    const uint64_t copy_cap = P.equality ? item_cap * kMaxHeavy + 1 : 1;  // equality buckets per level
+    ST_TRY(ensure(D.copy, copy_cap * sizeof(CopyItem)));
+    ST_TRY(ensure(D.copy_off, (copy_cap + 1) * 8));
     ST_TRY(ensure(D.base, base_cap * sizeof(BaseItem)));
     ST_TRY(ensure(D.counters, C_N * sizeof(uint64_t)));
     ST_TRY(ensure(D.plan, sizeof(Plan)));
@@ -409,7 +413,8 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     uint64_t prev_items = 0, prev_sum_n = 0, prev_closed = 0, prev_closed_keys = 0;
     for (int level = 0;; ++level) {
         k_plan<<<1, 1024, 0, s>>>((const Item*)D.items[cur].p, cnt, cur, (Plan*)D.plan.p, (uint64_t*)D.tile_off.p, (uint64_t*)D.sample_off.p,
-                                  (uint64_t*)D.fit_off.p, (uint64_t*)D.chunk_off.p, A, item_cap, bl);
+                                  (uint64_t*)D.fit_off.p, (uint64_t*)D.chunk_off.p, A, item_cap, bl,
+                                  (const CopyItem*)D.copy.p, (uint64_t*)D.copy_off.p, copy_cap);
         LAUNCH_CHECK();
         HIP_TRY(hipMemcpyAsync(D.plan_h, D.plan.p, sizeof(Plan), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
@@ -423,11 +428,24 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                 run.st.passes += prev_items - closed_now;
                 run.st.keys_partitioned += prev_sum_n - (pl.closed_keys - prev_closed_keys);
             }
-            run.st.closed = pl.closed;
+            run.st.closed = pl.closed + pl.eq_closed;
             run.st.fallback = pl.digit;
             run.st.l2pl_used = pl.l2pl;
             prev_closed = pl.closed;
             prev_closed_keys = pl.closed_keys;
+        }
+        if (pl.copy_count) {
+            // equality buckets the previous level left in the scratch buffer
+            ST_TRY(ensure(D.copy_map, pl.copy_tiles * 4));
+            k_expand<<<(unsigned)((pl.copy_tiles + 255) / 256), 256, 0, s>>>((const uint64_t*)D.copy_off.p,
+                                                                             pl.copy_count, pl.copy_tiles,
+                                                                             (uint32_t*)D.copy_map.p);
+            LAUNCH_CHECK();
+            k_copy<DT, PAY><<<(unsigned)pl.copy_tiles, 256, 0, s>>>((const CopyItem*)D.copy.p,
+                                                                    (const uint64_t*)D.copy_off.p,
+                                                                    (const uint32_t*)D.copy_map.p, pl.copy_tiles,
+                                                                    keys, pay, scratch, spay);
+            LAUNCH_CHECK();
         }
         if (pl.num_base) {
             ProfScope ps(2, (double)pl.base_keys * 2.0 * (kb + (PAY ? 4 : 0)), s);
@@ -490,7 +508,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         k_minmax<DT><<<(unsigned)nt, 256, 0, s>>>(items, (const uint64_t*)D.tile_off.p, (const uint32_t*)D.tile_map.p,
                                                   models, src, tile);
         LAUNCH_CHECK();
-        k_finalize<<<(unsigned)((ni + 255) / 256), 256, 0, s>>>(items, models, (const Model*)D.roots.p, ni, K,
+        k_finalize<DT><<<(unsigned)((ni + 255) / 256), 256, 0, s>>>(items, models, (const Model*)D.roots.p, ni, K,
                                                                 src_scratch ? 1 : 0, P.model,
                                                                 cnt + C_STATS, eq);
         LAUNCH_CHECK();
@@ -555,7 +573,8 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         // next level
         k_worklist<<<(unsigned)((ni * K + 255) / 256), 256, 0, s>>>(
             items, ni, models, (const uint64_t*)D.hist.p, (const uint64_t*)D.bstart.p, K, T_, src_scratch ? 0 : 1,
-            (Item*)D.items[cur ^ 1].p, (BaseItem*)D.base.p, bl, cnt, C_ITEMS0 + (cur ^ 1), item_cap);
+            (Item*)D.items[cur ^ 1].p, (BaseItem*)D.base.p, bl, cnt, C_ITEMS0 + (cur ^ 1), item_cap,
+            (CopyItem*)D.copy.p, copy_cap);
         LAUNCH_CHECK();
         cur ^= 1;
     }
