@@ -1239,20 +1239,21 @@ __device__ inline void cex(O& ka, O& kb, uint32_t& ia, uint32_t& ib, uint32_t& p
 
 // Merge sort of CAP = 16 NT keys held in LDS (pad16 layout, positions 0 .. CAP-1, padding keys
 // are kPad at the end) by NT threads t = 0 .. NT-1 of one group; the sorted keys are left in LDS.
-// Threads of the workgroup that are not among the NT pass active = false: they only take part in
-// the barriers.
+// Payload sorts (PAY) hold each key's original index in sp (padding slots: indices >= the bucket
+// size) and compare (ord, index), which is the stable order; the caller gathers the payloads by
+// index afterwards.  Threads of the workgroup that are not among the NT pass active = false: they
+// only take part in the barriers.
 template <typename O, bool PAY, int NT>
 __device__ inline void merge_sort_lds(O* sk, uint32_t* sp, int t_in, bool active = true) {
     const int t = active ? t_in : 0;  // inactive threads read in bounds and write nothing
     constexpr int IPT = 16, CAP = NT * IPT;
     constexpr O kPad = (O)~(O)0;
     O k[IPT];
-    uint32_t id[IPT], p[IPT];  // id: current position (payload sorts only)
+    uint32_t id[IPT], nop = 0;  // id: original index (payload sorts only)
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         k[i] = sk[pad16(t * IPT + i)];
-        id[i] = t * IPT + i;
-        p[i] = PAY ? sp[pad16(t * IPT + i)] : 0u;
+        id[i] = PAY ? sp[pad16(t * IPT + i)] : 0u;
     }
     // 1: bitonic sort of the thread's 16 keys
 #pragma unroll
@@ -1262,7 +1263,7 @@ __device__ inline void merge_sort_lds(O* sk, uint32_t* sp, int t_in, bool active
 #pragma unroll
             for (int i = 0; i < IPT; ++i) {
                 const int l = i ^ j;
-                if (l > i) cex<PAY>(k[i], k[l], id[i], id[l], p[i], p[l], (i & kk) == 0);
+                if (l > i) cex<PAY>(k[i], k[l], id[i], id[l], nop, nop, (i & kk) == 0);
             }
     // 2: merge rounds, runs of L keys -> 2L
 #pragma unroll 1
@@ -1272,7 +1273,7 @@ __device__ inline void merge_sort_lds(O* sk, uint32_t* sp, int t_in, bool active
 #pragma unroll
             for (int i = 0; i < IPT; ++i) {
                 sk[pad16(t * IPT + i)] = k[i];
-                if (PAY) sp[pad16(t * IPT + i)] = p[i];
+                if (PAY) sp[pad16(t * IPT + i)] = id[i];
             }
         }
         __syncthreads();
@@ -1286,33 +1287,31 @@ __device__ inline void merge_sort_lds(O* sk, uint32_t* sp, int t_in, bool active
         }
         const int ia = lo, ib = d - lo;
         O xa[IPT], xb[IPT];
-        uint32_t pa[IPT], pb[IPT];
+        uint32_t qa[IPT], qb[IPT];
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
             xa[j] = ia + j < L ? sk[pad16(a0 + ia + j)] : kPad;
             xb[j] = ib + j < L ? sk[pad16(b0 + ib + j)] : kPad;
             if (PAY) {
-                pa[j] = ia + j < L ? sp[pad16(a0 + ia + j)] : 0u;
-                pb[j] = ib + j < L ? sp[pad16(b0 + ib + j)] : 0u;
+                // past-the-end slots get indices past every real one, so real keys win ties
+                qa[j] = ia + j < L ? sp[pad16(a0 + ia + j)] : (uint32_t)(2 * CAP + j);
+                qb[j] = ib + j < L ? sp[pad16(b0 + ib + j)] : (uint32_t)(3 * CAP + j);
             }
         }
         // the 16 smallest of the two sorted windows: min(xa[j], xb[15-j]) is bitonic
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
-            // past-the-end slots get positions past both runs, so real keys win ties
-            const uint32_t qa = ia + j < L ? (uint32_t)(a0 + ia + j) : (uint32_t)(2 * CAP + j);
-            const uint32_t qb = ib + IPT - 1 - j < L ? (uint32_t)(b0 + ib + IPT - 1 - j) : (uint32_t)(3 * CAP + j);
-            const bool takeB = key_less<PAY>(xb[IPT - 1 - j], qb, xa[j], qa);
+            const uint32_t ua = PAY ? qa[j] : 0u, ub = PAY ? qb[IPT - 1 - j] : 0u;
+            const bool takeB = key_less<PAY>(xb[IPT - 1 - j], ub, xa[j], ua);
             k[j] = takeB ? xb[IPT - 1 - j] : xa[j];
-            id[j] = takeB ? qb : qa;
-            p[j] = PAY ? (takeB ? pb[IPT - 1 - j] : pa[j]) : 0u;
+            id[j] = takeB ? ub : ua;
         }
 #pragma unroll
         for (int j = IPT >> 1; j > 0; j >>= 1)
 #pragma unroll
             for (int i = 0; i < IPT; ++i) {
                 const int l = i ^ j;
-                if (l > i) cex<PAY>(k[i], k[l], id[i], id[l], p[i], p[l], true);
+                if (l > i) cex<PAY>(k[i], k[l], id[i], id[l], nop, nop, true);
             }
     }
     __syncthreads();
@@ -1320,7 +1319,7 @@ __device__ inline void merge_sort_lds(O* sk, uint32_t* sp, int t_in, bool active
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
             sk[pad16(t * IPT + i)] = k[i];
-            if (PAY) sp[pad16(t * IPT + i)] = p[i];
+            if (PAY) sp[pad16(t * IPT + i)] = id[i];
         }
     }
     __syncthreads();
@@ -1347,30 +1346,36 @@ __global__ __launch_bounds__(256) void k_base_sort(const BaseItem* list, uint64_
     uint32_t* sp = s_p + (PAY ? g * PCAP : 0);
     {
         typename KT::T v[IPT];
-        uint32_t pv[PAY ? IPT : 1];
 #pragma unroll
         for (int r = 0; r < IPT; ++r) {
             const int j = t + r * NT;
-            if (j < (int)n) {
-                v[r] = __builtin_nontemporal_load(&src[bi.lo + j]);
-                if (PAY) pv[r] = __builtin_nontemporal_load(&psrc[bi.lo + j]);
-            }
+            if (j < (int)n) v[r] = __builtin_nontemporal_load(&src[bi.lo + j]);
         }
 #pragma unroll
         for (int r = 0; r < IPT; ++r) {
             const int j = t + r * NT;
             sk[pad16(j)] = j < (int)n ? (O)KT::ord(v[r]) : kPad;
-            if (PAY) sp[pad16(j)] = j < (int)n ? pv[r] : 0u;
+            if (PAY) sp[pad16(j)] = (uint32_t)j;  // original index
         }
     }
     __syncthreads();
     merge_sort_lds<O, PAY, NT>(sk, sp, t);
+    // payloads by original index, all read before any is written (the source may be the output)
+    uint32_t pv[PAY ? IPT : 1];
+    if (PAY) {
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const int j = t + r * NT;
+            if (j < (int)n) pv[r] = psrc[bi.lo + sp[pad16(j)]];
+        }
+        __syncthreads();
+    }
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
         const int j = t + r * NT;
         if (j < (int)n) {
             keys[bi.lo + j] = KT::from_ord((uint64_t)sk[pad16(j)]);
-            if (PAY) pay[bi.lo + j] = sp[pad16(j)];
+            if (PAY) pay[bi.lo + j] = pv[r];
         }
     }
 }
@@ -1501,21 +1506,31 @@ __device__ inline void base_large_stable(const BaseItem& bi, typename Key<DT>::T
     const uint32_t most = block_count_digits<NW, IPT>(bk, n, wbase, s_wcnt, s_loc, s_cnt, s_scan, s_max, rk);
 
     if (nbits > 8 && most > kSubMax) {
-        // merge sort: keys to LDS at their input positions (padding keys at the end), then sort
+        // merge sort: keys (and original indices) to LDS at their input positions, padding at the
+        // end; then sort, and gather the payloads by index (all read before any is written)
 #pragma unroll
         for (int r = 0; r < IPT; ++r) {
             const uint32_t j = wbase + r * kWave + lane;
             s_k[pad16(j)] = o[r];
-            if (PAY) s_p[pad16(j)] = j < n ? p[r] : 0u;
+            if (PAY) s_p[pad16(j)] = j;
         }
         __syncthreads();
         merge_sort_lds<O, PAY, MT>(s_k, s_p, (int)tid, tid < (uint32_t)MT);
+        uint32_t pv[PAY ? IPT : 1];
+        if (PAY) {
+#pragma unroll
+            for (int r = 0; r < IPT; ++r) {
+                const uint32_t j = wbase + r * kWave + lane;
+                if (j < n) pv[r] = psrc[bi.lo + s_p[pad16(j)]];
+            }
+            __syncthreads();
+        }
 #pragma unroll
         for (int r = 0; r < IPT; ++r) {
             const uint32_t j = wbase + r * kWave + lane;
             if (j < n) {
                 keys[bi.lo + j] = KT::from_ord((uint64_t)s_k[pad16(j)]);
-                if (PAY) pay[bi.lo + j] = s_p[pad16(j)];
+                if (PAY) pay[bi.lo + j] = pv[r];
             }
         }
         return;
