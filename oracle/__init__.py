@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libipls_oracle.so")
 CFLAGS = ["-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-Wall"]
 
 F64, F32, U64 = 0, 1, 2
-MODEL_LINEAR, MODEL_MSD, MODEL_CLOSED, MODEL_L2PL = 0, 1, 2, 3
+MODEL_LINEAR, MODEL_MSD, MODEL_CLOSED, MODEL_L2PL, MODEL_TREE = 0, 1, 2, 3, 4
 _DT = {np.dtype(np.float64): F64, np.dtype(np.float32): F32, np.dtype(np.uint64): U64}
 
 
@@ -33,7 +33,8 @@ class Model(C.Structure):
     _fields_ = [("kind", C.c_uint32), ("K", C.c_uint32), ("a", C.c_double), ("b", C.c_double), ("D", C.c_uint64),
                 ("umin", C.c_uint64), ("shift", C.c_uint32), ("degenerate", C.c_uint32), ("S", C.c_uint64),
                 ("max_load_linear", C.c_uint64), ("max_load_l2pl", C.c_uint64), ("neq", C.c_uint32),
-                ("Km", C.c_uint32), ("const0", C.c_uint32), ("pad_", C.c_uint32), ("heavy", C.c_uint64 * 16)]
+                ("Km", C.c_uint32), ("const0", C.c_uint32), ("pad_", C.c_uint32), ("heavy", C.c_uint64 * 16),
+                ("tree_strict", C.c_uint32), ("pad2_", C.c_uint32), ("split", C.c_uint64 * 255)]
 
 
 class Stats(C.Structure):

@@ -42,6 +42,7 @@
 #define MODEL_MSD 1
 #define MODEL_CLOSED 2
 #define MODEL_L2PL 3
+#define MODEL_TREE 4
 
 typedef struct {
     uint32_t num_buckets;    /* K */
@@ -50,7 +51,8 @@ typedef struct {
     uint32_t sample_min;     /* ... but at least this (0 means 2K) ... */
     uint64_t sample_max;     /* ... and at most this (0 means no cap), never above n */
     uint64_t seed;           /* jitter of the sample positions */
-    uint32_t model;          /* 0 FMCD, 1 auto (two-level model iff lower max sample load), 2 two-level */
+    uint32_t model;          /* 0 FMCD, 1 auto (two-level model iff lower max sample load), 2 two-level,
+                              * 3 splitter tree */
     uint32_t leaves;         /* M leaves of the two-level model */
     uint32_t train_iters;    /* gradient steps of the two-level model */
     uint32_t sample_policy;  /* 0: S = ceil(n / divisor); 1: the paper's alpha*K - 1 */
@@ -74,6 +76,9 @@ typedef struct {
     uint32_t const0;          /* linear part unusable: every other key is in linear bucket 0 */
     uint32_t pad_;
     uint64_t heavy[16];       /* the heavy values' ords, ascending */
+    uint32_t tree_strict;     /* splitter tree: bucket = #{splitters < key} (1) or <= key (0) */
+    uint32_t pad2_;
+    uint64_t split[255];      /* splitter tree: the K-1 splitters' ords, ascending */
 } oracle_model;
 
 typedef struct {
@@ -518,6 +523,25 @@ static uint32_t bitlen(uint64_t v) {
 
 /* Model of the bucket keys[0..n) whose first key sits at offset lo_rel of its array.
  * l2 receives the two-level model when it is chosen (its leaf array is owned by the caller). */
+/* Splitter tree (the Decision Trees section: the comparison-based classifier of IPS4o, which the
+ * paper's models are measured against).  Splitters are the sample quantiles
+ * s_i = x[floor(i S / K)], i = 1 .. K-1, and a key goes to the number of splitters below it.  The
+ * comparison is strict, except when every splitter equals the sample's largest value: then keys
+ * equal to it must go past the splitters, or nothing would be split.  With at least two distinct
+ * sample values the smallest and the largest sampled value always land in different buckets. */
+static void fit_tree(const uint64_t* o, uint64_t S, uint32_t K, oracle_model* m) {
+    m->kind = MODEL_TREE;
+    m->degenerate = 0;
+    for (uint32_t i = 1; i < K; ++i) m->split[i - 1] = o[((uint64_t)i * S) / K];
+    m->tree_strict = m->split[0] < o[S - 1] ? 1u : 0u;
+}
+
+static uint32_t classify_tree(const oracle_model* m, uint64_t o) {
+    uint32_t b = 0;
+    for (uint32_t i = 0; i + 1 < m->K; ++i) b += (m->tree_strict ? m->split[i] < o : m->split[i] <= o) ? 1u : 0u;
+    return b;
+}
+
 /* Equality buckets (IPS4o; applied to the linear model): a value whose run in the sorted sample
  * is longer than S/K (run * K > S) is heavy; at most min(16, (K-4)/2) of them, the smallest
  * first.  The linear part is fitted by FMCD on the sample without the heavy runs, with K - 2E
@@ -580,6 +604,12 @@ static void fit_bucket(const void* keys, uint64_t n, int dtype, const oracle_par
     double* x = (double*)malloc((S ? S : 1) * sizeof(double));
     uint64_t* o = (uint64_t*)malloc((S ? S : 1) * sizeof(uint64_t));
     sorted_sample_ords(keys, n, dtype, lo_rel, S, p->seed, x, o);
+    if (p->model == 3 && S >= 1 && o[0] != o[S - 1]) {
+        fit_tree(o, S, K, m);
+        free(x);
+        free(o);
+        return;
+    }
     if (p->equality && fit_equality(x, o, S, K, m)) {
         free(x);
         free(o);
@@ -668,6 +698,7 @@ static uint32_t classify_equality(const oracle_model* m, uint64_t o, double v, i
 
 static uint32_t classify_key(const void* keys, uint64_t i, int dtype, const oracle_model* m, const l2pl_model* l2) {
     if (m->kind == MODEL_MSD) return (uint32_t)((oracle_ord_one(keys, i, dtype) - m->umin) >> m->shift);
+    if (m->kind == MODEL_TREE) return classify_tree(m, oracle_ord_one(keys, i, dtype));
     double v = oracle_val_one(keys, i, dtype);
     int neg = key_negative(keys, i, dtype);
     if (m->kind == MODEL_L2PL) return classify_l2pl(l2, m->K, v, neg);
