@@ -45,7 +45,7 @@ def test_splitters_are_sample_quantiles_and_buckets_match_searchsorted(dist, K):
 
 def test_every_splitter_at_the_max_uses_the_non_strict_rule():
     # a few 1.0 reach the sample, too few for a splitter: every splitter is 5.0, the maximum
-    k = np.array([1.0] * 300 + [5.0] * 99_700)
+    k = np.array([1.0] * 1500 + [5.0] * 98_500)
     np.random.default_rng(2).shuffle(k)
     p = tree_params(K=16, T=100)
     m, _, _ = oracle.fit_bucket(k, p)
@@ -57,7 +57,7 @@ def test_every_splitter_at_the_max_uses_the_non_strict_rule():
 
 
 def test_every_splitter_at_the_min_keeps_the_strict_rule():
-    k = np.array([1.0] * 99_700 + [5.0] * 300)
+    k = np.array([1.0] * 98_500 + [5.0] * 1500)
     np.random.default_rng(3).shuffle(k)
     p = tree_params(K=16, T=100)
     m, _, _ = oracle.fit_bucket(k, p)
