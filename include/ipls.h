@@ -51,7 +51,9 @@ typedef enum {
 typedef enum {
     IPLS_MODEL_FMCD = 0, /* linear model fitted by FMCD (the paper's IPLS) */
     IPLS_MODEL_AUTO = 1, /* two-level model iff its max sample load is strictly lower than FMCD's */
-    IPLS_MODEL_L2PL = 2  /* two-level model whenever it splits the sample (FMCD otherwise) */
+    IPLS_MODEL_L2PL = 2, /* two-level model whenever it splits the sample (FMCD otherwise) */
+    IPLS_MODEL_TREE = 3  /* splitter tree over the K-1 sample quantiles (IPS4o's comparison classifier,
+                          * the Decision Trees section): the A/B baseline of the learned models */
 } ipls_model_policy;
 
 /* Tuning parameters.  ipls_default_params() fills the defaults. */

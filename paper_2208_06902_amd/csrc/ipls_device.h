@@ -22,8 +22,15 @@ enum : uint32_t {
     kKindClosedKeep = 2,  // homogeneous bucket already in the caller's buffer: nothing to do
     kKindClosedMove = 3,  // homogeneous bucket in the scratch buffer: copied through bucket 0
     kKindL2pl = 4,        // two-level piecewise-linear CDF model
-    kKindPending = 5      // degenerate fit awaiting the bucket's min/max ord
+    kKindPending = 5,     // degenerate fit awaiting the bucket's min/max ord
+    kKindTree = 6         // splitter tree over K-1 sample quantiles (shift = 1: strict comparison)
 };
+
+// Number of leaf-table doubles a model's classification reads from LDS (two-level model: 4 M
+// coefficients; splitter tree: K - 1 splitter ords).
+__device__ inline uint32_t model_table_size(uint32_t kind, uint32_t K, uint32_t M) {
+    return kind == kKindL2pl ? 4 * M : (kind == kKindTree ? K - 1 : 0u);
+}
 
 // One bucket to partition at the current level: keys [lo, lo+n) of the level's source buffer;
 // lo_rel is its offset inside its top-level segment (sample positions hash it).
@@ -252,12 +259,27 @@ __device__ inline uint32_t classify_equality(const Model& m, typename Key<DT>::T
     return b + 2u * less + eq;
 }
 
+// Splitter tree (the Decision Trees section: IPS4o's classifier): the number of splitters below
+// the key (strict) or at most the key, by a branchless search over the sorted K-1 splitters.
+__device__ inline uint32_t classify_tree(const uint64_t* split, uint32_t K, uint64_t o, bool strict) {
+    const uint32_t ns = K - 1;
+    uint32_t step = 1u << (31 - __clz((int)ns)), b = 0;
+    for (; step; step >>= 1) {
+        if (b + step <= ns) {
+            const uint64_t sv = split[b + step - 1];
+            if (strict ? sv < o : sv <= o) b += step;
+        }
+    }
+    return b;
+}
+
 template <int DT>
 __device__ inline uint32_t classify_key(const Model& m, const double* leaf, uint32_t K, uint32_t M,
                                         typename Key<DT>::T u) {
     using KT = Key<DT>;
     switch (m.kind) {
         case kKindDigit: return (uint32_t)((KT::ord(u) - m.umin) >> m.shift);
+        case kKindTree: return classify_tree((const uint64_t*)leaf, K, KT::ord(u), m.shift != 0);
         case kKindClosedMove: return 0u;
         case kKindL2pl: return classify_l2pl(m.a, m.b, M, leaf, K, KT::val(u), KT::neg(u));
         default:

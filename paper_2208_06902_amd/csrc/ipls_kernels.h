@@ -682,6 +682,27 @@ __global__ __launch_bounds__(256) void k_minmax(const Item* items, const uint64_
 // Final model of every item: closes homogeneous buckets, sets the digit fallback, and picks the
 // two-level model when the policy and the sample loads ask for it.
 // stat_counts: [0] closed buckets, [1] digit splits, [2] two-level models, [3] keys in closed buckets
+// Splitter tree of every item: from the sorted sample, splitters s_i = x[floor(i S / K)],
+// i = 1 .. K-1 (ords, into the item's leaf table), compared strictly unless every splitter is
+// the sample's largest value.  tree[i] = 1 (strict), 2 (non-strict), or 0 when the sample holds
+// a single value (the degenerate rule decides).
+template <int DT>
+__global__ __launch_bounds__(256) void k_tree(const typename Key<DT>::T* sample, const uint64_t* sample_off,
+                                              uint64_t num_items, uint32_t K, double* leaves, uint32_t* tree) {
+    using KT = Key<DT>;
+    const uint64_t i = blockIdx.x;
+    if (i >= num_items) return;
+    const uint64_t off = sample_off[i], S = sample_off[i + 1] - off;
+    const typename KT::T* xs = sample + off;
+    const bool usable = S >= 1 && KT::ord(xs[0]) != KT::ord(xs[S - 1]);
+    uint64_t* split = (uint64_t*)(leaves + i * 4 * kMaxLeaves);
+    if (usable)
+        for (uint32_t q = threadIdx.x; q + 1 < K; q += blockDim.x)
+            split[q] = KT::ord(xs[((uint64_t)(q + 1) * S) / K]);
+    if (threadIdx.x == 0)
+        tree[i] = !usable ? 0u : (KT::ord(xs[S / K]) < KT::ord(xs[S - 1]) ? 1u : 2u);
+}
+
 // Equality buckets: the heavy values of every item's sorted sample and the sample without their
 // runs (one workgroup per item).  A value whose run is longer than S/K (run * K > S) spans at
 // least S/K + 1 positions, so it sits at one of the positions 0, m, 2m, ... with m = floor(S/K)+1;
@@ -771,11 +792,18 @@ __global__ __launch_bounds__(256) void k_heavy(const typename Key<DT>::T* sample
 
 template <int DT>
 __global__ void k_finalize(const Item* items, Model* models, const Model* roots, uint64_t num_items, uint32_t K,
-                           int src_is_scratch, uint32_t policy, uint64_t* stat_counts, const EqInfo* eq) {
+                           int src_is_scratch, uint32_t policy, uint64_t* stat_counts, const EqInfo* eq,
+                           const uint32_t* tree) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= num_items) return;
     Model m = models[i];
     m.neq = 0;
+    if (tree && tree[i]) {  // splitter tree: its splitters are in the item's leaf table
+        m.kind = kKindTree;
+        m.shift = tree[i] == 1 ? 1u : 0u;
+        models[i] = m;
+        return;
+    }
     if (eq && eq[i].neq) {
         // equality buckets: the linear part (fitted without the heavy runs) or a constant bucket 0
         m.neq = eq[i].neq;
@@ -799,7 +827,7 @@ __global__ void k_finalize(const Item* items, Model* models, const Model* roots,
             m.shift = sh > 0 ? (uint32_t)sh : 0u;
             atomicAdd((unsigned long long*)&stat_counts[1], 1ull);
         }
-    } else if (m.kind == kKindLinear && policy != 0 && m.l2_ok) {
+    } else if (m.kind == kKindLinear && (policy == 1 || policy == 2) && m.l2_ok) {
         const bool splits = m.load_l2 < m.S;
         if (splits && (policy == 2 || m.load_l2 < m.load_lin)) {
             m.kind = kKindL2pl;
@@ -939,8 +967,8 @@ __global__ __launch_bounds__(64 * NW) void k_classify_hist(const Item* items, co
     T cur[IPT], nxt[IPT];
     uint32_t nop[1];
     if (counting) load_tile<DT, false, IPT>(src, nullptr, it.lo + (t_first - t0) * TILE, tile_n(t_first), wbase, cur, nop);
-    if (m.kind == kKindL2pl)
-        for (uint32_t q = tid; q < 4 * M; q += NT) s_leaf[q] = leaves[(uint64_t)i * 4 * kMaxLeaves + q];
+    for (uint32_t q = tid, nq = model_table_size(m.kind, K, M); q < nq; q += NT)
+        s_leaf[q] = leaves[(uint64_t)i * 4 * kMaxLeaves + q];
     for (uint32_t b = tid; b < kChunk * kMaxBuckets; b += NT) (&h[0][0])[b] = 0;
     __syncthreads();
     for (uint64_t t = t_first; t < t_end; ++t) {
@@ -1088,9 +1116,8 @@ __global__ __launch_bounds__(64 * NW) void k_scatter(const Item* items, const ui
     if (tid < K)
         dbase = it.lo + bstart[(uint64_t)i * K + tid] + chunk_pref[c * K + tid] +
                 tile_pref[t * K + tid];
-    if (m.kind == kKindL2pl)
-        for (uint32_t q = tid; q < 4 * M; q += NT)
-            ((double*)s_stage)[q] = leaves[(uint64_t)i * 4 * kMaxLeaves + q];
+    for (uint32_t q = tid, nq = model_table_size(m.kind, K, M); q < nq; q += NT)
+        ((double*)s_stage)[q] = leaves[(uint64_t)i * 4 * kMaxLeaves + q];
     for (uint32_t b = tid; b < NW * kMaxBuckets; b += NT) (&s_wcnt[0][0])[b] = 0;
     __syncthreads();
     classify_tile<DT, IPT>(tn, wbase, m, s_leaf, K, M, k, bk);

@@ -60,7 +60,7 @@ ipls_status ensure(Buf& b, size_t bytes) {
 struct Depth {
     Buf scratch, spay, items[2], base, sample_base, counters, plan, tile_off, sample_off, fit_off, chunk_off, tile_map,
         fit_map, chunk_map, models, masks, hist, bstart, tile_pref, chunk_sum, chunk_pref, sample, leaves, seg, roots,
-        leaf_first, leaf_last, eqinfo, rsample, copy, copy_off, copy_map;
+        leaf_first, leaf_last, eqinfo, rsample, copy, copy_off, copy_map, treeflag;
     Plan* plan_h = nullptr;
 };
 
@@ -84,7 +84,7 @@ void release_device(Device& dv) {
                        &D.tile_off, &D.sample_off, &D.fit_off, &D.chunk_off, &D.tile_map, &D.fit_map, &D.chunk_map,
                        &D.models, &D.masks, &D.hist, &D.bstart, &D.tile_pref, &D.chunk_sum, &D.chunk_pref, &D.sample,
                        &D.leaves, &D.seg, &D.roots, &D.leaf_first, &D.leaf_last, &D.eqinfo, &D.rsample, &D.copy,
-                       &D.copy_off, &D.copy_map})
+                       &D.copy_off, &D.copy_map, &D.treeflag})
             release(*b);
         if (D.plan_h) (void)hipHostFree(D.plan_h);
         D.plan_h = nullptr;
@@ -499,7 +499,16 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         ST_TRY((fit_level<DT>(D, s, ni, pl.max_S, pl.total_fit_chunks,
                               eq ? (const T*)D.rsample.p : (const T*)D.sample.p, (const uint64_t*)D.sample_off.p,
                               (const uint64_t*)D.fit_off.p, models, K, eq)));
-        if (P.model != 0)
+        const uint32_t* tree = nullptr;
+        if (P.model == 3) {
+            ST_TRY(ensure(D.leaves, ni * 4 * kMaxLeaves * 8));
+            ST_TRY(ensure(D.treeflag, ni * 4));
+            k_tree<DT><<<(unsigned)ni, 256, 0, s>>>((const T*)D.sample.p, (const uint64_t*)D.sample_off.p, ni, K,
+                                                    (double*)D.leaves.p, (uint32_t*)D.treeflag.p);
+            LAUNCH_CHECK();
+            tree = (const uint32_t*)D.treeflag.p;
+        }
+        if (P.model == 1 || P.model == 2)
             ST_TRY((train_l2pl<DT>(D, s, ni, pl.max_S, pl.total_fit_chunks, (const T*)D.sample.p,
                                    (const uint64_t*)D.sample_off.p, (const uint64_t*)D.fit_off.p, models, K, P.leaves,
                                    P.train_iters)));
@@ -510,7 +519,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         LAUNCH_CHECK();
         k_finalize<DT><<<(unsigned)((ni + 255) / 256), 256, 0, s>>>(items, models, (const Model*)D.roots.p, ni, K,
                                                                 src_scratch ? 1 : 0, P.model,
-                                                                cnt + C_STATS, eq);
+                                                                cnt + C_STATS, eq, tree);
         LAUNCH_CHECK();
 
         // classify + per-tile counts, scan of the counts, bucket starts
@@ -649,7 +658,7 @@ ipls_status check_params(const ipls_params& p) {
     if (p.tile_keys != 0 && p.tile_keys != kTile && p.tile_keys != kSmallTile) return IPLS_ERR_INVALID;
     const uint64_t smin = p.sample_min ? p.sample_min : (p.sample_policy == 1 ? 0 : 2ull * p.num_buckets);
     if (smin > p.base_case_max) return IPLS_ERR_INVALID;
-    if (p.model > 2) return IPLS_ERR_INVALID;
+    if (p.model > 3) return IPLS_ERR_INVALID;
     if (p.leaves < 4) return IPLS_ERR_INVALID;
     if (p.num_buckets > (uint32_t)kMaxBuckets || p.base_case_max > (uint32_t)kMaxBase ||
         p.leaves > (uint32_t)kMaxLeaves)

@@ -45,7 +45,7 @@ def test_host_only_entry_points():
 
 
 @pytest.mark.parametrize("field,value", [("sample_policy", 2), ("num_buckets", 3), ("sample_divisor", 1),
-                                         ("sample_min", 5000), ("model", 3), ("leaves", 2)])
+                                         ("sample_min", 5000), ("model", 4), ("leaves", 2)])
 def test_invalid_params_rejected_before_any_device_work(field, value):
     # argument errors return synchronously; the key pointer is never dereferenced
     if not os.path.exists(ipls.LIB_PATH):

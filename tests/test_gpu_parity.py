@@ -91,6 +91,22 @@ def test_equality_buckets_f32_and_heavy_specials():
     check_sort(u, None, equality=1, num_buckets=64, base_case_max=256)
 
 
+@pytest.mark.parametrize("dist", ["normal", "lognormal2", "zipf_u64", "root_dups", "uniform_int"])
+@pytest.mark.parametrize("kw", [dict(model=3), dict(model=3, num_buckets=37, base_case_max=200),
+                                dict(model=3, num_buckets=64, base_case_max=1000, tile_keys=2048)])
+def test_sort_splitter_tree(dist, kw):
+    k = gen.make(dist, 200_000, 29)
+    check_sort(k, gen.index_payload(k.size), **kw)
+
+
+def test_splitter_tree_f32_specials():
+    r = np.random.default_rng(8)
+    k = r.standard_normal(120_000).astype(np.float32)
+    k[::5] = np.float32(np.nan)
+    k[1::13] = -np.float32(0.0)
+    check_sort(k, None, model=3, num_buckets=16, base_case_max=64)
+
+
 def test_sort_u64_uniform_and_zipf_payload():
     check_sort(gen.u64_uniform(400_000, 7))
     z = gen.zipf_u64(300_000, 8)
