@@ -600,7 +600,8 @@ def main():
         "config": {"workload": f"plain single-array sort, {n} fp64 keys per step, keys only, cycling "
                                + "/".join(dists), "n": n, "num_buckets": 256, "base_case_max": 4096,
                    "sample": f"1% jittered stratified, capped at {args.sample_max} keys",
-                   "model": ("FMCD", "auto (learned model when lower max load)", "learned")[args.sort_model],
+                   "model": ("FMCD", "auto (learned model when lower max load)", "learned",
+                             "splitter tree")[args.sort_model],
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu_baseline,
