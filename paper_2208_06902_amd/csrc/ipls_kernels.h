@@ -1627,138 +1627,21 @@ __device__ inline void base_large_stable(const BaseItem& bi, typename Key<DT>::T
 //  * otherwise a key's final place is its digit's start plus the keys of the digit before it in
 //    (ord, position) order; a digit of more than kSubMax keys (skewed buckets) sends the bucket to
 //    the merge sort instead.
-// LDS space of sort_keys_lds for one workgroup of NW waves and IPT keys a thread.
-template <typename O, int NW, int IPT>
-struct SortKeysSmem {
-    static constexpr int CAP = 64 * NW * IPT, PCAP = CAP + CAP / 16;
-    O k[PCAP];
-    uint32_t c[CAP + 1];
-    uint64_t scan[16];
-    O red[3][NW];
-    uint32_t most[NW];
-};
-
-// Sorts the n keys (ords) a workgroup holds in registers (o[r]: key wbase + 64 r + lane, padding
-// slots hold the largest ord) into LDS.  oref is any one of the keys.  Returns true when the
-// result is at sm.k[pad16(j)] (the merge-sort fallback), false when it is at sm.k[j].
-template <typename O, int NW, int IPT>
-__device__ inline bool sort_keys_lds(const O (&o)[IPT], uint32_t n, O oref, SortKeysSmem<O, NW, IPT>& sm) {
-    constexpr int NT = 64 * NW, CAP = NT * IPT, MT = CAP / 16;
-    constexpr int DB = CAP >= 4096 ? 12 : CAP >= 2048 ? 11 : CAP >= 1024 ? 10 : 9;  // digit bits
-    constexpr int ND = 1 << DB, CPT = ND / NT;                                     // digits, per thread
-    static_assert(ND == CAP && CPT == IPT, "one digit per key slot");
-    constexpr O kPad = (O)~(O)0;
-    const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
-    const uint32_t wbase = wave * kWave * IPT;
-    O mn = kPad, mx = 0, ov = 0;
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        if (wbase + r * kWave + lane < n) {
-            mn = o[r] < mn ? o[r] : mn;
-            mx = o[r] > mx ? o[r] : mx;
-            ov |= (O)(o[r] - oref);
-        }
-    }
-    mn = (O)~wave_max((O)~mn);
-    mx = wave_max(mx);
-#pragma unroll
-    for (int sft = 32; sft >= 1; sft >>= 1) ov |= (O)__shfl_xor(ov, sft, kWave);
-    for (uint32_t d = tid; d <= (uint32_t)ND; d += NT) sm.c[d] = 0;
-    if (lane == 0) {
-        sm.red[0][wave] = mn;
-        sm.red[1][wave] = mx;
-        sm.red[2][wave] = ov;
-    }
-    __syncthreads();
-    mn = sm.red[0][0];
-    mx = sm.red[1][0];
-    ov = sm.red[2][0];
-    for (int w = 1; w < NW; ++w) {
-        mn = sm.red[0][w] < mn ? sm.red[0][w] : mn;
-        mx = sm.red[1][w] > mx ? sm.red[1][w] : mx;
-        ov |= sm.red[2][w];
-    }
-    const int z = ov ? __builtin_ctzll((unsigned long long)ov) : 0;
-    const int nbits = (int)bit_length((uint64_t)((O)(mx - mn) >> z));
-    const int shift = z + (nbits > DB ? nbits - DB : 0);
-    const bool exact = nbits <= DB;
-    uint32_t dg[IPT], sl[IPT];
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        if (wbase + r * kWave + lane < n) {
-            dg[r] = (uint32_t)((uint64_t)(o[r] - mn) >> shift);
-            sl[r] = atomicAdd(&sm.c[dg[r]], 1u);
-        }
-    }
-    __syncthreads();
-    // digit starts: thread t owns digits [t CPT, (t+1) CPT)
-    uint32_t c[CPT], sum = 0, most = 0;
-#pragma unroll
-    for (int i = 0; i < CPT; ++i) {
-        c[i] = sm.c[tid * CPT + i];
-        sum += c[i];
-        most = c[i] > most ? c[i] : most;
-    }
-    most = wave_max(most);
-    if (lane == 0) sm.most[wave] = most;
-    uint64_t all;
-    uint32_t e = (uint32_t)block_exclusive_sum<uint64_t>(sum, sm.scan, &all);  // synchronises
-#pragma unroll
-    for (int i = 0; i < CPT; ++i) {
-        sm.c[tid * CPT + i] = e;
-        e += c[i];
-    }
-    if (tid == 0) sm.c[ND] = n;
-    most = 0;
-    for (int w = 0; w < NW; ++w) most = sm.most[w] > most ? sm.most[w] : most;
-    __syncthreads();
-
-    if (!exact && most > kSubMax) {
-        // merge sort: keys to LDS at their input positions (padding keys at the end), then sort
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) sm.k[pad16(wbase + r * kWave + lane)] = o[r];
-        __syncthreads();
-        merge_sort_lds<O, false, MT>(sm.k, nullptr, (int)tid, tid < (uint32_t)MT);
-        return true;
-    }
-#pragma unroll
-    for (int r = 0; r < IPT; ++r)
-        if (wbase + r * kWave + lane < n) sm.k[sm.c[dg[r]] + sl[r]] = o[r];
-    __syncthreads();
-    if (!exact) {
-        O xs[IPT];
-        uint32_t np[IPT];
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            const uint32_t j = wbase + r * kWave + lane;
-            if (j < n) {
-                xs[r] = sm.k[j];
-                const uint32_t d = (uint32_t)((uint64_t)(xs[r] - mn) >> shift);
-                const uint32_t start = sm.c[d], end = sm.c[d + 1];
-                uint32_t before = 0;
-                for (uint32_t q = start; q < end; ++q) {
-                    const O y = sm.k[q];
-                    before += (y < xs[r] || (y == xs[r] && q < j)) ? 1u : 0u;
-                }
-                np[r] = start + before;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < IPT; ++r)
-            if (wbase + r * kWave + lane < n) sm.k[np[r]] = xs[r];
-        __syncthreads();
-    }
-    return false;
-}
-
 template <int DT, int NW, int IPT>
 __device__ inline void base_large_keys(const BaseItem& bi, typename Key<DT>::T* keys,
                                        const typename Key<DT>::T* skeys) {
     using KT = Key<DT>;
     using O = typename KT::O;
+    constexpr int NT = 64 * NW, CAP = NT * IPT, PCAP = CAP + CAP / 16, MT = CAP / 16;
+    constexpr int DB = CAP >= 4096 ? 12 : CAP >= 2048 ? 11 : CAP >= 1024 ? 10 : 9;  // digit bits
+    constexpr int ND = 1 << DB, CPT = ND / NT;                                     // digits, per thread
+    static_assert(ND == CAP && CPT == IPT, "one digit per key slot");
     constexpr O kPad = (O)~(O)0;
-    __shared__ SortKeysSmem<O, NW, IPT> sm;
+    __shared__ O s_k[PCAP];
+    __shared__ uint32_t s_c[ND + 1];
+    __shared__ uint64_t s_scan[16];
+    __shared__ O s_red[3][NW];
+    __shared__ uint32_t s_most[NW];
     const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
     const uint32_t n = bi.n;
     const typename KT::T* src = bi.from_scratch ? skeys : keys;
@@ -1775,84 +1658,115 @@ __device__ inline void base_large_keys(const BaseItem& bi, typename Key<DT>::T* 
         for (int r = 0; r < IPT; ++r) o[r] = wbase + r * kWave + lane < n ? (O)KT::ord(v[r]) : kPad;
     }
     const O oref = (O)KT::ord(src[bi.lo]);  // n >= 1
-    const bool merged = sort_keys_lds<O, NW, IPT>(o, n, oref, sm);
+    O mn = kPad, mx = 0, ov = 0;
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
-        const uint32_t j = wbase + r * kWave + lane;
-        if (j < n) keys[bi.lo + j] = KT::from_ord((uint64_t)sm.k[merged ? pad16(j) : j]);
+        if (wbase + r * kWave + lane < n) {
+            mn = o[r] < mn ? o[r] : mn;
+            mx = o[r] > mx ? o[r] : mx;
+            ov |= (O)(o[r] - oref);
+        }
     }
-}
+    mn = (O)~wave_max((O)~mn);
+    mx = wave_max(mx);
+#pragma unroll
+    for (int sft = 32; sft >= 1; sft >>= 1) ov |= (O)__shfl_xor(ov, sft, kWave);
+    for (uint32_t d = tid; d <= (uint32_t)ND; d += NT) s_c[d] = 0;
+    if (lane == 0) {
+        s_red[0][wave] = mn;
+        s_red[1][wave] = mx;
+        s_red[2][wave] = ov;
+    }
+    __syncthreads();
+    mn = s_red[0][0];
+    mx = s_red[1][0];
+    ov = s_red[2][0];
+    for (int w = 1; w < NW; ++w) {
+        mn = s_red[0][w] < mn ? s_red[0][w] : mn;
+        mx = s_red[1][w] > mx ? s_red[1][w] : mx;
+        ov |= s_red[2][w];
+    }
+    const int z = ov ? __builtin_ctzll((unsigned long long)ov) : 0;
+    const int nbits = (int)bit_length((uint64_t)((O)(mx - mn) >> z));
+    const int shift = z + (nbits > DB ? nbits - DB : 0);
+    const bool exact = nbits <= DB;
+    uint32_t dg[IPT], sl[IPT];
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        if (wbase + r * kWave + lane < n) {
+            dg[r] = (uint32_t)((uint64_t)(o[r] - mn) >> shift);
+            sl[r] = atomicAdd(&s_c[dg[r]], 1u);
+        }
+    }
+    __syncthreads();
+    // digit starts: thread t owns digits [t CPT, (t+1) CPT)
+    uint32_t c[CPT], sum = 0, most = 0;
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+        c[i] = s_c[tid * CPT + i];
+        sum += c[i];
+        most = c[i] > most ? c[i] : most;
+    }
+    most = wave_max(most);
+    if (lane == 0) s_most[wave] = most;
+    uint64_t all;
+    uint32_t e = (uint32_t)block_exclusive_sum<uint64_t>(sum, s_scan, &all);  // synchronises
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+        s_c[tid * CPT + i] = e;
+        e += c[i];
+    }
+    if (tid == 0) s_c[ND] = n;
+    most = 0;
+    for (int w = 0; w < NW; ++w) most = s_most[w] > most ? s_most[w] : most;
+    __syncthreads();
 
-// Sample, sort and FMCD fit of every item whose sample has at most 4096 keys, one workgroup of
-// 512 threads per item: the same sample positions as k_sample, the keys sorted in LDS (and
-// written to the sample buffer for the other models), and the fit of k_fmcd_small read from LDS
-// (values converted from the sorted ords).  fit = 0 skips the fit (equality buckets fit a
-// reduced sample instead).
-template <int DT>
-__global__ __launch_bounds__(512) void k_sample_fit(const Item* items, uint64_t num_items, const uint64_t* sample_off,
-                                                    const typename Key<DT>::T* src, typename Key<DT>::T* sample,
-                                                    uint64_t seed, Model* models, uint32_t K, int fit) {
-    using KT = Key<DT>;
-    using O = typename KT::O;
-    constexpr int NW = 8, IPT = 8;
-    constexpr O kPad = (O)~(O)0;
-    __shared__ SortKeysSmem<O, NW, IPT> sm;
-    const uint64_t i = blockIdx.x;
-    if (i >= num_items) return;
-    const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
-    const uint32_t wbase = wave * kWave * IPT;
-    const Item it = items[i];
-    const uint64_t off = sample_off[i], S = sample_off[i + 1] - off;  // S <= 4096 (host-checked)
-    if (S == 0) {  // no sample (tiny K under the alpha*K - 1 policy): the fit is degenerate
-        if (fit && tid == 0) {
-            Model m = {};
-            model_degenerate(m);
-            models[i] = m;
+    if (!exact && most > kSubMax) {
+        // merge sort: keys to LDS at their input positions (padding keys at the end), then sort
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) s_k[pad16(wbase + r * kWave + lane)] = o[r];
+        __syncthreads();
+        merge_sort_lds<O, false, MT>(s_k, nullptr, (int)tid, tid < (uint32_t)MT);
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const uint32_t j = wbase + r * kWave + lane;
+            if (j < n) keys[bi.lo + j] = KT::from_ord((uint64_t)s_k[pad16(j)]);
         }
         return;
     }
-    const uint64_t q = it.n / S, rr = it.n % S;
-    const uint64_t stream = mix64(seed ^ mix64(it.lo_rel * kGamma + it.n));
-    auto position = [&](uint64_t j) {
-        const uint64_t a = j * q + (j * rr) / S;
-        const uint64_t b = (j + 1) * q + ((j + 1) * rr) / S;
-        return it.lo + a + mix64(stream + (j + 1) * kGamma) % (b - a);
-    };
-    O o[IPT];
+#pragma unroll
+    for (int r = 0; r < IPT; ++r)
+        if (wbase + r * kWave + lane < n) s_k[s_c[dg[r]] + sl[r]] = o[r];
+    __syncthreads();
+    if (!exact) {
+        O xs[IPT];
+        uint32_t np[IPT];
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const uint32_t j = wbase + r * kWave + lane;
+            if (j < n) {
+                xs[r] = s_k[j];
+                const uint32_t d = (uint32_t)((uint64_t)(xs[r] - mn) >> shift);
+                const uint32_t start = s_c[d], end = s_c[d + 1];
+                uint32_t before = 0;
+                for (uint32_t q = start; q < end; ++q) {
+                    const O y = s_k[q];
+                    before += (y < xs[r] || (y == xs[r] && q < j)) ? 1u : 0u;
+                }
+                np[r] = start + before;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < IPT; ++r)
+            if (wbase + r * kWave + lane < n) s_k[np[r]] = xs[r];
+        __syncthreads();
+    }
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
         const uint32_t j = wbase + r * kWave + lane;
-        o[r] = j < S ? (O)KT::ord(src[position(j)]) : kPad;
+        if (j < n) keys[bi.lo + j] = KT::from_ord((uint64_t)s_k[j]);
     }
-    const O oref = (O)KT::ord(src[position(0)]);
-    const bool merged = sort_keys_lds<O, NW, IPT>(o, (uint32_t)S, oref, sm);
-    auto at = [&](uint64_t j) { return sm.k[merged ? pad16((uint32_t)j) : (uint32_t)j]; };
-    for (uint64_t j = tid; j < S; j += blockDim.x) sample[off + j] = KT::from_ord((uint64_t)at(j));
-    if (!fit) return;
-    auto xv = [&](uint64_t j) { return KT::val(KT::from_ord((uint64_t)at(j))); };
-    Model m = {};
-    m.S = S;
-    bool usable = S >= 3 && isfinite(xv(0)) && isfinite(xv(S - 1));
-    if (usable) {
-        const uint64_t Dmax = S / 3;
-        uint64_t lo = 1, hi = Dmax + 1;
-        while (lo < hi) {
-            const uint64_t D = lo + ((hi - lo) >> 1);
-            const double u = fmcd_spread(xv(S - 1 - D), xv(D), K);
-            int fail = 0;
-            for (uint64_t w = tid; w + D < S; w += blockDim.x) fail |= !(xv(w + D) - xv(w) >= u);
-            if (__syncthreads_or(fail)) lo = D + 1;
-            else hi = D;
-        }
-        const uint64_t D = lo;
-        const uint64_t Du = D <= Dmax ? D : Dmax;
-        const double u = fmcd_spread(xv(S - 1 - Du), xv(Du), K);
-        fmcd_line(u, xv(S - 1 - D), xv(D), K, &m.a, &m.b);
-        m.D = D;
-        usable = fit_usable(m.a, m.b);
-    }
-    if (!usable) model_degenerate(m);
-    if (tid == 0) models[i] = m;
 }
 
 template <int DT, bool PAY, int NW, int IPT>

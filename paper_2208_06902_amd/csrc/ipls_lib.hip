@@ -25,7 +25,6 @@ namespace {
 constexpr uint32_t kSmallS = kFitLds;  // samples up to this size are fitted in one workgroup's LDS
 constexpr uint32_t kFitChunk = 2048;   // windows per workgroup in the multi-round fit
 constexpr uint32_t kCand = 15;         // candidate widths per fit round
-constexpr uint64_t kFusedSample = 4096;  // samples up to this size are gathered, sorted and fitted in one kernel
 constexpr uint32_t kSmallTile = 4 * kWave * kPassIPT;  // 2048 keys: 4 waves
 constexpr uint32_t kTile = 8 * kWave * kPassIPT;       // 4096 keys: 8 waves
 
@@ -482,18 +481,10 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         k_expand<<<(unsigned)((nt + 255) / 256), 256, 0, s>>>((const uint64_t*)D.tile_off.p, ni, nt,
                                                               (uint32_t*)D.tile_map.p);
         LAUNCH_CHECK();
-        // samples: gathered, sorted and fitted by one workgroup per item when they fit its LDS
-        const bool fused = pl.max_S <= kFusedSample;
-        if (fused) {
-            k_sample_fit<DT><<<(unsigned)ni, 512, 0, s>>>(items, ni, (const uint64_t*)D.sample_off.p, src,
-                                                          (T*)D.sample.p, P.seed, models, K, P.equality ? 0 : 1);
-            LAUNCH_CHECK();
-        } else {
-            k_sample<DT><<<(unsigned)((pl.total_samples + 255) / 256), 256, 0, s>>>(
-                items, ni, (const uint64_t*)D.sample_off.p, pl.total_samples, src, (T*)D.sample.p, P.seed);
-            LAUNCH_CHECK();
-            ST_TRY(sort_samples<DT>(dv, run, d, pl));
-        }
+        k_sample<DT><<<(unsigned)((pl.total_samples + 255) / 256), 256, 0, s>>>(
+            items, ni, (const uint64_t*)D.sample_off.p, pl.total_samples, src, (T*)D.sample.p, P.seed);
+        LAUNCH_CHECK();
+        ST_TRY(sort_samples<DT>(dv, run, d, pl));
 
         // FMCD fit (with equality buckets: on the sample without the heavy values' runs)
         const EqInfo* eq = nullptr;
@@ -505,10 +496,9 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             LAUNCH_CHECK();
             eq = (const EqInfo*)D.eqinfo.p;
         }
-        if (!fused || eq)
-            ST_TRY((fit_level<DT>(D, s, ni, pl.max_S, pl.total_fit_chunks,
-                                  eq ? (const T*)D.rsample.p : (const T*)D.sample.p, (const uint64_t*)D.sample_off.p,
-                                  (const uint64_t*)D.fit_off.p, models, K, eq)));
+        ST_TRY((fit_level<DT>(D, s, ni, pl.max_S, pl.total_fit_chunks,
+                              eq ? (const T*)D.rsample.p : (const T*)D.sample.p, (const uint64_t*)D.sample_off.p,
+                              (const uint64_t*)D.fit_off.p, models, K, eq)));
         const uint32_t* tree = nullptr;
         if (P.model == 3) {
             ST_TRY(ensure(D.leaves, ni * 4 * kMaxLeaves * 8));
