@@ -8,7 +8,10 @@
  * rest with an in-LDS base-case sort (paper: Proposed Algorithm chapter; the model and its
  * fit: Linear Models section; the sample -> sort -> train -> predict pipeline: Machine Learning
  * Models chapter).  Optionally a two-level piecewise-linear CDF model (Recursive Model Index
- * section) replaces FMCD on a bucket when its maximum sample load is lower.
+ * section) replaces FMCD on a bucket when its maximum sample load is lower; equality buckets
+ * (IPS4o's, for heavily repeated values) and IPS4o's splitter tree (the comparison classifier,
+ * Decision Trees section, as an A/B baseline) are available as options.  Beside the single-array
+ * sort: a segmented (batched) sort with an autotuner, and a request server.
  *
  * Conventions for every entry point:
  *   - Array pointers are DEVICE pointers unless marked "host".  The caller owns them; the
@@ -22,8 +25,10 @@
  *     payload the sort is stable, so the output is unique.
  *   - Argument errors are reported synchronously and nothing is enqueued.  No C++ exception
  *     crosses this interface.
- *   - Calls are serialised internally per process (one sort runs at a time); buffers the
- *     library allocates for its own use are cached per device and reused across calls.
+ *   - The plain entry points share one engine context per device: their calls are serialised
+ *     (one runs at a time), and the buffers the library allocates for its own use are cached in
+ *     that context and reused across calls.  The request server's lanes own contexts of their
+ *     own and run concurrently on their own streams.
  */
 #ifndef IPLS_H
 #define IPLS_H
@@ -127,8 +132,10 @@ ipls_status ipls_fit_model(const void* sample, size_t S, ipls_dtype dtype, int s
 /* One distribution pass over the whole array (the first level of ipls_sort_ex): sample, fit,
  * classify, stable scatter.  keys (and payload) are left partitioned into contiguous buckets in
  * bucket order; counts (device, K uint64) receives the bucket sizes; model (device, nullable)
- * receives the FMCD model used.  A bucket whose fit is degenerate is split by the digit
- * fallback or, when all its keys are equal, left as it is (counts then all zero). */
+ * receives the FMCD model used (with equality buckets: its linear part; with the splitter tree
+ * or a two-level model: the FMCD fit the pass computed alongside).  A bucket whose fit is
+ * degenerate is split by the digit fallback or, when all its keys are equal, left as it is
+ * (counts then all zero). */
 ipls_status ipls_partition(void* keys, uint32_t* payload, size_t n, ipls_dtype dtype, const ipls_params* p,
                            uint64_t* counts, ipls_linear_model* model, void* stream);
 
