@@ -132,10 +132,10 @@ ipls_status ipls_fit_model(const void* sample, size_t S, ipls_dtype dtype, int s
 /* One distribution pass over the whole array (the first level of ipls_sort_ex): sample, fit,
  * classify, stable scatter.  keys (and payload) are left partitioned into contiguous buckets in
  * bucket order; counts (device, K uint64) receives the bucket sizes; model (device, nullable)
- * receives the FMCD model used (with equality buckets: its linear part; with the splitter tree
- * or a two-level model: the FMCD fit the pass computed alongside).  A bucket whose fit is
- * degenerate is split by the digit fallback or, when all its keys are equal, left as it is
- * (counts then all zero). */
+ * receives the linear model the pass used: the FMCD line (with equality buckets, its linear
+ * part; with a two-level model, its root), or degenerate = 1 when the pass used none (the digit
+ * fallback, a closed bucket, or the splitter tree).  A bucket whose fit is degenerate is split by
+ * the digit fallback or, when all its keys are equal, left as it is (counts then all zero). */
 ipls_status ipls_partition(void* keys, uint32_t* payload, size_t n, ipls_dtype dtype, const ipls_params* p,
                            uint64_t* counts, ipls_linear_model* model, void* stream);
 
