@@ -399,6 +399,22 @@ __device__ inline uint64_t block_append(int ch, uint64_t keys, AppendScratch& sc
     return sc.gbase[ch] + woff + local;
 }
 
+// Inclusive max over the block of int values (blockDim.x a multiple of 64, at most 1024 threads);
+// `scratch` holds 16 values.
+__device__ inline int block_inclusive_max(int v, int* scratch) {
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+#pragma unroll
+    for (int s = 1; s < kWave; s <<= 1) {
+        const int o = __shfl_up(v, s, kWave);
+        if (lane >= (uint32_t)s) v = o > v ? o : v;
+    }
+    if (lane == kWave - 1) scratch[wave] = v;
+    __syncthreads();
+    for (uint32_t w = 0; w < wave && w < nw; ++w) v = scratch[w] > v ? scratch[w] : v;
+    __syncthreads();
+    return v;
+}
+
 __device__ inline uint32_t bit_length(uint64_t v) { return v ? 64u - (uint32_t)__clzll((long long)v) : 0u; }
 
 }  // namespace ipls

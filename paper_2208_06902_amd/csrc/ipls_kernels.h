@@ -1166,18 +1166,30 @@ __global__ __launch_bounds__(64 * NW) void k_scatter(const Item* items, const ui
 }
 
 // ------------------------------------------------------------------ worklist
-// Children of every item: > T keys -> next level's items; otherwise -> base case (a single key
-// needs the base case only to move out of the scratch buffer).  Closed buckets have no children.
+// Children of every item, one workgroup per item (thread b: bucket b): > T keys -> next level's
+// items; equality buckets are closed (moved back if they sit in the scratch buffer).  Buckets of
+// T/2 < n <= T keys go to the base case alone.  Runs of adjacent smaller buckets (1 <= n <= T/2,
+// not separated by a bucket with keys of another kind) are sorted together: buckets are in key
+// order and a key's bucket is a function of the key, so sorting the run as one range gives the
+// same result.  Inside a run, bucket b joins group floor(p_b / (T/2)) (p_b: the keys of the run
+// before it), so a group holds fewer than T keys; the group's first bucket emits it.  A group of
+// a single key already in the caller's buffer needs no work.
 __global__ __launch_bounds__(256) void k_worklist(const Item* items, uint64_t num_items, const Model* models,
                                                   const uint64_t* hist, const uint64_t* bstart, uint32_t K, uint32_t T,
                                                   int dst_is_scratch, Item* next, BaseItem* base, BaseLayout bl,
                                                   uint64_t* cnt, int next_slot, uint64_t next_cap, CopyItem* copy,
                                                   uint64_t copy_cap) {
     __shared__ AppendScratch sc;
-    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ uint64_t s_e[kMaxBuckets], s_p[kMaxBuckets], s_sum[kMaxBuckets];
+    __shared__ uint64_t s_scan[16];
+    __shared__ int s_iscan[16];
+    __shared__ int s_prev[kMaxBuckets + 1];
+    const uint64_t i = blockIdx.x;
+    const uint32_t b = threadIdx.x;
     uint64_t c = 0, lo = 0, lo_rel = 0;
-    if (g < num_items * K) {
-        const uint64_t i = g / K;
+    bool breaker = false;
+    if (i < num_items && b < K) {
+        const uint64_t g = i * K + b;
         const uint32_t kind = models[i].kind;
         if (kind != kKindClosedKeep && kind != kKindClosedMove) {
             c = hist[g];
@@ -1188,7 +1200,7 @@ __global__ __launch_bounds__(256) void k_worklist(const Item* items, uint64_t nu
             // an equality bucket holds one value: closed here; moved back if it sits in the scratch buffer
             const uint32_t neq = kind == kKindLinear ? models[i].neq : 0u;
             bool is_eq = false;
-            for (uint32_t e = 0; e < neq; ++e) is_eq |= models[i].eqb[e] == (uint32_t)(g % K);
+            for (uint32_t e = 0; e < neq; ++e) is_eq |= models[i].eqb[e] == b;
             if (is_eq && c > 0) {
                 atomicAdd((unsigned long long*)&cnt[C_EQCLOSED], 1ull);
                 if (dst_is_scratch) {
@@ -1197,15 +1209,49 @@ __global__ __launch_bounds__(256) void k_worklist(const Item* items, uint64_t nu
                     atomicAdd((unsigned long long*)&cnt[C_COPYKEYS], (unsigned long long)c);
                 }
                 c = 0;  // neither an item nor a base-case bucket
+                breaker = true;
             }
         }
     }
-    const bool small = c >= 2 ? c <= T : (c == 1 && dst_is_scratch);
-    const int cls = base_class((uint32_t)(c <= T ? c : 1));
-    const int ch = c > T ? 0 : (small ? 1 + cls : -1);
-    const uint64_t q = block_append(ch, c, sc, &cnt[next_slot], &cnt[C_CLS], &cnt[C_BASEKEYS]);
-    if (ch == 0 && q < next_cap) next[q] = Item{lo, c, lo_rel, 0};
-    if (ch > 0 && q < bl.cap[cls]) base[bl.off[cls] + q] = BaseItem{lo, (uint32_t)c, (uint32_t)dst_is_scratch};
+    const uint64_t half = T / 2 > 0 ? T / 2 : 1;
+    const bool small = c >= 1 && c <= half;
+    breaker = breaker || c > half;
+    // runs of small buckets: run start = one past the last breaker before b
+    const int last_break = block_inclusive_max(breaker ? (int)b : -1, s_iscan);
+    const uint32_t run_start = (uint32_t)(last_break + 1);  // for a breaker itself: b + 1 (unused)
+    uint64_t tot;
+    const uint64_t e = block_exclusive_sum<uint64_t>(small ? c : 0, s_scan, &tot);
+    s_e[b] = e;
+    __syncthreads();
+    const uint64_t p = small ? e - s_e[run_start < blockDim.x ? run_start : b] : 0;
+    s_p[b] = p;
+    s_sum[b] = 0;
+    // the small bucket before b: the inclusive max of thread b - 1, passed through LDS
+    const int prev_small = block_inclusive_max(small ? (int)b : -1, s_iscan);
+    s_prev[b + 1] = prev_small;
+    if (b == 0) s_prev[0] = -1;
+    __syncthreads();
+    const int ps = s_prev[b];
+    const bool leader = small && (ps < (int)run_start || s_p[ps] / half != p / half);
+    const int lead = block_inclusive_max(leader ? (int)b : -1, s_iscan);
+    if (small) atomicAdd((unsigned long long*)&s_sum[lead], (unsigned long long)c);
+    __syncthreads();
+    int ch = -1;
+    uint64_t n = 0;
+    if (c > T) {
+        ch = 0;
+        n = c;
+    } else if (c > half) {
+        n = c;
+        ch = 1 + base_class((uint32_t)c);
+    } else if (leader) {
+        n = s_sum[b];
+        if (n >= 2 || dst_is_scratch) ch = 1 + base_class((uint32_t)n);
+    }
+    const int cls = ch > 0 ? ch - 1 : 0;
+    const uint64_t q = block_append(ch, n, sc, &cnt[next_slot], &cnt[C_CLS], &cnt[C_BASEKEYS]);
+    if (ch == 0 && q < next_cap) next[q] = Item{lo, n, lo_rel, 0};
+    if (ch > 0 && q < bl.cap[cls]) base[bl.off[cls] + q] = BaseItem{lo, (uint32_t)n, (uint32_t)dst_is_scratch};
 }
 
 // Equality buckets a level wrote to the scratch buffer move back to the caller's buffer as they

@@ -580,7 +580,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         }
 
         // next level
-        k_worklist<<<(unsigned)((ni * K + 255) / 256), 256, 0, s>>>(
+        k_worklist<<<(unsigned)ni, 256, 0, s>>>(
             items, ni, models, (const uint64_t*)D.hist.p, (const uint64_t*)D.bstart.p, K, T_, src_scratch ? 0 : 1,
             (Item*)D.items[cur ^ 1].p, (BaseItem*)D.base.p, bl, cnt, C_ITEMS0 + (cur ^ 1), item_cap,
             (CopyItem*)D.copy.p, copy_cap);
