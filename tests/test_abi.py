@@ -61,3 +61,25 @@ def test_unknown_param_name_is_an_error():
         pytest.skip("libipls.so not built")
     with pytest.raises(TypeError):
         ipls.default_params(sample_polciy=1)
+
+
+def test_host_side_argument_errors():
+    # all reported synchronously, before any device work
+    if not os.path.exists(ipls.LIB_PATH):
+        pytest.skip("libipls.so not built")
+    lib = ipls.load()
+    p = ipls.default_params()
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.ipls_sort_ex(None, None, 10, ipls.F64, ctypes.byref(p), None, 0, None, None) == 1  # null keys
+    assert lib.ipls_sort_ex(fake, None, 10, 7, ctypes.byref(p), None, 0, None, None) == 2  # unknown dtype
+    assert lib.ipls_sort_ex(ctypes.c_void_p((1 << 20) + 4), None, 10, ipls.F64, ctypes.byref(p), None, 0,
+                            None, None) == 1  # misaligned fp64 keys
+    need = ipls.workspace_bytes(1000, ipls.F64, False)
+    assert lib.ipls_sort_ex(fake, None, 1000, ipls.F64, ctypes.byref(p), fake, need - 1, None, None) == 1
+    assert lib.ipls_sort_ex(fake, None, 1000, ipls.F64, ctypes.byref(p), ctypes.c_void_p((1 << 20) + 8), need,
+                            None, None) == 1  # workspace not 256-byte aligned
+    assert lib.ipls_sort_segmented(None, None, fake, 3, ipls.F64, None, None, None) == 1
+    assert lib.ipls_fit_model(fake, 100, ipls.F64, 1, 3, fake, None) == 1  # K < 4
+    assert lib.ipls_l2pl_train(fake, 2, 256, 256, 4, fake, fake, None, None) == 1  # S < 3
+    big = ipls.default_params(num_buckets=512)
+    assert lib.ipls_sort_ex(fake, None, 10, ipls.F64, ctypes.byref(big), None, 0, None, None) == 6  # K > 256
