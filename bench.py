@@ -178,7 +178,7 @@ def bench_large_u64(args):
     work = torch.empty_like(src)
     pay0 = torch.arange(n, dtype=torch.int32, device=dev) if zipf else None
     pay = torch.empty_like(pay0) if zipf else None
-    params = ipls.default_params(sample_max=args.sample_max, equality=args.equality)
+    params = ipls.default_params(sample_max=args.sample_max, equality=args.equality, inherit=args.inherit)
     stream = torch.cuda.current_stream()
     ipls.profile_enable(True)
     ms, stats = [], None
@@ -211,7 +211,7 @@ def bench_large_u64(args):
             if zipf else "plain single-array sort, 1000000000 uniform uint64 keys, keys only")
     line = _line(n / (mean_ms / 1e3), mean_ms, args.steps, args.warmup, "u64",
                  {"workload": desc, "n": n, "num_buckets": 256, "base_case_max": 4096,
-                  "sample": f"1% jittered stratified, capped at {args.sample_max} keys", "model": "FMCD",
+                  "sample": sample_label(args), "model": "FMCD",
                   "equality_buckets": bool(args.equality), "parallelism": "single GPU"},
                  roofline={"kernel": "k_scatter", "bound": "hbm",
                            "achieved": round(sc_gbs, 1) if sc_gbs else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -431,6 +431,11 @@ def bench_served(args):
     print(json.dumps(line), flush=True)
 
 
+def sample_label(args) -> str:
+    cap = f"capped at {args.sample_max} keys" if args.sample_max else "uncapped"
+    return f"1% jittered stratified, {cap}" + (", inherited by children" if args.inherit else "")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -443,6 +448,8 @@ def main():
     ap.add_argument("--tile-keys", type=int, default=0, help="keys per distribution tile (0 = library default)")
     ap.add_argument("--sort-model", type=int, default=0, help="sort: 0 FMCD (default), 1 auto, 2 learned")
     ap.add_argument("--equality", type=int, default=0, help="sort, u64, zipf: 1 = equality buckets for heavy values")
+    ap.add_argument("--inherit", type=int, default=0,
+                    help="sort, u64, zipf: 1 = children reuse their part of the parent's sample")
     ap.add_argument("--workload", choices=("sort", "u64", "zipf", "batched", "served"), default="sort",
                     help="sort: the 1e8 fp64 single-array sort (default); u64: 1e9 uniform uint64 keys; "
                          "zipf: 2e8 Zipf(1.1) uint64 keys with a uint32 index payload; batched; served")
@@ -487,7 +494,7 @@ def main():
     order = [dists[i % len(dists)] for i in range(total)]
 
     params = ipls.default_params(sample_max=args.sample_max, tile_keys=args.tile_keys, model=args.sort_model,
-                                 equality=args.equality)
+                                 equality=args.equality, inherit=args.inherit)
     stream = torch.cuda.current_stream()
 
     # warmup: also checks parity of each distribution's output against numpy's sort
@@ -573,7 +580,7 @@ def main():
         print(f"# cpu baseline: oracle on one full step ({d0}, {n} keys)", file=sys.stderr, flush=True)
         t = time.perf_counter()
         want, _, _ = oracle.sort(host_inputs[d0], None, oracle.params(sample_max=args.sample_max, model=args.sort_model,
-                                                                      equality=args.equality))
+                                                                      equality=args.equality, inherit=args.inherit))
         dt = time.perf_counter() - t
         # parity of the GPU result for this step against the oracle
         g = pristine[d0].clone()
@@ -599,7 +606,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"plain single-array sort, {n} fp64 keys per step, keys only, cycling "
                                + "/".join(dists), "n": n, "num_buckets": 256, "base_case_max": 4096,
-                   "sample": f"1% jittered stratified, capped at {args.sample_max} keys",
+                   "sample": sample_label(args),
                    "model": ("FMCD", "auto (learned model when lower max load)", "learned",
                              "splitter tree")[args.sort_model],
                    "parallelism": "single GPU"},

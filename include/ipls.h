@@ -80,6 +80,16 @@ typedef struct {
                               * run in the sorted sample is longer than S/K gets a bucket of its own (at
                               * most min(16, (K-4)/2) of them); the linear part is fitted on the sample
                               * without those runs with K - 2E buckets.  0 (default): the paper's IPLS */
+    uint32_t inherit;        /* 1: sample inheritance (needs model 0 and equality 0).  A child bucket that is
+                              * partitioned itself (more than T keys) reuses the parent's sorted sample
+                              * restricted to it (the keys the parent's line sends there, still sorted)
+                              * when that holds at least max(3, sample_min or 2K) keys and FMCD on it is
+                              * usable; every other bucket draws a fresh sample.  The child's line is
+                              * fitted before the parent's scatter, which also writes each key's class
+                              * under it (one byte a key, in a library buffer of n bytes), so the child's
+                              * counting pass reads one byte a key instead of the key.  Within the paper's
+                              * sample -> sort -> train -> predict pipeline (Machine Learning Models
+                              * chapter); the paper itself samples every bucket afresh.  0 (default) */
 } ipls_params;
 
 /* FMCD linear model of a sample: bucket(x) = clamp(floor(fma(a, x, b)), 0, K-1). */
@@ -101,9 +111,11 @@ typedef struct {
     uint64_t base_buckets;      /* base-case sorts */
     uint64_t level1_max_load;   /* largest bucket after the first level */
     uint64_t keys_partitioned;  /* sum over levels of keys that went through a distribution pass */
+    uint64_t inherited;         /* partitions whose line came from an inherited sample */
 } ipls_stats;
 
-/* Defaults: K 256, T 4096, divisor 100, sample_min 2K, no cap, FMCD, M 256, 4 steps, tile 4096, policy 0. */
+/* Defaults: K 256, T 4096, divisor 100, sample_min 2K, no cap, FMCD, M 256, 4 steps, tile 4096, policy 0,
+ * no equality buckets, no inheritance. */
 void ipls_default_params(ipls_params* p);
 
 /* Sort keys[0..n) (and payload[0..n) when non-null, stably) in place with default parameters.

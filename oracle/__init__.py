@@ -26,7 +26,7 @@ class Params(C.Structure):
     _fields_ = [("num_buckets", C.c_uint32), ("base_case_max", C.c_uint32), ("sample_divisor", C.c_uint32),
                 ("sample_min", C.c_uint32), ("sample_max", C.c_uint64), ("seed", C.c_uint64),
                 ("model", C.c_uint32), ("leaves", C.c_uint32), ("train_iters", C.c_uint32), ("sample_policy", C.c_uint32),
-                ("equality", C.c_uint32), ("pad_", C.c_uint32)]
+                ("equality", C.c_uint32), ("inherit", C.c_uint32)]
 
 
 class Model(C.Structure):
@@ -40,7 +40,8 @@ class Model(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("passes", C.c_uint64), ("max_level", C.c_uint64), ("closed", C.c_uint64),
                 ("fallback", C.c_uint64), ("base_cases", C.c_uint64), ("l2pl_used", C.c_uint64),
-                ("level1_max_load", C.c_uint64), ("keys_partitioned", C.c_uint64)]
+                ("level1_max_load", C.c_uint64), ("keys_partitioned", C.c_uint64),
+                ("inherited", C.c_uint64)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -50,8 +51,9 @@ DEFAULT_SEED = 0x1F5A_2208_0690_2000
 
 
 def params(K=256, T=4096, divisor=100, sample_min=0, sample_max=0, seed=DEFAULT_SEED, model=0, leaves=256,
-           train_iters=4, sample_policy=0, equality=0) -> Params:
-    return Params(K, T, divisor, sample_min, sample_max, seed, model, leaves, train_iters, sample_policy, equality, 0)
+           train_iters=4, sample_policy=0, equality=0, inherit=0) -> Params:
+    return Params(K, T, divisor, sample_min, sample_max, seed, model, leaves, train_iters, sample_policy, equality,
+                  inherit)
 
 
 def build(force: bool = False) -> str:
@@ -85,6 +87,7 @@ def lib():
             "oracle_fit_bucket": (i32, [P, u64, i32, C.POINTER(Params), u64, C.POINTER(Model), P, P]),
             "oracle_partition": (i32, [P, P, u64, i32, C.POINTER(Params), C.POINTER(Model), P]),
             "oracle_classify_linear": (None, [P, u64, i32, dbl, dbl, u32, P]),
+            "oracle_child_sample": (i32, [P, u64, i32, C.POINTER(Params), u32, P, C.POINTER(C.c_uint64)]),
             "oracle_classify_model": (None, [P, u64, i32, C.POINTER(Model), P, P, u32, P]),
             "oracle_stable_layout": (None, [P, u64, i32, P, u32, P]),
             "oracle_buffered_layout": (None, [P, u64, i32, P, u32, u32, P]),
@@ -192,6 +195,17 @@ def fit_bucket(keys: np.ndarray, p: Params | None = None, lo_rel: int = 0):
     if rc:
         raise ValueError("oracle_fit_bucket rejected its arguments")
     return m, root, leaf
+
+
+def child_sample(keys: np.ndarray, c: int, p: Params) -> np.ndarray:
+    """The sorted sample (as ords) that bucket c of the first level inherits; empty when it draws a
+    fresh one."""
+    keys = np.ascontiguousarray(keys)
+    out = np.zeros(max(sample_size(keys.size, p), 1), np.uint64)
+    ln = C.c_uint64()
+    if lib().oracle_child_sample(_p(keys), keys.size, _dt(keys), C.byref(p), c, _p(out), C.byref(ln)):
+        raise ValueError("oracle_child_sample rejected its arguments")
+    return out[: ln.value].copy()
 
 
 def partition(keys: np.ndarray, payload: np.ndarray | None = None, p: Params | None = None):

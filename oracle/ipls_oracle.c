@@ -27,7 +27,12 @@
  *     (IPS4o section, IPS2Ra's radix partitioning);
  *   - the two-level piecewise-linear CDF model (Recursive Model Index section, eCDF models
  *     trained by mean-squared error in the Machine Learning Models chapter).  Parity unpinned
- *     for this model beyond its definition: the paper prints no numbers for it.
+ *     for this model beyond its definition: the paper prints no numbers for it;
+ *   - equality buckets and the splitter tree (IPS4o's, Decision Trees section);
+ *   - sample inheritance (an extension inside the Machine Learning Models chapter's
+ *     sample -> sort -> train -> predict pipeline, not described by the paper): a child bucket
+ *     may reuse its part of the parent's sorted sample instead of drawing a fresh one.  Pinned
+ *     by the rule written out in numpy (restricted samples, sizes, usable fits) and by sorts.
  */
 #include <math.h>
 #include <stdint.h>
@@ -57,7 +62,7 @@ typedef struct {
     uint32_t train_iters;    /* gradient steps of the two-level model */
     uint32_t sample_policy;  /* 0: S = ceil(n / divisor); 1: the paper's alpha*K - 1 */
     uint32_t equality;       /* 1: equality buckets for heavy sample values (IPS4o) */
-    uint32_t pad_;
+    uint32_t inherit;        /* 1: a child bucket reuses its part of the parent's sorted sample */
 } oracle_params;
 
 typedef struct {
@@ -90,6 +95,7 @@ typedef struct {
     uint64_t l2pl_used;  /* partitions that used the two-level model */
     uint64_t level1_max_load;
     uint64_t keys_partitioned; /* sum of the sizes of the partitioned buckets */
+    uint64_t inherited;        /* partitioned buckets whose model came from the parent's sample */
 } oracle_stats;
 
 /* ---------------------------------------------------------------- key map */
@@ -594,16 +600,29 @@ static int fit_equality(const double* x, const uint64_t* o, uint64_t S, uint32_t
     return 1;
 }
 
+/* inh/inh_len: a sorted sample handed down by the parent (sample inheritance), used instead of a
+ * fresh one.  sample_out (nullable): receives the sorted sample's ords (caller frees). */
 static void fit_bucket(const void* keys, uint64_t n, int dtype, const oracle_params* p, uint64_t lo_rel,
-                       oracle_model* m, l2pl_model* l2, double* l2_leaf) {
+                       oracle_model* m, l2pl_model* l2, double* l2_leaf, const uint64_t* inh, uint64_t inh_len,
+                       uint64_t** sample_out, uint64_t* sample_len) {
     uint32_t K = p->num_buckets;
     memset(m, 0, sizeof(*m));
     m->K = K;
-    uint64_t S = oracle_sample_size(n, p);
+    uint64_t S = inh_len ? inh_len : oracle_sample_size(n, p);
     m->S = S;
     double* x = (double*)malloc((S ? S : 1) * sizeof(double));
     uint64_t* o = (uint64_t*)malloc((S ? S : 1) * sizeof(uint64_t));
-    sorted_sample_ords(keys, n, dtype, lo_rel, S, p->seed, x, o);
+    if (inh_len) {
+        memcpy(o, inh, S * sizeof(uint64_t));
+        for (uint64_t j = 0; j < S; ++j) x[j] = val_from_ord(o[j], dtype);
+    } else {
+        sorted_sample_ords(keys, n, dtype, lo_rel, S, p->seed, x, o);
+    }
+    if (sample_out) {
+        *sample_out = (uint64_t*)malloc((S ? S : 1) * sizeof(uint64_t));
+        memcpy(*sample_out, o, S * sizeof(uint64_t));
+        *sample_len = S;
+    }
     if (p->model == 3 && S >= 1 && o[0] != o[S - 1]) {
         fit_tree(o, S, K, m);
         free(x);
@@ -778,9 +797,81 @@ static void base_case(ctx_t* cx, char* keys, uint32_t* pay, uint64_t n) {
     cx->st->base_cases += 1;
 }
 
+/* ---------------------------------------------------------------- sample inheritance */
+
+/* The raw key whose ord is o (inverse of the key map). */
+static void key_from_ord(uint64_t o, int dtype, unsigned char* buf) {
+    if (dtype == OR_U64) {
+        memcpy(buf, &o, 8);
+    } else if (dtype == OR_F32) {
+        uint32_t u = (uint32_t)o;
+        u = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
+        memcpy(buf, &u, 4);
+    } else {
+        uint64_t u = (o >> 63) ? (o & 0x7fffffffffffffffull) : ~o;
+        memcpy(buf, &u, 8);
+    }
+}
+
+/* Smallest inherited sample that is used: sample_min (0 means 2K), and at least 3 (FMCD's own
+ * minimum). */
+static uint64_t inherit_min(const oracle_params* p) {
+    uint64_t t = p->sample_min ? p->sample_min : 2ull * p->num_buckets;
+    return t < 3 ? 3 : t;
+}
+
+/* Whether FMCD on the sorted sample o[0..S) gives a usable line: the test fit_bucket applies
+ * before it falls back to the degenerate rule. */
+static int fmcd_usable(const uint64_t* o, uint64_t S, int dtype, uint32_t K) {
+    if (S < 3) return 0;
+    double* x = (double*)malloc(S * sizeof(double));
+    for (uint64_t j = 0; j < S; ++j) x[j] = val_from_ord(o[j], dtype);
+    int ok = 0;
+    if (isfinite(x[0]) && isfinite(x[S - 1])) {
+        double a, b;
+        uint64_t D;
+        ok = oracle_fmcd(x, S, K, &a, &b, &D) == 0 && a > 0.0 && isfinite(a) && isfinite(b);
+    }
+    free(x);
+    return ok;
+}
+
+/* The parent's sorted sample smp[0..slen) split by the parent's model: the sample keys of child c,
+ * in their sorted order, are (*sub)[(*sub_off)[c] .. (*sub_off)[c+1]) (caller frees both). */
+static void restrict_sample(const uint64_t* smp, uint64_t slen, int dtype, const oracle_model* m,
+                            const l2pl_model* l2, uint64_t** sub, uint64_t** sub_off) {
+    const uint32_t K = m->K;
+    *sub = (uint64_t*)malloc((slen ? slen : 1) * sizeof(uint64_t));
+    *sub_off = (uint64_t*)calloc((size_t)K + 1, sizeof(uint64_t));
+    uint32_t* cls = (uint32_t*)malloc((slen ? slen : 1) * sizeof(uint32_t));
+    unsigned char kbuf[8];
+    for (uint64_t j = 0; j < slen; ++j) {
+        key_from_ord(smp[j], dtype, kbuf);
+        cls[j] = classify_key(kbuf, 0, dtype, m, l2);
+        (*sub_off)[cls[j] + 1] += 1;
+    }
+    for (uint32_t c = 0; c < K; ++c) (*sub_off)[c + 1] += (*sub_off)[c];
+    uint64_t* fill = (uint64_t*)malloc((size_t)K * sizeof(uint64_t));
+    memcpy(fill, *sub_off, (size_t)K * sizeof(uint64_t));
+    for (uint64_t j = 0; j < slen; ++j) (*sub)[fill[cls[j]]++] = smp[j];
+    free(fill);
+    free(cls);
+}
+
+/* Whether a child of n keys inherits the restricted sample r[0..len). */
+static int child_inherits(const oracle_params* p, uint64_t n, const uint64_t* r, uint64_t len, int dtype) {
+    return n > p->base_case_max && len >= inherit_min(p) && fmcd_usable(r, len, dtype, p->num_buckets);
+}
+
 /* ---------------------------------------------------------------- recursion (Proposed Algorithm) */
 
-static void ipls(ctx_t* cx, char* keys, uint32_t* pay, uint64_t n, uint64_t lo_rel, uint64_t level) {
+/* inh/inh_len: the bucket's inherited sorted sample (ords), or NULL/0 for a fresh sample.
+ * With inherit on, a child of a bucket partitioned by the FMCD line inherits the parent's sorted
+ * sample restricted to the child (the sample keys the line sends there, still sorted) when the
+ * child is partitioned itself (more than T keys), the restricted sample holds at least
+ * inherit_min keys and FMCD on it is usable; every other bucket draws a fresh sample. */
+static void ipls(ctx_t* cx, char* keys, uint32_t* pay, uint64_t n, uint64_t lo_rel, uint64_t level,
+                 const uint64_t* inh, uint64_t inh_len) {
     const oracle_params* p = cx->p;
     if (n <= p->base_case_max) {
         base_case(cx, keys, pay, n);
@@ -790,14 +881,18 @@ static void ipls(ctx_t* cx, char* keys, uint32_t* pay, uint64_t n, uint64_t lo_r
     l2pl_model l2 = {0, 0.0, 0.0, NULL};
     uint32_t M = p->leaves ? p->leaves : 256;
     double* leaf = p->model ? (double*)malloc(4 * (size_t)M * sizeof(double)) : NULL;
-    fit_bucket(keys, n, cx->dtype, p, lo_rel, &m, &l2, leaf);
+    uint64_t* smp = NULL;
+    uint64_t slen = 0;
+    fit_bucket(keys, n, cx->dtype, p, lo_rel, &m, &l2, leaf, inh, inh_len, p->inherit ? &smp : NULL, &slen);
     if (m.kind == MODEL_CLOSED) {
         cx->st->closed += 1;
         free(leaf);
+        free(smp);
         return;
     }
     if (m.kind == MODEL_MSD) cx->st->fallback += 1;
     if (m.kind == MODEL_L2PL) cx->st->l2pl_used += 1;
+    if (inh_len) cx->st->inherited += 1;
     cx->st->passes += 1;
     cx->st->keys_partitioned += n;
     if (level > cx->st->max_level) cx->st->max_level = level;
@@ -811,6 +906,10 @@ static void ipls(ctx_t* cx, char* keys, uint32_t* pay, uint64_t n, uint64_t lo_r
             if (counts[c] > mx) mx = counts[c];
         cx->st->level1_max_load = mx;
     }
+    uint64_t* sub = NULL;
+    uint64_t* sub_off = NULL;
+    if (smp && m.kind == MODEL_LINEAR && m.neq == 0) restrict_sample(smp, slen, cx->dtype, &m, &l2, &sub, &sub_off);
+    free(smp);
     /* an equality bucket holds one value only: it is closed where it is made */
     uint32_t eqb[16];
     const uint32_t neq = m.kind == MODEL_LINEAR ? m.neq : 0;
@@ -824,15 +923,29 @@ static void ipls(ctx_t* cx, char* keys, uint32_t* pay, uint64_t n, uint64_t lo_r
         uint64_t cnt = counts[c];
         int is_eq = 0;
         for (uint32_t e = 0; e < neq; ++e) is_eq |= eqb[e] == c;
-        if (cnt > 0 && is_eq) cx->st->closed += 1;
-        else if (cnt > 0) ipls(cx, keys + off * cx->kb, pay ? pay + off : NULL, cnt, lo_rel + off, level + 1);
+        if (cnt > 0 && is_eq) {
+            cx->st->closed += 1;
+        } else if (cnt > 0) {
+            const uint64_t* ci = NULL;
+            uint64_t cl = 0;
+            if (sub && child_inherits(p, cnt, sub + sub_off[c], sub_off[c + 1] - sub_off[c], cx->dtype)) {
+                ci = sub + sub_off[c];
+                cl = sub_off[c + 1] - sub_off[c];
+            }
+            ipls(cx, keys + off * cx->kb, pay ? pay + off : NULL, cnt, lo_rel + off, level + 1, ci, cl);
+        }
         off += cnt;
     }
+    free(sub);
+    free(sub_off);
     free(counts);
 }
 
+/* Sample inheritance is defined for the FMCD line alone (no two-level model, splitter tree or
+ * equality buckets). */
 static int params_ok(const oracle_params* p) {
-    return p && p->num_buckets >= 4 && p->base_case_max >= 1;
+    return p && p->num_buckets >= 4 && p->base_case_max >= 1 && p->inherit <= 1 &&
+           (!p->inherit || (p->model == 0 && !p->equality));
 }
 
 static int ctx_init(ctx_t* cx, int dtype, const oracle_params* p, oracle_stats* st, uint64_t n, int has_pay) {
@@ -864,7 +977,7 @@ int oracle_sort(void* keys, uint32_t* payload, uint64_t n, int dtype, const orac
         ctx_free(&cx);
         return -1;
     }
-    ipls(&cx, (char*)keys, payload, n, 0, 1);
+    ipls(&cx, (char*)keys, payload, n, 0, 1, NULL, 0);
     ctx_free(&cx);
     return 0;
 }
@@ -889,6 +1002,7 @@ int oracle_sort_segmented(void* keys, uint32_t* payload, const uint64_t* off, ui
         acc.base_cases += one.base_cases;
         acc.l2pl_used += one.l2pl_used;
         acc.keys_partitioned += one.keys_partitioned;
+        acc.inherited += one.inherited;
         if (one.max_level > acc.max_level) acc.max_level = one.max_level;
         if (one.level1_max_load > acc.level1_max_load) acc.level1_max_load = one.level1_max_load;
     }
@@ -904,13 +1018,41 @@ int oracle_fit_bucket(const void* keys, uint64_t n, int dtype, const oracle_para
     uint32_t M = p->leaves ? p->leaves : 256;
     l2pl_model l2 = {0, 0.0, 0.0, NULL};
     double* leaf = p->model ? (double*)malloc(4 * (size_t)M * sizeof(double)) : NULL;
-    fit_bucket(keys, n, dtype, p, lo_rel, m, &l2, leaf);
+    fit_bucket(keys, n, dtype, p, lo_rel, m, &l2, leaf, NULL, 0, NULL, NULL);
     if (m->kind == MODEL_L2PL && leaf_out && root_out) {
         memcpy(leaf_out, leaf, 4 * (size_t)M * sizeof(double));
         root_out[0] = l2.ra;
         root_out[1] = l2.rb;
     }
     free(leaf);
+    return 0;
+}
+
+/* The sorted sample (ords) that bucket c of the first level inherits, into out (room for the
+ * level's sample size); *len = 0 when it draws a fresh one.  Returns 0, or -1 on bad arguments. */
+int oracle_child_sample(const void* keys, uint64_t n, int dtype, const oracle_params* p, uint32_t c, uint64_t* out,
+                        uint64_t* len) {
+    *len = 0;
+    if (!params_ok(p) || !p->inherit || n < 2 || c >= p->num_buckets) return -1;
+    oracle_model m;
+    uint64_t* smp = NULL;
+    uint64_t slen = 0;
+    fit_bucket(keys, n, dtype, p, 0, &m, NULL, NULL, NULL, 0, &smp, &slen);
+    if (m.kind == MODEL_LINEAR && m.neq == 0 && n > p->base_case_max) {
+        uint64_t* sub = NULL;
+        uint64_t* sub_off = NULL;
+        restrict_sample(smp, slen, dtype, &m, NULL, &sub, &sub_off);
+        uint64_t cnt = 0;
+        for (uint64_t i = 0; i < n; ++i) cnt += classify_key(keys, i, dtype, &m, NULL) == c;
+        const uint64_t l = sub_off[c + 1] - sub_off[c];
+        if (child_inherits(p, cnt, sub + sub_off[c], l, dtype)) {
+            memcpy(out, sub + sub_off[c], l * sizeof(uint64_t));
+            *len = l;
+        }
+        free(sub);
+        free(sub_off);
+    }
+    free(smp);
     return 0;
 }
 
@@ -930,7 +1072,7 @@ int oracle_partition(void* keys, uint32_t* payload, uint64_t n, int dtype, const
     l2pl_model l2 = {0, 0.0, 0.0, NULL};
     double* leaf = p->model ? (double*)malloc(4 * (size_t)M * sizeof(double)) : NULL;
     oracle_model m;
-    fit_bucket(keys, n, dtype, p, 0, &m, &l2, leaf);
+    fit_bucket(keys, n, dtype, p, 0, &m, &l2, leaf, NULL, 0, NULL, NULL);
     for (uint32_t c = 0; c < p->num_buckets; ++c) counts[c] = 0;
     if (m.kind != MODEL_CLOSED) distribute(&cx, (char*)keys, payload, n, &m, &l2, counts);
     if (m_out) *m_out = m;

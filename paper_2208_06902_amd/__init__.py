@@ -39,7 +39,7 @@ class Params(C.Structure):
                 ("sample_min", C.c_uint32), ("sample_max", C.c_uint64), ("seed", C.c_uint64),
                 ("model", C.c_uint32), ("leaves", C.c_uint32), ("train_iters", C.c_uint32),
                 ("tile_keys", C.c_uint32), ("sample_policy", C.c_uint32),
-                ("equality", C.c_uint32)]
+                ("equality", C.c_uint32), ("inherit", C.c_uint32)]
 
 
 class LinearModel(C.Structure):
@@ -50,7 +50,8 @@ class LinearModel(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("levels", C.c_uint32), ("sample_depth", C.c_uint32), ("passes", C.c_uint64),
                 ("closed", C.c_uint64), ("fallback", C.c_uint64), ("l2pl_used", C.c_uint64),
-                ("base_buckets", C.c_uint64), ("level1_max_load", C.c_uint64), ("keys_partitioned", C.c_uint64)]
+                ("base_buckets", C.c_uint64), ("level1_max_load", C.c_uint64), ("keys_partitioned", C.c_uint64),
+                ("inherited", C.c_uint64)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

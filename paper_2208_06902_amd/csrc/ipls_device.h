@@ -33,9 +33,28 @@ __device__ inline uint32_t model_table_size(uint32_t kind, uint32_t K, uint32_t 
 }
 
 // One bucket to partition at the current level: keys [lo, lo+n) of the level's source buffer;
-// lo_rel is its offset inside its top-level segment (sample positions hash it).
+// lo_rel is its offset inside its top-level segment (sample positions hash it).  inh: 1 + the
+// index of its entry in the previous level's child list when it inherits its part of the parent's
+// sorted sample (and the model fitted on it), else 0.
 struct Item {
-    uint64_t lo, n, lo_rel, pad;
+    uint64_t lo, n, lo_rel, inh;
+};
+
+// Sample inheritance: a child bucket of a partition by the FMCD line that will be partitioned
+// itself reuses the parent's sorted sample restricted to it (a contiguous range, since the line
+// is monotone).  Its line is fitted before the parent's scatter, which then also writes each
+// key's class under that line (one byte per key), so the child's counting pass reads bytes
+// instead of keys.
+struct Child {
+    double a, b;         // FMCD line of the restricted sample; a = 0 when the fit is unusable
+    uint64_t D;          // its conflict degree
+    uint64_t s_lo;       // the restricted sample: [s_lo, s_lo + s_len) of the level's sample buffer
+    uint32_t s_len, c;   // c: the parent's bucket it is
+};
+
+// An item's entries in its level's child list: [base, base + count).
+struct ChildSpan {
+    uint32_t base, count;
 };
 
 // A bucket of <= T keys for the base case, at [lo, lo+n) of the caller's buffer (from_scratch = 0)
@@ -55,7 +74,8 @@ struct Model {
     uint64_t D, S;               // FMCD conflict degree, sample size
     uint64_t umin, umax;         // ord range (degenerate fits only)
     uint64_t load_lin, load_l2;  // max sample load of FMCD and of the two-level model
-    uint32_t l2_ok, pad;
+    uint32_t l2_ok;
+    uint32_t inh;                // 1: inherited line; the level's counts come from the class bytes
     // equality buckets: neq heavy values (ords, ascending); the linear part has km buckets, or
     // sends every other key to bucket 0 (const0)
     uint32_t neq, km, const0, pad2;
@@ -88,6 +108,8 @@ struct Plan {
     uint64_t total_chunks;
     uint64_t eq_closed;                // equality buckets closed so far
     uint64_t copy_count, copy_tiles;   // equality buckets to move back, in tiles of kCopyTile keys
+    uint64_t inherited;                // partitions whose model was inherited, so far
+    uint64_t inh_n;                    // keys of this level's items with inherited lines
 };
 
 constexpr uint32_t kCopyTile = 4096;
@@ -101,6 +123,8 @@ enum : int {
     C_EQCLOSED = 17,  // equality buckets closed where they were made (all levels)
     C_COPY = 18,      // equality buckets of this level to move from the scratch buffer
     C_COPYKEYS = 19,  // ... and their keys
+    C_CHILD = 20,     // entries of this level's child list
+    C_INHERITED = 21, // partitions with an inherited model (all levels)
     C_N = 32
 };
 

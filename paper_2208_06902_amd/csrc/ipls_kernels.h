@@ -30,9 +30,9 @@ struct LevelArgs {
 __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* cnt, int cur, Plan* plan, uint64_t* tile_off,
                                                uint64_t* sample_off, uint64_t* fit_off, uint64_t* chunk_off,
                                                LevelArgs A, uint64_t item_cap, BaseLayout bl, const CopyItem* copy,
-                                               uint64_t* copy_off, uint64_t copy_cap) {
+                                               uint64_t* copy_off, uint64_t copy_cap, const Child* prev_children) {
     __shared__ uint64_t sc[16];
-    __shared__ uint64_t s_max[3];
+    __shared__ uint64_t s_max[4];
     const uint64_t num = cnt[C_ITEMS0 + cur];
     uint64_t nb = 0;
     bool base_over = false;
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* cnt,
         nb += cnt[C_CLS + c];
         base_over |= cnt[C_CLS + c] > bl.cap[c];
     }
-    if (threadIdx.x == 0) { s_max[0] = s_max[1] = s_max[2] = 0; }
+    if (threadIdx.x == 0) { s_max[0] = s_max[1] = s_max[2] = s_max[3] = 0; }
     __syncthreads();
     uint64_t run_t = 0, run_s = 0, run_f = 0, run_c = 0;
     const uint64_t use = num < item_cap ? num : item_cap;
@@ -48,14 +48,17 @@ __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* cnt,
         uint64_t i = base + threadIdx.x;
         uint64_t nt = 0, ns = 0, nf = 0, nc = 0, n = 0;
         if (i < use) {
-            n = items[i].n;
+            const Item it = items[i];
+            n = it.n;
             nt = (n + A.tile_keys - 1) / A.tile_keys;
             nc = (nt + A.chunk - 1) / A.chunk;
-            ns = sample_size(n, A.div, A.smin, A.smax, A.policy, A.K);
+            ns = (it.inh && prev_children) ? prev_children[it.inh - 1].s_len
+                                           : sample_size(n, A.div, A.smin, A.smax, A.policy, A.K);
             nf = ns > A.small_S ? (ns + A.fit_chunk - 1) / A.fit_chunk : 0;
             atomicMax((unsigned long long*)&s_max[0], (unsigned long long)ns);
             atomicMax((unsigned long long*)&s_max[1], (unsigned long long)n);
             atomicAdd((unsigned long long*)&s_max[2], (unsigned long long)n);
+            if (it.inh && prev_children) atomicAdd((unsigned long long*)&s_max[3], (unsigned long long)n);
         }
         uint64_t tt, ts, tf, tc;
         uint64_t ec = block_exclusive_sum<uint64_t>(nc, sc, &tc);
@@ -90,6 +93,8 @@ __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* cnt,
         plan->copy_count = ncopy;
         plan->copy_tiles = run_k;
         plan->eq_closed = cnt[C_EQCLOSED];
+        plan->inherited = cnt[C_INHERITED];
+        cnt[C_CHILD] = 0;
         if (ncopy_all > copy_cap) cnt[C_ERR] |= kErrCapacity;
         cnt[C_COPY] = 0;
         cnt[C_COPYKEYS] = 0;
@@ -109,6 +114,7 @@ __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* cnt,
         plan->max_S = s_max[0];
         plan->max_n = s_max[1];
         plan->sum_n = s_max[2];
+        plan->inh_n = s_max[3];
         plan->err = e;
         plan->closed = cnt[C_STATS + 0];
         plan->digit = cnt[C_STATS + 1];
@@ -165,9 +171,12 @@ __global__ __launch_bounds__(256) void k_seed(const uint64_t* off, uint64_t nseg
 // One key per stratum j = [floor(j n / S), floor((j+1) n / S)) of every item, moved inside the
 // stratum by mix64(stream + (j+1) gamma), stream = mix64(seed ^ mix64(lo_rel gamma + n)).
 // floor(j n / S) = j q + floor(j r / S) with n = q S + r keeps the arithmetic in 64 bits (S < 2^32).
+// An item that inherits copies its restricted sample (already sorted) from the previous level's
+// sample buffer instead.
 template <int DT>
 __global__ void k_sample(const Item* items, uint64_t num_items, const uint64_t* sample_off, uint64_t total,
-                         const typename Key<DT>::T* src, typename Key<DT>::T* sample, uint64_t seed) {
+                         const typename Key<DT>::T* src, typename Key<DT>::T* sample, uint64_t seed,
+                         const Child* prev_children, const typename Key<DT>::T* prev_sample) {
     uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= total) return;
     uint64_t lo = 0, hi = num_items;
@@ -179,6 +188,10 @@ __global__ void k_sample(const Item* items, uint64_t num_items, const uint64_t* 
     const Item it = items[lo];
     const uint64_t S = sample_off[lo + 1] - sample_off[lo];
     const uint64_t j = s - sample_off[lo];
+    if (it.inh && prev_children) {
+        sample[s] = prev_sample[prev_children[it.inh - 1].s_lo + j];
+        return;
+    }
     const uint64_t q = it.n / S, r = it.n % S;
     const uint64_t a = j * q + (j * r) / S;
     const uint64_t b = (j + 1) * q + ((j + 1) * r) / S;
@@ -219,6 +232,27 @@ __device__ inline void model_degenerate(Model& m) {
     m.umax = 0ull;
 }
 
+// Binary search for FMCD's D over [1, S/3 + 1] by the whole block, x(j) the j-th value of a sorted
+// sample of S >= 3 keys with finite ends; then the line.  Every thread gets the same result.
+template <typename X>
+__device__ inline void fmcd_search(const X& x, uint64_t S, uint32_t K, double* a, double* b, uint64_t* Dout) {
+    const uint64_t Dmax = S / 3;
+    uint64_t lo = 1, hi = Dmax + 1;
+    while (lo < hi) {
+        const uint64_t D = lo + ((hi - lo) >> 1);
+        const double u = fmcd_spread(x(S - 1 - D), x(D), K);
+        int fail = 0;
+        for (uint64_t w = threadIdx.x; w + D < S; w += blockDim.x) fail |= !(x(w + D) - x(w) >= u);
+        if (__syncthreads_or(fail)) lo = D + 1;
+        else hi = D;
+    }
+    const uint64_t D = lo;
+    const uint64_t Du = D <= Dmax ? D : Dmax;
+    const double u = fmcd_spread(x(S - 1 - Du), x(Du), K);
+    fmcd_line(u, x(S - 1 - D), x(D), K, a, b);
+    *Dout = D;
+}
+
 // Small samples (S <= small_S <= kFitLds): one workgroup per item, the sample in LDS as fp64,
 // binary search.
 constexpr int kFitLds = 16384;
@@ -241,25 +275,96 @@ __global__ __launch_bounds__(256) void k_fmcd_small(const typename Key<DT>::T* s
     m.S = S;
     bool usable = S >= 3 && isfinite(sx[0]) && isfinite(sx[S - 1]);
     if (usable) {
-        const uint64_t Dmax = S / 3;
-        uint64_t lo = 1, hi = Dmax + 1;
-        while (lo < hi) {
-            const uint64_t D = lo + ((hi - lo) >> 1);
-            const double u = fmcd_spread(sx[S - 1 - D], sx[D], K);
-            int fail = 0;
-            for (uint64_t w = threadIdx.x; w + D < S; w += blockDim.x) fail |= !(sx[w + D] - sx[w] >= u);
-            if (__syncthreads_or(fail)) lo = D + 1;
-            else hi = D;
-        }
-        const uint64_t D = lo;
-        const uint64_t Du = D <= Dmax ? D : Dmax;
-        const double u = fmcd_spread(sx[S - 1 - Du], sx[Du], K);
-        fmcd_line(u, sx[S - 1 - D], sx[D], K, &m.a, &m.b);
-        m.D = D;
+        fmcd_search([&](uint64_t j) { return sx[j]; }, S, K, &m.a, &m.b, &m.D);
         usable = fit_usable(m.a, m.b);
     }
     if (!usable) model_degenerate(m);
     if (threadIdx.x == 0) models[i] = m;
+}
+
+// ------------------------------------------------------------------ sample inheritance
+// Children of every item partitioned by the FMCD line (one workgroup per item, thread c: bucket
+// c): the sorted sample's keys the line sends to bucket c form the range [lb(c), lb(c+1)), lb(c)
+// being the first sample position of class >= c (a binary search: the line is monotone in the key
+// order).  A child that will be partitioned itself (more than T keys) and whose range holds at
+// least `thr` keys is appended to the level's child list, its FMCD line still to fit.
+template <int DT>
+__global__ __launch_bounds__(256) void k_child_split(uint64_t num_items, const Model* models,
+                                                     const typename Key<DT>::T* sample, const uint64_t* sample_off,
+                                                     const uint64_t* hist, uint32_t K, uint32_t T, uint64_t thr,
+                                                     ChildSpan* spans, Child* children, uint64_t* cnt, uint64_t cap) {
+    using KT = Key<DT>;
+    __shared__ uint64_t s_lb[kMaxBuckets + 1];
+    __shared__ uint64_t s_scan[16];
+    __shared__ uint64_t s_base;
+    const uint64_t i = blockIdx.x;
+    const uint32_t c = threadIdx.x;
+    if (i >= num_items) return;
+    const Model m = models[i];
+    if (m.kind != kKindLinear || m.neq != 0) {
+        if (c == 0) spans[i] = ChildSpan{0u, 0u};
+        return;
+    }
+    const uint64_t off = sample_off[i], S = sample_off[i + 1] - off;
+    const typename KT::T* xs = sample + off;
+    if (c == 0) s_lb[K] = S;
+    if (c < K) {
+        uint64_t lo = 0, hi = S;  // first position whose class is >= c
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            const typename KT::T u = xs[mid];
+            if (classify_linear(m.a, m.b, K, KT::val(u), KT::neg(u)) < c) lo = mid + 1;
+            else hi = mid;
+        }
+        s_lb[c] = lo;
+    }
+    __syncthreads();
+    const uint64_t len = c < K ? s_lb[c + 1] - s_lb[c] : 0;
+    const bool take = c < K && hist[i * K + c] > T && len >= thr;
+    uint64_t nt;
+    const uint64_t rank = block_exclusive_sum<uint64_t>(take ? 1u : 0u, s_scan, &nt);
+    if (c == 0) s_base = nt ? atomicAdd((unsigned long long*)&cnt[C_CHILD], (unsigned long long)nt) : 0;
+    __syncthreads();
+    const uint64_t base = s_base;
+    const bool fits = base + nt <= cap;
+    if (take && fits) children[base + rank] = Child{0.0, 0.0, 0, off + s_lb[c], (uint32_t)len, c};
+    if (c == 0) {
+        spans[i] = ChildSpan{(uint32_t)base, fits ? (uint32_t)nt : 0u};
+        if (!fits) atomicOr((unsigned long long*)&cnt[C_ERR], (unsigned long long)kErrCapacity);
+    }
+}
+
+// FMCD line of every entry of the child list (one workgroup each; the sample in LDS when it fits,
+// else read from the sample buffer).  An unusable fit leaves a = 0: that child draws a fresh
+// sample at its level.
+template <int DT>
+__global__ __launch_bounds__(256) void k_child_fit(Child* children, const uint64_t* cnt, uint64_t cap,
+                                                   const typename Key<DT>::T* sample, uint32_t K) {
+    using KT = Key<DT>;
+    __shared__ double sx[kFitLds];
+    const uint64_t g = blockIdx.x;
+    if (g >= cnt[C_CHILD] || g >= cap) return;
+    const Child ch = children[g];
+    const uint64_t S = ch.s_len;
+    const typename KT::T* xs = sample + ch.s_lo;
+    double a = 0.0, b = 0.0;
+    uint64_t D = 0;
+    bool usable;
+    if (S <= (uint64_t)kFitLds) {
+        for (uint64_t j = threadIdx.x; j < S; j += blockDim.x) sx[j] = KT::val(xs[j]);
+        __syncthreads();
+        usable = S >= 3 && isfinite(sx[0]) && isfinite(sx[S - 1]);
+        if (usable) fmcd_search([&](uint64_t j) { return sx[j]; }, S, K, &a, &b, &D);
+    } else {
+        usable = isfinite(KT::val(xs[0])) && isfinite(KT::val(xs[S - 1]));
+        if (usable) fmcd_search([&](uint64_t j) { return KT::val(xs[j]); }, S, K, &a, &b, &D);
+    }
+    usable = usable && fit_usable(a, b);
+    if (threadIdx.x == 0) {
+        children[g].a = usable ? a : 0.0;
+        children[g].b = usable ? b : 0.0;
+        children[g].D = D;
+    }
 }
 
 // Large samples: rounds of `cand` candidate widths spread over the open interval [lo, hi] of D,
@@ -793,9 +898,24 @@ __global__ __launch_bounds__(256) void k_heavy(const typename Key<DT>::T* sample
 template <int DT>
 __global__ void k_finalize(const Item* items, Model* models, const Model* roots, uint64_t num_items, uint32_t K,
                            int src_is_scratch, uint32_t policy, uint64_t* stat_counts, const EqInfo* eq,
-                           const uint32_t* tree) {
+                           const uint32_t* tree, const Child* prev_children) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= num_items) return;
+    const uint64_t inh = items[i].inh;
+    if (inh && prev_children) {
+        // the line fitted on the inherited sample before the parent's scatter wrote the class bytes
+        const Child ch = prev_children[inh - 1];
+        Model m = {};
+        m.kind = kKindLinear;
+        m.a = ch.a;
+        m.b = ch.b;
+        m.D = ch.D;
+        m.S = ch.s_len;
+        m.inh = 1;
+        models[i] = m;
+        atomicAdd((unsigned long long*)&stat_counts[C_INHERITED - C_STATS], 1ull);
+        return;
+    }
     Model m = models[i];
     m.neq = 0;
     if (tree && tree[i]) {  // splitter tree: its splitters are in the item's leaf table
@@ -942,7 +1062,7 @@ __global__ __launch_bounds__(64 * NW) void k_classify_hist(const Item* items, co
                                                        uint64_t total_chunks, const Model* models,
                                                        const double* leaves, const typename Key<DT>::T* src,
                                                        uint32_t* tile_pref, uint32_t* chunk_sum, uint32_t K,
-                                                       uint32_t M) {
+                                                       uint32_t M, const uint8_t* src_cls) {
     // Every tile of the chunk has its own LDS histogram, so the waves count tile after tile (the
     // next tile's keys are loaded while this one is counted) with no barrier in between; one
     // barrier at the end, then thread b turns bucket b's counts into the tiles' prefixes.
@@ -963,7 +1083,9 @@ __global__ __launch_bounds__(64 * NW) void k_classify_hist(const Item* items, co
         const uint64_t rem = it.n - (t - t0) * TILE;
         return rem < (uint64_t)TILE ? (uint32_t)rem : (uint32_t)TILE;
     };
-    const bool counting = m.kind != kKindClosedKeep && m.kind != kKindClosedMove;
+    // an inherited line: the parent's scatter already wrote every key's class (one byte a key)
+    const bool bytes = m.inh && src_cls;
+    const bool counting = m.kind != kKindClosedKeep && m.kind != kKindClosedMove && !bytes;
     T cur[IPT], nxt[IPT];
     uint32_t nop[1];
     if (counting) load_tile<DT, false, IPT>(src, nullptr, it.lo + (t_first - t0) * TILE, tile_n(t_first), wbase, cur, nop);
@@ -971,6 +1093,32 @@ __global__ __launch_bounds__(64 * NW) void k_classify_hist(const Item* items, co
         s_leaf[q] = leaves[(uint64_t)i * 4 * kMaxLeaves + q];
     for (uint32_t b = tid; b < kChunk * kMaxBuckets; b += NT) (&h[0][0])[b] = 0;
     __syncthreads();
+    if (bytes) {
+        // the chunk's class bytes [A0, A1) as aligned 32-bit words, all loads issued first; the
+        // class buffer holds at least 3 bytes past the last key
+        const uint64_t r0 = (t_first - t0) * TILE;
+        const uint64_t r1 = (r0 + (t_end - t_first) * TILE < it.n) ? r0 + (t_end - t_first) * TILE : it.n;
+        const uint64_t A0 = it.lo + r0, A1 = it.lo + r1;
+        const uint64_t w0 = A0 >> 2, w1 = (A1 + 3) >> 2;
+        const uint32_t* cw = (const uint32_t*)src_cls;
+        constexpr int NWORD = (kChunk * TILE) / (4 * NT) + 1;
+        uint32_t v[NWORD];
+#pragma unroll
+        for (int q = 0; q < NWORD; ++q) {
+            const uint64_t w = w0 + tid + (uint64_t)q * NT;
+            v[q] = w < w1 ? cw[w] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < NWORD; ++q) {
+            const uint64_t w = w0 + tid + (uint64_t)q * NT;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const uint64_t pos = w * 4 + b;
+                if (pos >= A0 && pos < A1)
+                    atomicAdd(&h[(uint32_t)((pos - A0) / TILE)][(v[q] >> (8 * b)) & 0xffu], 1u);
+            }
+        }
+    }
     for (uint64_t t = t_first; t < t_end; ++t) {
         const uint32_t tn = tile_n(t), q = (uint32_t)(t - t_first);
         if (counting && t + 1 < t_end)
@@ -1072,27 +1220,37 @@ __device__ inline uint64_t xcd_tile(uint64_t g, uint64_t nt) {
     return x * q + (x < r ? x : r) + g / 8;
 }
 
-template <int DT, bool PAY, int NW, int IPT>
-__global__ __launch_bounds__(64 * NW) void k_scatter(const Item* items, const uint64_t* tile_off, const uint32_t* tile_map,
+// CLS: the level has children with inherited lines (sample inheritance).  Their lines are set in
+// the staging buffer while the keys are classified (the FMCD line reads no leaf table), each key of
+// such a child gets its class under the child's line in registers, the class is staged beside the
+// key and written to dst_cls at the key's destination.  No barrier is added.
+template <int DT, bool PAY, int NW, int IPT, bool CLS>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(CLS && !PAY ? 6 : 1))) void k_scatter(const Item* items, const uint64_t* tile_off, const uint32_t* tile_map,
                                                  uint64_t total_tiles, const uint64_t* chunk_off,
                                                  uint64_t total_chunks, const Model* models, const double* leaves,
                                                  const uint64_t* bstart, const uint64_t* chunk_pref,
                                                  const uint32_t* tile_pref, const typename Key<DT>::T* src,
                                                  const uint32_t* src_pay, typename Key<DT>::T* dst, uint32_t* dst_pay,
-                                                 uint32_t K, uint32_t M) {
+                                                 uint32_t K, uint32_t M, const ChildSpan* spans,
+                                                 const Child* children, uint8_t* dst_cls) {
     using T = typename Key<DT>::T;
+    using KT = Key<DT>;
     constexpr int NT = kWave * NW, TILE = NT * IPT;
     __shared__ uint32_t s_wcnt[NW][kMaxBuckets];
     __shared__ uint32_t s_loc[kMaxBuckets];
     __shared__ uint64_t s_base[kMaxBuckets];
     __shared__ uint64_t s_scan[16];
-    // The two-level model's leaves are only read by the classification, which ends (two barriers)
-    // before the first staging write: they share memory with the staged keys.
+    // The two-level model's leaves (or the children's lines) are only read by the classification,
+    // which ends (two barriers) before the first staging write: they share memory with the staged
+    // keys.
     constexpr int kStageBytes = TILE * (int)sizeof(T), kLeafBytes = 4 * kMaxLeaves * (int)sizeof(double);
     __shared__ __align__(16) unsigned char s_stage[kStageBytes > kLeafBytes ? kStageBytes : kLeafBytes];
     T* s_keys = (T*)s_stage;
     const double* s_leaf = (const double*)s_stage;
+    double2* s_line = (double2*)s_stage;  // CLS: child lines, a = 0 where a child has none
     __shared__ uint8_t s_bkt[TILE];
+    __shared__ uint8_t s_cls[CLS ? TILE : 1];
+    __shared__ uint32_t s_has[CLS ? kMaxBuckets / 32 : 1];  // CLS: children with a line
     __shared__ uint32_t s_pay[PAY ? TILE : 1];
 
     const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
@@ -1112,17 +1270,38 @@ __global__ __launch_bounds__(64 * NW) void k_scatter(const Item* items, const ui
     uint32_t bk[IPT], rk[IPT];
     const uint32_t wbase = wave * kWave * IPT;
     load_tile<DT, PAY, IPT>(src, src_pay, base, tn, wbase, k, p);
+    const ChildSpan sp = CLS ? spans[i] : ChildSpan{0u, 0u};
+    Child ch = {};
+    if (CLS && tid < sp.count) ch = children[sp.base + tid];
     uint64_t dbase = 0;
     if (tid < K)
         dbase = it.lo + bstart[(uint64_t)i * K + tid] + chunk_pref[c * K + tid] +
                 tile_pref[t * K + tid];
     for (uint32_t q = tid, nq = model_table_size(m.kind, K, M); q < nq; q += NT)
         ((double*)s_stage)[q] = leaves[(uint64_t)i * 4 * kMaxLeaves + q];
+    if (CLS && sp.count) {
+        if (tid < K) s_line[tid] = make_double2(0.0, 0.0);
+        if (tid < kMaxBuckets / 32) s_has[tid] = 0u;
+    }
     for (uint32_t b = tid; b < NW * kMaxBuckets; b += NT) (&s_wcnt[0][0])[b] = 0;
     __syncthreads();
     classify_tile<DT, IPT>(tn, wbase, m, s_leaf, K, M, k, bk);
+    if (CLS && tid < sp.count && ch.a != 0.0) {
+        s_line[ch.c] = make_double2(ch.a, ch.b);
+        atomicOr(&s_has[ch.c >> 5], 1u << (ch.c & 31));
+    }
     wave_count<IPT, true>(bk, tn, wbase, s_wcnt[wave], rk);
     __syncthreads();
+
+    // classes under the children's lines (registers), before the staging overwrites the lines
+    uint32_t cc[CLS ? IPT : 1];
+    if (CLS && sp.count) {
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const double2 ln = s_line[bk[r]];
+            cc[r] = ln.x != 0.0 ? classify_linear(ln.x, ln.y, K, KT::val(k[r]), KT::neg(k[r])) : 0u;
+        }
+    }
 
     // per-wave offsets and tile-local bucket offsets (bucket order)
     const uint32_t b = tid;
@@ -1150,6 +1329,7 @@ __global__ __launch_bounds__(64 * NW) void k_scatter(const Item* items, const ui
             const uint32_t pos = s_loc[bk[r]] + s_wcnt[wave][bk[r]] + rk[r];
             s_keys[pos] = k[r];
             s_bkt[pos] = (uint8_t)bk[r];
+            if (CLS) s_cls[pos] = (uint8_t)cc[r];
             if (PAY) s_pay[pos] = p[r];
         }
     }
@@ -1158,9 +1338,11 @@ __global__ __launch_bounds__(64 * NW) void k_scatter(const Item* items, const ui
     for (int r = 0; r < IPT; ++r) {
         const uint32_t j = tid + r * NT;
         if (j < tn) {
-            const uint64_t d = s_base[s_bkt[j]] + j;
+            const uint32_t bj = s_bkt[j];
+            const uint64_t d = s_base[bj] + j;
             dst[d] = s_keys[j];
             if (PAY) dst_pay[d] = s_pay[j];
+            if (CLS && sp.count && ((s_has[bj >> 5] >> (bj & 31)) & 1u)) dst_cls[d] = s_cls[j];
         }
     }
 }
@@ -1178,14 +1360,22 @@ __global__ __launch_bounds__(256) void k_worklist(const Item* items, uint64_t nu
                                                   const uint64_t* hist, const uint64_t* bstart, uint32_t K, uint32_t T,
                                                   int dst_is_scratch, Item* next, BaseItem* base, BaseLayout bl,
                                                   uint64_t* cnt, int next_slot, uint64_t next_cap, CopyItem* copy,
-                                                  uint64_t copy_cap) {
+                                                  uint64_t copy_cap, const ChildSpan* spans, const Child* children) {
     __shared__ AppendScratch sc;
+    __shared__ int s_ent[kMaxBuckets];  // bucket -> its entry in the child list with a usable line, or -1
     __shared__ uint64_t s_e[kMaxBuckets], s_p[kMaxBuckets], s_sum[kMaxBuckets];
     __shared__ uint64_t s_scan[16];
     __shared__ int s_iscan[16];
     __shared__ int s_prev[kMaxBuckets + 1];
     const uint64_t i = blockIdx.x;
     const uint32_t b = threadIdx.x;
+    const ChildSpan sp = (spans && i < num_items) ? spans[i] : ChildSpan{0u, 0u};
+    if (b < kMaxBuckets) s_ent[b] = -1;
+    __syncthreads();
+    if (b < sp.count) {
+        const Child ch = children[sp.base + b];
+        if (ch.a != 0.0) s_ent[ch.c] = (int)(sp.base + b);
+    }
     uint64_t c = 0, lo = 0, lo_rel = 0;
     bool breaker = false;
     if (i < num_items && b < K) {
@@ -1250,7 +1440,7 @@ __global__ __launch_bounds__(256) void k_worklist(const Item* items, uint64_t nu
     }
     const int cls = ch > 0 ? ch - 1 : 0;
     const uint64_t q = block_append(ch, n, sc, &cnt[next_slot], &cnt[C_CLS], &cnt[C_BASEKEYS]);
-    if (ch == 0 && q < next_cap) next[q] = Item{lo, n, lo_rel, 0};
+    if (ch == 0 && q < next_cap) next[q] = Item{lo, n, lo_rel, (uint64_t)(s_ent[b] + 1)};
     if (ch > 0 && q < bl.cap[cls]) base[bl.off[cls] + q] = BaseItem{lo, (uint32_t)n, (uint32_t)dst_is_scratch};
 }
 

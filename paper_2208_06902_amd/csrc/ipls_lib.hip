@@ -60,7 +60,7 @@ ipls_status ensure(Buf& b, size_t bytes) {
 struct Depth {
     Buf scratch, spay, items[2], base, sample_base, counters, plan, tile_off, sample_off, fit_off, chunk_off, tile_map,
         fit_map, chunk_map, models, masks, hist, bstart, tile_pref, chunk_sum, chunk_pref, sample, leaves, seg, roots,
-        leaf_first, leaf_last, eqinfo, rsample, copy, copy_off, copy_map, treeflag;
+        leaf_first, leaf_last, eqinfo, rsample, copy, copy_off, copy_map, treeflag, sample2, children[2], spans, cls;
     Plan* plan_h = nullptr;
 };
 
@@ -84,7 +84,8 @@ void release_device(Device& dv) {
                        &D.tile_off, &D.sample_off, &D.fit_off, &D.chunk_off, &D.tile_map, &D.fit_map, &D.chunk_map,
                        &D.models, &D.masks, &D.hist, &D.bstart, &D.tile_pref, &D.chunk_sum, &D.chunk_pref, &D.sample,
                        &D.leaves, &D.seg, &D.roots, &D.leaf_first, &D.leaf_last, &D.eqinfo, &D.rsample, &D.copy,
-                       &D.copy_off, &D.copy_map, &D.treeflag})
+                       &D.copy_off, &D.copy_map, &D.treeflag, &D.sample2, &D.children[0], &D.children[1],
+                       &D.spans, &D.cls})
             release(*b);
         if (D.plan_h) (void)hipHostFree(D.plan_h);
         D.plan_h = nullptr;
@@ -163,6 +164,13 @@ struct ProfScope {
         }
     }
 };
+
+// Bytes of a kernel known only after its launch was recorded (the class bytes a scatter wrote).
+void prof_add_bytes(int kernel, double bytes) {
+    if (!g_prof.on) return;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof.bytes[kernel] += bytes;
+}
 
 // Accumulates the finished records (the caller has synchronised the streams they were on).
 void prof_collect() {
@@ -324,8 +332,7 @@ ipls_status launch_base(hipStream_t s, int cls, const BaseItem* list, uint64_t c
 
 // Sort the samples of a level: base case when every sample fits, else the engine one level deeper.
 template <int DT>
-ipls_status sort_samples(Device& dv, Run& run, int d, const Plan& pl) {
-    using T = typename Key<DT>::T;
+ipls_status sort_samples(Device& dv, Run& run, int d, const Plan& pl, typename Key<DT>::T* sample) {
     Depth& D = dv.depth[d];
     hipStream_t s = run.s;
     if (pl.max_S <= run.p.base_case_max) {
@@ -334,11 +341,11 @@ ipls_status sort_samples(Device& dv, Run& run, int d, const Plan& pl) {
                                                                             pl.num_items, (BaseItem*)D.sample_base.p);
         LAUNCH_CHECK();
         return launch_base<DT, false>(s, base_class((uint32_t)pl.max_S), (const BaseItem*)D.sample_base.p,
-                                      pl.num_items, (T*)D.sample.p, nullptr, nullptr, nullptr);
+                                      pl.num_items, sample, nullptr, nullptr, nullptr);
     }
     if (d + 1 >= kMaxDepth) return IPLS_ERR_DEVICE;
     run.st.sample_depth = std::max<uint32_t>(run.st.sample_depth, (uint32_t)(d + 1));
-    return sort_segments<DT, false>(dv, run, d + 1, (T*)D.sample.p, nullptr, pl.total_samples,
+    return sort_segments<DT, false>(dv, run, d + 1, sample, nullptr, pl.total_samples,
                                     (const uint64_t*)D.sample_off.p, pl.num_items, nullptr, false);
 }
 
@@ -387,6 +394,12 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     ST_TRY(ensure(D.chunk_off, (item_cap + 1) * 8));
     if (!D.plan_h) HIP_TRY(hipHostMalloc((void**)&D.plan_h, sizeof(Plan), hipHostMallocDefault));
     uint64_t* cnt = (uint64_t*)D.counters.p;
+    // sample inheritance: samples and child lists alternate between two buffers by level parity
+    // (a level reads its parent level's); one class byte per key
+    const bool inherit = P.inherit && !run.single_pass;
+    const uint64_t thr = std::max<uint64_t>(3, P.sample_min ? P.sample_min : 2ull * K);
+    if (inherit) ST_TRY(ensure(D.cls, len + 16));  // the counting pass reads whole aligned words
+    uint8_t* cls = inherit ? (uint8_t*)D.cls.p : nullptr;
 
     HIP_TRY(hipMemsetAsync(cnt, 0, C_N * sizeof(uint64_t), s));
     k_seed<<<(unsigned)((nseg + 255) / 256), 256, 0, s>>>(seg_off, nseg, T_, (Item*)D.items[0].p,
@@ -412,14 +425,17 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     int cur = 0;
     uint64_t prev_items = 0, prev_sum_n = 0, prev_closed = 0, prev_closed_keys = 0;
     for (int level = 0;; ++level) {
+        const int par = level & 1;
+        const Child* prev_children = (inherit && level > 0) ? (const Child*)D.children[par ^ 1].p : nullptr;
         k_plan<<<1, 1024, 0, s>>>((const Item*)D.items[cur].p, cnt, cur, (Plan*)D.plan.p, (uint64_t*)D.tile_off.p, (uint64_t*)D.sample_off.p,
                                   (uint64_t*)D.fit_off.p, (uint64_t*)D.chunk_off.p, A, item_cap, bl,
-                                  (const CopyItem*)D.copy.p, (uint64_t*)D.copy_off.p, copy_cap);
+                                  (const CopyItem*)D.copy.p, (uint64_t*)D.copy_off.p, copy_cap, prev_children);
         LAUNCH_CHECK();
         HIP_TRY(hipMemcpyAsync(D.plan_h, D.plan.p, sizeof(Plan), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         const Plan pl = *D.plan_h;
         if (pl.err) return IPLS_ERR_DEVICE;
+        if (top && inherit) prof_add_bytes(0, (double)pl.inh_n);  // class bytes the last scatter wrote
         if (top && level > 0) {
             // the previous level's buckets that were not closed were partitioned
             const uint64_t closed_now = pl.closed - prev_closed;
@@ -429,6 +445,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                 run.st.keys_partitioned += prev_sum_n - (pl.closed_keys - prev_closed_keys);
             }
             run.st.closed = pl.closed + pl.eq_closed;
+            run.st.inherited = pl.inherited;
             run.st.fallback = pl.digit;
             run.st.l2pl_used = pl.l2pl;
             prev_closed = pl.closed;
@@ -466,7 +483,10 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
 
         const uint64_t ni = pl.num_items, nt = pl.total_tiles;
         ST_TRY(ensure(D.tile_map, nt * 4));
-        ST_TRY(ensure(D.sample, pl.total_samples * kb));
+        Buf& sbuf = (inherit && par) ? D.sample2 : D.sample;
+        ST_TRY(ensure(sbuf, pl.total_samples * kb));
+        T* sample = (T*)sbuf.p;
+        const T* prev_sample = (inherit && level > 0) ? (const T*)(par ? D.sample.p : D.sample2.p) : nullptr;
         ST_TRY(ensure(D.models, ni * sizeof(Model)));
         ST_TRY(ensure(D.hist, ni * K * 8));
         ST_TRY(ensure(D.bstart, ni * K * 8));
@@ -482,34 +502,35 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                                                               (uint32_t*)D.tile_map.p);
         LAUNCH_CHECK();
         k_sample<DT><<<(unsigned)((pl.total_samples + 255) / 256), 256, 0, s>>>(
-            items, ni, (const uint64_t*)D.sample_off.p, pl.total_samples, src, (T*)D.sample.p, P.seed);
+            items, ni, (const uint64_t*)D.sample_off.p, pl.total_samples, src, sample, P.seed, prev_children,
+            prev_sample);
         LAUNCH_CHECK();
-        ST_TRY(sort_samples<DT>(dv, run, d, pl));
+        ST_TRY(sort_samples<DT>(dv, run, d, pl, sample));
 
         // FMCD fit (with equality buckets: on the sample without the heavy values' runs)
         const EqInfo* eq = nullptr;
         if (P.equality) {
             ST_TRY(ensure(D.eqinfo, ni * sizeof(EqInfo)));
             ST_TRY(ensure(D.rsample, pl.total_samples * kb));
-            k_heavy<DT><<<(unsigned)ni, 256, 0, s>>>((const T*)D.sample.p, (const uint64_t*)D.sample_off.p, ni, K,
+            k_heavy<DT><<<(unsigned)ni, 256, 0, s>>>((const T*)sample, (const uint64_t*)D.sample_off.p, ni, K,
                                                      (EqInfo*)D.eqinfo.p, (T*)D.rsample.p);
             LAUNCH_CHECK();
             eq = (const EqInfo*)D.eqinfo.p;
         }
         ST_TRY((fit_level<DT>(D, s, ni, pl.max_S, pl.total_fit_chunks,
-                              eq ? (const T*)D.rsample.p : (const T*)D.sample.p, (const uint64_t*)D.sample_off.p,
+                              eq ? (const T*)D.rsample.p : (const T*)sample, (const uint64_t*)D.sample_off.p,
                               (const uint64_t*)D.fit_off.p, models, K, eq)));
         const uint32_t* tree = nullptr;
         if (P.model == 3) {
             ST_TRY(ensure(D.leaves, ni * 4 * kMaxLeaves * 8));
             ST_TRY(ensure(D.treeflag, ni * 4));
-            k_tree<DT><<<(unsigned)ni, 256, 0, s>>>((const T*)D.sample.p, (const uint64_t*)D.sample_off.p, ni, K,
+            k_tree<DT><<<(unsigned)ni, 256, 0, s>>>((const T*)sample, (const uint64_t*)D.sample_off.p, ni, K,
                                                     (double*)D.leaves.p, (uint32_t*)D.treeflag.p);
             LAUNCH_CHECK();
             tree = (const uint32_t*)D.treeflag.p;
         }
         if (P.model == 1 || P.model == 2)
-            ST_TRY((train_l2pl<DT>(D, s, ni, pl.max_S, pl.total_fit_chunks, (const T*)D.sample.p,
+            ST_TRY((train_l2pl<DT>(D, s, ni, pl.max_S, pl.total_fit_chunks, (const T*)sample,
                                    (const uint64_t*)D.sample_off.p, (const uint64_t*)D.fit_off.p, models, K, P.leaves,
                                    P.train_iters)));
 
@@ -519,7 +540,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         LAUNCH_CHECK();
         k_finalize<DT><<<(unsigned)((ni + 255) / 256), 256, 0, s>>>(items, models, (const Model*)D.roots.p, ni, K,
                                                                 src_scratch ? 1 : 0, P.model,
-                                                                cnt + C_STATS, eq, tree);
+                                                                cnt + C_STATS, eq, tree, prev_children);
         LAUNCH_CHECK();
 
         // classify + per-tile counts, scan of the counts, bucket starts
@@ -527,12 +548,12 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                                                               (uint32_t*)D.chunk_map.p);
         LAUNCH_CHECK();
         {
-            ProfScope ps(1, (double)pl.sum_n * kb, s);
+            ProfScope ps(1, (double)(pl.sum_n - pl.inh_n) * kb + (double)pl.inh_n, s);
             auto kc = tile == kTile ? k_classify_hist<DT, 8, kPassIPT> : k_classify_hist<DT, 4, kPassIPT>;
             kc<<<(unsigned)nc, tile / kPassIPT, 0, s>>>(
                 items, (const uint64_t*)D.tile_off.p, (const uint64_t*)D.chunk_off.p, (const uint32_t*)D.chunk_map.p,
                 nc, models, (const double*)D.leaves.p, src, (uint32_t*)D.tile_pref.p, (uint32_t*)D.chunk_sum.p, K,
-                P.leaves);
+                P.leaves, cls);
             LAUNCH_CHECK();
         }
         k_scan_chunks<<<(unsigned)((ni * K + 255) / 256), 256, 0, s>>>((const uint64_t*)D.chunk_off.p, ni, K,
@@ -549,14 +570,35 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         k_bucket_starts<<<(unsigned)ni, 256, 0, s>>>((const uint64_t*)D.hist.p, (uint64_t*)D.bstart.p, K);
         LAUNCH_CHECK();
 
+        // children that inherit their part of the sample: ranges, then their lines (before the scatter,
+        // which writes the class bytes).  Each entry holds at least thr sample keys and more than T
+        // keys, which bounds the list.
+        const ChildSpan* spans = nullptr;
+        Child* children = nullptr;
+        if (inherit) {
+            const uint64_t ccap = std::min<uint64_t>(pl.total_samples / thr, pl.sum_n / ((uint64_t)T_ + 1)) + 1;
+            ST_TRY(ensure(D.children[par], ccap * sizeof(Child)));
+            ST_TRY(ensure(D.spans, ni * sizeof(ChildSpan)));
+            children = (Child*)D.children[par].p;
+            spans = (const ChildSpan*)D.spans.p;
+            k_child_split<DT><<<(unsigned)ni, 256, 0, s>>>(ni, models, sample, (const uint64_t*)D.sample_off.p,
+                                                           (const uint64_t*)D.hist.p, K, T_, thr,
+                                                           (ChildSpan*)D.spans.p, children, cnt, ccap);
+            LAUNCH_CHECK();
+            k_child_fit<DT><<<(unsigned)ccap, 256, 0, s>>>(children, cnt, ccap, sample, K);
+            LAUNCH_CHECK();
+        }
+
         // scatter
         {
             ProfScope ps(0, (double)pl.sum_n * 2.0 * (kb + (PAY ? 4 : 0)), s);
-            auto ks = tile == kTile ? k_scatter<DT, PAY, 8, kPassIPT> : k_scatter<DT, PAY, 4, kPassIPT>;
+            auto ks = inherit ? (tile == kTile ? k_scatter<DT, PAY, 8, kPassIPT, true> : k_scatter<DT, PAY, 4, kPassIPT, true>)
+                              : (tile == kTile ? k_scatter<DT, PAY, 8, kPassIPT, false>
+                                               : k_scatter<DT, PAY, 4, kPassIPT, false>);
             ks<<<(unsigned)nt, tile / kPassIPT, 0, s>>>(
                 items, (const uint64_t*)D.tile_off.p, (const uint32_t*)D.tile_map.p, nt, (const uint64_t*)D.chunk_off.p,
                 nc, models, (const double*)D.leaves.p, (const uint64_t*)D.bstart.p, (const uint64_t*)D.chunk_pref.p,
-                (const uint32_t*)D.tile_pref.p, src, psrc, dst, pdst, K, P.leaves);
+                (const uint32_t*)D.tile_pref.p, src, psrc, dst, pdst, K, P.leaves, spans, children, cls);
             LAUNCH_CHECK();
         }
         if (top && level == 0 && run.single_pass) {
@@ -583,7 +625,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         k_worklist<<<(unsigned)ni, 256, 0, s>>>(
             items, ni, models, (const uint64_t*)D.hist.p, (const uint64_t*)D.bstart.p, K, T_, src_scratch ? 0 : 1,
             (Item*)D.items[cur ^ 1].p, (BaseItem*)D.base.p, bl, cnt, C_ITEMS0 + (cur ^ 1), item_cap,
-            (CopyItem*)D.copy.p, copy_cap);
+            (CopyItem*)D.copy.p, copy_cap, spans, children);
         LAUNCH_CHECK();
         cur ^= 1;
     }
@@ -654,7 +696,8 @@ ipls_status l2pl_entry(Device& dv, hipStream_t s, const double* x, uint64_t S, u
 
 ipls_status check_params(const ipls_params& p) {
     if (p.num_buckets < 4 || p.base_case_max < 1 || p.sample_divisor < 2) return IPLS_ERR_INVALID;
-    if (p.sample_policy > 1 || p.equality > 1) return IPLS_ERR_INVALID;
+    if (p.sample_policy > 1 || p.equality > 1 || p.inherit > 1) return IPLS_ERR_INVALID;
+    if (p.inherit && (p.model != 0 || p.equality)) return IPLS_ERR_INVALID;  // defined for the FMCD line alone
     if (p.tile_keys != 0 && p.tile_keys != kTile && p.tile_keys != kSmallTile) return IPLS_ERR_INVALID;
     const uint64_t smin = p.sample_min ? p.sample_min : (p.sample_policy == 1 ? 0 : 2ull * p.num_buckets);
     if (smin > p.base_case_max) return IPLS_ERR_INVALID;
@@ -821,6 +864,7 @@ void ipls_default_params(ipls_params* p) {
     p->tile_keys = 0;
     p->sample_policy = 0;
     p->equality = 0;
+    p->inherit = 0;
 }
 
 const char* ipls_status_string(ipls_status st) {
