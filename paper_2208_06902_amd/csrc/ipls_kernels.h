@@ -760,25 +760,52 @@ __global__ __launch_bounds__(256) void k_l2pl_load(const typename Key<DT>::T* sa
 
 // ------------------------------------------------------------------ degenerate buckets
 // min and max ord of every bucket whose fit was degenerate (homogeneity check, Learned Sort
-// section; digit fallback, IPS4o section).
+// section; digit fallback, IPS4o section).  One workgroup per chunk of `chunk` tiles: a block
+// reduction, then one atomic pair per chunk (a bucket of 10^8 equal keys would otherwise send
+// hundreds of thousands of atomics to the same two words).
 template <int DT>
-__global__ __launch_bounds__(256) void k_minmax(const Item* items, const uint64_t* tile_off, const uint32_t* tile_map,
-                                                Model* models, const typename Key<DT>::T* src, uint32_t tile_keys) {
+__global__ __launch_bounds__(256) void k_minmax(const Item* items, const uint64_t* chunk_off, const uint32_t* chunk_map,
+                                                Model* models, const typename Key<DT>::T* src, uint32_t tile_keys,
+                                                uint32_t chunk) {
     using KT = Key<DT>;
-    const uint32_t i = tile_map[blockIdx.x];
+    __shared__ uint64_t s_mn[kBlock / kWave], s_mx[kBlock / kWave];
+    const uint32_t i = chunk_map[blockIdx.x];
     if (models[i].kind != kKindPending) return;
     const Item it = items[i];
-    const uint64_t base = (blockIdx.x - tile_off[i]) * tile_keys;
-    const uint64_t end = (base + tile_keys < it.n) ? base + tile_keys : it.n;
+    const uint64_t span = (uint64_t)tile_keys * chunk;
+    const uint64_t base = (blockIdx.x - chunk_off[i]) * span;
+    const uint64_t end = (base + span < it.n) ? base + span : it.n;
+    const typename KT::T* p = src + it.lo;
     uint64_t mn = ~0ull, mx = 0;
-    for (uint64_t j = base + threadIdx.x; j < end; j += blockDim.x) {
-        const uint64_t o = KT::ord(src[it.lo + j]);
-        mn = o < mn ? o : mn;
-        mx = o > mx ? o : mx;
+    constexpr int U = 8;  // loads in flight per thread
+    for (uint64_t j0 = base + threadIdx.x; j0 < end; j0 += (uint64_t)U * blockDim.x) {
+        uint64_t o[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t j = j0 + (uint64_t)u * blockDim.x;
+            o[u] = j < end ? KT::ord(__builtin_nontemporal_load(&p[j])) : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (j0 + (uint64_t)u * blockDim.x < end) {
+                mn = o[u] < mn ? o[u] : mn;
+                mx = o[u] > mx ? o[u] : mx;
+            }
+        }
     }
     mx = wave_max(mx);
     mn = ~wave_max(~mn);
+    const uint32_t wave = threadIdx.x / kWave;
     if (lane_id() == 0) {
+        s_mn[wave] = mn;
+        s_mx[wave] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (uint32_t w = 1; w < blockDim.x / kWave; ++w) {
+            mn = s_mn[w] < mn ? s_mn[w] : mn;
+            mx = s_mx[w] > mx ? s_mx[w] : mx;
+        }
         atomicMin((unsigned long long*)&models[i].umin, (unsigned long long)mn);
         atomicMax((unsigned long long*)&models[i].umax, (unsigned long long)mx);
     }
@@ -1589,7 +1616,7 @@ __device__ inline void merge_sort_lds(O* sk, uint32_t* sp, int t_in, bool active
 }
 
 template <int DT, bool PAY, int NT>
-__global__ __launch_bounds__(256) void k_base_sort(const BaseItem* list, uint64_t count, typename Key<DT>::T* keys,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PAY ? 4 : 1))) void k_base_sort(const BaseItem* list, uint64_t count, typename Key<DT>::T* keys,
                                                    uint32_t* pay, const typename Key<DT>::T* skeys,
                                                    const uint32_t* spay) {
     using KT = Key<DT>;
@@ -2006,7 +2033,8 @@ __device__ inline void base_large_keys(const BaseItem& bi, typename Key<DT>::T* 
 }
 
 template <int DT, bool PAY, int NW, int IPT>
-__global__ __launch_bounds__(64 * NW) void k_base_large(const BaseItem* list, uint64_t count,
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PAY ? 4 : 6))) void k_base_large(
+    const BaseItem* list, uint64_t count,
                                                        typename Key<DT>::T* keys, uint32_t* pay,
                                                        const typename Key<DT>::T* skeys, const uint32_t* spay) {
     if (blockIdx.x >= count) return;

@@ -535,8 +535,11 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                                    P.train_iters)));
 
         // degenerate buckets and final model
-        k_minmax<DT><<<(unsigned)nt, 256, 0, s>>>(items, (const uint64_t*)D.tile_off.p, (const uint32_t*)D.tile_map.p,
-                                                  models, src, tile);
+        k_expand<<<(unsigned)((nc + 255) / 256), 256, 0, s>>>((const uint64_t*)D.chunk_off.p, ni, nc,
+                                                              (uint32_t*)D.chunk_map.p);
+        LAUNCH_CHECK();
+        k_minmax<DT><<<(unsigned)nc, 256, 0, s>>>(items, (const uint64_t*)D.chunk_off.p, (const uint32_t*)D.chunk_map.p,
+                                                  models, src, tile, kChunk);
         LAUNCH_CHECK();
         k_finalize<DT><<<(unsigned)((ni + 255) / 256), 256, 0, s>>>(items, models, (const Model*)D.roots.p, ni, K,
                                                                 src_scratch ? 1 : 0, P.model,
@@ -544,9 +547,6 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         LAUNCH_CHECK();
 
         // classify + per-tile counts, scan of the counts, bucket starts
-        k_expand<<<(unsigned)((nc + 255) / 256), 256, 0, s>>>((const uint64_t*)D.chunk_off.p, ni, nc,
-                                                              (uint32_t*)D.chunk_map.p);
-        LAUNCH_CHECK();
         {
             ProfScope ps(1, (double)(pl.sum_n - pl.inh_n) * kb + (double)pl.inh_n, s);
             auto kc = tile == kTile ? k_classify_hist<DT, 8, kPassIPT> : k_classify_hist<DT, 4, kPassIPT>;
