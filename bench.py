@@ -109,16 +109,18 @@ def summarize_profiles(ktrace_dir: str, fetch_dir: str, write_dir: str, bench_js
     big = [(f, w) for f, w in zip(sf, sw) if f > 1e8]
     t = {"kernel": "k_scatter", "kernel_sha": kernel_hash(), "bytes_per_launch": round(per_launch),
          "launches": n_launch, "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
-         "workload": "bench.py --steps 2 --warmup 1 --no-cpu-baseline --dists normal (3 sorts of 1e8 normal fp64)",
+         "workload": "bench.py --steps 5 --warmup 5 --no-cpu-baseline (10 sorts of 1e8 fp64, all five distributions)",
          "large_launches_bytes": [[round(f), round(w)] for f, w in big[:6]],
          "algorithmic_bytes_large_launch": 1_600_000_000}
     json.dump(t, open(os.path.join(out_dir, "scatter_traffic.json"), "w"), indent=1)
     md = ["# HBM traffic of k_scatter (rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE, separate runs)", "",
           "Commands (from the repository root, GPU box), one counter per run:", "",
           "    rocprofv3 --pmc FETCH_SIZE -f csv -d <dir> -o bench -- \\",
-          "        python3 -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --dists normal",
+          "        python3 -u bench.py --steps 5 --warmup 5 --no-cpu-baseline",
           "    rocprofv3 --pmc WRITE_SIZE -f csv -d <dir> -o bench -- \\",
-          "        python3 -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --dists normal", "",
+          "        python3 -u bench.py --steps 5 --warmup 5 --no-cpu-baseline", "",
+          "The same command as the kernel trace: 10 sorts, two of each of the five distributions, the launch "
+          "mix of the bench's timed steps.", "",
           f"Calibration: the bench's device-to-device copies of one 800,000,000-byte input read as "
           f"FETCH_SIZE x {f_scale:.3f} and WRITE_SIZE x {w_scale:.3f}; every k_scatter value below is scaled "
           f"by those factors.", "",
@@ -126,8 +128,12 @@ def summarize_profiles(ktrace_dir: str, fetch_dir: str, write_dir: str, bench_js
           "|---|---:|---:|---:|"]
     for i, (f, w) in enumerate(big[:6]):
         md.append(f"| {i} | {f / 1e6:.1f} | {w / 1e6:.1f} | 1600.0 |")
+    alg = bench["roofline"].get("algorithmic_bytes_per_launch")
     md += ["", f"Mean over all {n_launch} scatter launches of the run: {per_launch / 1e6:.1f} MB per launch "
                f"(bench.py reports it as roofline.traffic while the kernel source is unchanged, sha {t['kernel_sha']})."]
+    if alg:
+        md += ["", f"Algorithmic bytes per launch of the kernel-trace run (same command): {alg / 1e6:.1f} MB; "
+                   f"measured / algorithmic = {per_launch / alg:.3f}."]
     open(os.path.join(out_dir, "scatter_traffic.md"), "w").write("\n".join(md) + "\n")
 
 
