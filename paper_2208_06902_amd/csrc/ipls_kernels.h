@@ -2,9 +2,11 @@
 //
 // A level partitions every "item" (a bucket of more than T keys) of the current source buffer
 // into K sub-buckets of the other buffer:
-//   plan -> expand -> sample gather -> (sort samples) -> FMCD fit [-> two-level model]
-//   -> min/max of degenerate buckets -> finalize -> classify + histogram -> bucket starts
-//   -> scatter (stable, decoupled look-back) -> worklist (next items, base-case buckets)
+//   plan -> expand -> sample gather -> (sort samples) -> FMCD fit [-> two-level model, splitter
+//   tree, equality buckets] -> min/max of degenerate buckets -> finalize -> classify + per-tile
+//   counts -> scan of the chunk totals -> bucket starts [-> children's inherited lines]
+//   -> scatter (stable; destinations from the scanned counts) -> worklist (next items, base-case
+//   buckets)
 // and the base case sorts the small buckets in LDS into the caller's buffer.  The paper's
 // IPS4o framework does the same steps with threads and in-place block permutation (Background,
 // IPS4o section); here the GPU's many workgroups replace the task scheduler and the level's
