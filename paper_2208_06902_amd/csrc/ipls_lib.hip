@@ -58,7 +58,7 @@ ipls_status ensure(Buf& b, size_t bytes) {
 
 
 struct Depth {
-    Buf scratch, spay, items[2], base, sample_base, counters, plan, tile_off, sample_off, fit_off, chunk_off, tile_map,
+    Buf scratch, spay, items[2], base[2], sample_base, counters, plan, tile_off, sample_off, fit_off, chunk_off, tile_map,
         fit_map, chunk_map, models, masks, hist, bstart, tile_pref, chunk_sum, chunk_pref, sample, leaves, seg, roots,
         leaf_first, leaf_last, eqinfo, rsample, copy, copy_off, copy_map, treeflag, sample2, children[2], spans, cls;
     Plan* plan_h = nullptr;
@@ -70,6 +70,10 @@ struct Device {
     Depth depth[kMaxDepth];
     std::mutex mu;
     uint64_t* seg_h = nullptr;  // pinned staging of a single segment's offsets
+    // The top-level sort's base case runs on a stream of its own (non-blocking, default priority),
+    // beside the next level's partition; ev_base[parity] marks the end of a level's base launch.
+    hipStream_t side = nullptr;
+    hipEvent_t ev_base[2] = {nullptr, nullptr};
 };
 
 void release(Buf& b) {
@@ -80,7 +84,7 @@ void release(Buf& b) {
 
 void release_device(Device& dv) {
     for (Depth& D : dv.depth) {
-        for (Buf* b : {&D.scratch, &D.spay, &D.items[0], &D.items[1], &D.base, &D.sample_base, &D.counters, &D.plan,
+        for (Buf* b : {&D.scratch, &D.spay, &D.items[0], &D.items[1], &D.base[0], &D.base[1], &D.sample_base, &D.counters, &D.plan,
                        &D.tile_off, &D.sample_off, &D.fit_off, &D.chunk_off, &D.tile_map, &D.fit_map, &D.chunk_map,
                        &D.models, &D.masks, &D.hist, &D.bstart, &D.tile_pref, &D.chunk_sum, &D.chunk_pref, &D.sample,
                        &D.leaves, &D.seg, &D.roots, &D.leaf_first, &D.leaf_last, &D.eqinfo, &D.rsample, &D.copy,
@@ -92,6 +96,12 @@ void release_device(Device& dv) {
     }
     if (dv.seg_h) (void)hipHostFree(dv.seg_h);
     dv.seg_h = nullptr;
+    for (hipEvent_t& e : dv.ev_base) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
+    if (dv.side) (void)hipStreamDestroy(dv.side);
+    dv.side = nullptr;
 }
 
 struct Prof {
@@ -385,7 +395,27 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     const uint64_t copy_cap = P.equality ? item_cap * kMaxHeavy + 1 : 1;  // equality buckets per level
     ST_TRY(ensure(D.copy, copy_cap * sizeof(CopyItem)));
     ST_TRY(ensure(D.copy_off, (copy_cap + 1) * 8));
-    ST_TRY(ensure(D.base, base_cap * sizeof(BaseItem)));
+    ST_TRY(ensure(D.base[0], base_cap * sizeof(BaseItem)));
+    ST_TRY(ensure(D.base[1], base_cap * sizeof(BaseItem)));
+    // Base-case lists alternate by level parity: level L's worklist writes base[L & 1], which the
+    // base launch of level L + 1 reads (the seeds count as level -1).  The top-level sort runs those
+    // launches on the side stream; the main stream waits for them only before the list is written
+    // again, two levels later, and at the end of the sort.
+    const bool overlap = top;
+    if (overlap && !dv.side) {
+        HIP_TRY(hipStreamCreateWithFlags(&dv.side, hipStreamNonBlocking));
+        for (hipEvent_t& e : dv.ev_base) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    hipStream_t sb = overlap ? dv.side : s;  // stream of the base-case launches
+    bool base_pending[2] = {false, false};   // a side-stream base launch read base[parity]
+    auto join = [&]() -> ipls_status {       // the main stream continues after the base case
+        for (int q = 0; q < 2; ++q)
+            if (base_pending[q]) {
+                if (hipStreamWaitEvent(s, dv.ev_base[q], 0) != hipSuccess) return IPLS_ERR_HIP;
+                base_pending[q] = false;
+            }
+        return IPLS_OK;
+    };
     ST_TRY(ensure(D.counters, C_N * sizeof(uint64_t)));
     ST_TRY(ensure(D.plan, sizeof(Plan)));
     ST_TRY(ensure(D.tile_off, (item_cap + 1) * 8));
@@ -403,7 +433,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
 
     HIP_TRY(hipMemsetAsync(cnt, 0, C_N * sizeof(uint64_t), s));
     k_seed<<<(unsigned)((nseg + 255) / 256), 256, 0, s>>>(seg_off, nseg, T_, (Item*)D.items[0].p,
-                                                          (BaseItem*)D.base.p, bl, cnt, item_cap);
+                                                          (BaseItem*)D.base[1].p, bl, cnt, item_cap);
     LAUNCH_CHECK();
 
     LevelArgs A;
@@ -434,7 +464,10 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         HIP_TRY(hipMemcpyAsync(D.plan_h, D.plan.p, sizeof(Plan), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         const Plan pl = *D.plan_h;
-        if (pl.err) return IPLS_ERR_DEVICE;
+        if (pl.err) {
+            ST_TRY(join());
+            return IPLS_ERR_DEVICE;
+        }
         if (top && inherit) prof_add_bytes(0, (double)pl.inh_n);  // class bytes the last scatter wrote
         if (top && level > 0) {
             // the previous level's buckets that were not closed were partitioned
@@ -465,14 +498,26 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             LAUNCH_CHECK();
         }
         if (pl.num_base) {
-            ProfScope ps(2, (double)pl.base_keys * 2.0 * (kb + (PAY ? 4 : 0)), s);
-            for (int c = 0; c < kBaseClasses; ++c)
-                ST_TRY((launch_base<DT, PAY>(s, c, (const BaseItem*)D.base.p + bl.off[c], pl.cls_count[c], keys, pay,
-                                             scratch, spay)));
+            // the previous level's buckets of <= T keys: base[(level - 1) & 1], complete (the host
+            // has just synchronised the main stream for the plan)
+            const int bp = (level + 1) & 1;
+            {
+                ProfScope ps(2, (double)pl.base_keys * 2.0 * (kb + (PAY ? 4 : 0)), sb);
+                for (int c = 0; c < kBaseClasses; ++c)
+                    ST_TRY((launch_base<DT, PAY>(sb, c, (const BaseItem*)D.base[bp].p + bl.off[c], pl.cls_count[c],
+                                                 keys, pay, scratch, spay)));
+            }
+            if (overlap) {
+                HIP_TRY(hipEventRecord(dv.ev_base[bp], sb));
+                base_pending[bp] = true;
+            }
             if (top) run.st.base_buckets += pl.num_base;
         }
         if (pl.num_items == 0) break;
-        if (level + 1 > kMaxLevels) return IPLS_ERR_DEVICE;
+        if (level + 1 > kMaxLevels) {
+            ST_TRY(join());
+            return IPLS_ERR_DEVICE;
+        }
         const bool src_scratch = (level & 1) != 0;
         T* src = src_scratch ? scratch : keys;
         T* dst = src_scratch ? keys : scratch;
@@ -608,6 +653,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             Model m0;
             HIP_TRY(hipMemcpyAsync(&m0, models, sizeof(Model), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
+            ST_TRY(join());
             if (m0.kind != kKindClosedKeep) {
                 HIP_TRY(hipMemcpyAsync(keys, scratch, len * kb, hipMemcpyDeviceToDevice, s));
                 if (PAY) HIP_TRY(hipMemcpyAsync(pay, spay, len * 4, hipMemcpyDeviceToDevice, s));
@@ -621,15 +667,20 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             if (ni == 1) run.st.level1_max_load = *std::max_element(h.begin(), h.end());
         }
 
-        // next level
+        // next level; this level's base-case list is base[level & 1], whose last reader may still run
+        if (base_pending[par]) {
+            HIP_TRY(hipStreamWaitEvent(s, dv.ev_base[par], 0));
+            base_pending[par] = false;
+        }
         k_worklist<<<(unsigned)ni, 256, 0, s>>>(
             items, ni, models, (const uint64_t*)D.hist.p, (const uint64_t*)D.bstart.p, K, T_, src_scratch ? 0 : 1,
-            (Item*)D.items[cur ^ 1].p, (BaseItem*)D.base.p, bl, cnt, C_ITEMS0 + (cur ^ 1), item_cap,
+            (Item*)D.items[cur ^ 1].p, (BaseItem*)D.base[par].p, bl, cnt, C_ITEMS0 + (cur ^ 1), item_cap,
             (CopyItem*)D.copy.p, copy_cap, spans, children);
         LAUNCH_CHECK();
         cur ^= 1;
     }
-    return IPLS_OK;
+    // the caller's stream completes only after the base case
+    return join();
 }
 
 template <int DT>
@@ -778,6 +829,7 @@ ipls_status sort_single(Device& dv, void* keys, uint32_t* payload, size_t n, ipl
     if (hipMemcpyAsync(D0.seg.p, dv.seg_h, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, s) != hipSuccess)
         return IPLS_ERR_HIP;
     st = dispatch(dv, run, keys, payload, n, (const uint64_t*)D0.seg.p, 1, workspace);
+    if (st != IPLS_OK && dv.side) (void)hipStreamSynchronize(dv.side);
     st = finish(st, s);
     if (stats) *stats = run.st;
     return st;
@@ -811,6 +863,7 @@ ipls_status sort_multi(Device& dv, void* keys, uint32_t* payload, const uint64_t
     run.dtype = dtype;
     std::memset(&run.st, 0, sizeof(run.st));
     st = dispatch(dv, run, keys, payload, len, seg_offsets, nseg, workspace);
+    if (st != IPLS_OK && dv.side) (void)hipStreamSynchronize(dv.side);
     st = finish(st, s);
     if (stats) *stats = run.st;
     return st;
