@@ -110,6 +110,8 @@ struct Plan {
     uint64_t copy_count, copy_tiles;   // equality buckets to move back, in tiles of kCopyTile keys
     uint64_t inherited;                // partitions whose model was inherited, so far
     uint64_t inh_n;                    // keys of this level's items with inherited lines
+    uint64_t l1max;                    // largest bucket of the first level (single-array sorts)
+    uint64_t seq;                      // the host's number of the k_plan launch that wrote it
 };
 
 constexpr uint32_t kCopyTile = 4096;
@@ -125,6 +127,7 @@ enum : int {
     C_COPYKEYS = 19,  // ... and their keys
     C_CHILD = 20,     // entries of this level's child list
     C_INHERITED = 21, // partitions with an inherited model (all levels)
+    C_L1MAX = 22,     // largest bucket of the first level (single-array sorts)
     C_N = 32
 };
 

@@ -32,7 +32,8 @@ struct LevelArgs {
 __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* cnt, int cur, Plan* plan, uint64_t* tile_off,
                                                uint64_t* sample_off, uint64_t* fit_off, uint64_t* chunk_off,
                                                LevelArgs A, uint64_t item_cap, BaseLayout bl, const CopyItem* copy,
-                                               uint64_t* copy_off, uint64_t copy_cap, const Child* prev_children) {
+                                               uint64_t* copy_off, uint64_t copy_cap, const Child* prev_children,
+                                               Plan* plan_host, uint64_t seq) {
     __shared__ uint64_t sc[16];
     __shared__ uint64_t s_max[4];
     const uint64_t num = cnt[C_ITEMS0 + cur];
@@ -96,6 +97,7 @@ __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* cnt,
         plan->copy_tiles = run_k;
         plan->eq_closed = cnt[C_EQCLOSED];
         plan->inherited = cnt[C_INHERITED];
+        plan->l1max = cnt[C_L1MAX];
         cnt[C_CHILD] = 0;
         if (ncopy_all > copy_cap) cnt[C_ERR] |= kErrCapacity;
         cnt[C_COPY] = 0;
@@ -132,6 +134,15 @@ __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* cnt,
         cnt[C_ITEMS0 + cur] = 0;  // this level's list is consumed
         cnt[C_ITEMS0 + (cur ^ 1)] = 0;
         cnt[C_BASE] = 0;
+        plan->seq = seq;
+        if (plan_host) {
+            // the same plan straight into the host's pinned (coherent) buffer, its number last
+            Plan h = *plan;
+            h.seq = 0;
+            *plan_host = h;
+            __threadfence_system();
+            plan_host->seq = seq;
+        }
     }
 }
 
@@ -1389,7 +1400,8 @@ __global__ __launch_bounds__(256) void k_worklist(const Item* items, uint64_t nu
                                                   const uint64_t* hist, const uint64_t* bstart, uint32_t K, uint32_t T,
                                                   int dst_is_scratch, Item* next, BaseItem* base, BaseLayout bl,
                                                   uint64_t* cnt, int next_slot, uint64_t next_cap, CopyItem* copy,
-                                                  uint64_t copy_cap, const ChildSpan* spans, const Child* children) {
+                                                  uint64_t copy_cap, const ChildSpan* spans, const Child* children,
+                                                  uint64_t* l1max) {
     __shared__ AppendScratch sc;
     __shared__ int s_ent[kMaxBuckets];  // bucket -> its entry in the child list with a usable line, or -1
     __shared__ uint64_t s_e[kMaxBuckets], s_p[kMaxBuckets], s_sum[kMaxBuckets];
@@ -1430,6 +1442,17 @@ __global__ __launch_bounds__(256) void k_worklist(const Item* items, uint64_t nu
                 c = 0;  // neither an item nor a base-case bucket
                 breaker = true;
             }
+        }
+    }
+    if (l1max) {  // the first level of a single array: its largest bucket, for the statistics
+        __shared__ uint64_t s_mx[kBlock / kWave];
+        const uint64_t h = wave_max<uint64_t>((i < num_items && b < K) ? hist[i * K + b] : 0);
+        if (lane_id() == 0) s_mx[b / kWave] = h;
+        __syncthreads();
+        if (b == 0) {
+            uint64_t mx = 0;
+            for (uint32_t w = 0; w < blockDim.x / kWave; ++w) mx = s_mx[w] > mx ? s_mx[w] : mx;
+            *l1max = mx;
         }
     }
     const uint64_t half = T / 2 > 0 ? T / 2 : 1;

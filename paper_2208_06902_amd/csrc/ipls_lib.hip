@@ -61,7 +61,9 @@ struct Depth {
     Buf scratch, spay, items[2], base[2], sample_base, counters, plan, tile_off, sample_off, fit_off, chunk_off, tile_map,
         fit_map, chunk_map, models, masks, hist, bstart, tile_pref, chunk_sum, chunk_pref, sample, leaves, seg, roots,
         leaf_first, leaf_last, eqinfo, rsample, copy, copy_off, copy_map, treeflag, sample2, children[2], spans, cls;
-    Plan* plan_h = nullptr;
+    Plan* plan_h = nullptr;     // pinned, coherent: k_plan writes it directly
+    Plan* plan_hd = nullptr;    // its device address
+    uint64_t plan_seq = 0;      // k_plan launches so far
 };
 
 // One engine context: the cached buffers of every nesting depth.  Calls on one context are
@@ -93,6 +95,7 @@ void release_device(Device& dv) {
             release(*b);
         if (D.plan_h) (void)hipHostFree(D.plan_h);
         D.plan_h = nullptr;
+        D.plan_hd = nullptr;
     }
     if (dv.seg_h) (void)hipHostFree(dv.seg_h);
     dv.seg_h = nullptr;
@@ -422,7 +425,11 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     ST_TRY(ensure(D.sample_off, (item_cap + 1) * 8));
     ST_TRY(ensure(D.fit_off, (item_cap + 1) * 8));
     ST_TRY(ensure(D.chunk_off, (item_cap + 1) * 8));
-    if (!D.plan_h) HIP_TRY(hipHostMalloc((void**)&D.plan_h, sizeof(Plan), hipHostMallocDefault));
+    if (!D.plan_h) {
+        HIP_TRY(hipHostMalloc((void**)&D.plan_h, sizeof(Plan), hipHostMallocMapped | hipHostMallocCoherent));
+        std::memset(D.plan_h, 0, sizeof(Plan));
+        HIP_TRY(hipHostGetDevicePointer((void**)&D.plan_hd, D.plan_h, 0));
+    }
     uint64_t* cnt = (uint64_t*)D.counters.p;
     // sample inheritance: samples and child lists alternate between two buffers by level parity
     // (a level reads its parent level's); one class byte per key
@@ -459,10 +466,19 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         const Child* prev_children = (inherit && level > 0) ? (const Child*)D.children[par ^ 1].p : nullptr;
         k_plan<<<1, 1024, 0, s>>>((const Item*)D.items[cur].p, cnt, cur, (Plan*)D.plan.p, (uint64_t*)D.tile_off.p, (uint64_t*)D.sample_off.p,
                                   (uint64_t*)D.fit_off.p, (uint64_t*)D.chunk_off.p, A, item_cap, bl,
-                                  (const CopyItem*)D.copy.p, (uint64_t*)D.copy_off.p, copy_cap, prev_children);
+                                  (const CopyItem*)D.copy.p, (uint64_t*)D.copy_off.p, copy_cap, prev_children,
+                                  D.plan_hd, ++D.plan_seq);
         LAUNCH_CHECK();
-        HIP_TRY(hipMemcpyAsync(D.plan_h, D.plan.p, sizeof(Plan), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        if (((volatile Plan*)D.plan_h)->seq != D.plan_seq) {
+            // not visible yet through the mapped buffer: copy the device's plan instead
+            HIP_TRY(hipMemcpyAsync(D.plan_h, D.plan.p, sizeof(Plan), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (D.plan_h->seq != D.plan_seq) {
+                ST_TRY(join());
+                return IPLS_ERR_DEVICE;
+            }
+        }
         const Plan pl = *D.plan_h;
         if (pl.err) {
             ST_TRY(join());
@@ -479,6 +495,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             }
             run.st.closed = pl.closed + pl.eq_closed;
             run.st.inherited = pl.inherited;
+            if (level == 1) run.st.level1_max_load = pl.l1max;
             run.st.fallback = pl.digit;
             run.st.l2pl_used = pl.l2pl;
             prev_closed = pl.closed;
@@ -660,12 +677,6 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             }
             return IPLS_OK;
         }
-        if (top && level == 0 && run.st.level1_max_load == 0) {
-            std::vector<uint64_t> h(K);
-            HIP_TRY(hipMemcpyAsync(h.data(), D.hist.p, K * 8, hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            if (ni == 1) run.st.level1_max_load = *std::max_element(h.begin(), h.end());
-        }
 
         // next level; this level's base-case list is base[level & 1], whose last reader may still run
         if (base_pending[par]) {
@@ -675,7 +686,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         k_worklist<<<(unsigned)ni, 256, 0, s>>>(
             items, ni, models, (const uint64_t*)D.hist.p, (const uint64_t*)D.bstart.p, K, T_, src_scratch ? 0 : 1,
             (Item*)D.items[cur ^ 1].p, (BaseItem*)D.base[par].p, bl, cnt, C_ITEMS0 + (cur ^ 1), item_cap,
-            (CopyItem*)D.copy.p, copy_cap, spans, children);
+            (CopyItem*)D.copy.p, copy_cap, spans, children, (top && level == 0 && ni == 1) ? cnt + C_L1MAX : nullptr);
         LAUNCH_CHECK();
         cur ^= 1;
     }

@@ -42,6 +42,7 @@ def check_sort(keys, payload=None, **kw):
         assert np.array_equal(gpay, wpay)
     assert st["passes"] == ost["passes"], (st, ost)
     assert st["levels"] == ost["max_level"], (st, ost)
+    assert st["level1_max_load"] == ost["level1_max_load"], (st, ost)
     return st
 
 
