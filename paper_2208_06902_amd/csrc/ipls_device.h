@@ -111,6 +111,7 @@ struct Plan {
     uint64_t inherited;                // partitions whose model was inherited, so far
     uint64_t inh_n;                    // keys of this level's items with inherited lines
     uint64_t l1max;                    // largest bucket of the first level (single-array sorts)
+    uint64_t n_wide;                   // items of more than kScanSerial chunks
     uint64_t seq;                      // the host's number of the k_plan launch that wrote it
 };
 
@@ -351,6 +352,33 @@ __device__ inline V block_exclusive_sum(V v, V* scratch, V* total) {
     __syncthreads();
     *total = all;
     return before + inc - v;
+}
+
+// Exclusive sums of NV values per thread over the block in one exchange (blockDim.x a multiple of
+// 64, at most 1024 threads); tot gets the block's sums.  `scratch` holds 16 * NV values.
+template <int NV>
+__device__ inline void block_exclusive_sums(const uint64_t (&v)[NV], uint64_t (&ex)[NV], uint64_t (&tot)[NV],
+                                            uint64_t* scratch) {
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    uint64_t inc[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) inc[j] = wave_inclusive_sum<uint64_t>(v[j]);
+    if (lane == kWave - 1)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) scratch[wave * NV + j] = inc[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        uint64_t before = 0, all = 0;
+        for (uint32_t w = 0; w < nw; ++w) {
+            const uint64_t x = scratch[w * NV + j];
+            if (w < wave) before += x;
+            all += x;
+        }
+        ex[j] = before + inc[j] - v[j];
+        tot[j] = all;
+    }
+    __syncthreads();
 }
 
 template <typename V>

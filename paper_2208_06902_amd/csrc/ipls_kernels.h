@@ -18,6 +18,9 @@
 
 namespace ipls {
 
+// Items of more than kScanSerial chunks have their chunk totals scanned by a workgroup per bucket.
+constexpr uint64_t kScanSerial = 64;
+
 struct LevelArgs {
     uint32_t K, T, M;
     uint64_t div, smin, smax, seed;
@@ -33,8 +36,10 @@ __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* cnt,
                                                uint64_t* sample_off, uint64_t* fit_off, uint64_t* chunk_off,
                                                LevelArgs A, uint64_t item_cap, BaseLayout bl, const CopyItem* copy,
                                                uint64_t* copy_off, uint64_t copy_cap, const Child* prev_children,
-                                               Plan* plan_host, uint64_t seq) {
+                                               Plan* plan_host, uint64_t seq, BaseItem* sample_base,
+                                               uint32_t* wide_items) {
     __shared__ uint64_t sc[16];
+    __shared__ uint64_t sc6[16 * 7];
     __shared__ uint64_t s_max[4];
     const uint64_t num = cnt[C_ITEMS0 + cur];
     uint64_t nb = 0;
@@ -45,11 +50,11 @@ __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* cnt,
     }
     if (threadIdx.x == 0) { s_max[0] = s_max[1] = s_max[2] = s_max[3] = 0; }
     __syncthreads();
-    uint64_t run_t = 0, run_s = 0, run_f = 0, run_c = 0;
+    uint64_t run_t = 0, run_s = 0, run_f = 0, run_c = 0, run_w = 0, sum_n = 0, sum_inh = 0;
     const uint64_t use = num < item_cap ? num : item_cap;
     for (uint64_t base = 0; base < use; base += blockDim.x) {
         uint64_t i = base + threadIdx.x;
-        uint64_t nt = 0, ns = 0, nf = 0, nc = 0, n = 0;
+        uint64_t nt = 0, ns = 0, nf = 0, nc = 0, n = 0, ninh = 0;
         if (i < use) {
             const Item it = items[i];
             n = it.n;
@@ -58,26 +63,38 @@ __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* cnt,
             ns = (it.inh && prev_children) ? prev_children[it.inh - 1].s_len
                                            : sample_size(n, A.div, A.smin, A.smax, A.policy, A.K);
             nf = ns > A.small_S ? (ns + A.fit_chunk - 1) / A.fit_chunk : 0;
-            atomicMax((unsigned long long*)&s_max[0], (unsigned long long)ns);
-            atomicMax((unsigned long long*)&s_max[1], (unsigned long long)n);
-            atomicAdd((unsigned long long*)&s_max[2], (unsigned long long)n);
-            if (it.inh && prev_children) atomicAdd((unsigned long long*)&s_max[3], (unsigned long long)n);
+            ninh = (it.inh && prev_children) ? n : 0;
         }
-        uint64_t tt, ts, tf, tc;
-        uint64_t ec = block_exclusive_sum<uint64_t>(nc, sc, &tc);
-        uint64_t et = block_exclusive_sum<uint64_t>(nt, sc, &tt);
-        uint64_t es = block_exclusive_sum<uint64_t>(ns, sc, &ts);
-        uint64_t ef = block_exclusive_sum<uint64_t>(nf, sc, &tf);
+        // maxima: one LDS atomic per wave
+        const uint64_t mS = wave_max<uint64_t>(ns), mN = wave_max<uint64_t>(n);
+        if (lane_id() == 0) {
+            atomicMax((unsigned long long*)&s_max[0], (unsigned long long)mS);
+            atomicMax((unsigned long long*)&s_max[1], (unsigned long long)mN);
+        }
+        const uint64_t wide = nc > kScanSerial ? 1 : 0;
+        const uint64_t v[7] = {nc, nt, ns, nf, n, ninh, wide};
+        uint64_t ex[7], tot[7];
+        block_exclusive_sums<7>(v, ex, tot, sc6);
         if (i < use) {
-            tile_off[i] = run_t + et;
-            sample_off[i] = run_s + es;
-            fit_off[i] = run_f + ef;
-            chunk_off[i] = run_c + ec;
+            chunk_off[i] = run_c + ex[0];
+            tile_off[i] = run_t + ex[1];
+            sample_off[i] = run_s + ex[2];
+            fit_off[i] = run_f + ex[3];
+            // the samples as base-case buckets of the sample buffer (used when every sample has <= T keys)
+            if (sample_base) sample_base[i] = BaseItem{run_s + ex[2], (uint32_t)ns, 0};
+            if (wide) wide_items[run_w + ex[6]] = (uint32_t)i;  // items whose chunks a workgroup per bucket scans
         }
-        run_c += tc;
-        run_t += tt;
-        run_s += ts;
-        run_f += tf;
+        run_c += tot[0];
+        run_t += tot[1];
+        run_s += tot[2];
+        run_f += tot[3];
+        sum_n += tot[4];
+        sum_inh += tot[5];
+        run_w += tot[6];
+    }
+    if (threadIdx.x == 0) {
+        s_max[2] = sum_n;
+        s_max[3] = sum_inh;
     }
     // tiles of the equality buckets the previous level left in the scratch buffer
     const uint64_t ncopy_all = cnt[C_COPY], ncopy = ncopy_all < copy_cap ? ncopy_all : copy_cap;
@@ -119,6 +136,7 @@ __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* cnt,
         plan->max_n = s_max[1];
         plan->sum_n = s_max[2];
         plan->inh_n = s_max[3];
+        plan->n_wide = run_w;
         plan->err = e;
         plan->closed = cnt[C_STATS + 0];
         plan->digit = cnt[C_STATS + 1];
@@ -157,6 +175,24 @@ __global__ void k_expand(const uint64_t* off, uint64_t num_items, uint64_t total
         else hi = mid;
     }
     map[t] = (uint32_t)lo;
+}
+
+// Two maps in one launch: map1 over [0, total1) from off1, map2 over [0, total2) from off2 (both
+// with num_items ranges).
+__global__ void k_expand2(const uint64_t* off1, uint64_t total1, uint32_t* map1, const uint64_t* off2,
+                          uint64_t total2, uint32_t* map2, uint64_t num_items) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    auto find = [&](const uint64_t* off) {
+        uint64_t lo = 0, hi = num_items;  // largest i with off[i] <= t
+        while (hi - lo > 1) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (off[mid] <= t) lo = mid;
+            else hi = mid;
+        }
+        return (uint32_t)lo;
+    };
+    if (t < total1) map1[t] = find(off1);
+    if (t < total2) map2[t] = find(off2);
 }
 
 // ------------------------------------------------------------------ seeds
@@ -211,13 +247,6 @@ __global__ void k_sample(const Item* items, uint64_t num_items, const uint64_t* 
     const uint64_t stream = mix64(seed ^ mix64(it.lo_rel * kGamma + it.n));
     const uint64_t h = mix64(stream + (j + 1) * kGamma);
     sample[s] = src[it.lo + a + h % (b - a)];
-}
-
-// sample segments as base-case buckets of the sample buffer (when every sample has <= T keys)
-__global__ void k_sample_base(const uint64_t* sample_off, uint64_t num_items, BaseItem* base) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= num_items) return;
-    base[i] = BaseItem{sample_off[i], (uint32_t)(sample_off[i + 1] - sample_off[i]), 0};
 }
 
 // ------------------------------------------------------------------ FMCD fit (Linear Models section)
@@ -1188,9 +1217,7 @@ __global__ __launch_bounds__(64 * NW) void k_classify_hist(const Item* items, co
 // Exclusive prefix of every item's chunk totals, per bucket (chunk_pref[c][b]); the total is the
 // item's bucket size hist[i][b].  Items of at most kScanSerial chunks: one thread per (item, bucket)
 // walks the chunks (neighbouring threads read neighbouring buckets).  Larger items (only at the
-// first levels of big arrays): one wave per (item, bucket), 64 chunks per step, a wave-wide
-// inclusive scan plus the running carry.
-constexpr uint64_t kScanSerial = 64;
+// first levels of big arrays): one workgroup per (item, bucket).
 
 __global__ __launch_bounds__(256) void k_scan_chunks(const uint64_t* chunk_off, uint64_t num_items, uint32_t K,
                                                      const uint32_t* chunk_sum, uint64_t* chunk_pref,
@@ -1209,33 +1236,37 @@ __global__ __launch_bounds__(256) void k_scan_chunks(const uint64_t* chunk_off, 
     hist[i * K + b] = run;
 }
 
-__global__ __launch_bounds__(256) void k_scan_chunks_wide(const uint64_t* chunk_off, uint64_t num_items, uint32_t K,
-                                                          const uint32_t* chunk_sum, uint64_t* chunk_pref,
+__global__ __launch_bounds__(256) void k_scan_chunks_wide(const uint64_t* chunk_off, const uint32_t* wide_items,
+                                                          uint32_t K, const uint32_t* chunk_sum, uint64_t* chunk_pref,
                                                           uint64_t* hist) {
-    const uint64_t w = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    if (w >= num_items * K) return;
-    const uint64_t i = w / K, b = w % K;
-    const uint32_t lane = lane_id();
+    // one workgroup per (wide item, bucket): thread t sums a contiguous run of the item's chunks,
+    // one block scan of those sums, then each thread writes its run's prefixes
+    __shared__ uint64_t sc[16];
+    const uint64_t g = blockIdx.x;
+    const uint64_t i = wide_items[g / K], b = g % K;
     const uint64_t c0 = chunk_off[i], c1 = chunk_off[i + 1];
-    if (c1 - c0 <= kScanSerial) return;
-    uint64_t carry = 0;
-    constexpr int U = 4;  // rounds of 64 chunks whose loads are issued together
-    for (uint64_t c = c0; c < c1; c += U * kWave) {
-        uint64_t v[U];
+    const uint64_t C = c1 - c0;
+    if (C <= kScanSerial) return;
+    const uint64_t per = (C + blockDim.x - 1) / blockDim.x;
+    const uint64_t lo = c0 + threadIdx.x * per;
+    const uint64_t hi = lo + per < c1 ? lo + per : c1;
+    uint64_t sum = 0;
+    constexpr int U = 8;  // loads in flight
+    for (uint64_t c = lo; c < hi; c += U) {
+        uint32_t v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint64_t j = c + u * kWave + lane;
-            v[u] = j < c1 ? chunk_sum[j * K + b] : 0;
-        }
+        for (int u = 0; u < U; ++u) v[u] = c + u < hi ? chunk_sum[(c + u) * K + b] : 0u;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint64_t j = c + u * kWave + lane;
-            const uint64_t inc = wave_inclusive_sum<uint64_t>(v[u]);
-            if (j < c1) chunk_pref[j * K + b] = carry + inc - v[u];
-            carry += __shfl(inc, kWave - 1, kWave);
-        }
+        for (int u = 0; u < U; ++u) sum += v[u];
     }
-    if (lane == 0) hist[i * K + b] = carry;
+    uint64_t total;
+    uint64_t run = block_exclusive_sum<uint64_t>(sum, sc, &total);
+    for (uint64_t c = lo; c < hi; ++c) {
+        const uint64_t v = chunk_sum[c * K + b];
+        chunk_pref[c * K + b] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) hist[i * K + b] = total;
 }
 
 // Bucket starts of every item: exclusive prefix of its K counts.

@@ -60,7 +60,7 @@ ipls_status ensure(Buf& b, size_t bytes) {
 struct Depth {
     Buf scratch, spay, items[2], base[2], sample_base, counters, plan, tile_off, sample_off, fit_off, chunk_off, tile_map,
         fit_map, chunk_map, models, masks, hist, bstart, tile_pref, chunk_sum, chunk_pref, sample, leaves, seg, roots,
-        leaf_first, leaf_last, eqinfo, rsample, copy, copy_off, copy_map, treeflag, sample2, children[2], spans, cls;
+        leaf_first, leaf_last, eqinfo, rsample, copy, copy_off, copy_map, treeflag, sample2, children[2], spans, cls, wide;
     Plan* plan_h = nullptr;     // pinned, coherent: k_plan writes it directly
     Plan* plan_hd = nullptr;    // its device address
     uint64_t plan_seq = 0;      // k_plan launches so far
@@ -91,7 +91,7 @@ void release_device(Device& dv) {
                        &D.models, &D.masks, &D.hist, &D.bstart, &D.tile_pref, &D.chunk_sum, &D.chunk_pref, &D.sample,
                        &D.leaves, &D.seg, &D.roots, &D.leaf_first, &D.leaf_last, &D.eqinfo, &D.rsample, &D.copy,
                        &D.copy_off, &D.copy_map, &D.treeflag, &D.sample2, &D.children[0], &D.children[1],
-                       &D.spans, &D.cls})
+                       &D.spans, &D.cls, &D.wide})
             release(*b);
         if (D.plan_h) (void)hipHostFree(D.plan_h);
         D.plan_h = nullptr;
@@ -349,10 +349,7 @@ ipls_status sort_samples(Device& dv, Run& run, int d, const Plan& pl, typename K
     Depth& D = dv.depth[d];
     hipStream_t s = run.s;
     if (pl.max_S <= run.p.base_case_max) {
-        ST_TRY(ensure(D.sample_base, pl.num_items * sizeof(BaseItem)));
-        k_sample_base<<<(unsigned)((pl.num_items + 255) / 256), 256, 0, s>>>((const uint64_t*)D.sample_off.p,
-                                                                            pl.num_items, (BaseItem*)D.sample_base.p);
-        LAUNCH_CHECK();
+        // k_plan has written every sample as a base-case bucket of the sample buffer
         return launch_base<DT, false>(s, base_class((uint32_t)pl.max_S), (const BaseItem*)D.sample_base.p,
                                       pl.num_items, sample, nullptr, nullptr, nullptr);
     }
@@ -425,6 +422,8 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     ST_TRY(ensure(D.sample_off, (item_cap + 1) * 8));
     ST_TRY(ensure(D.fit_off, (item_cap + 1) * 8));
     ST_TRY(ensure(D.chunk_off, (item_cap + 1) * 8));
+    ST_TRY(ensure(D.sample_base, item_cap * sizeof(BaseItem)));
+    ST_TRY(ensure(D.wide, item_cap * 4));
     if (!D.plan_h) {
         HIP_TRY(hipHostMalloc((void**)&D.plan_h, sizeof(Plan), hipHostMallocMapped | hipHostMallocCoherent));
         std::memset(D.plan_h, 0, sizeof(Plan));
@@ -467,7 +466,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         k_plan<<<1, 1024, 0, s>>>((const Item*)D.items[cur].p, cnt, cur, (Plan*)D.plan.p, (uint64_t*)D.tile_off.p, (uint64_t*)D.sample_off.p,
                                   (uint64_t*)D.fit_off.p, (uint64_t*)D.chunk_off.p, A, item_cap, bl,
                                   (const CopyItem*)D.copy.p, (uint64_t*)D.copy_off.p, copy_cap, prev_children,
-                                  D.plan_hd, ++D.plan_seq);
+                                  D.plan_hd, ++D.plan_seq, (BaseItem*)D.sample_base.p, (uint32_t*)D.wide.p);
         LAUNCH_CHECK();
         HIP_TRY(hipStreamSynchronize(s));
         if (((volatile Plan*)D.plan_h)->seq != D.plan_seq) {
@@ -560,8 +559,9 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         const Item* items = (const Item*)D.items[cur].p;
         Model* models = (Model*)D.models.p;
 
-        k_expand<<<(unsigned)((nt + 255) / 256), 256, 0, s>>>((const uint64_t*)D.tile_off.p, ni, nt,
-                                                              (uint32_t*)D.tile_map.p);
+        k_expand2<<<(unsigned)((std::max(nt, nc) + 255) / 256), 256, 0, s>>>(
+            (const uint64_t*)D.tile_off.p, nt, (uint32_t*)D.tile_map.p, (const uint64_t*)D.chunk_off.p, nc,
+            (uint32_t*)D.chunk_map.p, ni);
         LAUNCH_CHECK();
         k_sample<DT><<<(unsigned)((pl.total_samples + 255) / 256), 256, 0, s>>>(
             items, ni, (const uint64_t*)D.sample_off.p, pl.total_samples, src, sample, P.seed, prev_children,
@@ -597,9 +597,6 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                                    P.train_iters)));
 
         // degenerate buckets and final model
-        k_expand<<<(unsigned)((nc + 255) / 256), 256, 0, s>>>((const uint64_t*)D.chunk_off.p, ni, nc,
-                                                              (uint32_t*)D.chunk_map.p);
-        LAUNCH_CHECK();
         k_minmax<DT><<<(unsigned)nc, 256, 0, s>>>(items, (const uint64_t*)D.chunk_off.p, (const uint32_t*)D.chunk_map.p,
                                                   models, src, tile, kChunk);
         LAUNCH_CHECK();
@@ -622,11 +619,10 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                                                                        (const uint32_t*)D.chunk_sum.p,
                                                                        (uint64_t*)D.chunk_pref.p, (uint64_t*)D.hist.p);
         LAUNCH_CHECK();
-        if ((pl.max_n + (uint64_t)tile * kChunk - 1) / ((uint64_t)tile * kChunk) > kScanSerial) {
-            k_scan_chunks_wide<<<(unsigned)((ni * K + 3) / 4), 256, 0, s>>>((const uint64_t*)D.chunk_off.p, ni, K,
-                                                                            (const uint32_t*)D.chunk_sum.p,
-                                                                            (uint64_t*)D.chunk_pref.p,
-                                                                            (uint64_t*)D.hist.p);
+        if (pl.n_wide) {
+            k_scan_chunks_wide<<<(unsigned)(pl.n_wide * K), 256, 0, s>>>(
+                (const uint64_t*)D.chunk_off.p, (const uint32_t*)D.wide.p, K, (const uint32_t*)D.chunk_sum.p,
+                (uint64_t*)D.chunk_pref.p, (uint64_t*)D.hist.p);
             LAUNCH_CHECK();
         }
         k_bucket_starts<<<(unsigned)ni, 256, 0, s>>>((const uint64_t*)D.hist.p, (uint64_t*)D.bstart.p, K);
