@@ -1527,9 +1527,10 @@ __global__ __launch_bounds__(256) void k_worklist(const Item* items, uint64_t nu
     if (ch > 0 && q < bl.cap[cls]) base[bl.off[cls] + q] = BaseItem{lo, (uint32_t)n, (uint32_t)dst_is_scratch};
 }
 
-// Equality buckets a level wrote to the scratch buffer move back to the caller's buffer as they
-// are (their keys are equal, their payloads in stable order): one workgroup per tile of
-// kCopyTile keys, tile t of copy item map[t].
+// Equality buckets a level wrote to the scratch buffer move back to the caller's buffer: every key
+// of such a bucket is the same value (the same bits: the key map is one to one), so the keys are
+// filled from its first one and only the payloads (in stable order) are copied.  One workgroup per
+// tile of kCopyTile keys, tile t of copy item map[t].
 template <int DT, bool PAY>
 __global__ __launch_bounds__(256) void k_copy(const CopyItem* copy, const uint64_t* copy_off, const uint32_t* map,
                                               uint64_t total_tiles, typename Key<DT>::T* keys, uint32_t* pay,
@@ -1541,8 +1542,9 @@ __global__ __launch_bounds__(256) void k_copy(const CopyItem* copy, const uint64
     const uint64_t base = (t - copy_off[q]) * kCopyTile;
     const uint64_t rem = ci.n - base;
     const uint32_t n = rem < kCopyTile ? (uint32_t)rem : kCopyTile;
+    const typename Key<DT>::T v = skeys[ci.lo];
     for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
-        keys[ci.lo + base + j] = __builtin_nontemporal_load(&skeys[ci.lo + base + j]);
+        keys[ci.lo + base + j] = v;
         if (PAY) pay[ci.lo + base + j] = __builtin_nontemporal_load(&spay[ci.lo + base + j]);
     }
 }
