@@ -295,15 +295,17 @@ __device__ inline void fmcd_search(const X& x, uint64_t S, uint32_t K, double* a
     *Dout = D;
 }
 
-// Small samples (S <= small_S <= kFitLds): one workgroup per item, the sample in LDS as fp64,
-// binary search.
+// Small samples (S <= small_S <= LDS_KEYS): one workgroup per item, the sample in LDS as fp64,
+// binary search.  LDS_KEYS is kFitLds, or 4096 when every sample of the level is that small: a
+// 32 KB workgroup finds room beside other kernels' workgroups (a 128 KB one waits for an empty CU).
 constexpr int kFitLds = 16384;
+constexpr int kFitLdsSmall = 4096;
 
-template <int DT>
+template <int DT, int LDS_KEYS>
 __global__ __launch_bounds__(256) void k_fmcd_small(const typename Key<DT>::T* sample, const uint64_t* sample_off,
                                                     uint64_t num_items, Model* models, uint32_t K_all, uint32_t small_S,
                                                     const EqInfo* eq) {
-    __shared__ double sx[kFitLds];
+    __shared__ double sx[LDS_KEYS];
     using KT = Key<DT>;
     const uint64_t i = blockIdx.x;
     if (i >= num_items) return;
