@@ -41,15 +41,20 @@ __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* cnt,
     __shared__ uint64_t sc[16];
     __shared__ uint64_t sc6[16 * 7];
     __shared__ uint64_t s_max[4];
-    const uint64_t num = cnt[C_ITEMS0 + cur];
+    __shared__ uint64_t s_cnt[C_N];  // the counters, read once, all in parallel
+    constexpr int kPlanWords = (int)(sizeof(Plan) / 8);
+    static_assert(sizeof(Plan) % 8 == 0 && offsetof(Plan, seq) == sizeof(Plan) - 8, "seq is the plan's last word");
+    __shared__ uint64_t s_plan[kPlanWords];
+    if (threadIdx.x < (uint32_t)C_N) s_cnt[threadIdx.x] = cnt[threadIdx.x];
+    if (threadIdx.x == 0) { s_max[0] = s_max[1] = s_max[2] = s_max[3] = 0; }
+    __syncthreads();
+    const uint64_t num = s_cnt[C_ITEMS0 + cur];
     uint64_t nb = 0;
     bool base_over = false;
     for (int c = 0; c < kBaseClasses; ++c) {
-        nb += cnt[C_CLS + c];
-        base_over |= cnt[C_CLS + c] > bl.cap[c];
+        nb += s_cnt[C_CLS + c];
+        base_over |= s_cnt[C_CLS + c] > bl.cap[c];
     }
-    if (threadIdx.x == 0) { s_max[0] = s_max[1] = s_max[2] = s_max[3] = 0; }
-    __syncthreads();
     uint64_t run_t = 0, run_s = 0, run_f = 0, run_c = 0, run_w = 0, sum_n = 0, sum_inh = 0;
     const uint64_t use = num < item_cap ? num : item_cap;
     for (uint64_t base = 0; base < use; base += blockDim.x) {
@@ -97,7 +102,7 @@ __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* cnt,
         s_max[3] = sum_inh;
     }
     // tiles of the equality buckets the previous level left in the scratch buffer
-    const uint64_t ncopy_all = cnt[C_COPY], ncopy = ncopy_all < copy_cap ? ncopy_all : copy_cap;
+    const uint64_t ncopy_all = s_cnt[C_COPY], ncopy = ncopy_all < copy_cap ? ncopy_all : copy_cap;
     uint64_t run_k = 0;
     for (uint64_t base = 0; base < ncopy; base += blockDim.x) {
         const uint64_t q = base + threadIdx.x;
@@ -109,58 +114,60 @@ __global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* cnt,
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        Plan& P = *(Plan*)s_plan;
         copy_off[ncopy] = run_k;
-        plan->copy_count = ncopy;
-        plan->copy_tiles = run_k;
-        plan->eq_closed = cnt[C_EQCLOSED];
-        plan->inherited = cnt[C_INHERITED];
-        plan->l1max = cnt[C_L1MAX];
-        cnt[C_CHILD] = 0;
-        if (ncopy_all > copy_cap) cnt[C_ERR] |= kErrCapacity;
-        cnt[C_COPY] = 0;
-        cnt[C_COPYKEYS] = 0;
+        P.copy_count = ncopy;
+        P.copy_tiles = run_k;
+        P.eq_closed = s_cnt[C_EQCLOSED];
+        P.inherited = s_cnt[C_INHERITED];
+        P.l1max = s_cnt[C_L1MAX];
         tile_off[use] = run_t;
         sample_off[use] = run_s;
         fit_off[use] = run_f;
         chunk_off[use] = run_c;
-        plan->total_chunks = run_c;
-        uint64_t e = cnt[C_ERR];
-        if (num > item_cap || base_over) e |= kErrCapacity;
+        P.total_chunks = run_c;
+        uint64_t e = s_cnt[C_ERR];
+        if (num > item_cap || base_over || ncopy_all > copy_cap) e |= kErrCapacity;
         cnt[C_ERR] = e;
-        plan->num_items = use;
-        plan->num_base = nb;
-        plan->total_tiles = run_t;
-        plan->total_samples = run_s;
-        plan->total_fit_chunks = run_f;
-        plan->max_S = s_max[0];
-        plan->max_n = s_max[1];
-        plan->sum_n = s_max[2];
-        plan->inh_n = s_max[3];
-        plan->n_wide = run_w;
-        plan->err = e;
-        plan->closed = cnt[C_STATS + 0];
-        plan->digit = cnt[C_STATS + 1];
-        plan->l2pl = cnt[C_STATS + 2];
-        plan->closed_keys = cnt[C_STATS + 3];
-        plan->base_keys = cnt[C_BASEKEYS];
+        P.num_items = use;
+        P.num_base = nb;
+        P.total_tiles = run_t;
+        P.total_samples = run_s;
+        P.total_fit_chunks = run_f;
+        P.max_S = s_max[0];
+        P.max_n = s_max[1];
+        P.sum_n = s_max[2];
+        P.inh_n = s_max[3];
+        P.n_wide = run_w;
+        P.err = e;
+        P.closed = s_cnt[C_STATS + 0];
+        P.digit = s_cnt[C_STATS + 1];
+        P.l2pl = s_cnt[C_STATS + 2];
+        P.closed_keys = s_cnt[C_STATS + 3];
+        P.base_keys = s_cnt[C_BASEKEYS];
         for (int c = 0; c < kBaseClasses; ++c) {
-            const uint64_t k = cnt[C_CLS + c];
-            plan->cls_count[c] = k < bl.cap[c] ? k : bl.cap[c];
-            cnt[C_CLS + c] = 0;
+            const uint64_t k = s_cnt[C_CLS + c];
+            P.cls_count[c] = k < bl.cap[c] ? k : bl.cap[c];
         }
-        cnt[C_BASEKEYS] = 0;
-        cnt[C_ITEMS0 + cur] = 0;  // this level's list is consumed
-        cnt[C_ITEMS0 + (cur ^ 1)] = 0;
-        cnt[C_BASE] = 0;
-        plan->seq = seq;
-        if (plan_host) {
-            // the same plan straight into the host's pinned (coherent) buffer, its number last
-            Plan h = *plan;
-            h.seq = 0;
-            *plan_host = h;
-            __threadfence_system();
-            plan_host->seq = seq;
-        }
+        P.seq = seq;
+    }
+    // counters the coming level appends to start from zero; this level's list is consumed
+    const uint32_t t = threadIdx.x;
+    if (t == C_CHILD || t == C_COPY || t == C_COPYKEYS || t == C_BASEKEYS || t == C_BASE ||
+        t == (uint32_t)(C_ITEMS0 + cur) || t == (uint32_t)(C_ITEMS0 + (cur ^ 1)) ||
+        (t >= (uint32_t)C_CLS && t < (uint32_t)(C_CLS + kBaseClasses)))
+        cnt[t] = 0;
+    __syncthreads();
+    // the plan, word by word in parallel, to the device copy and to the host's pinned (coherent)
+    // buffer; the host's copy gets its number last
+    if (t < (uint32_t)kPlanWords) {
+        ((uint64_t*)plan)[t] = s_plan[t];
+        if (plan_host && t + 1 < (uint32_t)kPlanWords) ((uint64_t*)plan_host)[t] = s_plan[t];
+    }
+    if (plan_host) {
+        __threadfence_system();
+        __syncthreads();
+        if (t == 0) plan_host->seq = seq;
     }
 }
 
@@ -274,6 +281,25 @@ __device__ inline void model_degenerate(Model& m) {
     m.umax = 0ull;
 }
 
+// x[0..S) = val(sample[0..S)) into LDS, eight loads in flight per thread.
+template <int DT>
+__device__ inline void fill_sample_lds(double* x, const typename Key<DT>::T* xs, uint64_t S) {
+    constexpr int U = 8;
+    for (uint64_t j0 = threadIdx.x; j0 < S; j0 += (uint64_t)U * blockDim.x) {
+        typename Key<DT>::T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t j = j0 + (uint64_t)u * blockDim.x;
+            if (j < S) v[u] = xs[j];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t j = j0 + (uint64_t)u * blockDim.x;
+            if (j < S) x[j] = Key<DT>::val(v[u]);
+        }
+    }
+}
+
 // Binary search for FMCD's D over [1, S/3 + 1] by the whole block, x(j) the j-th value of a sorted
 // sample of S >= 3 keys with finite ends; then the line.  Every thread gets the same result.
 template <typename X>
@@ -313,7 +339,7 @@ __global__ __launch_bounds__(256) void k_fmcd_small(const typename Key<DT>::T* s
     const uint64_t off = sample_off[i], S = eq ? eq[i].sr : sample_off[i + 1] - off;
     const uint32_t K = eq ? eq[i].km : K_all;
     if (S > small_S) return;
-    for (uint64_t j = threadIdx.x; j < S; j += blockDim.x) sx[j] = KT::val(sample[off + j]);
+    fill_sample_lds<DT>(sx, sample + off, S);
     __syncthreads();
     Model m = {};
     m.S = S;
@@ -395,7 +421,7 @@ __global__ __launch_bounds__(256) void k_child_fit(Child* children, const uint64
     uint64_t D = 0;
     bool usable;
     if (S <= (uint64_t)kFitLds) {
-        for (uint64_t j = threadIdx.x; j < S; j += blockDim.x) sx[j] = KT::val(xs[j]);
+        fill_sample_lds<DT>(sx, xs, S);
         __syncthreads();
         usable = S >= 3 && isfinite(sx[0]) && isfinite(sx[S - 1]);
         if (usable) fmcd_search([&](uint64_t j) { return sx[j]; }, S, K, &a, &b, &D);
