@@ -29,10 +29,10 @@ struct LevelArgs {
 };
 
 // ------------------------------------------------------------------ plan
-// One workgroup of 1024 threads: per-item prefix sums of tiles, samples and large-sample fit
+// One workgroup of 256 threads (small enough to start beside a running base case): per-item prefix sums of tiles, samples and large-sample fit
 // chunks; totals and maxima for the host.  Consumes the item and base-case counters of the
 // previous level and resets the counters the coming level appends to.
-__global__ __launch_bounds__(1024) void k_plan(const Item* items, uint64_t* cnt, int cur, Plan* plan, uint64_t* tile_off,
+__global__ __launch_bounds__(256) void k_plan(const Item* items, uint64_t* cnt, int cur, Plan* plan, uint64_t* tile_off,
                                                uint64_t* sample_off, uint64_t* fit_off, uint64_t* chunk_off,
                                                LevelArgs A, uint64_t item_cap, BaseLayout bl, const CopyItem* copy,
                                                uint64_t* copy_off, uint64_t copy_cap, const Child* prev_children,

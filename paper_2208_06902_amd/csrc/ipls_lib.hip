@@ -466,7 +466,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     for (int level = 0;; ++level) {
         const int par = level & 1;
         const Child* prev_children = (inherit && level > 0) ? (const Child*)D.children[par ^ 1].p : nullptr;
-        k_plan<<<1, 1024, 0, s>>>((const Item*)D.items[cur].p, cnt, cur, (Plan*)D.plan.p, (uint64_t*)D.tile_off.p, (uint64_t*)D.sample_off.p,
+        k_plan<<<1, 256, 0, s>>>((const Item*)D.items[cur].p, cnt, cur, (Plan*)D.plan.p, (uint64_t*)D.tile_off.p, (uint64_t*)D.sample_off.p,
                                   (uint64_t*)D.fit_off.p, (uint64_t*)D.chunk_off.p, A, item_cap, bl,
                                   (const CopyItem*)D.copy.p, (uint64_t*)D.copy_off.p, copy_cap, prev_children,
                                   D.plan_hd, ++D.plan_seq, (BaseItem*)D.sample_base.p, (uint32_t*)D.wide.p);
@@ -520,13 +520,15 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             // the previous level's buckets of <= T keys: base[(level - 1) & 1], complete (the host
             // has just synchronised the main stream for the plan)
             const int bp = (level + 1) & 1;
+            const bool side = overlap;
+            hipStream_t sl = side ? sb : s;
             {
-                ProfScope ps(2, (double)pl.base_keys * 2.0 * (kb + (PAY ? 4 : 0)), sb);
+                ProfScope ps(2, (double)pl.base_keys * 2.0 * (kb + (PAY ? 4 : 0)), sl);
                 for (int c = 0; c < kBaseClasses; ++c)
-                    ST_TRY((launch_base<DT, PAY>(sb, c, (const BaseItem*)D.base[bp].p + bl.off[c], pl.cls_count[c],
+                    ST_TRY((launch_base<DT, PAY>(sl, c, (const BaseItem*)D.base[bp].p + bl.off[c], pl.cls_count[c],
                                                  keys, pay, scratch, spay)));
             }
-            if (overlap) {
+            if (side) {
                 HIP_TRY(hipEventRecord(dv.ev_base[bp], sb));
                 base_pending[bp] = true;
             }
