@@ -332,7 +332,6 @@ __global__ __launch_bounds__(256) void k_fmcd_small(const typename Key<DT>::T* s
                                                     uint64_t num_items, Model* models, uint32_t K_all, uint32_t small_S,
                                                     const EqInfo* eq) {
     __shared__ double sx[LDS_KEYS];
-    using KT = Key<DT>;
     const uint64_t i = blockIdx.x;
     if (i >= num_items) return;
     // with equality buckets: the sample without heavy runs, and K - 2E buckets
@@ -1324,7 +1323,7 @@ __device__ inline uint64_t xcd_tile(uint64_t g, uint64_t nt) {
 // such a child gets its class under the child's line in registers, the class is staged beside the
 // key and written to dst_cls at the key's destination.  No barrier is added.
 template <int DT, bool PAY, int NW, int IPT, bool CLS>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(CLS && !PAY ? 6 : 1))) void k_scatter(const Item* items, const uint64_t* tile_off, const uint32_t* tile_map,
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(CLS && !PAY && NW == 8 ? 6 : 1))) void k_scatter(const Item* items, const uint64_t* tile_off, const uint32_t* tile_map,
                                                  uint64_t total_tiles, const uint64_t* chunk_off,
                                                  uint64_t total_chunks, const Model* models, const double* leaves,
                                                  const uint64_t* bstart, const uint64_t* chunk_pref,
@@ -1702,7 +1701,7 @@ __device__ inline void merge_sort_lds(O* sk, uint32_t* sp, int t_in, bool active
 }
 
 template <int DT, bool PAY, int NT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PAY ? 4 : 1))) void k_base_sort(const BaseItem* list, uint64_t count, typename Key<DT>::T* keys,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PAY ? 3 : 1))) void k_base_sort(const BaseItem* list, uint64_t count, typename Key<DT>::T* keys,
                                                    uint32_t* pay, const typename Key<DT>::T* skeys,
                                                    const uint32_t* spay) {
     using KT = Key<DT>;
