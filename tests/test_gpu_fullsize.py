@@ -2,6 +2,8 @@
 
 * 10^8 fp64 keys of each of the five distributions: the whole output against the oracle, bit
   for bit, with the benchmark's parameters (K 256, T 4096, sample capped at 4096 keys).
+* 10^8 normal fp64 keys with sample inheritance (a 131072-key first sample): the whole output and
+  the count of inherited partitions against the oracle.
 * 2*10^8 Zipf(1.1) uint64 keys with their uint32 index as payload: the whole output, keys and
   payload, against the oracle (stable order is unique).
 * 10^9 uniform uint64 keys: too large for the oracle in a test, so checked by properties that
@@ -49,6 +51,20 @@ def test_1e8_fp64_against_oracle(dist, seed):
     want, _, ost = oracle.sort(keys, None, oracle.params(sample_max=4096))
     assert same_bits(got, want)
     assert (st["passes"], st["levels"]) == (ost["passes"], ost["max_level"])
+
+
+def test_1e8_fp64_sample_inheritance_against_oracle():
+    # a 131072-key first sample gives the 256 children about 512 sample keys each: they inherit
+    n = 100_000_000
+    print(f"full size normal n={n} with sample inheritance", flush=True)
+    keys = gen.make("normal", n, 2)
+    kd, _, st = _sort_on_device(keys, num_buckets=256, base_case_max=4096, sample_max=131072, inherit=1)
+    got = kd.cpu().numpy()
+    del kd
+    want, _, ost = oracle.sort(keys, None, oracle.params(sample_max=131072, inherit=1))
+    assert same_bits(got, want)
+    assert (st["passes"], st["levels"]) == (ost["passes"], ost["max_level"])
+    assert st["inherited"] == ost["inherited"] > 100
 
 
 @pytest.mark.parametrize("equality", [0, 1])
