@@ -7,8 +7,9 @@ it.  The child's counting pass then reads those bytes.  Each case is checked for
 * the count of inherited partitions equal to the oracle's count;
 * passes and levels equal to the oracle's.
 
-The cases cover two and three levels of inheritance, every dtype, NaNs and infinities, segmented
-batches, and the default parameters at a size where the 1% sample gives children enough keys.
+The cases cover two and three levels of inheritance, every dtype, both tile sizes, NaNs and
+infinities, segmented batches, and the default parameters at a size where the 1% sample gives
+children enough keys.
 """
 import numpy as np
 import pytest
@@ -66,6 +67,14 @@ def test_three_levels_with_payload(dist):
 def test_other_dtypes(dt):
     k = gen.as_dtype(gen.make("normal", 300_000, 9), {np.float32: ipls.F32, np.uint64: ipls.U64}[dt])
     check(k, gen.index_payload(k.size), **DEEP)
+
+
+@pytest.mark.parametrize("pay", [False, True])
+def test_small_tiles(pay):
+    # 2048-key tiles: the 4-wave variants of the counting and class-byte scatter kernels
+    k = gen.make("normal", 400_000, 15)
+    st = check(k, gen.index_payload(k.size) if pay else None, tile_keys=2048, **DEEP)
+    assert st["inherited"] > 16
 
 
 def test_specials_and_ragged_sizes():
