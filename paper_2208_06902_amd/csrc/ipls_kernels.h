@@ -184,11 +184,11 @@ __global__ void k_expand(const uint64_t* off, uint64_t num_items, uint64_t total
     map[t] = (uint32_t)lo;
 }
 
-// Two maps in one launch: map1 over [0, total1) from off1, map2 over [0, total2) from off2 (both
-// with num_items ranges).
-__global__ void k_expand2(const uint64_t* off1, uint64_t total1, uint32_t* map1, const uint64_t* off2,
-                          uint64_t total2, uint32_t* map2, uint64_t num_items) {
-    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Two maps from one workgroup index: map1 over [0, total1) from off1, map2 over [0, total2) from
+// off2 (both with num_items ranges).
+__device__ inline void expand2(uint64_t block, const uint64_t* off1, uint64_t total1, uint32_t* map1,
+                               const uint64_t* off2, uint64_t total2, uint32_t* map2, uint64_t num_items) {
+    const uint64_t t = block * blockDim.x + threadIdx.x;
     auto find = [&](const uint64_t* off) {
         uint64_t lo = 0, hi = num_items;  // largest i with off[i] <= t
         while (hi - lo > 1) {
@@ -229,11 +229,19 @@ __global__ __launch_bounds__(256) void k_seed(const uint64_t* off, uint64_t nseg
 // floor(j n / S) = j q + floor(j r / S) with n = q S + r keeps the arithmetic in 64 bits (S < 2^32).
 // An item that inherits copies its restricted sample (already sorted) from the previous level's
 // sample buffer instead.
+// The same launch also builds the tile and chunk maps (expand2) in its first expand_blocks
+// workgroups.
 template <int DT>
 __global__ void k_sample(const Item* items, uint64_t num_items, const uint64_t* sample_off, uint64_t total,
                          const typename Key<DT>::T* src, typename Key<DT>::T* sample, uint64_t seed,
-                         const Child* prev_children, const typename Key<DT>::T* prev_sample) {
-    uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                         const Child* prev_children, const typename Key<DT>::T* prev_sample, uint64_t expand_blocks,
+                         const uint64_t* tile_off, uint64_t total_tiles, uint32_t* tile_map, const uint64_t* chunk_off,
+                         uint64_t total_chunks, uint32_t* chunk_map) {
+    if (blockIdx.x < expand_blocks) {
+        expand2(blockIdx.x, tile_off, total_tiles, tile_map, chunk_off, total_chunks, chunk_map, num_items);
+        return;
+    }
+    uint64_t s = (uint64_t)(blockIdx.x - expand_blocks) * blockDim.x + threadIdx.x;
     if (s >= total) return;
     uint64_t lo = 0, hi = num_items;
     while (hi - lo > 1) {
@@ -1246,21 +1254,26 @@ __global__ __launch_bounds__(64 * NW) void k_classify_hist(const Item* items, co
 // walks the chunks (neighbouring threads read neighbouring buckets).  Larger items (only at the
 // first levels of big arrays): one workgroup per (item, bucket).
 
-__global__ __launch_bounds__(256) void k_scan_chunks(const uint64_t* chunk_off, uint64_t num_items, uint32_t K,
-                                                     const uint32_t* chunk_sum, uint64_t* chunk_pref,
-                                                     uint64_t* hist) {
-    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= num_items * K) return;
-    const uint64_t i = g / K, b = g % K;
+__global__ __launch_bounds__(256) void k_scan_chunks(const uint64_t* chunk_off, uint32_t K, const uint32_t* chunk_sum,
+                                                     uint64_t* chunk_pref, uint64_t* hist, uint64_t* bstart) {
+    // one workgroup per item, thread b walks bucket b's chunks; then the bucket starts
+    __shared__ uint64_t sc[16];
+    const uint64_t i = blockIdx.x;
+    const uint32_t b = threadIdx.x;
     const uint64_t c0 = chunk_off[i], c1 = chunk_off[i + 1];
-    if (c1 - c0 > kScanSerial) return;
+    if (c1 - c0 > kScanSerial) return;  // a wide item: k_scan_chunks_wide, then k_bucket_starts
     uint64_t run = 0;
-    for (uint64_t c = c0; c < c1; ++c) {
-        const uint64_t v = chunk_sum[c * K + b];
-        chunk_pref[c * K + b] = run;
-        run += v;
+    if (b < K) {
+        for (uint64_t c = c0; c < c1; ++c) {
+            const uint64_t v = chunk_sum[c * K + b];
+            chunk_pref[c * K + b] = run;
+            run += v;
+        }
+        hist[i * K + b] = run;
     }
-    hist[i * K + b] = run;
+    uint64_t tot;
+    const uint64_t e = block_exclusive_sum<uint64_t>(b < K ? run : 0, sc, &tot);
+    if (b < K) bstart[i * K + b] = e;
 }
 
 __global__ __launch_bounds__(256) void k_scan_chunks_wide(const uint64_t* chunk_off, const uint32_t* wide_items,
@@ -1296,10 +1309,12 @@ __global__ __launch_bounds__(256) void k_scan_chunks_wide(const uint64_t* chunk_
     if (threadIdx.x == 0) hist[i * K + b] = total;
 }
 
-// Bucket starts of every item: exclusive prefix of its K counts.
-__global__ __launch_bounds__(256) void k_bucket_starts(const uint64_t* hist, uint64_t* bstart, uint32_t K) {
+// Bucket starts of the wide items (the others get theirs in k_scan_chunks): exclusive prefix of
+// the K counts.
+__global__ __launch_bounds__(256) void k_bucket_starts(const uint64_t* hist, uint64_t* bstart, uint32_t K,
+                                                       const uint32_t* wide_items) {
     __shared__ uint64_t sc[16];
-    const uint64_t i = blockIdx.x;
+    const uint64_t i = wide_items[blockIdx.x];
     const uint64_t v = threadIdx.x < K ? hist[i * K + threadIdx.x] : 0;
     uint64_t tot;
     const uint64_t e = block_exclusive_sum<uint64_t>(v, sc, &tot);

@@ -564,13 +564,12 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         const Item* items = (const Item*)D.items[cur].p;
         Model* models = (Model*)D.models.p;
 
-        k_expand2<<<(unsigned)((std::max(nt, nc) + 255) / 256), 256, 0, s>>>(
-            (const uint64_t*)D.tile_off.p, nt, (uint32_t*)D.tile_map.p, (const uint64_t*)D.chunk_off.p, nc,
-            (uint32_t*)D.chunk_map.p, ni);
-        LAUNCH_CHECK();
-        k_sample<DT><<<(unsigned)((pl.total_samples + 255) / 256), 256, 0, s>>>(
+        // the sample gather and the tile and chunk maps, in one launch
+        const uint64_t eb = (std::max(nt, nc) + 255) / 256;
+        k_sample<DT><<<(unsigned)(eb + (pl.total_samples + 255) / 256), 256, 0, s>>>(
             items, ni, (const uint64_t*)D.sample_off.p, pl.total_samples, src, sample, P.seed, prev_children,
-            prev_sample);
+            prev_sample, eb, (const uint64_t*)D.tile_off.p, nt, (uint32_t*)D.tile_map.p,
+            (const uint64_t*)D.chunk_off.p, nc, (uint32_t*)D.chunk_map.p);
         LAUNCH_CHECK();
         ST_TRY(sort_samples<DT>(dv, run, d, pl, sample));
 
@@ -620,18 +619,21 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                 P.leaves, cls);
             LAUNCH_CHECK();
         }
-        k_scan_chunks<<<(unsigned)((ni * K + 255) / 256), 256, 0, s>>>((const uint64_t*)D.chunk_off.p, ni, K,
-                                                                       (const uint32_t*)D.chunk_sum.p,
-                                                                       (uint64_t*)D.chunk_pref.p, (uint64_t*)D.hist.p);
+        // chunk prefixes, bucket sizes and bucket starts: a workgroup per item; wide items by a
+        // workgroup per (item, bucket), then their starts
+        k_scan_chunks<<<(unsigned)ni, 256, 0, s>>>((const uint64_t*)D.chunk_off.p, K, (const uint32_t*)D.chunk_sum.p,
+                                                   (uint64_t*)D.chunk_pref.p, (uint64_t*)D.hist.p,
+                                                   (uint64_t*)D.bstart.p);
         LAUNCH_CHECK();
         if (pl.n_wide) {
             k_scan_chunks_wide<<<(unsigned)(pl.n_wide * K), 256, 0, s>>>(
                 (const uint64_t*)D.chunk_off.p, (const uint32_t*)D.wide.p, K, (const uint32_t*)D.chunk_sum.p,
                 (uint64_t*)D.chunk_pref.p, (uint64_t*)D.hist.p);
             LAUNCH_CHECK();
+            k_bucket_starts<<<(unsigned)pl.n_wide, 256, 0, s>>>((const uint64_t*)D.hist.p, (uint64_t*)D.bstart.p, K,
+                                                                (const uint32_t*)D.wide.p);
+            LAUNCH_CHECK();
         }
-        k_bucket_starts<<<(unsigned)ni, 256, 0, s>>>((const uint64_t*)D.hist.p, (uint64_t*)D.bstart.p, K);
-        LAUNCH_CHECK();
 
         // children that inherit their part of the sample: ranges, then their lines (before the scatter,
         // which writes the class bytes).  Each entry holds at least thr sample keys and more than T
