@@ -178,12 +178,14 @@ ipls_status ipls_stream_status(void* stream);
 /* Static string naming a status code. */
 const char* ipls_status_string(ipls_status st);
 
-/* Kernel timing for measurement.  While enabled, the library records HIP events around every
- * launch of the distribution-pass kernels on the caller's stream and accumulates their elapsed
- * times; ipls_profile_read returns, for kernel id 0 (scatter), 1 (classify + histogram),
- * 2 (base case), the number of launches, the summed milliseconds and the summed algorithmic
- * bytes (keys and payload each kernel must read and write).  Enabling resets the counters. */
-void ipls_profile_enable(int on);
+/* Kernel timing for measurement.  mask: bit k enables kernel id k, 0 (scatter), 1 (classify +
+ * histogram), 2 (base case); 7 = all, 0 = off.  While enabled, the library records HIP events
+ * around every launch of the enabled kernels on the stream it is launched on and accumulates
+ * their elapsed times (each event record costs a few microseconds of host time, so time a run with
+ * only the kernels it reports); ipls_profile_read returns, for a kernel id, the number of launches,
+ * the summed milliseconds and the summed algorithmic bytes (keys and payload each kernel must read
+ * and write).  Enabling resets the counters. */
+void ipls_profile_enable(int mask);
 void ipls_profile_read(int kernel, uint64_t* launches, double* ms, double* bytes);
 
 /* ---------------------------------------------------------------- batched form: autotuner

@@ -266,8 +266,10 @@ def workspace_bytes(n: int, dtype: int, has_payload: bool, params: Params | None
     return int(load().ipls_workspace_bytes(n, dtype, int(has_payload), C.byref(params) if params else None))
 
 
-def profile_enable(on: bool = True):
-    load().ipls_profile_enable(int(on))
+def profile_enable(on=True):
+    """on: True (every kernel), False (off) or a bit mask of kernel ids (1 << KERNEL_SCATTER, ...)."""
+    mask = (7 if on else 0) if isinstance(on, bool) else int(on)
+    load().ipls_profile_enable(mask)
 
 
 def profile_read(kernel: int):

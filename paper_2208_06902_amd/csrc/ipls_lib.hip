@@ -108,7 +108,7 @@ void release_device(Device& dv) {
 }
 
 struct Prof {
-    std::atomic<bool> on{false};
+    std::atomic<int> mask{0};  // bit k: record kernel id k
     struct Rec {
         hipEvent_t a, b;
         int kernel;
@@ -156,7 +156,7 @@ struct ProfScope {
     double bytes;
     hipStream_t s;
     ProfScope(int k, double by, hipStream_t st) : kernel(k), bytes(by), s(st) {
-        if (g_prof.on) {
+        if (g_prof.mask & (1 << k)) {
             {
                 std::lock_guard<std::mutex> g(g_prof_mu);
                 a = prof_event();
@@ -180,7 +180,7 @@ struct ProfScope {
 
 // Bytes of a kernel known only after its launch was recorded (the class bytes a scatter wrote).
 void prof_add_bytes(int kernel, double bytes) {
-    if (!g_prof.on) return;
+    if (!(g_prof.mask & (1 << kernel))) return;
     std::lock_guard<std::mutex> g(g_prof_mu);
     g_prof.bytes[kernel] += bytes;
 }
@@ -797,7 +797,7 @@ ipls_status finish(ipls_status st, hipStream_t s) {
         (void)hipGetLastError();
         st = IPLS_ERR_HIP;
     }
-    if (g_prof.on) prof_collect();
+    if (g_prof.mask) prof_collect();
     std::lock_guard<std::mutex> g(g_status_mu);
     g_stream_status[(void*)s] = st;
     return st;
@@ -1056,9 +1056,9 @@ ipls_status ipls_l2pl_grad(const double* x, size_t S, uint32_t K, uint32_t M, co
     return finish(st, s);
 }
 
-void ipls_profile_enable(int on) {
+void ipls_profile_enable(int mask) {
     std::lock_guard<std::mutex> g(g_prof_mu);
-    g_prof.on = on != 0;
+    g_prof.mask = mask & 7;
     for (int k = 0; k < 3; ++k) {
         g_prof.launches[k] = 0;
         g_prof.ms[k] = 0;
