@@ -221,6 +221,24 @@ void prof_collect() {
     } while (0)
 #define LAUNCH_CHECK() HIP_TRY(hipGetLastError())
 
+// Waits until stream s has run the k_plan launch numbered seq.  The host polls the plan's number in
+// the pinned buffer, which k_plan writes last (a stream synchronisation wakes the host some tens of
+// microseconds after the kernel ends); every 256 polls it asks the stream, which ends the wait on an
+// error, or once the stream has drained without the number showing (the caller then copies the
+// plan instead).
+static hipError_t wait_plan(hipStream_t s, const volatile Plan* ph, uint64_t seq) {
+    for (uint32_t i = 1;; ++i) {
+        if (ph->seq == seq) {
+            std::atomic_thread_fence(std::memory_order_acquire);
+            return hipSuccess;
+        }
+        if ((i & 255) == 0) {
+            const hipError_t q = hipStreamQuery(s);
+            if (q != hipErrorNotReady) return q;
+        }
+    }
+}
+
 int fit_rounds(uint64_t max_S) {
     uint64_t L = max_S / 3;
     int r = 0;
@@ -471,7 +489,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                                   (const CopyItem*)D.copy.p, (uint64_t*)D.copy_off.p, copy_cap, prev_children,
                                   D.plan_hd, ++D.plan_seq, (BaseItem*)D.sample_base.p, (uint32_t*)D.wide.p);
         LAUNCH_CHECK();
-        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(wait_plan(s, (const volatile Plan*)D.plan_h, D.plan_seq));
         if (((volatile Plan*)D.plan_h)->seq != D.plan_seq) {
             // not visible yet through the mapped buffer: copy the device's plan instead
             HIP_TRY(hipMemcpyAsync(D.plan_h, D.plan.p, sizeof(Plan), hipMemcpyDeviceToHost, s));
