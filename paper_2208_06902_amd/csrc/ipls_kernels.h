@@ -1990,6 +1990,110 @@ __device__ inline void base_large_stable(const BaseItem& bi, typename Key<DT>::T
 //  * otherwise a key's final place is its digit's start plus the keys of the digit before it in
 //    (ord, position) order; a digit of more than kSubMax keys (skewed buckets) sends the bucket to
 //    the merge sort instead.
+// A value that is the same in every lane, moved to scalar registers (frees vector registers).
+template <typename V>
+__device__ inline V uniform(V v) {
+    static_assert(sizeof(V) == 4 || sizeof(V) == 8, "32- or 64-bit values");
+    if constexpr (sizeof(V) == 4) {
+        return __builtin_bit_cast(V, (uint32_t)__builtin_amdgcn_readfirstlane(__builtin_bit_cast(uint32_t, v)));
+    } else {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)u);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+        return __builtin_bit_cast(V, ((uint64_t)hi << 32) | lo);
+    }
+}
+
+// Digit of a key of the keys-only base case: the bits below the top varying bit of ord - min, or
+// (BY_VALUE) a linear map of the value onto [0, ND); t >= 0 since every key is at least min.
+template <typename KT, int ND, bool BY_VALUE, typename O>
+__device__ inline uint32_t base_digit(O x, O mn, int shift, double vlo, double vscale) {
+    if constexpr (BY_VALUE) {
+        const double t = (KT::val(KT::from_ord((uint64_t)x)) - vlo) * vscale;
+        return t < (double)(ND - 1) ? (uint32_t)t : (uint32_t)(ND - 1);
+    } else {
+        return (uint32_t)((uint64_t)(x - mn) >> shift);
+    }
+}
+
+// The keys-only base case's counting: each key's slot among its digit's keys (LDS atomics on s_c,
+// which starts at zero), then the digit starts in s_c[0..ND) and n in s_c[ND].  Returns the largest
+// digit count.  Thread t owns digits [t CPT, (t+1) CPT).  The digits are not kept: the placement
+// computes them again, which holds fewer registers across the scan.
+template <typename KT, int NW, int IPT, int ND, bool BY_VALUE, typename O>
+__device__ inline uint32_t base_count(const O (&o)[IPT], uint32_t n, uint32_t wbase, O mn, int shift, double vlo,
+                                      double vscale, uint32_t (&sl)[IPT], uint32_t* s_c,
+                                      uint64_t* s_scan, uint32_t* s_most) {
+    constexpr int NT = 64 * NW, CPT = ND / NT;
+    const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        if (wbase + r * kWave + lane < n) sl[r] = atomicAdd(&s_c[base_digit<KT, ND, BY_VALUE>(o[r], mn, shift, vlo, vscale)], 1u);
+    }
+    __syncthreads();
+    uint32_t c[CPT], sum = 0, most = 0;
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+        c[i] = s_c[tid * CPT + i];
+        sum += c[i];
+        most = c[i] > most ? c[i] : most;
+    }
+    most = wave_max(most);
+    if (lane == 0) s_most[wave] = most;
+    uint64_t all;
+    uint32_t e = (uint32_t)block_exclusive_sum<uint64_t>(sum, s_scan, &all);  // synchronises
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+        s_c[tid * CPT + i] = e;
+        e += c[i];
+    }
+    if (tid == 0) s_c[ND] = n;
+    most = 0;
+    for (int w = 0; w < NW; ++w) most = s_most[w] > most ? s_most[w] : most;
+    __syncthreads();
+    return most;
+}
+
+// The keys-only base case's placement: each key to its digit's start plus its slot.
+template <typename KT, int IPT, int ND, bool BY_VALUE, typename O>
+__device__ inline void base_place(const O (&o)[IPT], const uint32_t (&sl)[IPT], uint32_t n, uint32_t wbase, O mn,
+                                  int shift, double vlo, double vscale, O* s_k, const uint32_t* s_c) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int r = 0; r < IPT; ++r)
+        if (wbase + r * kWave + lane < n) s_k[s_c[base_digit<KT, ND, BY_VALUE>(o[r], mn, shift, vlo, vscale)] + sl[r]] = o[r];
+}
+
+// The keys-only base case's last step for a bucket whose digits do not fit the varying bits: each
+// key's place is its digit's start plus the keys of its digit before it in (ord, position) order.
+template <typename KT, int NW, int IPT, int ND, bool BY_VALUE, typename O>
+__device__ inline void base_fixup(uint32_t n, uint32_t wbase, O mn, int shift, double vlo, double vscale, O* s_k,
+                                  const uint32_t* s_c) {
+    const uint32_t lane = lane_id();
+    O xs[IPT];
+    uint32_t np[IPT];
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint32_t j = wbase + r * kWave + lane;
+        if (j < n) {
+            xs[r] = s_k[j];
+            const uint32_t d = base_digit<KT, ND, BY_VALUE>(xs[r], mn, shift, vlo, vscale);
+            const uint32_t start = s_c[d], end = s_c[d + 1];
+            uint32_t before = 0;
+            for (uint32_t q = start; q < end; ++q) {
+                const O y = s_k[q];
+                before += (y < xs[r] || (y == xs[r] && q < j)) ? 1u : 0u;
+            }
+            np[r] = start + before;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < IPT; ++r)
+        if (wbase + r * kWave + lane < n) s_k[np[r]] = xs[r];
+    __syncthreads();
+}
+
 template <int DT, int NW, int IPT>
 __device__ inline void base_large_keys(const BaseItem& bi, typename Key<DT>::T* keys,
                                        const typename Key<DT>::T* skeys) {
@@ -2132,7 +2236,124 @@ __device__ inline void base_large_keys(const BaseItem& bi, typename Key<DT>::T* 
     }
 }
 
-template <int DT, bool PAY, int NW, int IPT>
+// The keys-only base case for sorted samples, which span their whole bucket: as base_large_keys,
+// but when a digit holds more than kSubMax keys (a float range over several binades, whose top
+// varying bits are exponent bits) the bucket is counted again with digits from a linear map of the
+// key's value over [min, max]; if a digit still holds more than kSubMax keys, the merge sort runs.
+template <int DT, int NW, int IPT>
+__device__ inline void base_large_keys_vmap(const BaseItem& bi, typename Key<DT>::T* keys,
+                                       const typename Key<DT>::T* skeys) {
+    using KT = Key<DT>;
+    using O = typename KT::O;
+    constexpr int NT = 64 * NW, CAP = NT * IPT, PCAP = CAP + CAP / 16, MT = CAP / 16;
+    constexpr int DB = CAP >= 4096 ? 12 : CAP >= 2048 ? 11 : CAP >= 1024 ? 10 : 9;  // digit bits
+    constexpr int ND = 1 << DB, CPT = ND / NT;                                     // digits, per thread
+    static_assert(ND == CAP && CPT == IPT, "one digit per key slot");
+    constexpr O kPad = (O)~(O)0;
+    __shared__ O s_k[PCAP];
+    __shared__ uint32_t s_c[ND + 1];
+    __shared__ uint64_t s_scan[16];
+    __shared__ O s_red[3][NW];
+    __shared__ uint32_t s_most[NW];
+    const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
+    const uint32_t n = bi.n;
+    const typename KT::T* src = bi.from_scratch ? skeys : keys;
+    const uint32_t wbase = wave * kWave * IPT;
+    O o[IPT];
+    {
+        typename KT::T v[IPT];
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const uint32_t j = wbase + r * kWave + lane;
+            if (j < n) v[r] = __builtin_nontemporal_load(&src[bi.lo + j]);
+        }
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) o[r] = wbase + r * kWave + lane < n ? (O)KT::ord(v[r]) : kPad;
+    }
+    const O oref = (O)KT::ord(src[bi.lo]);  // n >= 1
+    O mn = kPad, mx = 0, ov = 0;
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        if (wbase + r * kWave + lane < n) {
+            mn = o[r] < mn ? o[r] : mn;
+            mx = o[r] > mx ? o[r] : mx;
+            ov |= (O)(o[r] - oref);
+        }
+    }
+    mn = (O)~wave_max((O)~mn);
+    mx = wave_max(mx);
+#pragma unroll
+    for (int sft = 32; sft >= 1; sft >>= 1) ov |= (O)__shfl_xor(ov, sft, kWave);
+    for (uint32_t d = tid; d <= (uint32_t)ND; d += NT) s_c[d] = 0;
+    if (lane == 0) {
+        s_red[0][wave] = mn;
+        s_red[1][wave] = mx;
+        s_red[2][wave] = ov;
+    }
+    __syncthreads();
+    mn = s_red[0][0];
+    mx = s_red[1][0];
+    ov = s_red[2][0];
+    for (int w = 1; w < NW; ++w) {
+        mn = s_red[0][w] < mn ? s_red[0][w] : mn;
+        mx = s_red[1][w] > mx ? s_red[1][w] : mx;
+        ov |= s_red[2][w];
+    }
+    mn = uniform(mn);
+    mx = uniform(mx);
+    ov = uniform(ov);
+    const int z = ov ? __builtin_ctzll((unsigned long long)ov) : 0;
+    const int nbits = (int)bit_length((uint64_t)((O)(mx - mn) >> z));
+    const int shift = z + (nbits > DB ? nbits - DB : 0);
+    const bool exact = nbits <= DB;
+    uint32_t sl[IPT];
+    uint32_t most = base_count<KT, NW, IPT, ND, false>(o, n, wbase, mn, shift, 0.0, 0.0, sl, s_c, s_scan, s_most);
+    // Digits of a float range that spans several binades are mostly exponent bits, and a few digits
+    // take most keys.  Such a bucket is counted again with digits from a linear map of the key's
+    // value (monotone in the key order, as every digit function must be); a bucket that is still
+    // skewed is merge sorted.  The decision is uniform over the block.
+    bool by_value = false;
+    double vlo = 0.0, vscale = 0.0;
+    if (!exact && most > kSubMax) {
+        vlo = uniform(KT::val(KT::from_ord((uint64_t)mn)));
+        const double vhi = KT::val(KT::from_ord((uint64_t)mx));
+        vscale = uniform((double)ND / (vhi - vlo));
+        if (__builtin_isfinite(vlo) && __builtin_isfinite(vhi) && vhi > vlo && __builtin_isfinite(vscale)) {
+            by_value = true;
+            for (uint32_t d = tid; d <= (uint32_t)ND; d += NT) s_c[d] = 0;
+            __syncthreads();
+            most = base_count<KT, NW, IPT, ND, true>(o, n, wbase, mn, shift, vlo, vscale, sl, s_c, s_scan, s_most);
+        }
+    }
+
+    if (!exact && most > kSubMax) {
+        // merge sort: keys to LDS at their input positions (padding keys at the end), then sort
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) s_k[pad16(wbase + r * kWave + lane)] = o[r];
+        __syncthreads();
+        merge_sort_lds<O, false, MT>(s_k, nullptr, (int)tid, tid < (uint32_t)MT);
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const uint32_t j = wbase + r * kWave + lane;
+            if (j < n) keys[bi.lo + j] = KT::from_ord((uint64_t)s_k[pad16(j)]);
+        }
+        return;
+    }
+    if (by_value) base_place<KT, IPT, ND, true>(o, sl, n, wbase, mn, shift, vlo, vscale, s_k, s_c);
+    else base_place<KT, IPT, ND, false>(o, sl, n, wbase, mn, shift, vlo, vscale, s_k, s_c);
+    __syncthreads();
+    if (by_value) base_fixup<KT, NW, IPT, ND, true>(n, wbase, mn, shift, vlo, vscale, s_k, s_c);
+    else if (!exact) base_fixup<KT, NW, IPT, ND, false>(n, wbase, mn, shift, vlo, vscale, s_k, s_c);
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint32_t j = wbase + r * kWave + lane;
+        if (j < n) keys[bi.lo + j] = KT::from_ord((uint64_t)s_k[j]);
+    }
+}
+
+// VMAP: skewed buckets are counted again by value before the merge sort is taken (sorted samples,
+// which span their whole bucket; the bulk of the base case runs without it).
+template <int DT, bool PAY, int NW, int IPT, bool VMAP = false>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PAY ? 4 : 6))) void k_base_large(
     const BaseItem* list, uint64_t count,
                                                        typename Key<DT>::T* keys, uint32_t* pay,
@@ -2140,6 +2361,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PAY ? 4
     if (blockIdx.x >= count) return;
     const BaseItem bi = list[blockIdx.x];
     if constexpr (PAY) base_large_stable<DT, true, NW, IPT>(bi, keys, pay, skeys, spay);
+    else if constexpr (VMAP) base_large_keys_vmap<DT, NW, IPT>(bi, keys, skeys);
     else base_large_keys<DT, NW, IPT>(bi, keys, skeys);
 }
 

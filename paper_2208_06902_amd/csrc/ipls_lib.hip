@@ -340,7 +340,8 @@ ipls_status launch_base_nt(hipStream_t s, const BaseItem* list, uint64_t count, 
     return IPLS_OK;
 }
 
-template <int DT, bool PAY>
+// VMAP (keys only): the large classes count skewed buckets again by value (used for samples).
+template <int DT, bool PAY, bool VMAP = false>
 ipls_status launch_base(hipStream_t s, int cls, const BaseItem* list, uint64_t count, typename Key<DT>::T* keys,
                         uint32_t* pay, const typename Key<DT>::T* sk, const uint32_t* sp) {
     if (count == 0) return IPLS_OK;
@@ -350,15 +351,15 @@ ipls_status launch_base(hipStream_t s, int cls, const BaseItem* list, uint64_t c
         case 2: return launch_base_nt<DT, PAY, 16>(s, list, count, keys, pay, sk, sp);
         case 3: return launch_base_nt<DT, PAY, 32>(s, list, count, keys, pay, sk, sp);
         case 4:
-            k_base_large<DT, PAY, 2, 8><<<(unsigned)count, 128, 0, s>>>(list, count, keys, pay, sk, sp);
+            k_base_large<DT, PAY, 2, 8, VMAP><<<(unsigned)count, 128, 0, s>>>(list, count, keys, pay, sk, sp);
             LAUNCH_CHECK();
             return IPLS_OK;
         case 5:
-            k_base_large<DT, PAY, 4, 8><<<(unsigned)count, 256, 0, s>>>(list, count, keys, pay, sk, sp);
+            k_base_large<DT, PAY, 4, 8, VMAP><<<(unsigned)count, 256, 0, s>>>(list, count, keys, pay, sk, sp);
             LAUNCH_CHECK();
             return IPLS_OK;
         default:
-            k_base_large<DT, PAY, 8, 8><<<(unsigned)count, 512, 0, s>>>(list, count, keys, pay, sk, sp);
+            k_base_large<DT, PAY, 8, 8, VMAP><<<(unsigned)count, 512, 0, s>>>(list, count, keys, pay, sk, sp);
             LAUNCH_CHECK();
             return IPLS_OK;
     }
@@ -371,7 +372,7 @@ ipls_status sort_samples(Device& dv, Run& run, int d, const Plan& pl, typename K
     hipStream_t s = run.s;
     if (pl.max_S <= run.p.base_case_max) {
         // k_plan has written every sample as a base-case bucket of the sample buffer
-        return launch_base<DT, false>(s, base_class((uint32_t)pl.max_S), (const BaseItem*)D.sample_base.p,
+        return launch_base<DT, false, true>(s, base_class((uint32_t)pl.max_S), (const BaseItem*)D.sample_base.p,
                                       pl.num_items, sample, nullptr, nullptr, nullptr);
     }
     if (d + 1 >= kMaxDepth) return IPLS_ERR_DEVICE;
