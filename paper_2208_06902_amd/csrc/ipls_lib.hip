@@ -537,9 +537,12 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         }
         if (pl.num_base) {
             // the previous level's buckets of <= T keys: base[(level - 1) & 1], complete (the host
-            // has just synchronised the main stream for the plan)
+            // has just seen the plan, so the main stream's earlier work is done).  They go to the
+            // side stream while another level follows on the main stream; the last level's go to
+            // the main stream, beside the side stream's earlier (larger) base-case launch, whose
+            // tail leaves most of the device idle
             const int bp = (level + 1) & 1;
-            const bool side = overlap;
+            const bool side = overlap && pl.num_items > 0;
             hipStream_t sl = side ? sb : s;
             {
                 ProfScope ps(2, (double)pl.base_keys * 2.0 * (kb + (PAY ? 4 : 0)), sl);
