@@ -32,6 +32,23 @@ struct LevelArgs {
 // One workgroup of 256 threads (small enough to start beside a running base case): per-item prefix sums of tiles, samples and large-sample fit
 // chunks; totals and maxima for the host.  Consumes the item and base-case counters of the
 // previous level and resets the counters the coming level appends to.
+// One item's share of a level: {chunks, tiles, sample keys, fit chunks, keys, keys with an
+// inherited line, 1 if its chunk scan takes a workgroup per bucket}.
+__device__ inline void plan_item(const Item& it, const Child* prev_children, const LevelArgs& A, uint64_t (&w)[7]) {
+    const uint64_t n = it.n;
+    const uint64_t nt = (n + A.tile_keys - 1) / A.tile_keys;
+    const uint64_t nc = (nt + A.chunk - 1) / A.chunk;
+    const uint64_t ns = (it.inh && prev_children) ? prev_children[it.inh - 1].s_len
+                                                  : sample_size(n, A.div, A.smin, A.smax, A.policy, A.K);
+    w[0] = nc;
+    w[1] = nt;
+    w[2] = ns;
+    w[3] = ns > A.small_S ? (ns + A.fit_chunk - 1) / A.fit_chunk : 0;
+    w[4] = n;
+    w[5] = (it.inh && prev_children) ? n : 0;
+    w[6] = nc > kScanSerial ? 1 : 0;
+}
+
 __global__ __launch_bounds__(256) void k_plan(const Item* items, uint64_t* cnt, int cur, Plan* plan, uint64_t* tile_off,
                                                uint64_t* sample_off, uint64_t* fit_off, uint64_t* chunk_off,
                                                LevelArgs A, uint64_t item_cap, BaseLayout bl, const CopyItem* copy,
@@ -57,37 +74,51 @@ __global__ __launch_bounds__(256) void k_plan(const Item* items, uint64_t* cnt, 
     }
     uint64_t run_t = 0, run_s = 0, run_f = 0, run_c = 0, run_w = 0, sum_n = 0, sum_inh = 0;
     const uint64_t use = num < item_cap ? num : item_cap;
-    for (uint64_t base = 0; base < use; base += blockDim.x) {
-        uint64_t i = base + threadIdx.x;
-        uint64_t nt = 0, ns = 0, nf = 0, nc = 0, n = 0, ninh = 0;
-        if (i < use) {
-            const Item it = items[i];
-            n = it.n;
-            nt = (n + A.tile_keys - 1) / A.tile_keys;
-            nc = (nt + A.chunk - 1) / A.chunk;
-            ns = (it.inh && prev_children) ? prev_children[it.inh - 1].s_len
-                                           : sample_size(n, A.div, A.smin, A.smax, A.policy, A.K);
-            nf = ns > A.small_S ? (ns + A.fit_chunk - 1) / A.fit_chunk : 0;
-            ninh = (it.inh && prev_children) ? n : 0;
+    // kPlanIPT consecutive items per thread: a pass for the thread's sums, one block scan, then a
+    // pass that writes the item's offsets (levels of many items take few block scans)
+    constexpr int kPlanIPT = 8;
+    for (uint64_t base = 0; base < use; base += (uint64_t)blockDim.x * kPlanIPT) {
+        const uint64_t i0 = base + (uint64_t)threadIdx.x * kPlanIPT;
+        uint64_t v[7] = {0, 0, 0, 0, 0, 0, 0}, mS = 0, mN = 0;
+#pragma unroll
+        for (int k = 0; k < kPlanIPT; ++k) {
+            if (i0 + k < use) {
+                uint64_t w[7];
+                plan_item(items[i0 + k], prev_children, A, w);
+#pragma unroll
+                for (int j = 0; j < 7; ++j) v[j] += w[j];
+                mS = w[2] > mS ? w[2] : mS;
+                mN = w[4] > mN ? w[4] : mN;
+            }
         }
         // maxima: one LDS atomic per wave
-        const uint64_t mS = wave_max<uint64_t>(ns), mN = wave_max<uint64_t>(n);
+        mS = wave_max<uint64_t>(mS);
+        mN = wave_max<uint64_t>(mN);
         if (lane_id() == 0) {
             atomicMax((unsigned long long*)&s_max[0], (unsigned long long)mS);
             atomicMax((unsigned long long*)&s_max[1], (unsigned long long)mN);
         }
-        const uint64_t wide = nc > kScanSerial ? 1 : 0;
-        const uint64_t v[7] = {nc, nt, ns, nf, n, ninh, wide};
         uint64_t ex[7], tot[7];
         block_exclusive_sums<7>(v, ex, tot, sc6);
-        if (i < use) {
-            chunk_off[i] = run_c + ex[0];
-            tile_off[i] = run_t + ex[1];
-            sample_off[i] = run_s + ex[2];
-            fit_off[i] = run_f + ex[3];
+        uint64_t at_c = run_c + ex[0], at_t = run_t + ex[1], at_s = run_s + ex[2], at_f = run_f + ex[3],
+                 at_w = run_w + ex[6];
+        for (int k = 0; k < kPlanIPT; ++k) {
+            const uint64_t i = i0 + k;
+            if (i >= use) break;
+            uint64_t w[7];
+            plan_item(items[i], prev_children, A, w);
+            chunk_off[i] = at_c;
+            tile_off[i] = at_t;
+            sample_off[i] = at_s;
+            fit_off[i] = at_f;
             // the samples as base-case buckets of the sample buffer (used when every sample has <= T keys)
-            if (sample_base) sample_base[i] = BaseItem{run_s + ex[2], (uint32_t)ns, 0};
-            if (wide) wide_items[run_w + ex[6]] = (uint32_t)i;  // items whose chunks a workgroup per bucket scans
+            if (sample_base) sample_base[i] = BaseItem{at_s, (uint32_t)w[2], 0};
+            if (w[6]) wide_items[at_w] = (uint32_t)i;  // items whose chunks a workgroup per bucket scans
+            at_c += w[0];
+            at_t += w[1];
+            at_s += w[2];
+            at_f += w[3];
+            at_w += w[6];
         }
         run_c += tot[0];
         run_t += tot[1];
@@ -330,10 +361,12 @@ __device__ inline void fmcd_search(const X& x, uint64_t S, uint32_t K, double* a
 }
 
 // Small samples (S <= small_S <= LDS_KEYS): one workgroup per item, the sample in LDS as fp64,
-// binary search.  LDS_KEYS is kFitLds, or 4096 when every sample of the level is that small: a
-// 32 KB workgroup finds room beside other kernels' workgroups (a 128 KB one waits for an empty CU).
+// binary search.  LDS_KEYS is kFitLds, or 4096 or 1024 when every sample of the level is that
+// small: a 32 KB workgroup finds room beside other kernels' workgroups (a 128 KB one waits for an
+// empty CU), and levels of many small items (samples of 2K keys) fit more 8 KB workgroups per CU.
 constexpr int kFitLds = 16384;
 constexpr int kFitLdsSmall = 4096;
+constexpr int kFitLdsTiny = 1024;
 
 template <int DT, int LDS_KEYS>
 __global__ __launch_bounds__(256) void k_fmcd_small(const typename Key<DT>::T* sample, const uint64_t* sample_off,

@@ -268,7 +268,9 @@ template <int DT>
 ipls_status fit_level(Depth& D, hipStream_t s, uint64_t ni, uint64_t max_S, uint64_t total_fit_chunks,
                       const typename Key<DT>::T* sample, const uint64_t* sample_off, const uint64_t* fit_off,
                       Model* models, uint32_t K, const EqInfo* eq = nullptr) {
-    if (max_S <= (uint64_t)kFitLdsSmall)
+    if (max_S <= (uint64_t)kFitLdsTiny)
+        k_fmcd_small<DT, kFitLdsTiny><<<(unsigned)ni, 256, 0, s>>>(sample, sample_off, ni, models, K, kSmallS, eq);
+    else if (max_S <= (uint64_t)kFitLdsSmall)
         k_fmcd_small<DT, kFitLdsSmall><<<(unsigned)ni, 256, 0, s>>>(sample, sample_off, ni, models, K, kSmallS, eq);
     else
         k_fmcd_small<DT, kFitLds><<<(unsigned)ni, 256, 0, s>>>(sample, sample_off, ni, models, K, kSmallS, eq);
