@@ -18,11 +18,12 @@
  *     library never frees or keeps them after the call returns.
  *   - Work is enqueued on `stream` (NULL = the default stream).  The sort entry points read a
  *     few bytes back from the device once per recursion level to size the next level's
- *     launches (the device writes them into pinned host memory), so they return only after the
- *     sort has completed on `stream`.  Each engine context also owns one stream of its own
- *     (non-blocking, default priority) on which the base case of a level runs beside the next
- *     level's partition; `stream` waits for it (events) before the call returns, so work the
- *     caller queues on `stream` afterwards sees the finished result.
+ *     launches (the device writes them into pinned host memory, where the calling thread polls
+ *     for them), so they return only after the sort has completed on `stream`.  Each engine
+ *     context also owns one stream of its own (non-blocking, default priority) on which the base
+ *     case of a level runs beside the next level's partition (the last level's runs on
+ *     `stream`); `stream` waits for it (events) before the call returns, so work the caller
+ *     queues on `stream` afterwards sees the finished result.
  *   - Keys are ordered by IEEE 754 totalOrder (-0 before +0; NaNs are accepted and sort to the
  *     end their sign bit gives).  u64 keys are plain unsigned integers.
  *   - Results are deterministic and bit-identical for identical inputs and parameters; with a
