@@ -79,7 +79,8 @@ def summarize_profiles(ktrace_dir: str, fetch_dir: str, write_dir: str, bench_js
              f"Bench line of the same run: {bench['value']:.4g} keys/s, {bench['ms_per_step']} ms per step; "
              f"k_scatter average launch by HIP events in bench.py: {bench['roofline']['avg_launch_ms']} ms over "
              f"{bench['roofline']['launches']} timed launches.", "",
-             "10 sorts (5 warmup + 5 timed, all five distributions).  `__amd_rocclr_copyBuffer` is the bench's "
+             "15 sorts (5 warmup, 5 timed, then the timed steps again, untimed, for the counting and base-case "
+             "timings; all five distributions).  `__amd_rocclr_copyBuffer` is the bench's "
              "own staging of inputs, outside the timed steps.", "",
              "| kernel | calls | avg us | total ms | % |", "|---|---:|---:|---:|---:|"]
     for r in stats[:28]:
@@ -109,7 +110,7 @@ def summarize_profiles(ktrace_dir: str, fetch_dir: str, write_dir: str, bench_js
     big = [(f, w) for f, w in zip(sf, sw) if f > 1e8]
     t = {"kernel": "k_scatter", "kernel_sha": kernel_hash(), "bytes_per_launch": round(per_launch),
          "launches": n_launch, "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
-         "workload": "bench.py --steps 5 --warmup 5 --no-cpu-baseline (10 sorts of 1e8 fp64, all five distributions)",
+         "workload": "bench.py --steps 5 --warmup 5 --no-cpu-baseline (15 sorts of 1e8 fp64, all five distributions)",
          "large_launches_bytes": [[round(f), round(w)] for f, w in big[:6]],
          "algorithmic_bytes_large_launch": 1_600_000_000}
     json.dump(t, open(os.path.join(out_dir, "scatter_traffic.json"), "w"), indent=1)
@@ -119,7 +120,7 @@ def summarize_profiles(ktrace_dir: str, fetch_dir: str, write_dir: str, bench_js
           "        python3 -u bench.py --steps 5 --warmup 5 --no-cpu-baseline",
           "    rocprofv3 --pmc WRITE_SIZE -f csv -d <dir> -o bench -- \\",
           "        python3 -u bench.py --steps 5 --warmup 5 --no-cpu-baseline", "",
-          "The same command as the kernel trace: 10 sorts, two of each of the five distributions, the launch "
+          "The same command as the kernel trace: 15 sorts, three of each of the five distributions, the launch "
           "mix of the bench's timed steps.", "",
           f"Calibration: the bench's device-to-device copies of one 800,000,000-byte input read as "
           f"FETCH_SIZE x {f_scale:.3f} and WRITE_SIZE x {w_scale:.3f}; every k_scatter value below is scaled "
