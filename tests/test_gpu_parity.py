@@ -242,3 +242,21 @@ def test_segmented_matches_oracle(nseg, seed):
     want, wpay, _ = oracle.sort_segmented(keys, off, pay, oracle.params())
     assert same_bits(host(kd, keys.dtype), want)
     assert np.array_equal(host(pd, np.uint32), wpay)
+
+
+def test_segmented_many_items():
+    # 5000 segments above T: a first level of 5000 items (several rounds of the plan kernel's
+    # eight-items-a-thread scan), every sample of 2K keys (the 8 KB fit)
+    r = np.random.default_rng(21)
+    sizes = r.integers(4097, 9000, 5000)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    keys = r.standard_normal(int(off[-1])) * r.choice([1e-3, 1.0, 1e3], int(off[-1]))
+    pay = gen.index_payload(keys.size)
+    print(f"segmented many items nseg={sizes.size} total={keys.size}", flush=True)
+    kd, pd = dev(keys), dev(pay)
+    st = ipls.sort_segmented_(kd, dev(off), pd, stats=True)
+    torch.cuda.synchronize()
+    want, wpay, ost = oracle.sort_segmented(keys, off, pay, oracle.params())
+    assert same_bits(host(kd, keys.dtype), want)
+    assert np.array_equal(host(pd, np.uint32), wpay)
+    assert (st["passes"], st["levels"]) == (ost["passes"], ost["max_level"]), (st, ost)
