@@ -23,6 +23,7 @@ namespace ipls {
 namespace {
 
 constexpr uint32_t kSmallS = kFitLds;  // samples up to this size are fitted in one workgroup's LDS
+constexpr uint64_t kDeferBaseItems = 2048;  // levels of at least this many items run before the previous level's base case
 constexpr uint32_t kFitChunk = 2048;   // windows per workgroup in the multi-round fit
 constexpr uint32_t kCand = 15;         // candidate widths per fit round
 constexpr uint32_t kSmallTile = 4 * kWave * kPassIPT;  // 2048 keys: 4 waves
@@ -76,6 +77,7 @@ struct Device {
     // beside the next level's partition; ev_base[parity] marks the end of a level's base launch.
     hipStream_t side = nullptr;
     hipEvent_t ev_base[2] = {nullptr, nullptr};
+    hipEvent_t ev_defer = nullptr;  // a level's scatter, which a deferred base launch waits for
 };
 
 void release(Buf& b) {
@@ -99,9 +101,9 @@ void release_device(Device& dv) {
     }
     if (dv.seg_h) (void)hipHostFree(dv.seg_h);
     dv.seg_h = nullptr;
-    for (hipEvent_t& e : dv.ev_base) {
-        if (e) (void)hipEventDestroy(e);
-        e = nullptr;
+    for (hipEvent_t* e : {&dv.ev_base[0], &dv.ev_base[1], &dv.ev_defer}) {
+        if (*e) (void)hipEventDestroy(*e);
+        *e = nullptr;
     }
     if (dv.side) (void)hipStreamDestroy(dv.side);
     dv.side = nullptr;
@@ -428,7 +430,8 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     const bool overlap = top;
     if (overlap && !dv.side) {
         HIP_TRY(hipStreamCreateWithFlags(&dv.side, hipStreamNonBlocking));
-        for (hipEvent_t& e : dv.ev_base) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        for (hipEvent_t* e : {&dv.ev_base[0], &dv.ev_base[1], &dv.ev_defer})
+            HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
     }
     hipStream_t sb = overlap ? dv.side : s;  // stream of the base-case launches
     bool base_pending[2] = {false, false};   // a side-stream base launch read base[parity]
@@ -537,27 +540,31 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                                                                     keys, pay, scratch, spay);
             LAUNCH_CHECK();
         }
-        if (pl.num_base) {
-            // the previous level's buckets of <= T keys: base[(level - 1) & 1], complete (the host
-            // has just seen the plan, so the main stream's earlier work is done).  They go to the
-            // side stream while another level follows on the main stream; the last level's go to
-            // the main stream, beside the side stream's earlier (larger) base-case launch, whose
-            // tail leaves most of the device idle
-            const int bp = (level + 1) & 1;
-            const bool side = overlap && pl.num_items > 0;
-            hipStream_t sl = side ? sb : s;
-            {
-                ProfScope ps(2, (double)pl.base_keys * 2.0 * (kb + (PAY ? 4 : 0)), sl);
-                for (int c = 0; c < kBaseClasses; ++c)
-                    ST_TRY((launch_base<DT, PAY>(sl, c, (const BaseItem*)D.base[bp].p + bl.off[c], pl.cls_count[c],
-                                                 keys, pay, scratch, spay)));
-            }
+        // the previous level's buckets of <= T keys: base[(level - 1) & 1], complete (the host has
+        // just seen the plan, so the main stream's earlier work is done)
+        const int bp = (level + 1) & 1;
+        auto launch_level_base = [&](hipStream_t sl) -> ipls_status {
+            ProfScope ps(2, (double)pl.base_keys * 2.0 * (kb + (PAY ? 4 : 0)), sl);
+            for (int c = 0; c < kBaseClasses; ++c)
+                ST_TRY((launch_base<DT, PAY>(sl, c, (const BaseItem*)D.base[bp].p + bl.off[c], pl.cls_count[c], keys,
+                                             pay, scratch, spay)));
+            return IPLS_OK;
+        };
+        // They go to the side stream while another level follows on the main stream; the last
+        // level's go to the main stream, beside the side stream's earlier (larger) base-case
+        // launch, whose tail leaves most of the device idle.  Before a level of many items the
+        // launch waits for that level's scatter: its latency-bound per-item kernels would
+        // otherwise wait for CUs held by the base case's large-LDS workgroups.
+        const bool side = overlap && pl.num_items > 0;
+        const bool defer_base = side && pl.num_base && pl.num_items >= kDeferBaseItems;
+        if (pl.num_base && !defer_base) {
+            ST_TRY(launch_level_base(side ? sb : s));
             if (side) {
                 HIP_TRY(hipEventRecord(dv.ev_base[bp], sb));
                 base_pending[bp] = true;
             }
-            if (top) run.st.base_buckets += pl.num_base;
         }
+        if (top) run.st.base_buckets += pl.num_base;
         if (pl.num_items == 0) break;
         if (level + 1 > kMaxLevels) {
             ST_TRY(join());
@@ -689,6 +696,13 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                 nc, models, (const double*)D.leaves.p, (const uint64_t*)D.bstart.p, (const uint64_t*)D.chunk_pref.p,
                 (const uint32_t*)D.tile_pref.p, src, psrc, dst, pdst, K, P.leaves, spans, children, cls);
             LAUNCH_CHECK();
+        }
+        if (defer_base) {
+            HIP_TRY(hipEventRecord(dv.ev_defer, s));
+            HIP_TRY(hipStreamWaitEvent(sb, dv.ev_defer, 0));
+            ST_TRY(launch_level_base(sb));
+            HIP_TRY(hipEventRecord(dv.ev_base[bp], sb));
+            base_pending[bp] = true;
         }
         if (top && level == 0 && run.single_pass) {
             k_export_model<<<1, 1, 0, s>>>(models, run.part_model, K);
