@@ -77,7 +77,7 @@ struct Device {
     // beside the next level's partition; ev_base[parity] marks the end of a level's base launch.
     hipStream_t side = nullptr;
     hipEvent_t ev_base[2] = {nullptr, nullptr};
-    hipEvent_t ev_defer = nullptr;  // a level's scatter, which a deferred base launch waits for
+    hipEvent_t ev_defer = nullptr;  // a level's worklist, which a deferred base launch waits for
 };
 
 void release(Buf& b) {
@@ -553,7 +553,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         // They go to the side stream while another level follows on the main stream; the last
         // level's go to the main stream, beside the side stream's earlier (larger) base-case
         // launch, whose tail leaves most of the device idle.  Before a level of many items the
-        // launch waits for that level's scatter: its latency-bound per-item kernels would
+        // launch waits for that level's worklist: its latency-bound per-item kernels would
         // otherwise wait for CUs held by the base case's large-LDS workgroups.
         const bool side = overlap && pl.num_items > 0;
         const bool defer_base = side && pl.num_base && pl.num_items >= kDeferBaseItems;
@@ -697,13 +697,6 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                 (const uint32_t*)D.tile_pref.p, src, psrc, dst, pdst, K, P.leaves, spans, children, cls);
             LAUNCH_CHECK();
         }
-        if (defer_base) {
-            HIP_TRY(hipEventRecord(dv.ev_defer, s));
-            HIP_TRY(hipStreamWaitEvent(sb, dv.ev_defer, 0));
-            ST_TRY(launch_level_base(sb));
-            HIP_TRY(hipEventRecord(dv.ev_base[bp], sb));
-            base_pending[bp] = true;
-        }
         if (top && level == 0 && run.single_pass) {
             k_export_model<<<1, 1, 0, s>>>(models, run.part_model, K);
             LAUNCH_CHECK();
@@ -729,6 +722,13 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             (Item*)D.items[cur ^ 1].p, (BaseItem*)D.base[par].p, bl, cnt, C_ITEMS0 + (cur ^ 1), item_cap,
             (CopyItem*)D.copy.p, copy_cap, spans, children, (top && level == 0 && ni == 1) ? cnt + C_L1MAX : nullptr);
         LAUNCH_CHECK();
+        if (defer_base) {
+            HIP_TRY(hipEventRecord(dv.ev_defer, s));
+            HIP_TRY(hipStreamWaitEvent(sb, dv.ev_defer, 0));
+            ST_TRY(launch_level_base(sb));
+            HIP_TRY(hipEventRecord(dv.ev_base[bp], sb));
+            base_pending[bp] = true;
+        }
         cur ^= 1;
     }
     // the caller's stream completes only after the base case
