@@ -17,7 +17,7 @@
  *     Sort section: a 1% sample works well);
  *   - sort of the sample (Machine Learning Models chapter: the sample is sorted by another
  *     algorithm; the sorted sample is unique, so any sort gives the same bits);
- *   - FMCD fit (Linear Models section and its C++ listing), in fp64;
+ *   - FMCD fit (Linear Models section: the smallest conflict degree D), in fp64;
  *   - the clamped linear partition model (Linear Models section, the piecewise F(x));
  *   - stable distribution into contiguous buckets (Proposed Algorithm, Worked Example: the
  *     layout after "a pass to make the buckets contiguous" is the stable counting-sort layout);
@@ -274,24 +274,45 @@ static double fmcd_spread(const double* x, uint64_t S, uint64_t D, uint32_t K) {
     return (x[S - 1 - D] - x[D]) / (double)(K - 2);
 }
 
-/* Fastest Minimum Conflict Degree on the sorted sample x[0..S), in fp64.
+/* The conflict-degree condition of FMCD for one D: every window of D+1 consecutive sorted
+ * sample keys, x[w] .. x[w+D], spans at least u(D). */
+static int fmcd_windows_span(const double* x, uint64_t S, uint64_t D, double u) {
+    for (uint64_t w = 0; w + D < S; ++w)
+        if (!(x[w + D] - x[w] >= u)) return 0;
+    return 1;
+}
+
+/* Fastest Minimum Conflict Degree on the sorted sample x[0..S), in fp64, from its definition
+ * (Linear Models section): the conflict degree D is the smallest D >= 1 for which the window
+ * condition above holds, searched over 1 <= D <= floor(S/3).  When no such D exists the
+ * search gives up: D becomes floor(S/3) + 1 while the spread stays u(floor(S/3)) (the printed
+ * procedure stops there with the spread of the last D it tried).  The model is then
+ * a = 1/u and b = (K - a (x[S-1-D] + x[D])) / 2, which puts x[D] near t = 1 and x[S-1-D] near
+ * t = K-1.
  *
- * Walk the windows (x[i], x[i+D]) from the left.  A window that spans at least u(D) is passed;
- * a narrower one makes D one larger (and u(D) smaller), and the walk resumes at the same
- * window, since every window already passed still spans the new, smaller spread.  The walk
- * ends when no window is left (every window of the current D spans u(D)) or when 3D exceeds S;
- * in the latter case the spread of the previous D is kept while the model's offset uses the
- * new D.  Slope a = 1/u, offset b = (K - a (x[S-1-D] + x[D])) / 2, so that x[D] lands near
- * t = 1 and x[S-1-D] near t = K-1.  Returns 0, or -1 when S < 3 or K < 4. */
+ * The condition is monotone in D, also in fp64: a window's span x[w+D+1] - x[w] is at least
+ * x[w+D] - x[w] (rounding is monotone), and u(D+1) <= u(D) because the trimmed range shrinks.
+ * So the smallest D is found by bisection over [1, floor(S/3)], in O(S log S).
+ * Returns 0, or -1 when S < 3 or K < 4. */
 int oracle_fmcd(const double* x, uint64_t S, uint32_t K, double* a_out, double* b_out, uint64_t* D_out) {
     if (S < 3 || K < 4) return -1;
-    uint64_t D = 1, i = 0;
-    double u = fmcd_spread(x, S, D, K);
-    for (;;) {
-        while (i + D < S && x[i + D] - x[i] >= u) i += 1;
-        if (i + D >= S) break; /* every window spans u */
-        D += 1;
-        if (3 * D > S) break; /* give up: keep the previous spread */
+    const uint64_t Dmax = S / 3;
+    uint64_t D;
+    double u;
+    if (!fmcd_windows_span(x, S, Dmax, fmcd_spread(x, S, Dmax, K))) {
+        D = Dmax + 1;
+        u = fmcd_spread(x, S, Dmax, K);
+    } else {
+        /* condition false below lo (or lo = 1), true at hi */
+        uint64_t lo = 1, hi = Dmax;
+        while (lo < hi) {
+            uint64_t mid = lo + (hi - lo) / 2;
+            if (fmcd_windows_span(x, S, mid, fmcd_spread(x, S, mid, K)))
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        D = hi;
         u = fmcd_spread(x, S, D, K);
     }
     double a = 1.0 / u;

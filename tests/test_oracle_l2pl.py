@@ -6,6 +6,8 @@ mathematics instead: the loss against its definition evaluated by numpy, the gra
 central finite differences, the trained leaves against each leaf's closed-form least-squares
 line, and the envelope and classifier against monotonicity.
 """
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -136,3 +138,40 @@ def test_learned_model_lowers_max_load_on_skew(dist):
     lin = oracle.Model(kind=oracle.MODEL_LINEAR, K=256, a=m.a, b=m.b)
     full_lin = np.bincount(oracle.classify_model(k, lin), minlength=256).max()
     assert full < full_lin
+
+
+def fma_exact(a, x, b):
+    """fma(a, x, b): the exact a*x + b rounded once (Fraction -> float rounds to nearest even)."""
+    return float(Fraction(a) * Fraction(x) + Fraction(b))
+
+
+@pytest.mark.parametrize("dist", ["lognormal2", "mixgauss20", "normal"])
+def test_exported_leaf_line_is_the_trained_line(dist):
+    # A leaf is trained as t = alpha u + beta in its centred coordinate u = (x - c)/h and exported
+    # for classification as t = fma(A, x, B).  The export must be that same line in x: for every
+    # sample key of every non-empty leaf, fma(A, x, B) agrees with the exact alpha (x - c)/h + beta
+    # up to the rounding of A = alpha/h, of A c and B = beta - A c, and of the fma itself, each at
+    # most half an ulp: |error| <= 2^-52 (|A x| + 3 |A c| + |beta| + |t|).  A B that dropped the
+    # 1/h, or a line in the wrong coordinate, misses by whole buckets.
+    K, M = 256, 256
+    x = sample_of(dist, 12000, 9)
+    root, leaf, ab = oracle.l2pl_train(x, K, M, 4)
+    first, c, h, _ = oracle.l2pl_geometry(x, M, root[0], root[1])
+    first = first.astype(np.int64)
+    eps = Fraction(1, 2**52)
+    checked = 0
+    for l in range(M):
+        j0, j1 = first[l], first[l + 1]
+        if j1 == j0:
+            continue
+        A, B = leaf[4 * l], leaf[4 * l + 1]
+        alpha, beta = Fraction(ab[2 * l]), Fraction(ab[2 * l + 1])
+        cl, hl = Fraction(c[l]), Fraction(h[l])
+        for j in range(j0, j1, max(1, (j1 - j0) // 4)):
+            xj = Fraction(x[j])
+            exact = alpha * (xj - cl) / hl + beta
+            got = Fraction(fma_exact(A, x[j], B))
+            bound = eps * (abs(Fraction(A) * xj) + 3 * abs(Fraction(A) * cl) + abs(beta) + abs(exact))
+            assert abs(got - exact) <= bound, (l, j, float(got), float(exact))
+            checked += 1
+    assert checked > 200
