@@ -95,6 +95,12 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"libipls.so not built at {path}; run python -m paper_2208_06902_amd.build")
+    # torch brings its own HIP runtime; load it first so that the library binds to the same one
+    # (the library loaded first would bind the system's runtime, and torch would then share it)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(path)
     P, sz, u32, u64, i32, dbl = C.c_void_p, C.c_size_t, C.c_uint32, C.c_uint64, C.c_int, C.c_double
     sig = {
@@ -173,16 +179,23 @@ def _check_tensor(t, name):
         raise ValueError(f"{name} must be a contiguous device tensor")
 
 
+def _check_payload(payload, keys):
+    """A payload is a contiguous 32-bit device tensor with one element per key: the library can
+    only check its pointer's alignment, so a shorter or strided tensor is refused here."""
+    import torch
+    if payload is None:
+        return
+    _check_tensor(payload, "payload")
+    if payload.dtype != torch.int32 and payload.dtype != torch.uint32:
+        raise TypeError("payload must be 32-bit")
+    if payload.numel() != keys.numel():
+        raise ValueError("payload and keys differ in length")
+
+
 def sort_(keys, payload=None, params: Params | None = None, workspace=None, stream=None, stats: bool = False):
     """Sort `keys` (and `payload`, stably) in place on the GPU.  Returns stats if asked."""
-    import torch
     _check_tensor(keys, "keys")
-    if payload is not None:
-        _check_tensor(payload, "payload")
-        if payload.dtype != torch.int32 and payload.dtype != torch.uint32:
-            raise TypeError("payload must be 32-bit")
-        if payload.numel() != keys.numel():
-            raise ValueError("payload and keys differ in length")
+    _check_payload(payload, keys)
     st = Stats()
     ws, wsb = (None, 0) if workspace is None else (_ptr(workspace), workspace.numel() * workspace.element_size())
     rc = load().ipls_sort_ex(_ptr(keys), _ptr(payload), keys.numel(), _dtype_code(keys),
@@ -194,6 +207,7 @@ def sort_(keys, payload=None, params: Params | None = None, workspace=None, stre
 def sort_plain(keys, payload=None, stream=None):
     """ipls_sort: default parameters."""
     _check_tensor(keys, "keys")
+    _check_payload(payload, keys)
     rc = load().ipls_sort(_ptr(keys), _ptr(payload), keys.numel(), _dtype_code(keys), _stream(stream))
     _check(rc, "ipls_sort")
 
@@ -205,6 +219,9 @@ def sort_segmented_(keys, offsets, payload=None, params: Params | None = None, s
     _check_tensor(offsets, "offsets")
     if offsets.dtype not in (torch.int64, torch.uint64):
         raise TypeError("offsets must be 64-bit")
+    if offsets.numel() < 1:
+        raise ValueError("offsets needs at least one element (nseg + 1)")
+    _check_payload(payload, keys)
     st = Stats()
     rc = load().ipls_sort_segmented(_ptr(keys), _ptr(payload), _ptr(offsets), offsets.numel() - 1,
                                     _dtype_code(keys), C.byref(params) if params is not None else None,
@@ -229,6 +246,7 @@ def partition_(keys, payload=None, params: Params | None = None, stream=None):
     """One distribution pass in place: returns (counts tensor (K, uint64), (a, b, D, degenerate))."""
     import torch
     _check_tensor(keys, "keys")
+    _check_payload(payload, keys)
     p = params if params is not None else default_params()
     counts = torch.zeros(p.num_buckets, dtype=torch.uint64, device=keys.device)
     mbuf = torch.zeros(C.sizeof(LinearModel), dtype=torch.uint8, device=keys.device)

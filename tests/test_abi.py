@@ -83,3 +83,43 @@ def test_host_side_argument_errors():
     assert lib.ipls_l2pl_train(fake, 2, 256, 256, 4, fake, fake, None, None) == 1  # S < 3
     big = ipls.default_params(num_buckets=512)
     assert lib.ipls_sort_ex(fake, None, 10, ipls.F64, ctypes.byref(big), None, 0, None, None) == 6  # K > 256
+
+
+class _FakeDeviceTensor:
+    """Stands in for a device tensor on a host without a GPU: the wrapper's checks read only these."""
+
+    def __init__(self, n, dtype, contiguous=True):
+        self._n, self.dtype, self._c = n, dtype, contiguous
+        self.is_cuda = True
+
+    def is_contiguous(self):
+        return self._c
+
+    def numel(self):
+        return self._n
+
+    def data_ptr(self):
+        raise AssertionError("the wrapper reached the library call")
+
+
+@pytest.mark.parametrize("bad", ["short", "strided", "dtype"])
+@pytest.mark.parametrize("entry", ["sort_", "sort_plain", "sort_segmented_", "partition_"])
+def test_wrapper_refuses_a_bad_payload_before_any_launch(monkeypatch, entry, bad):
+    import torch
+
+    def no_library(*a, **k):
+        raise AssertionError("the wrapper reached the library")
+
+    monkeypatch.setattr(ipls, "load", no_library)
+    keys = _FakeDeviceTensor(100, torch.float64)
+    pay = {"short": _FakeDeviceTensor(99, torch.int32),
+           "strided": _FakeDeviceTensor(100, torch.int32, contiguous=False),
+           "dtype": _FakeDeviceTensor(100, torch.int64)}[bad]
+    with pytest.raises((ValueError, TypeError)):
+        if entry == "sort_segmented_":
+            ipls.sort_segmented_(keys, _FakeDeviceTensor(3, torch.int64), payload=pay)
+        elif entry == "partition_":
+            ipls.partition_(keys, payload=pay, params=object())
+        else:
+            getattr(ipls, entry)(keys, pay)
+
