@@ -224,8 +224,9 @@ ipls_status ipls_autotune_segmented(const void* keys, const uint64_t* seg_offset
  *   server's sort waits for that stream's work with an event -> wait/poll -> caller reads the
  *   sorted slot -> release.
  *   Execution: `lanes` threads, each with its own stream and engine context, take submitted work
- *   in order: a large request, or a whole batch (taking a batch closes it).  Lanes overlap on the
- *   device.  A request's result is bit-identical to ipls_sort_ex of its keys alone with the same
+ *   in order: a large request, or the slots of a batch submitted so far (taking a batch closes it
+ *   to new requests; its slots still only reserved are sorted once submitted, so a caller may wait
+ *   on one request before submitting the others).  Lanes overlap on the device.  A request's result is bit-identical to ipls_sort_ex of its keys alone with the same
  *   parameters.  Timestamps are CLOCK_MONOTONIC seconds. */
 typedef struct ipls_server ipls_server;
 
@@ -266,8 +267,8 @@ ipls_status ipls_server_poll(ipls_server* srv, ipls_server_done* out, size_t max
 /* Frees a done request's memory; its slot must not be used afterwards. */
 ipls_status ipls_server_release(ipls_server* srv, uint64_t req_id);
 ipls_status ipls_server_stats_get(ipls_server* srv, ipls_server_stats* out);
-/* Finishes submitted work (a batch with unsubmitted slots fails with IPLS_ERR_INVALID), stops
- * the lanes and frees the server (not the arena). */
+/* Finishes submitted work (requests reserved but never submitted are dropped), stops the lanes
+ * and frees the server (not the arena). */
 ipls_status ipls_server_destroy(ipls_server* srv);
 
 #ifdef __cplusplus

@@ -12,8 +12,8 @@
 // the request; the server orders its sort after that work with an event.
 //
 // Execution.  `lanes` worker threads, each with its own stream and engine context, take work in
-// submission order: a large request, or a batch (taking a batch closes it, so later small
-// requests open a new one).  Lanes run concurrently, so requests that arrive while others are on
+// submission order: a large request, or the submitted slots of a batch (taking a batch closes it,
+// so later small requests open a new one; its slots submitted later are taken afterwards).  Lanes run concurrently, so requests that arrive while others are on
 // the GPU start as soon as a lane and memory are free, and their kernels overlap on the device.
 // Every request's result is the sort of its own keys alone: a segmented sort never moves a key
 // across a segment boundary.
@@ -122,7 +122,8 @@ struct Batch {
     uint64_t keys_off = 0, pay_off = 0, ws_off = 0, ws_bytes = 0, offs_off = 0;
     std::vector<uint64_t> reqs;
     bool closed = false, queued = false;
-    uint32_t live = 0;  // requests not yet released
+    bool running = false;  // a lane is sorting some of its submitted slots
+    uint32_t live = 0;     // requests not yet released
 };
 
 struct WorkItem {
@@ -155,8 +156,52 @@ struct ipls_server {
     void lane_main(int lane);
     void run_request(ipls::Engine& e, hipStream_t s, uint64_t rid, uint64_t* offs_h);
     void run_batch(ipls::Engine& e, hipStream_t s, int64_t bid, uint64_t* offs_h);
+    std::vector<std::vector<Request>> take_batch_locked(int64_t bid);
+    void end_batch_locked(int64_t bid);
     void free_batch_locked(Batch& b);
 };
+
+// Takes a batch for a lane: closes it (later small requests open a new one) and hands over the
+// slots submitted so far, as runs of adjacent slots (each run is contiguous in the batch buffer).
+// Slots still only reserved stay behind and are taken when they are submitted, after this lane
+// is done with the batch, so a lane never waits for a caller.
+std::vector<std::vector<Request>> ipls_server::take_batch_locked(int64_t bid) {
+    Batch& b = batches[bid];
+    b.closed = true;
+    b.queued = false;
+    b.running = true;
+    if (open_batch[b.cls] == bid) open_batch[b.cls] = -1;
+    std::vector<std::vector<Request>> runs;
+    bool adjacent = false;
+    const double t = now_s();
+    for (uint64_t id : b.reqs) {
+        Request& q = reqs[id];
+        if (q.state != kSubmitted) {
+            adjacent = false;
+            continue;
+        }
+        q.state = kRunning;
+        q.t_start = t;
+        if (!adjacent) runs.emplace_back();
+        runs.back().push_back(q);
+        adjacent = true;
+    }
+    return runs;
+}
+
+// A lane is done with a batch: slots submitted meanwhile make it queued again.
+void ipls_server::end_batch_locked(int64_t bid) {
+    Batch& b = batches[bid];
+    b.running = false;
+    for (uint64_t id : b.reqs) {
+        if (reqs[id].state == kSubmitted) {
+            b.queued = true;
+            queue.push_back({true, bid});
+            cv_work.notify_all();
+            break;
+        }
+    }
+}
 
 void ipls_server::free_batch_locked(Batch& b) {
     alloc.release(b.alloc_off, b.alloc_bytes);
@@ -193,60 +238,51 @@ void ipls_server::run_request(ipls::Engine& e, hipStream_t s, uint64_t rid, uint
 
 void ipls_server::run_batch(ipls::Engine& e, hipStream_t s, int64_t bid, uint64_t* offs_h) {
     Batch b;
-    std::vector<Request> rs;
-    bool complete = true;
+    std::vector<std::vector<Request>> runs;
     {
-        std::unique_lock<std::mutex> g(mu);
-        Batch& q = batches[bid];
-        q.closed = true;
-        if (open_batch[q.cls] == bid) open_batch[q.cls] = -1;
-        // the caller fills a slot right after reserving it: wait until every slot is submitted
-        auto all_submitted = [&] {
-            for (uint64_t id : batches[bid].reqs)
-                if (reqs[id].state == kReserved) return false;
-            return true;
-        };
-        cv_work.wait(g, [&] { return stop || all_submitted(); });
-        complete = all_submitted();
+        std::lock_guard<std::mutex> g(mu);
+        runs = take_batch_locked(bid);
         b = batches[bid];
-        const double t = now_s();
-        for (uint64_t id : b.reqs) {
-            reqs[id].state = kRunning;
-            reqs[id].t_start = t;
-            rs.push_back(reqs[id]);
+    }
+    const uint64_t w = key_width(b.dtype);
+    uint64_t* offs_d = (uint64_t*)(arena + b.offs_off);
+    for (const std::vector<Request>& rs : runs) {
+        // one segmented sort per run of adjacent submitted slots; runs are sorted one after the
+        // other on this lane's stream, so they share the batch's workspace and offsets buffer
+        // (each engine call returns after its stream has completed)
+        ipls_status status = IPLS_OK;
+        for (const Request& r : rs) {
+            if (status != IPLS_OK) break;
+            if (r.ready && hipStreamWaitEvent(s, r.ready, 0) != hipSuccess) status = IPLS_ERR_HIP;
         }
+        const uint64_t nseg = rs.size(), k0 = rs[0].keys_off;
+        if (status == IPLS_OK) {
+            for (uint64_t i = 0; i < nseg; ++i) offs_h[i] = (rs[i].keys_off - k0) / w;
+            offs_h[nseg] = offs_h[nseg - 1] + rs[nseg - 1].n;
+            if (hipMemcpyAsync(offs_d, offs_h, (nseg + 1) * 8, hipMemcpyHostToDevice, s) != hipSuccess)
+                status = IPLS_ERR_HIP;
+            if (status == IPLS_OK)
+                status = ipls::engine_sort_segmented(e, arena + k0, b.pay ? (uint32_t*)(arena + rs[0].pay_off) : nullptr,
+                                                     offs_d, nseg, b.dtype, &cfg.params, arena + b.ws_off, b.ws_bytes,
+                                                     nullptr, s);
+        }
+        const double t = now_s();
+        std::lock_guard<std::mutex> g(mu);
+        for (const Request& r : rs) {
+            Request& q = reqs[r.id];
+            q.state = kDone;
+            q.status = status;
+            q.t_done = t;
+            q.batch_size = (uint32_t)nseg;
+            done_order.push_back(r.id);
+            st.completed += 1;
+            st.keys_sorted += r.n;
+        }
+        st.batches_run += 1;
+        cv_done.notify_all();
     }
-    ipls_status status = complete ? IPLS_OK : IPLS_ERR_INVALID;  // server stopped before every slot was filled
-    for (const Request& r : rs) {
-        if (status != IPLS_OK) break;
-        if (r.ready && hipStreamWaitEvent(s, r.ready, 0) != hipSuccess) status = IPLS_ERR_HIP;
-    }
-    const uint64_t nseg = rs.size();
-    if (status == IPLS_OK && nseg) {
-        for (uint64_t i = 0; i < nseg; ++i) offs_h[i] = (rs[i].keys_off - b.keys_off) / key_width(b.dtype);
-        offs_h[nseg] = b.used_keys;
-        uint64_t* offs_d = (uint64_t*)(arena + b.offs_off);
-        if (hipMemcpyAsync(offs_d, offs_h, (nseg + 1) * 8, hipMemcpyHostToDevice, s) != hipSuccess)
-            status = IPLS_ERR_HIP;
-        if (status == IPLS_OK)
-            status = ipls::engine_sort_segmented(e, arena + b.keys_off, b.pay ? (uint32_t*)(arena + b.pay_off) : nullptr,
-                                                 offs_d, nseg, b.dtype, &cfg.params, arena + b.ws_off, b.ws_bytes,
-                                                 nullptr, s);
-    }
-    const double t = now_s();
     std::lock_guard<std::mutex> g(mu);
-    for (const Request& r : rs) {
-        Request& q = reqs[r.id];
-        q.state = kDone;
-        q.status = status;
-        q.t_done = t;
-        q.batch_size = (uint32_t)nseg;
-        done_order.push_back(r.id);
-        st.completed += 1;
-        st.keys_sorted += r.n;
-    }
-    st.batches_run += 1;
-    cv_done.notify_all();
+    end_batch_locked(bid);
 }
 
 void ipls_server::lane_main(int lane) {
@@ -267,16 +303,22 @@ void ipls_server::lane_main(int lane) {
             queue.pop_front();
         }
         if (!ok) {
+            // no stream or staging buffer on this lane: the work it takes fails
             std::lock_guard<std::mutex> g(mu);
             std::vector<uint64_t> ids;
-            if (w.is_batch) ids = batches[w.id].reqs;
-            else ids.push_back((uint64_t)w.id);
+            if (w.is_batch) {
+                for (const std::vector<Request>& rs : take_batch_locked(w.id))
+                    for (const Request& r : rs) ids.push_back(r.id);
+            } else {
+                ids.push_back((uint64_t)w.id);
+            }
             for (uint64_t id : ids) {
                 reqs[id].state = kDone;
                 reqs[id].status = IPLS_ERR_HIP;
                 reqs[id].t_done = now_s();
                 done_order.push_back(id);
             }
+            if (w.is_batch) end_batch_locked(w.id);
             cv_done.notify_all();
             continue;
         }
@@ -428,8 +470,9 @@ ipls_status ipls_server_submit(ipls_server* s, uint64_t req_id, void* producer_s
     if (r.batch < 0) {
         s->queue.push_back({false, (int64_t)r.id});
     } else {
+        // a batch a lane is sorting is queued again when that lane is done with it
         Batch& b = s->batches[r.batch];
-        if (!b.queued) {
+        if (!b.queued && !b.running) {
             b.queued = true;
             s->queue.push_back({true, b.id});
         }

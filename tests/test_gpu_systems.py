@@ -142,3 +142,27 @@ def test_server_results_equal_alone_and_oracle(model):
         assert same_bits(got, want), i
         if pay is not None:
             assert np.array_equal(gpay, wpay), i
+
+
+def test_server_wait_before_the_rest_of_a_batch_is_submitted():
+    # reserve three small requests (one batch), submit only the first, wait on it: the lane takes
+    # the submitted slot alone; the others run once submitted, and every result is its own sort
+    cfg = ipls.server_config(ipls.default_params(), lanes=1, batch_max_keys=1 << 16, batch_keys=1 << 18)
+    xs = [gen.make("normal", n, 70 + i) for i, n in enumerate((5000, 3000, 7000))]
+    arena = torch.empty(64 << 20, dtype=torch.uint8, device="cuda:0")
+    print("server partial batch", [x.size for x in xs], flush=True)
+    with ipls.Server(arena, cfg) as srv:
+        got = [srv.reserve(x.size, ipls.F64) for x in xs]
+        for (rid, kv, _), x in zip(got, xs):
+            _fill(kv, x)
+        srv.submit(got[0][0])
+        i0 = srv.wait(got[0][0])
+        assert i0["status"] == 0 and i0["batch_size"] == 1
+        srv.submit(got[2][0])
+        srv.submit(got[1][0])
+        i1, i2 = srv.wait(got[1][0]), srv.wait(got[2][0])
+        assert i1["status"] == 0 and i2["status"] == 0
+        for (rid, kv, _), x in zip(got, xs):
+            want, _, _ = oracle.sort(x, None, oracle.params())
+            assert same_bits(_read(kv, np.float64), want)
+            srv.release(rid)
