@@ -260,3 +260,31 @@ def test_segmented_many_items():
     assert same_bits(host(kd, keys.dtype), want)
     assert np.array_equal(host(pd, np.uint32), wpay)
     assert (st["passes"], st["levels"]) == (ost["passes"], ost["max_level"]), (st, ost)
+
+
+def test_decreasing_segment_offsets_set_the_device_error_word():
+    # the offsets check runs on the device (the library never reads the offsets on the host): a
+    # segment whose end is below its start sets the error word, no kernel writes a key, the call
+    # returns IPLS_ERR_DEVICE and ipls_stream_status reports it; the same context then sorts a
+    # valid batch exactly as the oracle does
+    import ctypes as C
+
+    keys = gen.make("normal", 20_000, 33)
+    off = np.array([0, 5000, 3000, 20_000], dtype=np.uint64)
+    print(f"case decreasing offsets {off.tolist()}", flush=True)
+    kd, od = dev(keys), dev(off)
+    stream = torch.cuda.current_stream()
+    lib = ipls.load()
+    rc = lib.ipls_sort_segmented(C.c_void_p(kd.data_ptr()), None, C.c_void_p(od.data_ptr()), off.size - 1,
+                                 ipls.F64, None, None, C.c_void_p(stream.cuda_stream))
+    torch.cuda.synchronize()
+    assert rc == 5  # IPLS_ERR_DEVICE
+    assert lib.ipls_stream_status(C.c_void_p(stream.cuda_stream)) == 5
+    assert same_bits(host(kd, keys.dtype), keys)  # nothing was moved
+    good = np.array([0, 3000, 5000, 20_000], dtype=np.uint64)
+    od = dev(good)
+    ipls.sort_segmented_(kd, od)
+    torch.cuda.synchronize()
+    assert lib.ipls_stream_status(C.c_void_p(stream.cuda_stream)) == 0
+    want, _, _ = oracle.sort_segmented(keys, good, None, oracle_params())
+    assert same_bits(host(kd, keys.dtype), want)
