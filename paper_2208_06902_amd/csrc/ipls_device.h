@@ -236,7 +236,9 @@ __device__ __host__ inline uint64_t sample_size(uint64_t n, uint64_t div, uint64
         if (s < smin) s = smin;
         if (s > (n + 1) / 2) s = (n + 1) / 2;
     } else {
-        s = (n + div - 1) / div;
+        // ceil(n / div); in 32 bits when it fits (the same quotient, far fewer instructions)
+        const uint64_t t = n + div - 1;
+        s = (t >> 32) == 0 ? (uint64_t)((uint32_t)t / (uint32_t)div) : t / div;
         if (s < smin) s = smin;
     }
     if (smax && s > smax) s = smax;
@@ -248,24 +250,23 @@ __device__ __host__ inline uint64_t sample_size(uint64_t n, uint64_t div, uint64
 // Clamped linear model (Linear Models section): comparing t is the same as comparing floor(t)
 // with 0 and K; a NaN t (NaN key) goes to the end its sign gives.  One explicit fp64 fma.
 __device__ inline uint32_t classify_linear(double a, double b, uint32_t K, double v, bool neg) {
-    double t = __builtin_fma(a, v, b);
-    if (t != t) return neg ? 0u : K - 1u;
-    if (t < 0.0) return 0u;
-    if (t >= (double)K) return K - 1u;
-    return (uint32_t)t;
+    // straight-line form of: t < 0 -> 0; t >= K -> K - 1; else floor(t) (t in [K - 1, K) floors to
+    // K - 1, so clamping t to [0, K - 1] first gives the same bucket); a NaN t (a NaN key) -> the
+    // end its sign bit names.  fmax returns 0 for a NaN t, so the conversion is always in range.
+    const double t = __builtin_fma(a, v, b);
+    const uint32_t c = (uint32_t)__builtin_fmin(__builtin_fmax(t, 0.0), (double)(K - 1u));
+    return t == t ? c : (neg ? 0u : K - 1u);
 }
 
 // Two-level model: root routes to a leaf, the leaf's line is clipped to its envelope [LO, HI].
 __device__ inline uint32_t classify_l2pl(double ra, double rb, uint32_t M, const double* leaf, uint32_t K, double v,
                                          bool neg) {
-    if (v != v) return neg ? 0u : K - 1u;
+    // leaf from the root line (a NaN key reads the last leaf and is sent to its end below), then
+    // the leaf's line clamped to its envelope [q[2], q[3]], then the bucket as classify_linear
     const double* q = leaf + 4 * classify_linear(ra, rb, M, v, false);
-    double t = __builtin_fma(q[0], v, q[1]);
-    if (t < q[2]) t = q[2];
-    if (t > q[3]) t = q[3];
-    if (t < 0.0) return 0u;
-    if (t >= (double)K) return K - 1u;
-    return (uint32_t)t;
+    const double t = __builtin_fmin(__builtin_fmax(__builtin_fma(q[0], v, q[1]), q[2]), q[3]);
+    const uint32_t c = (uint32_t)__builtin_fmin(__builtin_fmax(t, 0.0), (double)(K - 1u));
+    return v == v ? c : (neg ? 0u : K - 1u);
 }
 
 // Equality buckets (IPS4o's): with heavy values h_0 < ... < h_(E-1) a key goes to
@@ -452,6 +453,37 @@ __device__ inline uint64_t block_append(int ch, uint64_t keys, AppendScratch& sc
     uint32_t woff = 0;
     for (uint32_t w = 0; w < wave; ++w) woff += sc.wc[ch][w];
     return sc.gbase[ch] + woff + local;
+}
+
+// As block_append, with the workgroup's own counters in LDS (lc: one per class, lkeys: keys of
+// base-case buckets): returns the entry's rank among the workgroup's entries of its class so far.
+// The workgroup adds its totals to the device counters once, after all its items.
+__device__ inline uint32_t block_append_local(int ch, uint64_t keys, AppendScratch& sc, uint32_t* lc,
+                                              unsigned long long* lkeys) {
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
+    uint32_t local = 0;
+    for (int c = 0; c <= kBaseClasses; ++c) {
+        const uint64_t m = __ballot(ch == c);
+        if (lane == 0) sc.wc[c][wave] = (uint32_t)__popcll(m);
+        if (ch == c) local = count_below(m);
+    }
+    uint64_t v = ch > 0 ? keys : 0;
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, kWave);
+    __syncthreads();
+    if (lane == 0 && v) atomicAdd(lkeys, (unsigned long long)v);
+    if (threadIdx.x <= (uint32_t)kBaseClasses) {
+        const int c = threadIdx.x;
+        uint32_t tot = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) tot += sc.wc[c][w];
+        sc.gbase[c] = lc[c];
+        lc[c] += tot;
+    }
+    __syncthreads();
+    if (ch < 0) return 0;
+    uint32_t woff = 0;
+    for (uint32_t w = 0; w < wave; ++w) woff += sc.wc[ch][w];
+    return (uint32_t)sc.gbase[ch] + woff + local;
 }
 
 // Inclusive max over the block of int values (blockDim.x a multiple of 64, at most 1024 threads);

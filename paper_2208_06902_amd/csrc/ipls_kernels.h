@@ -34,16 +34,18 @@ struct LevelArgs {
 // previous level and resets the counters the coming level appends to.
 // One item's share of a level: {chunks, tiles, sample keys, fit chunks, keys, keys with an
 // inherited line, 1 if its chunk scan takes a workgroup per bucket}.
+// The tile, chunk and fit-chunk sizes are powers of two (the host checks): shifts, not divisions.
 __device__ inline void plan_item(const Item& it, const Child* prev_children, const LevelArgs& A, uint64_t (&w)[7]) {
     const uint64_t n = it.n;
-    const uint64_t nt = (n + A.tile_keys - 1) / A.tile_keys;
-    const uint64_t nc = (nt + A.chunk - 1) / A.chunk;
+    const uint32_t ts = __builtin_ctz(A.tile_keys), cs = __builtin_ctz(A.chunk), fs = __builtin_ctz(A.fit_chunk);
+    const uint64_t nt = (n + A.tile_keys - 1) >> ts;
+    const uint64_t nc = (nt + A.chunk - 1) >> cs;
     const uint64_t ns = (it.inh && prev_children) ? prev_children[it.inh - 1].s_len
                                                   : sample_size(n, A.div, A.smin, A.smax, A.policy, A.K);
     w[0] = nc;
     w[1] = nt;
     w[2] = ns;
-    w[3] = ns > A.small_S ? (ns + A.fit_chunk - 1) / A.fit_chunk : 0;
+    w[3] = ns > A.small_S ? (ns + A.fit_chunk - 1) >> fs : 0;
     w[4] = n;
     w[5] = (it.inh && prev_children) ? n : 0;
     w[6] = nc > kScanSerial ? 1 : 0;
@@ -62,6 +64,8 @@ __global__ __launch_bounds__(256) void k_plan(const Item* items, uint64_t* cnt, 
     constexpr int kPlanWords = (int)(sizeof(Plan) / 8);
     static_assert(sizeof(Plan) % 8 == 0 && offsetof(Plan, seq) == sizeof(Plan) - 8, "seq is the plan's last word");
     __shared__ uint64_t s_plan[kPlanWords];
+    constexpr int kPlanIPT = 8;  // consecutive items per thread and round
+    __shared__ uint4 s_w[kPlanIPT][256];  // an item's chunks, tiles, samples, fit chunks (first pass)
     if (threadIdx.x < (uint32_t)C_N) s_cnt[threadIdx.x] = cnt[threadIdx.x];
     if (threadIdx.x == 0) { s_max[0] = s_max[1] = s_max[2] = s_max[3] = 0; }
     __syncthreads();
@@ -74,9 +78,9 @@ __global__ __launch_bounds__(256) void k_plan(const Item* items, uint64_t* cnt, 
     }
     uint64_t run_t = 0, run_s = 0, run_f = 0, run_c = 0, run_w = 0, sum_n = 0, sum_inh = 0;
     const uint64_t use = num < item_cap ? num : item_cap;
-    // kPlanIPT consecutive items per thread: a pass for the thread's sums, one block scan, then a
-    // pass that writes the item's offsets (levels of many items take few block scans)
-    constexpr int kPlanIPT = 8;
+    // kPlanIPT consecutive items per thread: a pass for the thread's sums (which keeps each item's
+    // figures in LDS), one block scan, then a pass that writes the item's offsets (levels of many
+    // items take few block scans)
     for (uint64_t base = 0; base < use; base += (uint64_t)blockDim.x * kPlanIPT) {
         const uint64_t i0 = base + (uint64_t)threadIdx.x * kPlanIPT;
         uint64_t v[7] = {0, 0, 0, 0, 0, 0, 0}, mS = 0, mN = 0;
@@ -89,6 +93,8 @@ __global__ __launch_bounds__(256) void k_plan(const Item* items, uint64_t* cnt, 
                 for (int j = 0; j < 7; ++j) v[j] += w[j];
                 mS = w[2] > mS ? w[2] : mS;
                 mN = w[4] > mN ? w[4] : mN;
+                // each fits 32 bits: an item has fewer than 2^44 keys, its sample fewer than 2^32
+                s_w[k][threadIdx.x] = make_uint4((uint32_t)w[0], (uint32_t)w[1], (uint32_t)w[2], (uint32_t)w[3]);
             }
         }
         // maxima: one LDS atomic per wave
@@ -105,8 +111,8 @@ __global__ __launch_bounds__(256) void k_plan(const Item* items, uint64_t* cnt, 
         for (int k = 0; k < kPlanIPT; ++k) {
             const uint64_t i = i0 + k;
             if (i >= use) break;
-            uint64_t w[7];
-            plan_item(items[i], prev_children, A, w);
+            const uint4 q = s_w[k][threadIdx.x];
+            const uint64_t w[7] = {q.x, q.y, q.z, q.w, 0, 0, q.x > kScanSerial ? 1u : 0u};
             chunk_off[i] = at_c;
             tile_off[i] = at_t;
             sample_off[i] = at_s;
@@ -1115,7 +1121,7 @@ constexpr int kChunk = 8;
 
 // Wave-level counting of one tile's keys: wave w owns keys [w * 64 * IPT, (w+1) * 64 * IPT) of the
 // tile, row r = 64 consecutive keys.  Lanes of a row holding the same bucket are found with 8
-// ballots on the bucket bits; the row's leader lane adds their number to the wave's LDS counter of
+// ballots on the bucket bits (four vector instructions a bit); the row's leader lane adds their number to the wave's LDS counter of
 // that bucket with an atomic that returns the previous count.  LDS executes a wave's operations in
 // order, so the 16 rows' atomics are issued back to back and each returns the count of the wave's
 // earlier rows; the leaders' values are then broadcast to their lanes.  rk (when RANKS) receives
@@ -1125,22 +1131,26 @@ template <int IPT, bool RANKS>
 __device__ inline void wave_count(const uint32_t (&bk)[IPT], uint32_t tn, uint32_t wbase, uint32_t* wc,
                                   uint32_t (&rk)[IPT]) {
     const uint32_t lane = lane_id();
+    const bool full = wbase + (uint32_t)(IPT * kWave) <= tn;  // the same for the whole wave
     uint32_t prev[IPT], lead[IPT], below[IPT];
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
-        const bool valid = wbase + r * kWave + lane < tn;
+        const bool valid = full || wbase + r * kWave + lane < tn;
         const uint32_t b = bk[r];
-        const uint64_t vm = __ballot(valid);
-        uint32_t same_lo = (uint32_t)vm, same_hi = (uint32_t)(vm >> 32);
+        // diff: lanes whose bucket differs from this lane's in some bit (or that hold no key).
+        // Per bit: m = 0 or ~0 from this lane's bit, ones = the lanes with the bit set, and
+        // diff |= ones ^ m in one three-input logic op (truth table 0xF6 over (diff, ones, m)).
+        const uint64_t vm = full ? ~0ull : __ballot(valid);
+        uint32_t diff_lo = ~(uint32_t)vm, diff_hi = ~(uint32_t)(vm >> 32);
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
-            // m = 0 or ~0 from this lane's bit; lanes agreeing with it: ~(ballot ^ m)
-            const uint32_t m = (uint32_t)(((int32_t)(b << (31 - bit))) >> 31);
+            uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)b, (uint32_t)bit, 1u);
+            asm("" : "+v"(m));  // keeps the compare on m: one bit extract serves both uses
             const uint64_t ones = __ballot(m != 0u);
-            same_lo &= ~((uint32_t)ones ^ m);
-            same_hi &= ~((uint32_t)(ones >> 32) ^ m);
+            diff_lo = __builtin_amdgcn_bitop3_b32(diff_lo, (uint32_t)ones, m, 0xF6);
+            diff_hi = __builtin_amdgcn_bitop3_b32(diff_hi, (uint32_t)(ones >> 32), m, 0xF6);
         }
-        const uint64_t same = ((uint64_t)same_hi << 32) | same_lo;
+        const uint64_t same = ~(((uint64_t)diff_hi << 32) | diff_lo);
         below[r] = count_below(same);
         lead[r] = valid ? (uint32_t)(__ffsll((unsigned long long)same) - 1) : lane;
         prev[r] = 0;
@@ -1161,32 +1171,74 @@ template <int DT, bool PAY, int IPT>
 __device__ inline void load_tile(const typename Key<DT>::T* src, const uint32_t* src_pay, uint64_t base, uint32_t tn,
                                  uint32_t wbase, typename Key<DT>::T (&k)[IPT], uint32_t (&p)[PAY ? IPT : 1]) {
     const uint32_t lane = lane_id();
+    // streamed once: non-temporal loads (non-temporal stores measured slower: the scatter's
+    // partial-line runs need the L2 to combine them).  Lanes past the tile's end get key 0.
+    if (wbase + (uint32_t)(IPT * kWave) <= tn) {
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            k[r] = __builtin_nontemporal_load(&src[base + wbase + r * kWave + lane]);
+            if (PAY) p[r] = __builtin_nontemporal_load(&src_pay[base + wbase + r * kWave + lane]);
+        }
+        return;
+    }
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
         const uint32_t idx = wbase + r * kWave + lane;
+        k[r] = 0;
+        if (PAY) p[r] = 0u;
         if (idx < tn) {
-            // streamed once: non-temporal loads (non-temporal stores measured slower: the
-            // scatter's partial-line runs need the L2 to combine them)
             k[r] = __builtin_nontemporal_load(&src[base + idx]);
             if (PAY) p[r] = __builtin_nontemporal_load(&src_pay[base + idx]);
         }
     }
 }
 
+// Calls f(r, bucket) for every row r of a tile's keys held by this thread.  The model's kind is the
+// same for every key of the tile, so it is dispatched once and each kind's row loop is
+// straight-line code.  Keys past the tile's end are classified too (every classifier reads only
+// its own tables); f masks them.
+template <int DT, int IPT, class F>
+__device__ inline void classify_rows(const Model& m, const double* leaf, uint32_t K, uint32_t M,
+                                     const typename Key<DT>::T (&k)[IPT], F&& f) {
+    using KT = Key<DT>;
+    switch (m.kind) {
+        case kKindClosedMove:
+#pragma unroll
+            for (int r = 0; r < IPT; ++r) f(r, 0u);
+            break;
+        case kKindDigit:
+#pragma unroll
+            for (int r = 0; r < IPT; ++r) f(r, (uint32_t)((KT::ord(k[r]) - m.umin) >> m.shift));
+            break;
+        case kKindTree:
+#pragma unroll
+            for (int r = 0; r < IPT; ++r) f(r, classify_tree((const uint64_t*)leaf, K, KT::ord(k[r]), m.shift != 0));
+            break;
+        case kKindL2pl:
+#pragma unroll
+            for (int r = 0; r < IPT; ++r) f(r, classify_l2pl(m.a, m.b, M, leaf, K, KT::val(k[r]), KT::neg(k[r])));
+            break;
+        default:
+            if (m.neq) {
+#pragma unroll
+                for (int r = 0; r < IPT; ++r) f(r, classify_equality<DT>(m, k[r]));
+            } else {
+#pragma unroll
+                for (int r = 0; r < IPT; ++r) f(r, classify_linear(m.a, m.b, K, KT::val(k[r]), KT::neg(k[r])));
+            }
+            break;
+    }
+}
+
+// The buckets of a tile's keys (0 for lanes past the tile's end).
 template <int DT, int IPT>
 __device__ inline void classify_tile(uint32_t tn, uint32_t wbase, const Model& m, const double* leaf, uint32_t K,
                                      uint32_t M, const typename Key<DT>::T (&k)[IPT], uint32_t (&bk)[IPT]) {
     const uint32_t lane = lane_id();
-    if (m.kind == kKindClosedMove) {
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) bk[r] = 0u;
-        return;
-    }
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const uint32_t idx = wbase + r * kWave + lane;
-        bk[r] = idx < tn ? classify_key<DT>(m, leaf, K, M, k[r]) : 0u;
-    }
+    const bool full = wbase + (uint32_t)(IPT * kWave) <= tn;
+    classify_rows<DT, IPT>(m, leaf, K, M, k, [&](int r, uint32_t b) {
+        bk[r] = (full || wbase + r * kWave + lane < tn) ? b : 0u;
+    });
 }
 
 // ------------------------------------------------------------------ classify + histogram
@@ -1194,7 +1246,7 @@ __device__ inline void classify_tile(uint32_t tn, uint32_t wbase, const Model& m
 // tile's exclusive prefix inside the chunk (tile_pref[t][b]); at the end the chunk's totals
 // (chunk_sum[c][b]).
 template <int DT, int NW, int IPT>
-__global__ __launch_bounds__(64 * NW) void k_classify_hist(const Item* items, const uint64_t* tile_off,
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(6))) void k_classify_hist(const Item* items, const uint64_t* tile_off,
                                                        const uint64_t* chunk_off, const uint32_t* chunk_map,
                                                        uint64_t total_chunks, const Model* models,
                                                        const double* leaves, const typename Key<DT>::T* src,
@@ -1261,10 +1313,10 @@ __global__ __launch_bounds__(64 * NW) void k_classify_hist(const Item* items, co
         if (counting && t + 1 < t_end)
             load_tile<DT, false, IPT>(src, nullptr, it.lo + (t + 1 - t0) * TILE, tile_n(t + 1), wbase, nxt, nop);
         if (counting) {
-#pragma unroll
-            for (int r = 0; r < IPT; ++r)
-                if (wbase + r * kWave + lane_id() < tn)
-                    atomicAdd(&h[q][classify_key<DT>(m, s_leaf, K, M, cur[r])], 1u);
+            const uint32_t lane = lane_id();
+            classify_rows<DT, IPT>(m, s_leaf, K, M, cur, [&](int r, uint32_t b) {
+                if (wbase + r * kWave + lane < tn) atomicAdd(&h[q][b], 1u);
+            });
         } else if (m.kind == kKindClosedMove && tid == 0) {
             h[q][0] = tn;
         }
@@ -1383,7 +1435,6 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(CLS && 
     using KT = Key<DT>;
     constexpr int NT = kWave * NW, TILE = NT * IPT;
     __shared__ uint32_t s_wcnt[NW][kMaxBuckets];
-    __shared__ uint32_t s_loc[kMaxBuckets];
     __shared__ uint64_t s_base[kMaxBuckets];
     __shared__ uint64_t s_scan[16];
     // The two-level model's leaves (or the children's lines) are only read by the classification,
@@ -1463,8 +1514,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(CLS && 
     uint64_t tot;
     const uint32_t loc = (uint32_t)block_exclusive_sum<uint64_t>(cnt, s_scan, &tot);
     if (b < K) {
-        s_loc[b] = loc;
-        s_base[b] = dbase - loc;
+        // each wave's first slot of bucket b in the staging buffer: one LDS read per key below
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s_wcnt[w][b] += loc;
+        // keys only: the destination address of the bucket's staging slot 0 (one add per key below)
+        s_base[b] = (!PAY && !CLS) ? (uint64_t)(uintptr_t)(dst + (dbase - loc)) : dbase - loc;
     }
     __syncthreads();
 
@@ -1472,7 +1526,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(CLS && 
     for (int r = 0; r < IPT; ++r) {
         const uint32_t idx = wbase + r * kWave + lane;
         if (idx < tn) {
-            const uint32_t pos = s_loc[bk[r]] + s_wcnt[wave][bk[r]] + rk[r];
+            const uint32_t pos = s_wcnt[wave][bk[r]] + rk[r];
             s_keys[pos] = k[r];
             s_bkt[pos] = (uint8_t)bk[r];
             if (CLS) s_cls[pos] = (uint8_t)cc[r];
@@ -1485,6 +1539,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(CLS && 
         const uint32_t j = tid + r * NT;
         if (j < tn) {
             const uint32_t bj = s_bkt[j];
+            if constexpr (!PAY && !CLS) {
+                ((T*)(uintptr_t)s_base[bj])[j] = s_keys[j];
+                continue;
+            }
             const uint64_t d = s_base[bj] + j;
             dst[d] = s_keys[j];
             if (PAY) dst_pay[d] = s_pay[j];
@@ -1502,104 +1560,142 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(CLS && 
 // same result.  Inside a run, bucket b joins group floor(p_b / (T/2)) (p_b: the keys of the run
 // before it), so a group holds fewer than T keys; the group's first bucket emits it.  A group of
 // a single key already in the caller's buffer needs no work.
+template <int IPW>
 __global__ __launch_bounds__(256) void k_worklist(const Item* items, uint64_t num_items, const Model* models,
                                                   const uint64_t* hist, const uint64_t* bstart, uint32_t K, uint32_t T,
                                                   int dst_is_scratch, Item* next, BaseItem* base, BaseLayout bl,
                                                   uint64_t* cnt, int next_slot, uint64_t next_cap, CopyItem* copy,
                                                   uint64_t copy_cap, const ChildSpan* spans, const Child* children,
                                                   uint64_t* l1max) {
+    // IPW items per workgroup: each item's entries are ranked among the workgroup's entries of
+    // their class in LDS, then the workgroup reserves its ranges with one device atomic per class
+    // (one per item made a level of thousands of items wait on the same few counters) and writes.
     __shared__ AppendScratch sc;
     __shared__ int s_ent[kMaxBuckets];  // bucket -> its entry in the child list with a usable line, or -1
     __shared__ uint64_t s_e[kMaxBuckets], s_p[kMaxBuckets], s_sum[kMaxBuckets];
     __shared__ uint64_t s_scan[16];
     __shared__ int s_iscan[16];
     __shared__ int s_prev[kMaxBuckets + 1];
-    const uint64_t i = blockIdx.x;
+    __shared__ uint32_t s_lc[kBaseClasses + 1];
+    __shared__ unsigned long long s_lkeys;
+    __shared__ uint64_t s_gb[kBaseClasses + 1];
+    __shared__ uint64_t s_n[IPW][kMaxBuckets];     // an entry's keys
+    __shared__ uint32_t s_rank[IPW][kMaxBuckets];  // its rank in its class, 4 bits of class + 1 above
+    __shared__ int s_inh[IPW][kMaxBuckets];        // its child-list entry + 1 (0: none)
     const uint32_t b = threadIdx.x;
-    const ChildSpan sp = (spans && i < num_items) ? spans[i] : ChildSpan{0u, 0u};
-    if (b < kMaxBuckets) s_ent[b] = -1;
-    __syncthreads();
-    if (b < sp.count) {
-        const Child ch = children[sp.base + b];
-        if (ch.a != 0.0) s_ent[ch.c] = (int)(sp.base + b);
-    }
-    uint64_t c = 0, lo = 0, lo_rel = 0;
-    bool breaker = false;
-    if (i < num_items && b < K) {
-        const uint64_t g = i * K + b;
-        const uint32_t kind = models[i].kind;
-        if (kind != kKindClosedKeep && kind != kKindClosedMove) {
-            c = hist[g];
-            const Item it = items[i];
-            const uint64_t start = bstart[g];
-            lo = it.lo + start;
-            lo_rel = it.lo_rel + start;
-            // an equality bucket holds one value: closed here; moved back if it sits in the scratch buffer
-            const uint32_t neq = kind == kKindLinear ? models[i].neq : 0u;
-            bool is_eq = false;
-            for (uint32_t e = 0; e < neq; ++e) is_eq |= models[i].eqb[e] == b;
-            if (is_eq && c > 0) {
-                atomicAdd((unsigned long long*)&cnt[C_EQCLOSED], 1ull);
-                if (dst_is_scratch) {
-                    const uint64_t q = atomicAdd((unsigned long long*)&cnt[C_COPY], 1ull);
-                    if (q < copy_cap) copy[q] = CopyItem{lo, c};
-                    atomicAdd((unsigned long long*)&cnt[C_COPYKEYS], (unsigned long long)c);
+    if (b <= (uint32_t)kBaseClasses) s_lc[b] = 0;
+    if (b == 0) s_lkeys = 0;
+    const uint64_t i0 = (uint64_t)blockIdx.x * IPW;
+    for (int j = 0; j < IPW; ++j) {
+        const uint64_t i = i0 + j;
+        if (i >= num_items) break;  // the same for the whole workgroup
+        const ChildSpan sp = spans ? spans[i] : ChildSpan{0u, 0u};
+        if (b < kMaxBuckets) s_ent[b] = -1;
+        __syncthreads();
+        if (b < sp.count) {
+            const Child ch = children[sp.base + b];
+            if (ch.a != 0.0) s_ent[ch.c] = (int)(sp.base + b);
+        }
+        uint64_t c = 0, lo = 0;
+        bool breaker = false;
+        if (b < K) {
+            const uint64_t g = i * K + b;
+            const uint32_t kind = models[i].kind;
+            if (kind != kKindClosedKeep && kind != kKindClosedMove) {
+                c = hist[g];
+                lo = items[i].lo + bstart[g];
+                // an equality bucket holds one value: closed here; moved back if it sits in the scratch buffer
+                const uint32_t neq = kind == kKindLinear ? models[i].neq : 0u;
+                bool is_eq = false;
+                for (uint32_t e = 0; e < neq; ++e) is_eq |= models[i].eqb[e] == b;
+                if (is_eq && c > 0) {
+                    atomicAdd((unsigned long long*)&cnt[C_EQCLOSED], 1ull);
+                    if (dst_is_scratch) {
+                        const uint64_t q = atomicAdd((unsigned long long*)&cnt[C_COPY], 1ull);
+                        if (q < copy_cap) copy[q] = CopyItem{lo, c};
+                        atomicAdd((unsigned long long*)&cnt[C_COPYKEYS], (unsigned long long)c);
+                    }
+                    c = 0;  // neither an item nor a base-case bucket
+                    breaker = true;
                 }
-                c = 0;  // neither an item nor a base-case bucket
-                breaker = true;
             }
         }
-    }
-    if (l1max) {  // the first level of a single array: its largest bucket, for the statistics
-        __shared__ uint64_t s_mx[kBlock / kWave];
-        const uint64_t h = wave_max<uint64_t>((i < num_items && b < K) ? hist[i * K + b] : 0);
-        if (lane_id() == 0) s_mx[b / kWave] = h;
-        __syncthreads();
-        if (b == 0) {
-            uint64_t mx = 0;
-            for (uint32_t w = 0; w < blockDim.x / kWave; ++w) mx = s_mx[w] > mx ? s_mx[w] : mx;
-            *l1max = mx;
+        if (l1max) {  // the first level of a single array: its largest bucket, for the statistics
+            __shared__ uint64_t s_mx[kBlock / kWave];
+            const uint64_t h = wave_max<uint64_t>(b < K ? hist[i * K + b] : 0);
+            if (lane_id() == 0) s_mx[b / kWave] = h;
+            __syncthreads();
+            if (b == 0) {
+                uint64_t mx = 0;
+                for (uint32_t w = 0; w < blockDim.x / kWave; ++w) mx = s_mx[w] > mx ? s_mx[w] : mx;
+                *l1max = mx;
+            }
         }
+        const uint64_t half = T / 2 > 0 ? T / 2 : 1;
+        const bool small = c >= 1 && c <= half;
+        breaker = breaker || c > half;
+        // runs of small buckets: run start = one past the last breaker before b
+        const int last_break = block_inclusive_max(breaker ? (int)b : -1, s_iscan);
+        const uint32_t run_start = (uint32_t)(last_break + 1);  // for a breaker itself: b + 1 (unused)
+        uint64_t tot;
+        const uint64_t e = block_exclusive_sum<uint64_t>(small ? c : 0, s_scan, &tot);
+        s_e[b] = e;
+        __syncthreads();
+        const uint64_t p = small ? e - s_e[run_start < blockDim.x ? run_start : b] : 0;
+        s_p[b] = p;
+        s_sum[b] = 0;
+        // the small bucket before b: the inclusive max of thread b - 1, passed through LDS
+        const int prev_small = block_inclusive_max(small ? (int)b : -1, s_iscan);
+        s_prev[b + 1] = prev_small;
+        if (b == 0) s_prev[0] = -1;
+        __syncthreads();
+        const int ps = s_prev[b];
+        const bool leader = small && (ps < (int)run_start || s_p[ps] / half != p / half);
+        const int lead = block_inclusive_max(leader ? (int)b : -1, s_iscan);
+        if (small) atomicAdd((unsigned long long*)&s_sum[lead], (unsigned long long)c);
+        __syncthreads();
+        int ch = -1;
+        uint64_t n = 0;
+        if (c > T) {
+            ch = 0;
+            n = c;
+        } else if (c > half) {
+            n = c;
+            ch = 1 + base_class((uint32_t)c);
+        } else if (leader) {
+            n = s_sum[b];
+            if (n >= 2 || dst_is_scratch) ch = 1 + base_class((uint32_t)n);
+        }
+        const uint32_t r = block_append_local(ch, n, sc, s_lc, &s_lkeys);
+        s_n[j][b] = n;
+        s_rank[j][b] = ch < 0 ? 0u : ((r << 4) | (uint32_t)(ch + 1));
+        s_inh[j][b] = s_ent[b] + 1;
+        (void)lo;
+        __syncthreads();
     }
-    const uint64_t half = T / 2 > 0 ? T / 2 : 1;
-    const bool small = c >= 1 && c <= half;
-    breaker = breaker || c > half;
-    // runs of small buckets: run start = one past the last breaker before b
-    const int last_break = block_inclusive_max(breaker ? (int)b : -1, s_iscan);
-    const uint32_t run_start = (uint32_t)(last_break + 1);  // for a breaker itself: b + 1 (unused)
-    uint64_t tot;
-    const uint64_t e = block_exclusive_sum<uint64_t>(small ? c : 0, s_scan, &tot);
-    s_e[b] = e;
-    __syncthreads();
-    const uint64_t p = small ? e - s_e[run_start < blockDim.x ? run_start : b] : 0;
-    s_p[b] = p;
-    s_sum[b] = 0;
-    // the small bucket before b: the inclusive max of thread b - 1, passed through LDS
-    const int prev_small = block_inclusive_max(small ? (int)b : -1, s_iscan);
-    s_prev[b + 1] = prev_small;
-    if (b == 0) s_prev[0] = -1;
-    __syncthreads();
-    const int ps = s_prev[b];
-    const bool leader = small && (ps < (int)run_start || s_p[ps] / half != p / half);
-    const int lead = block_inclusive_max(leader ? (int)b : -1, s_iscan);
-    if (small) atomicAdd((unsigned long long*)&s_sum[lead], (unsigned long long)c);
-    __syncthreads();
-    int ch = -1;
-    uint64_t n = 0;
-    if (c > T) {
-        ch = 0;
-        n = c;
-    } else if (c > half) {
-        n = c;
-        ch = 1 + base_class((uint32_t)c);
-    } else if (leader) {
-        n = s_sum[b];
-        if (n >= 2 || dst_is_scratch) ch = 1 + base_class((uint32_t)n);
+    // the workgroup's ranges: one device atomic per class, one for the base-case keys
+    if (b <= (uint32_t)kBaseClasses) {
+        uint64_t* ctr = b == 0 ? &cnt[next_slot] : &cnt[C_CLS + b - 1];
+        s_gb[b] = s_lc[b] ? atomicAdd((unsigned long long*)ctr, (unsigned long long)s_lc[b]) : 0;
     }
-    const int cls = ch > 0 ? ch - 1 : 0;
-    const uint64_t q = block_append(ch, n, sc, &cnt[next_slot], &cnt[C_CLS], &cnt[C_BASEKEYS]);
-    if (ch == 0 && q < next_cap) next[q] = Item{lo, n, lo_rel, (uint64_t)(s_ent[b] + 1)};
-    if (ch > 0 && q < bl.cap[cls]) base[bl.off[cls] + q] = BaseItem{lo, (uint32_t)n, (uint32_t)dst_is_scratch};
+    if (b == 0 && s_lkeys) atomicAdd((unsigned long long*)&cnt[C_BASEKEYS], s_lkeys);
+    __syncthreads();
+    if (b >= K) return;
+    for (int j = 0; j < IPW; ++j) {
+        const uint64_t i = i0 + j;
+        if (i >= num_items) break;
+        const uint32_t rk = s_rank[j][b];
+        if (rk == 0) continue;
+        const int ch = (int)(rk & 15u) - 1;
+        const uint64_t q = s_gb[ch] + (rk >> 4);
+        const uint64_t g = i * K + b;
+        const Item it = items[i];
+        const uint64_t lo = it.lo + bstart[g];
+        const uint64_t n = s_n[j][b];
+        const int cls = ch > 0 ? ch - 1 : 0;
+        if (ch == 0 && q < next_cap) next[q] = Item{lo, n, it.lo_rel + bstart[g], (uint64_t)s_inh[j][b]};
+        if (ch > 0 && q < bl.cap[cls]) base[bl.off[cls] + q] = BaseItem{lo, (uint32_t)n, (uint32_t)dst_is_scratch};
+    }
 }
 
 // Equality buckets a level wrote to the scratch buffer move back to the caller's buffer: every key
@@ -1624,778 +1720,7 @@ __global__ __launch_bounds__(256) void k_copy(const CopyItem* copy, const uint64
     }
 }
 
-// ------------------------------------------------------------------ base case
-// Buckets of <= T keys are sorted by ord and written into the caller's buffer (the paper's base
-// case below 2^12 keys, Proposed Algorithm).  A group of NT threads sorts one bucket of up to
-// 16 NT keys; 256 / NT buckets share a workgroup.
-//   1. every thread sorts 16 keys in registers with a bitonic network;
-//   2. log2(NT) rounds merge pairs of sorted runs through LDS.  A thread finds where its 16
-//      outputs start in the two runs with a merge-path search, loads the next 16 keys of each
-//      run (independent loads), keeps the 16 smallest with one compare-exchange stage (their
-//      sequence is bitonic) and sorts them with a 4-stage bitonic merge.
-// With a payload every key carries its current position and compares as (ord, position); the
-// left run's keys come first on ties, which is exactly the stable order.
-// LDS index with one pad slot every 16 elements, so that a thread's 16 consecutive elements start
-// in different banks.
-__device__ inline int pad16(int j) { return j + (j >> 4); }
-
-template <bool PAY, typename O>
-__device__ inline bool key_less(O ka, uint32_t ia, O kb, uint32_t ib) {
-    return PAY ? (ka < kb || (ka == kb && ia < ib)) : (ka < kb);
-}
-
-// compare-exchange: afterwards (a, b) is in ascending (up) or descending order
-template <bool PAY, typename O>
-__device__ inline void cex(O& ka, O& kb, uint32_t& ia, uint32_t& ib, uint32_t& pa, uint32_t& pb, bool up) {
-    const bool sw = up ? key_less<PAY>(kb, ib, ka, ia) : key_less<PAY>(ka, ia, kb, ib);
-    const O k0 = sw ? kb : ka, k1 = sw ? ka : kb;
-    ka = k0;
-    kb = k1;
-    if (PAY) {
-        const uint32_t i0 = sw ? ib : ia, i1 = sw ? ia : ib, p0 = sw ? pb : pa, p1 = sw ? pa : pb;
-        ia = i0;
-        ib = i1;
-        pa = p0;
-        pb = p1;
-    }
-}
-
-// Merge sort of CAP = 16 NT keys held in LDS (pad16 layout, positions 0 .. CAP-1, padding keys
-// are kPad at the end) by NT threads t = 0 .. NT-1 of one group; the sorted keys are left in LDS.
-// Payload sorts (PAY) hold each key's original index in sp (padding slots: indices >= the bucket
-// size) and compare (ord, index), which is the stable order; the caller gathers the payloads by
-// index afterwards.  Threads of the workgroup that are not among the NT pass active = false: they
-// only take part in the barriers.
-template <typename O, bool PAY, int NT>
-__device__ inline void merge_sort_lds(O* sk, uint32_t* sp, int t_in, bool active = true) {
-    const int t = active ? t_in : 0;  // inactive threads read in bounds and write nothing
-    constexpr int IPT = 16, CAP = NT * IPT;
-    constexpr O kPad = (O)~(O)0;
-    O k[IPT];
-    uint32_t id[IPT], nop = 0;  // id: original index (payload sorts only)
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-        k[i] = sk[pad16(t * IPT + i)];
-        id[i] = PAY ? sp[pad16(t * IPT + i)] : 0u;
-    }
-    // 1: bitonic sort of the thread's 16 keys
-#pragma unroll
-    for (int kk = 2; kk <= IPT; kk <<= 1)
-#pragma unroll
-        for (int j = kk >> 1; j > 0; j >>= 1)
-#pragma unroll
-            for (int i = 0; i < IPT; ++i) {
-                const int l = i ^ j;
-                if (l > i) cex<PAY>(k[i], k[l], id[i], id[l], nop, nop, (i & kk) == 0);
-            }
-    // 2: merge rounds, runs of L keys -> 2L
-#pragma unroll 1
-    for (int L = IPT; L < CAP; L <<= 1) {
-        __syncthreads();
-        if (active) {
-#pragma unroll
-            for (int i = 0; i < IPT; ++i) {
-                sk[pad16(t * IPT + i)] = k[i];
-                if (PAY) sp[pad16(t * IPT + i)] = id[i];
-            }
-        }
-        __syncthreads();
-        const int q = (t * IPT) / (2 * L), d = t * IPT - q * 2 * L;
-        const int a0 = q * 2 * L, b0 = a0 + L;  // unpadded starts of the two runs
-        int lo = d > L ? d - L : 0, hi = d < L ? d : L;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (sk[pad16(a0 + mid)] <= sk[pad16(b0 + d - 1 - mid)]) lo = mid + 1;
-            else hi = mid;
-        }
-        const int ia = lo, ib = d - lo;
-        O xa[IPT], xb[IPT];
-        uint32_t qa[IPT], qb[IPT];
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-            xa[j] = ia + j < L ? sk[pad16(a0 + ia + j)] : kPad;
-            xb[j] = ib + j < L ? sk[pad16(b0 + ib + j)] : kPad;
-            if (PAY) {
-                // past-the-end slots get indices past every real one, so real keys win ties
-                qa[j] = ia + j < L ? sp[pad16(a0 + ia + j)] : (uint32_t)(2 * CAP + j);
-                qb[j] = ib + j < L ? sp[pad16(b0 + ib + j)] : (uint32_t)(3 * CAP + j);
-            }
-        }
-        // the 16 smallest of the two sorted windows: min(xa[j], xb[15-j]) is bitonic
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-            const uint32_t ua = PAY ? qa[j] : 0u, ub = PAY ? qb[IPT - 1 - j] : 0u;
-            const bool takeB = key_less<PAY>(xb[IPT - 1 - j], ub, xa[j], ua);
-            k[j] = takeB ? xb[IPT - 1 - j] : xa[j];
-            id[j] = takeB ? ub : ua;
-        }
-#pragma unroll
-        for (int j = IPT >> 1; j > 0; j >>= 1)
-#pragma unroll
-            for (int i = 0; i < IPT; ++i) {
-                const int l = i ^ j;
-                if (l > i) cex<PAY>(k[i], k[l], id[i], id[l], nop, nop, true);
-            }
-    }
-    __syncthreads();
-    if (active) {
-#pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-            sk[pad16(t * IPT + i)] = k[i];
-            if (PAY) sp[pad16(t * IPT + i)] = id[i];
-        }
-    }
-    __syncthreads();
-}
-
-template <int DT, bool PAY, int NT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PAY ? 3 : 1))) void k_base_sort(const BaseItem* list, uint64_t count, typename Key<DT>::T* keys,
-                                                   uint32_t* pay, const typename Key<DT>::T* skeys,
-                                                   const uint32_t* spay) {
-    using KT = Key<DT>;
-    using O = typename KT::O;
-    constexpr int IPT = 16, G = kBlock / NT, CAP = NT * IPT, PCAP = CAP + CAP / 16;
-    constexpr O kPad = (O)~(O)0;
-    __shared__ O s_k[G * PCAP];
-    __shared__ uint32_t s_p[PAY ? G * PCAP : 1];
-    const int g = threadIdx.x / NT, t = threadIdx.x % NT;
-    const uint64_t bidx = (uint64_t)blockIdx.x * G + g;
-    BaseItem bi = {0, 0, 0};
-    if (bidx < count) bi = list[bidx];
-    const uint32_t n = bi.n;
-    const typename KT::T* src = bi.from_scratch ? skeys : keys;
-    const uint32_t* psrc = bi.from_scratch ? spay : pay;
-    O* sk = s_k + g * PCAP;
-    uint32_t* sp = s_p + (PAY ? g * PCAP : 0);
-    {
-        typename KT::T v[IPT];
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            const int j = t + r * NT;
-            if (j < (int)n) v[r] = __builtin_nontemporal_load(&src[bi.lo + j]);
-        }
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            const int j = t + r * NT;
-            sk[pad16(j)] = j < (int)n ? (O)KT::ord(v[r]) : kPad;
-            if (PAY) sp[pad16(j)] = (uint32_t)j;  // original index
-        }
-    }
-    __syncthreads();
-    merge_sort_lds<O, PAY, NT>(sk, sp, t);
-    // payloads by original index, all read before any is written (the source may be the output)
-    uint32_t pv[PAY ? IPT : 1];
-    if (PAY) {
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            const int j = t + r * NT;
-            if (j < (int)n) pv[r] = psrc[bi.lo + sp[pad16(j)]];
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const int j = t + r * NT;
-        if (j < (int)n) {
-            keys[bi.lo + j] = KT::from_ord((uint64_t)sk[pad16(j)]);
-            if (PAY) pay[bi.lo + j] = pv[r];
-        }
-    }
-}
-
-// Stable counting of one digit (0..255) per key over a workgroup of NW waves, with the same
-// ballot ranking as the scatter.  Afterwards the key of wave w with digit b and rank rk among the
-// wave's earlier keys of b belongs at s_loc[b] + s_wcnt[w][b] + rk; s_cnt[b] is digit b's count.
-// Returns the largest count.
-template <int NW, int IPT>
-__device__ inline uint32_t block_count_digits(const uint32_t (&bk)[IPT], uint32_t n, uint32_t wbase,
-                                              uint32_t (*s_wcnt)[kMaxBuckets], uint32_t* s_loc, uint32_t* s_cnt,
-                                              uint64_t* s_scan, uint32_t* s_max, uint32_t (&rk)[IPT]) {
-    constexpr int NT = kWave * NW, DPT = NT >= kMaxBuckets ? 1 : kMaxBuckets / NT;  // digits per thread
-    const uint32_t tid = threadIdx.x, wave = tid / kWave;
-    for (uint32_t b = tid; b < NW * kMaxBuckets; b += NT) (&s_wcnt[0][0])[b] = 0;
-    __syncthreads();
-    wave_count<IPT, true>(bk, n, wbase, s_wcnt[wave], rk);
-    __syncthreads();
-    uint32_t tot[DPT], sum = 0, mx = 0;
-#pragma unroll
-    for (int i = 0; i < DPT; ++i) {
-        const uint32_t dg = tid * DPT + i;
-        uint32_t run = 0;
-        if (dg < (uint32_t)kMaxBuckets) {
-            for (int w = 0; w < NW; ++w) {
-                const uint32_t c = s_wcnt[w][dg];
-                s_wcnt[w][dg] = run;
-                run += c;
-            }
-        }
-        tot[i] = run;
-        sum += run;
-        mx = run > mx ? run : mx;
-    }
-    mx = wave_max(mx);
-    if (lane_id() == 0) s_max[wave] = mx;
-    uint64_t all;
-    uint32_t e = (uint32_t)block_exclusive_sum<uint64_t>(sum, s_scan, &all);  // synchronises
-#pragma unroll
-    for (int i = 0; i < DPT; ++i) {
-        const uint32_t dg = tid * DPT + i;
-        if (dg < (uint32_t)kMaxBuckets) {
-            s_loc[dg] = e;
-            s_cnt[dg] = tot[i];
-        }
-        e += tot[i];
-    }
-    mx = 0;
-    for (int w = 0; w < NW; ++w) mx = s_max[w] > mx ? s_max[w] : mx;
-    __syncthreads();
-    return mx;
-}
-
-// Stable base case (used for payload sorts) for one bucket of at most 64 NW IPT keys per workgroup
-// of NW waves (IPT keys a thread).
-// The bucket's smallest ord (min) and the low bits z that are zero in every ord - min are found
-// first; x = (ord - min) >> z keeps only the bits where the keys differ, nbits of them.
-//  * nbits <= 8: one stable counting pass on x sorts the bucket.
-//  * otherwise a stable counting pass on the top 8 bits of x splits it into 256 ordered
-//    sub-buckets (an MSD radix step, as SkaSort starts); each key's final place is its
-//    sub-bucket's start plus the number of keys of its sub-bucket that precede it in (ord,
-//    position) order.  A sub-bucket of more than kSubMax keys (skewed buckets) sends the whole
-//    bucket to the merge sort instead.
-// All paths are stable.
-constexpr uint32_t kSubMax = 64;
-
-template <int DT, bool PAY, int NW, int IPT>
-__device__ inline void base_large_stable(const BaseItem& bi, typename Key<DT>::T* keys, uint32_t* pay,
-                                         const typename Key<DT>::T* skeys, const uint32_t* spay) {
-    using KT = Key<DT>;
-    using O = typename KT::O;
-    constexpr int NT = 64 * NW, CAP = NT * IPT, PCAP = CAP + CAP / 16;
-    constexpr int MT = CAP / 16;  // threads of the merge-sort fallback (16 keys each)
-    constexpr O kPad = (O)~(O)0;
-    __shared__ O s_k[PCAP];
-    __shared__ uint32_t s_p[PAY ? PCAP : 1];
-    __shared__ uint32_t s_wcnt[NW][kMaxBuckets];
-    __shared__ uint32_t s_loc[kMaxBuckets], s_cnt[kMaxBuckets];
-    __shared__ uint64_t s_scan[16];
-    __shared__ uint32_t s_max[NW];
-    __shared__ O s_red[2][NW];
-    const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
-    const uint32_t n = bi.n;
-    const typename KT::T* src = bi.from_scratch ? skeys : keys;
-    const uint32_t* psrc = bi.from_scratch ? spay : pay;
-    const uint32_t wbase = wave * kWave * IPT;
-    O o[IPT];
-    uint32_t p[IPT];
-    {
-        typename KT::T v[IPT];
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            const uint32_t j = wbase + r * kWave + lane;
-            if (j < n) {
-                v[r] = __builtin_nontemporal_load(&src[bi.lo + j]);
-                p[r] = PAY ? __builtin_nontemporal_load(&psrc[bi.lo + j]) : 0u;
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) o[r] = wbase + r * kWave + lane < n ? (O)KT::ord(v[r]) : kPad;
-    }
-    // min over the bucket, then the OR of ord - min (its trailing zeros and bit length)
-    O mn = kPad;
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) mn = o[r] < mn ? o[r] : mn;
-    mn = (O)~wave_max((O)~mn);
-    if (lane == 0) s_red[0][wave] = mn;
-    __syncthreads();
-    mn = s_red[0][0];
-    for (int w = 1; w < NW; ++w) mn = s_red[0][w] < mn ? s_red[0][w] : mn;
-    O orv = 0;
-#pragma unroll
-    for (int r = 0; r < IPT; ++r)
-        if (wbase + r * kWave + lane < n) orv |= (O)(o[r] - mn);
-#pragma unroll
-    for (int sft = 32; sft >= 1; sft >>= 1) orv |= (O)__shfl_xor(orv, sft, kWave);
-    if (lane == 0) s_red[1][wave] = orv;
-    __syncthreads();
-    orv = 0;
-    for (int w = 0; w < NW; ++w) orv |= s_red[1][w];
-    const int z = orv ? __builtin_ctzll((unsigned long long)orv) : 0;
-    const int nbits = orv ? (int)bit_length((uint64_t)(orv >> z)) : 0;
-
-    uint32_t bk[IPT], rk[IPT];
-    const int shift = nbits <= 8 ? z : z + nbits - 8;  // the low digit, or the top 8 varying bits
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) bk[r] = (uint32_t)(((uint64_t)(o[r] - mn) >> shift) & 255u);
-    const uint32_t most = block_count_digits<NW, IPT>(bk, n, wbase, s_wcnt, s_loc, s_cnt, s_scan, s_max, rk);
-
-    if (nbits > 8 && most > kSubMax) {
-        // merge sort: keys (and original indices) to LDS at their input positions, padding at the
-        // end; then sort, and gather the payloads by index (all read before any is written)
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            const uint32_t j = wbase + r * kWave + lane;
-            s_k[pad16(j)] = o[r];
-            if (PAY) s_p[pad16(j)] = j;
-        }
-        __syncthreads();
-        merge_sort_lds<O, PAY, MT>(s_k, s_p, (int)tid, tid < (uint32_t)MT);
-        uint32_t pv[PAY ? IPT : 1];
-        if (PAY) {
-#pragma unroll
-            for (int r = 0; r < IPT; ++r) {
-                const uint32_t j = wbase + r * kWave + lane;
-                if (j < n) pv[r] = psrc[bi.lo + s_p[pad16(j)]];
-            }
-            __syncthreads();
-        }
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            const uint32_t j = wbase + r * kWave + lane;
-            if (j < n) {
-                keys[bi.lo + j] = KT::from_ord((uint64_t)s_k[pad16(j)]);
-                if (PAY) pay[bi.lo + j] = pv[r];
-            }
-        }
-        return;
-    }
-
-    // keys in digit order (stable)
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        if (wbase + r * kWave + lane < n) {
-            const uint32_t pos = s_loc[bk[r]] + s_wcnt[wave][bk[r]] + rk[r];
-            s_k[pos] = o[r];
-            if (PAY) s_p[pos] = p[r];
-        }
-    }
-    __syncthreads();
-    if (nbits > 8) {
-        // final place inside the sub-bucket: the keys of the sub-bucket that precede this one in
-        // (ord, position) order.  Lane j takes position j of the digit order, so the lanes of a
-        // wave mostly share a sub-bucket and its LDS reads are broadcasts.
-        O xs[IPT];
-        uint32_t ps[IPT], np[IPT];
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            const uint32_t j = wbase + r * kWave + lane;
-            if (j < n) {
-                xs[r] = s_k[j];
-                ps[r] = PAY ? s_p[j] : 0u;
-                const uint32_t d = (uint32_t)(((uint64_t)(xs[r] - mn) >> shift) & 255u);
-                const uint32_t start = s_loc[d], cnt = s_cnt[d];
-                uint32_t before = 0;
-                for (uint32_t q = 0; q < cnt; ++q) {
-                    const O x = s_k[start + q];
-                    before += (x < xs[r] || (x == xs[r] && start + q < j)) ? 1u : 0u;
-                }
-                np[r] = start + before;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            if (wbase + r * kWave + lane < n) {
-                s_k[np[r]] = xs[r];
-                if (PAY) s_p[np[r]] = ps[r];
-            }
-        }
-        __syncthreads();
-    }
-    // sorted keys at positions 0 .. n-1: write out (coalesced)
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const uint32_t j = wbase + r * kWave + lane;
-        if (j < n) {
-            keys[bi.lo + j] = KT::from_ord((uint64_t)s_k[j]);
-            if (PAY) pay[bi.lo + j] = s_p[j];
-        }
-    }
-}
-
-
-// Base case of keys-only sorts for one bucket of at most CAP = 64 NW IPT keys per workgroup.  Keys
-// with equal ord are identical, so any order among them is the sorted order and the pass need not
-// be stable.  One reduction finds the bucket's min, max and the low bits z shared by all keys
-// (the trailing zeros of every key's difference to the bucket's first key); a histogram of
-// log2(CAP)-bit digits of (ord - min) >> z, taken from the top of the varying bits, with LDS atomics,
-// places every key in its digit's range.  Digits then hold one key on average:
-//  * when the varying bits fit the digit, keys of a digit are equal and the bucket is sorted;
-//  * otherwise a key's final place is its digit's start plus the keys of the digit before it in
-//    (ord, position) order; a digit of more than kSubMax keys (skewed buckets) sends the bucket to
-//    the merge sort instead.
-// A value that is the same in every lane, moved to scalar registers (frees vector registers).
-template <typename V>
-__device__ inline V uniform(V v) {
-    static_assert(sizeof(V) == 4 || sizeof(V) == 8, "32- or 64-bit values");
-    if constexpr (sizeof(V) == 4) {
-        return __builtin_bit_cast(V, (uint32_t)__builtin_amdgcn_readfirstlane(__builtin_bit_cast(uint32_t, v)));
-    } else {
-        const uint64_t u = __builtin_bit_cast(uint64_t, v);
-        const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)u);
-        const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
-        return __builtin_bit_cast(V, ((uint64_t)hi << 32) | lo);
-    }
-}
-
-// Digit of a key of the keys-only base case: the bits below the top varying bit of ord - min, or
-// (BY_VALUE) a linear map of the value onto [0, ND); t >= 0 since every key is at least min.
-template <typename KT, int ND, bool BY_VALUE, typename O>
-__device__ inline uint32_t base_digit(O x, O mn, int shift, double vlo, double vscale) {
-    if constexpr (BY_VALUE) {
-        const double t = (KT::val(KT::from_ord((uint64_t)x)) - vlo) * vscale;
-        return t < (double)(ND - 1) ? (uint32_t)t : (uint32_t)(ND - 1);
-    } else {
-        return (uint32_t)((uint64_t)(x - mn) >> shift);
-    }
-}
-
-// The keys-only base case's counting: each key's slot among its digit's keys (LDS atomics on s_c,
-// which starts at zero), then the digit starts in s_c[0..ND) and n in s_c[ND].  Returns the largest
-// digit count.  Thread t owns digits [t CPT, (t+1) CPT).  The digits are not kept: the placement
-// computes them again, which holds fewer registers across the scan.
-template <typename KT, int NW, int IPT, int ND, bool BY_VALUE, typename O>
-__device__ inline uint32_t base_count(const O (&o)[IPT], uint32_t n, uint32_t wbase, O mn, int shift, double vlo,
-                                      double vscale, uint32_t (&sl)[IPT], uint32_t* s_c,
-                                      uint64_t* s_scan, uint32_t* s_most) {
-    constexpr int NT = 64 * NW, CPT = ND / NT;
-    const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        if (wbase + r * kWave + lane < n) sl[r] = atomicAdd(&s_c[base_digit<KT, ND, BY_VALUE>(o[r], mn, shift, vlo, vscale)], 1u);
-    }
-    __syncthreads();
-    uint32_t c[CPT], sum = 0, most = 0;
-#pragma unroll
-    for (int i = 0; i < CPT; ++i) {
-        c[i] = s_c[tid * CPT + i];
-        sum += c[i];
-        most = c[i] > most ? c[i] : most;
-    }
-    most = wave_max(most);
-    if (lane == 0) s_most[wave] = most;
-    uint64_t all;
-    uint32_t e = (uint32_t)block_exclusive_sum<uint64_t>(sum, s_scan, &all);  // synchronises
-#pragma unroll
-    for (int i = 0; i < CPT; ++i) {
-        s_c[tid * CPT + i] = e;
-        e += c[i];
-    }
-    if (tid == 0) s_c[ND] = n;
-    most = 0;
-    for (int w = 0; w < NW; ++w) most = s_most[w] > most ? s_most[w] : most;
-    __syncthreads();
-    return most;
-}
-
-// The keys-only base case's placement: each key to its digit's start plus its slot.
-template <typename KT, int IPT, int ND, bool BY_VALUE, typename O>
-__device__ inline void base_place(const O (&o)[IPT], const uint32_t (&sl)[IPT], uint32_t n, uint32_t wbase, O mn,
-                                  int shift, double vlo, double vscale, O* s_k, const uint32_t* s_c) {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (int r = 0; r < IPT; ++r)
-        if (wbase + r * kWave + lane < n) s_k[s_c[base_digit<KT, ND, BY_VALUE>(o[r], mn, shift, vlo, vscale)] + sl[r]] = o[r];
-}
-
-// The keys-only base case's last step for a bucket whose digits do not fit the varying bits: each
-// key's place is its digit's start plus the keys of its digit before it in (ord, position) order.
-template <typename KT, int NW, int IPT, int ND, bool BY_VALUE, typename O>
-__device__ inline void base_fixup(uint32_t n, uint32_t wbase, O mn, int shift, double vlo, double vscale, O* s_k,
-                                  const uint32_t* s_c) {
-    const uint32_t lane = lane_id();
-    O xs[IPT];
-    uint32_t np[IPT];
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const uint32_t j = wbase + r * kWave + lane;
-        if (j < n) {
-            xs[r] = s_k[j];
-            const uint32_t d = base_digit<KT, ND, BY_VALUE>(xs[r], mn, shift, vlo, vscale);
-            const uint32_t start = s_c[d], end = s_c[d + 1];
-            uint32_t before = 0;
-            for (uint32_t q = start; q < end; ++q) {
-                const O y = s_k[q];
-                before += (y < xs[r] || (y == xs[r] && q < j)) ? 1u : 0u;
-            }
-            np[r] = start + before;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < IPT; ++r)
-        if (wbase + r * kWave + lane < n) s_k[np[r]] = xs[r];
-    __syncthreads();
-}
-
-template <int DT, int NW, int IPT>
-__device__ inline void base_large_keys(const BaseItem& bi, typename Key<DT>::T* keys,
-                                       const typename Key<DT>::T* skeys) {
-    using KT = Key<DT>;
-    using O = typename KT::O;
-    constexpr int NT = 64 * NW, CAP = NT * IPT, PCAP = CAP + CAP / 16, MT = CAP / 16;
-    constexpr int DB = CAP >= 4096 ? 12 : CAP >= 2048 ? 11 : CAP >= 1024 ? 10 : 9;  // digit bits
-    constexpr int ND = 1 << DB, CPT = ND / NT;                                     // digits, per thread
-    static_assert(ND == CAP && CPT == IPT, "one digit per key slot");
-    constexpr O kPad = (O)~(O)0;
-    __shared__ O s_k[PCAP];
-    __shared__ uint32_t s_c[ND + 1];
-    __shared__ uint64_t s_scan[16];
-    __shared__ O s_red[3][NW];
-    __shared__ uint32_t s_most[NW];
-    const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
-    const uint32_t n = bi.n;
-    const typename KT::T* src = bi.from_scratch ? skeys : keys;
-    const uint32_t wbase = wave * kWave * IPT;
-    O o[IPT];
-    {
-        typename KT::T v[IPT];
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            const uint32_t j = wbase + r * kWave + lane;
-            if (j < n) v[r] = __builtin_nontemporal_load(&src[bi.lo + j]);
-        }
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) o[r] = wbase + r * kWave + lane < n ? (O)KT::ord(v[r]) : kPad;
-    }
-    const O oref = (O)KT::ord(src[bi.lo]);  // n >= 1
-    O mn = kPad, mx = 0, ov = 0;
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        if (wbase + r * kWave + lane < n) {
-            mn = o[r] < mn ? o[r] : mn;
-            mx = o[r] > mx ? o[r] : mx;
-            ov |= (O)(o[r] - oref);
-        }
-    }
-    mn = (O)~wave_max((O)~mn);
-    mx = wave_max(mx);
-#pragma unroll
-    for (int sft = 32; sft >= 1; sft >>= 1) ov |= (O)__shfl_xor(ov, sft, kWave);
-    for (uint32_t d = tid; d <= (uint32_t)ND; d += NT) s_c[d] = 0;
-    if (lane == 0) {
-        s_red[0][wave] = mn;
-        s_red[1][wave] = mx;
-        s_red[2][wave] = ov;
-    }
-    __syncthreads();
-    mn = s_red[0][0];
-    mx = s_red[1][0];
-    ov = s_red[2][0];
-    for (int w = 1; w < NW; ++w) {
-        mn = s_red[0][w] < mn ? s_red[0][w] : mn;
-        mx = s_red[1][w] > mx ? s_red[1][w] : mx;
-        ov |= s_red[2][w];
-    }
-    const int z = ov ? __builtin_ctzll((unsigned long long)ov) : 0;
-    const int nbits = (int)bit_length((uint64_t)((O)(mx - mn) >> z));
-    const int shift = z + (nbits > DB ? nbits - DB : 0);
-    const bool exact = nbits <= DB;
-    uint32_t dg[IPT], sl[IPT];
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        if (wbase + r * kWave + lane < n) {
-            dg[r] = (uint32_t)((uint64_t)(o[r] - mn) >> shift);
-            sl[r] = atomicAdd(&s_c[dg[r]], 1u);
-        }
-    }
-    __syncthreads();
-    // digit starts: thread t owns digits [t CPT, (t+1) CPT)
-    uint32_t c[CPT], sum = 0, most = 0;
-#pragma unroll
-    for (int i = 0; i < CPT; ++i) {
-        c[i] = s_c[tid * CPT + i];
-        sum += c[i];
-        most = c[i] > most ? c[i] : most;
-    }
-    most = wave_max(most);
-    if (lane == 0) s_most[wave] = most;
-    uint64_t all;
-    uint32_t e = (uint32_t)block_exclusive_sum<uint64_t>(sum, s_scan, &all);  // synchronises
-#pragma unroll
-    for (int i = 0; i < CPT; ++i) {
-        s_c[tid * CPT + i] = e;
-        e += c[i];
-    }
-    if (tid == 0) s_c[ND] = n;
-    most = 0;
-    for (int w = 0; w < NW; ++w) most = s_most[w] > most ? s_most[w] : most;
-    __syncthreads();
-
-    if (!exact && most > kSubMax) {
-        // merge sort: keys to LDS at their input positions (padding keys at the end), then sort
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) s_k[pad16(wbase + r * kWave + lane)] = o[r];
-        __syncthreads();
-        merge_sort_lds<O, false, MT>(s_k, nullptr, (int)tid, tid < (uint32_t)MT);
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            const uint32_t j = wbase + r * kWave + lane;
-            if (j < n) keys[bi.lo + j] = KT::from_ord((uint64_t)s_k[pad16(j)]);
-        }
-        return;
-    }
-#pragma unroll
-    for (int r = 0; r < IPT; ++r)
-        if (wbase + r * kWave + lane < n) s_k[s_c[dg[r]] + sl[r]] = o[r];
-    __syncthreads();
-    if (!exact) {
-        O xs[IPT];
-        uint32_t np[IPT];
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            const uint32_t j = wbase + r * kWave + lane;
-            if (j < n) {
-                xs[r] = s_k[j];
-                const uint32_t d = (uint32_t)((uint64_t)(xs[r] - mn) >> shift);
-                const uint32_t start = s_c[d], end = s_c[d + 1];
-                uint32_t before = 0;
-                for (uint32_t q = start; q < end; ++q) {
-                    const O y = s_k[q];
-                    before += (y < xs[r] || (y == xs[r] && q < j)) ? 1u : 0u;
-                }
-                np[r] = start + before;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < IPT; ++r)
-            if (wbase + r * kWave + lane < n) s_k[np[r]] = xs[r];
-        __syncthreads();
-    }
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const uint32_t j = wbase + r * kWave + lane;
-        if (j < n) keys[bi.lo + j] = KT::from_ord((uint64_t)s_k[j]);
-    }
-}
-
-// The keys-only base case for sorted samples, which span their whole bucket: as base_large_keys,
-// but when a digit holds more than kSubMax keys (a float range over several binades, whose top
-// varying bits are exponent bits) the bucket is counted again with digits from a linear map of the
-// key's value over [min, max]; if a digit still holds more than kSubMax keys, the merge sort runs.
-template <int DT, int NW, int IPT>
-__device__ inline void base_large_keys_vmap(const BaseItem& bi, typename Key<DT>::T* keys,
-                                       const typename Key<DT>::T* skeys) {
-    using KT = Key<DT>;
-    using O = typename KT::O;
-    constexpr int NT = 64 * NW, CAP = NT * IPT, PCAP = CAP + CAP / 16, MT = CAP / 16;
-    constexpr int DB = CAP >= 4096 ? 12 : CAP >= 2048 ? 11 : CAP >= 1024 ? 10 : 9;  // digit bits
-    constexpr int ND = 1 << DB, CPT = ND / NT;                                     // digits, per thread
-    static_assert(ND == CAP && CPT == IPT, "one digit per key slot");
-    constexpr O kPad = (O)~(O)0;
-    __shared__ O s_k[PCAP];
-    __shared__ uint32_t s_c[ND + 1];
-    __shared__ uint64_t s_scan[16];
-    __shared__ O s_red[3][NW];
-    __shared__ uint32_t s_most[NW];
-    const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
-    const uint32_t n = bi.n;
-    const typename KT::T* src = bi.from_scratch ? skeys : keys;
-    const uint32_t wbase = wave * kWave * IPT;
-    O o[IPT];
-    {
-        typename KT::T v[IPT];
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            const uint32_t j = wbase + r * kWave + lane;
-            if (j < n) v[r] = __builtin_nontemporal_load(&src[bi.lo + j]);
-        }
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) o[r] = wbase + r * kWave + lane < n ? (O)KT::ord(v[r]) : kPad;
-    }
-    const O oref = (O)KT::ord(src[bi.lo]);  // n >= 1
-    O mn = kPad, mx = 0, ov = 0;
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        if (wbase + r * kWave + lane < n) {
-            mn = o[r] < mn ? o[r] : mn;
-            mx = o[r] > mx ? o[r] : mx;
-            ov |= (O)(o[r] - oref);
-        }
-    }
-    mn = (O)~wave_max((O)~mn);
-    mx = wave_max(mx);
-#pragma unroll
-    for (int sft = 32; sft >= 1; sft >>= 1) ov |= (O)__shfl_xor(ov, sft, kWave);
-    for (uint32_t d = tid; d <= (uint32_t)ND; d += NT) s_c[d] = 0;
-    if (lane == 0) {
-        s_red[0][wave] = mn;
-        s_red[1][wave] = mx;
-        s_red[2][wave] = ov;
-    }
-    __syncthreads();
-    mn = s_red[0][0];
-    mx = s_red[1][0];
-    ov = s_red[2][0];
-    for (int w = 1; w < NW; ++w) {
-        mn = s_red[0][w] < mn ? s_red[0][w] : mn;
-        mx = s_red[1][w] > mx ? s_red[1][w] : mx;
-        ov |= s_red[2][w];
-    }
-    mn = uniform(mn);
-    mx = uniform(mx);
-    ov = uniform(ov);
-    const int z = ov ? __builtin_ctzll((unsigned long long)ov) : 0;
-    const int nbits = (int)bit_length((uint64_t)((O)(mx - mn) >> z));
-    const int shift = z + (nbits > DB ? nbits - DB : 0);
-    const bool exact = nbits <= DB;
-    uint32_t sl[IPT];
-    uint32_t most = base_count<KT, NW, IPT, ND, false>(o, n, wbase, mn, shift, 0.0, 0.0, sl, s_c, s_scan, s_most);
-    // Digits of a float range that spans several binades are mostly exponent bits, and a few digits
-    // take most keys.  Such a bucket is counted again with digits from a linear map of the key's
-    // value (monotone in the key order, as every digit function must be); a bucket that is still
-    // skewed is merge sorted.  The decision is uniform over the block.
-    bool by_value = false;
-    double vlo = 0.0, vscale = 0.0;
-    if (!exact && most > kSubMax) {
-        vlo = uniform(KT::val(KT::from_ord((uint64_t)mn)));
-        const double vhi = KT::val(KT::from_ord((uint64_t)mx));
-        vscale = uniform((double)ND / (vhi - vlo));
-        if (__builtin_isfinite(vlo) && __builtin_isfinite(vhi) && vhi > vlo && __builtin_isfinite(vscale)) {
-            by_value = true;
-            for (uint32_t d = tid; d <= (uint32_t)ND; d += NT) s_c[d] = 0;
-            __syncthreads();
-            most = base_count<KT, NW, IPT, ND, true>(o, n, wbase, mn, shift, vlo, vscale, sl, s_c, s_scan, s_most);
-        }
-    }
-
-    if (!exact && most > kSubMax) {
-        // merge sort: keys to LDS at their input positions (padding keys at the end), then sort
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) s_k[pad16(wbase + r * kWave + lane)] = o[r];
-        __syncthreads();
-        merge_sort_lds<O, false, MT>(s_k, nullptr, (int)tid, tid < (uint32_t)MT);
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            const uint32_t j = wbase + r * kWave + lane;
-            if (j < n) keys[bi.lo + j] = KT::from_ord((uint64_t)s_k[pad16(j)]);
-        }
-        return;
-    }
-    if (by_value) base_place<KT, IPT, ND, true>(o, sl, n, wbase, mn, shift, vlo, vscale, s_k, s_c);
-    else base_place<KT, IPT, ND, false>(o, sl, n, wbase, mn, shift, vlo, vscale, s_k, s_c);
-    __syncthreads();
-    if (by_value) base_fixup<KT, NW, IPT, ND, true>(n, wbase, mn, shift, vlo, vscale, s_k, s_c);
-    else if (!exact) base_fixup<KT, NW, IPT, ND, false>(n, wbase, mn, shift, vlo, vscale, s_k, s_c);
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const uint32_t j = wbase + r * kWave + lane;
-        if (j < n) keys[bi.lo + j] = KT::from_ord((uint64_t)s_k[j]);
-    }
-}
-
-// VMAP: skewed buckets are counted again by value before the merge sort is taken (sorted samples,
-// which span their whole bucket; the bulk of the base case runs without it).
-template <int DT, bool PAY, int NW, int IPT, bool VMAP = false>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PAY ? 4 : 6))) void k_base_large(
-    const BaseItem* list, uint64_t count,
-                                                       typename Key<DT>::T* keys, uint32_t* pay,
-                                                       const typename Key<DT>::T* skeys, const uint32_t* spay) {
-    if (blockIdx.x >= count) return;
-    const BaseItem bi = list[blockIdx.x];
-    if constexpr (PAY) base_large_stable<DT, true, NW, IPT>(bi, keys, pay, skeys, spay);
-    else if constexpr (VMAP) base_large_keys_vmap<DT, NW, IPT>(bi, keys, skeys);
-    else base_large_keys<DT, NW, IPT>(bi, keys, skeys);
-}
-
 }  // namespace ipls
+
+// The base case (buckets of at most T keys) lives in its own header.
+#include "ipls_base.h"

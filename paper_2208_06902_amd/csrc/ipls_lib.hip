@@ -23,6 +23,7 @@ namespace ipls {
 namespace {
 
 constexpr uint32_t kSmallS = kFitLds;  // samples up to this size are fitted in one workgroup's LDS
+constexpr int kWorklistItems = 8;      // items per k_worklist workgroup
 constexpr uint64_t kDeferBaseItems = 2048;  // levels of at least this many items run before the previous level's base case
 constexpr uint32_t kFitChunk = 2048;   // windows per workgroup in the multi-round fit
 constexpr uint32_t kCand = 15;         // candidate widths per fit round
@@ -479,6 +480,9 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     A.policy = P.sample_policy;
     A.seed = P.seed;
     const uint32_t tile = tile_keys_of(P);
+    static_assert((kTile & (kTile - 1)) == 0 && (kSmallTile & (kSmallTile - 1)) == 0 &&
+                      (kChunk & (kChunk - 1)) == 0 && (kFitChunk & (kFitChunk - 1)) == 0,
+                  "k_plan divides by shifts");
     A.tile_keys = tile;
     A.small_S = kSmallS;
     A.fit_chunk = kFitChunk;
@@ -717,7 +721,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             HIP_TRY(hipStreamWaitEvent(s, dv.ev_base[par], 0));
             base_pending[par] = false;
         }
-        k_worklist<<<(unsigned)ni, 256, 0, s>>>(
+        k_worklist<kWorklistItems><<<(unsigned)((ni + kWorklistItems - 1) / kWorklistItems), 256, 0, s>>>(
             items, ni, models, (const uint64_t*)D.hist.p, (const uint64_t*)D.bstart.p, K, T_, src_scratch ? 0 : 1,
             (Item*)D.items[cur ^ 1].p, (BaseItem*)D.base[par].p, bl, cnt, C_ITEMS0 + (cur ^ 1), item_cap,
             (CopyItem*)D.copy.p, copy_cap, spans, children, (top && level == 0 && ni == 1) ? cnt + C_L1MAX : nullptr);
