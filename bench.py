@@ -30,13 +30,17 @@ METRIC = "sorted keys/s + HBM GB/s (% peak) per pass, 1e8 fp64; p50/p99 latency 
 HBM_PEAK_GBS = 8000.0
 DISTS = ("normal", "lognormal", "exponential", "mixgauss", "uniform_int")
 SEEDS = {"normal": 2, "lognormal": 3, "exponential": 4, "mixgauss": 5, "uniform_int": 6}
-KERNEL_SRC = os.path.join(ROOT, "paper_2208_06902_amd", "csrc", "ipls_kernels.h")
+# the scatter and the helpers it uses (the base case lives in ipls_base.h and does not count)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2208_06902_amd", "csrc", f) for f in ("ipls_kernels.h", "ipls_device.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scatter_traffic.json")
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_per_launch():
@@ -75,7 +79,7 @@ def summarize_profiles(ktrace_dir: str, fetch_dir: str, write_dir: str, bench_js
     lines = ["# Kernel time of the 1e8 fp64 sort bench (rocprofv3 --kernel-trace --stats)", "",
              "Command (from the repository root, GPU box):", "",
              "    rocprofv3 --kernel-trace --stats -f csv -d <dir> -o bench -- \\",
-             "        python3 -u bench.py --steps 5 --warmup 5 --no-cpu-baseline", "",
+             "        python3 -u bench.py --steps 5 --warmup 5 --no-cpu-baseline --no-extras", "",
              f"Bench line of the same run: {bench['value']:.4g} keys/s, {bench['ms_per_step']} ms per step; "
              f"k_scatter average launch by HIP events in bench.py: {bench['roofline']['avg_launch_ms']} ms over "
              f"{bench['roofline']['launches']} timed launches.", "",
@@ -110,16 +114,16 @@ def summarize_profiles(ktrace_dir: str, fetch_dir: str, write_dir: str, bench_js
     big = [(f, w) for f, w in zip(sf, sw) if f > 1e8]
     t = {"kernel": "k_scatter", "kernel_sha": kernel_hash(), "bytes_per_launch": round(per_launch),
          "launches": n_launch, "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
-         "workload": "bench.py --steps 5 --warmup 5 --no-cpu-baseline (15 sorts of 1e8 fp64, all five distributions)",
+         "workload": "bench.py --steps 5 --warmup 5 --no-cpu-baseline --no-extras (15 sorts of 1e8 fp64, all five distributions)",
          "large_launches_bytes": [[round(f), round(w)] for f, w in big[:6]],
          "algorithmic_bytes_large_launch": 1_600_000_000}
     json.dump(t, open(os.path.join(out_dir, "scatter_traffic.json"), "w"), indent=1)
     md = ["# HBM traffic of k_scatter (rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE, separate runs)", "",
           "Commands (from the repository root, GPU box), one counter per run:", "",
           "    rocprofv3 --pmc FETCH_SIZE -f csv -d <dir> -o bench -- \\",
-          "        python3 -u bench.py --steps 5 --warmup 5 --no-cpu-baseline",
+          "        python3 -u bench.py --steps 5 --warmup 5 --no-cpu-baseline --no-extras",
           "    rocprofv3 --pmc WRITE_SIZE -f csv -d <dir> -o bench -- \\",
-          "        python3 -u bench.py --steps 5 --warmup 5 --no-cpu-baseline", "",
+          "        python3 -u bench.py --steps 5 --warmup 5 --no-cpu-baseline --no-extras", "",
           "The same command as the kernel trace: 15 sorts, three of each of the five distributions, the launch "
           "mix of the bench's timed steps.", "",
           f"Calibration: the bench's device-to-device copies of one 800,000,000-byte input read as "
@@ -156,6 +160,43 @@ def _line(value, ms_per_step, steps, warmup, dtype, config, **extra):
             "roofline": None, "cpu_baseline": None}
     line.update(extra)
     return line
+
+
+def _ord_i64(t, dtype_code, torch):
+    """A monotone int64 image of keys: IEEE totalOrder for fp64 (0) and fp32 (1), unsigned order for
+    uint64 (2).  One to one, so equal images mean equal bits."""
+    if dtype_code == 1:
+        s = t.view(torch.int32)
+        return torch.bitwise_xor(s, torch.bitwise_and(s >> 31, 0x7FFFFFFF)).to(torch.int64)
+    s = t.view(torch.int64)
+    if dtype_code == 2:
+        return torch.bitwise_xor(s, torch.tensor(-(2**63), dtype=torch.int64, device=t.device))
+    return torch.bitwise_xor(s, torch.bitwise_and(s >> 63, 0x7FFFFFFFFFFFFFFF))
+
+
+def _sorted_equal(out, inp, dtype_code, torch):
+    """Exact check of one keys-only sort: out equals the input's keys in ascending order (the
+    sorted sequence of a multiset is unique), compared through the ord image with torch's sort."""
+    want = torch.sort(_ord_i64(inp, dtype_code, torch)).values
+    return bool(torch.equal(want, _ord_i64(out, dtype_code, torch)))
+
+
+def _segments_sorted_equal(out, inp, sizes_t, torch):
+    """Exact check of a keys-only segmented fp64 sort over every segment: the input's keys sorted
+    by (segment, ord) with two stable sorts equal the output."""
+    nseg = sizes_t.numel()
+    seg = torch.repeat_interleave(torch.arange(nseg, device=inp.device), sizes_t)
+    v1, i1 = torch.sort(_ord_i64(inp, 0, torch), stable=True)
+    s1 = seg[i1]
+    del seg, i1
+    _, i2 = torch.sort(s1, stable=True)
+    del s1
+    want = v1[i2]
+    del v1, i2
+    ok = bool(torch.equal(want, _ord_i64(out, 0, torch)))
+    del want
+    torch.cuda.empty_cache()
+    return ok
 
 
 def _u64_sorted(t, torch):
@@ -280,14 +321,12 @@ def bench_batched(args):
     run(tuned, args.warmup)
     tuned_ms = run(tuned, args.steps)
     base_ms = run(base, max(1, args.steps // 2))
-    # correctness on a sample of arrays: sorted and a permutation of the input (device sort as reference)
+    # correctness of every array: the output equals the input sorted by (array, totalOrder) with
+    # torch's stable sorts (keys only: the sorted sequence of each array is unique)
     work.copy_(pristine)
     ipls.sort_segmented_(work, offs, params=tuned)
     torch.cuda.synchronize()
-    ok = True
-    for i in np.random.default_rng(12).integers(0, nseg, 64):
-        a, b = int(off[i]), int(off[i + 1])
-        ok &= torch.equal(work[a:b], torch.sort(pristine[a:b]).values)
+    ok = _segments_sorted_equal(work, pristine, torch.from_numpy(sizes.astype(np.int64)).to(dev), torch)
     # plain launches, one per array, on the leading arrays up to args.plain_keys keys
     m = int(np.searchsorted(off, args.plain_keys, side="right")) - 1
     m = max(1, min(m, nseg))
@@ -322,17 +361,19 @@ def bench_batched(args):
                  plain_per_array={"arrays": m, "keys": sub_keys, "plain_keys_per_s": round(sub_keys / (plain_ms / 1e3), 1),
                                   "batched_keys_per_s": round(sub_keys / (sub_batched_ms / 1e3), 1),
                                   "speedup": round(plain_ms / sub_batched_ms, 2)},
-                 outputs_sorted=bool(ok))
+                 outputs_sorted=bool(ok), outputs_checked=f"all {nseg} arrays, exact against torch's sort")
     print(json.dumps(line), flush=True)
 
 
-def bench_served(args):
+def run_served(args, validate=True):
     """Served form: Poisson arrivals at args.rate requests/s (seed 9), sizes log-uniform in
     [1e3, 1e8], dtypes 50% fp64 / 30% uint64 / 20% fp32, distributions including lognormal(sigma=2)
     and a 20-component Gaussian mixture, admitted under a 64 GB HBM budget, the learned model
     chosen when its max bucket load is lower.  Inputs are generated on the device into the
-    admitted slots.  Reports latency (arrival to completion) percentiles and throughput, then the
-    same requests all at once (capacity) and as plain one-at-a-time ipls_sort launches."""
+    admitted slots.  Measures latency (arrival to completion) percentiles and throughput, then the
+    same requests all at once (capacity) and as plain one-at-a-time ipls_sort launches.  With
+    validate, the stream is served once more, untimed, and every request's output is compared with
+    torch's sort of its regenerated input.  Returns a dict."""
     import numpy as np
     import torch
 
@@ -355,12 +396,15 @@ def bench_served(args):
     arena = torch.empty(budget, dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
     print(f"# served: {count} requests, {total} keys, budget {args.budget_gb} GB", file=sys.stderr, flush=True)
+    tmp = {0: torch.empty(int(sizes.max()), dtype=torch.float64, device=dev),
+           1: torch.empty(int(sizes.max()), dtype=torch.float32, device=dev),
+           2: torch.empty(int(sizes.max()), dtype=torch.int64, device=dev)}
 
     srv = ipls.Server(arena, ipls.server_config(params, lanes=args.lanes))
 
-    def serve(arrivals, k):
+    def serve(arrivals, k, check=False):
         done_t = {}
-        checked = [True]
+        bad = []
         before = srv.stats()
         views = {}
 
@@ -370,8 +414,19 @@ def bench_served(args):
                 if d["status"] != 0:
                     raise RuntimeError(f"request {i} failed: {d}")
                 done_t[i] = d["t_done"]
-                if i % 97 == 0:  # spot check of the order before the slot is released
-                    checked[0] &= _u64_sorted(kv, torch) if dtypes[i] == 2 else bool((kv[1:] >= kv[:-1]).all())
+                if check:
+                    n, dt = int(sizes[i]), int(dtypes[i])
+                    ref = tmp[dt][:n]
+                    gdev.request_keys(dnames[which[i]], n, 50_000 + i, dt, ref, device=dev)
+                    if not _sorted_equal(kv, ref, dt, torch):
+                        want = torch.sort(_ord_i64(ref, dt, torch)).values
+                        got = _ord_i64(kv, dt, torch)
+                        diff = torch.nonzero(want != got).flatten()
+                        bad.append({"request": i, "n": n, "dtype": dt, "dist": dnames[which[i]],
+                                    "batch_size": d["batch_size"], "mismatches": int(diff.numel()),
+                                    "first": int(diff[0]) if diff.numel() else None,
+                                    "last": int(diff[-1]) if diff.numel() else None,
+                                    "sorted": bool((got[1:] >= got[:-1]).all())})
                 srv.release(d["req_id"])
 
         t0 = time.monotonic() + 0.02
@@ -397,44 +452,60 @@ def bench_served(args):
         st["peak_bytes_in_use"] = after["peak_bytes_in_use"]
         lat = np.array([done_t[i] - (t0 + arrivals[i]) for i in range(k)]) * 1e3
         span = max(done_t.values()) - t0
-        return lat, span, st, checked[0]
+        return lat, span, st, bad
 
     serve(np.zeros(count), min(count, 200))  # warm the lanes' contexts
-    lat, span, st, ok1 = serve(arrival, count)
-    lat_sat, span_sat, st_sat, ok2 = serve(np.zeros(count), count)
+    lat, span, st, _ = serve(arrival, count)
+    lat_sat, span_sat, st_sat, _ = serve(np.zeros(count), count)
+    bad = None
+    if validate:
+        print("# served: validating every request", file=sys.stderr, flush=True)
+        _, _, _, bad = serve(np.zeros(count), count, check=True)
     srv.close()
+    del arena
     # plain: one request at a time through ipls_sort, same generation
-    bufs = {0: torch.empty(int(sizes.max()), dtype=torch.float64, device=dev),
-            1: torch.empty(int(sizes.max()), dtype=torch.float32, device=dev),
-            2: torch.empty(int(sizes.max()), dtype=torch.int64, device=dev)}
     torch.cuda.synchronize()
     t = time.monotonic()
     for i in range(count):
         n = int(sizes[i])
-        b = bufs[int(dtypes[i])][:n]
+        b = tmp[int(dtypes[i])][:n]
         gdev.request_keys(dnames[which[i]], n, 50_000 + i, int(dtypes[i]), b, device=dev)
         ipls.sort_(b.view(torch.uint64) if dtypes[i] == 2 else b, None, params)
     torch.cuda.synchronize()
     plain_s = time.monotonic() - t
-    achieved = total / span
-    line = _line(achieved, span * 1e3 / count, count, 0, "mixed f64/u64/f32",
+    del tmp
+    torch.cuda.empty_cache()
+    return {"requests": count, "keys": total, "span_s": span,
+            "achieved_keys_per_s": round(total / span, 1),
+            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                           "p99": round(float(np.percentile(lat, 99)), 3),
+                           "mean": round(float(lat.mean()), 3), "max": round(float(lat.max()), 3)},
+            "offered_keys_per_s": round(total / float(arrival[-1]), 1),
+            "saturated": {"keys_per_s": round(total / span_sat, 1),
+                          "latency_p50_ms": round(float(np.percentile(lat_sat, 50)), 3),
+                          "latency_p99_ms": round(float(np.percentile(lat_sat, 99)), 3)},
+            "plain_one_at_a_time_keys_per_s": round(total / plain_s, 1),
+            "saturated_vs_plain": round(plain_s / span_sat, 2),
+            "server": {"batches_run": st["batches_run"], "singles_run": st["singles_run"],
+                       "max_queue_depth": st["max_queue_depth"], "rejected_reserves": st["rejected"],
+                       "peak_bytes_in_use": st["peak_bytes_in_use"]},
+            "outputs_checked": (f"all {count} requests, exact against torch's sort of each regenerated input"
+                                if validate else "not checked"),
+            "outputs_ok": None if bad is None else not bad,
+            "failed_requests": None if bad is None else bad[:10]}
+
+
+def bench_served(args):
+    """The served form's own line (see run_served)."""
+    res = run_served(args)
+    count = res["requests"]
+    line = _line(res["achieved_keys_per_s"], res["span_s"] * 1e3 / count, count, 0, "mixed f64/u64/f32",
                  {"workload": f"served: {count} requests, Poisson {args.rate:g}/s, sizes log-uniform [1e3, 1e8], "
                               f"dtypes 50/30/20 f64/u64/f32, {args.budget_gb} GB budget, learned model when lower "
-                              f"max load", "requests": count, "keys": total, "lanes": args.lanes,
+                              f"max load", "requests": count, "keys": res["keys"], "lanes": args.lanes,
                   "parallelism": "single GPU"},
-                 latency_ms={"p50": round(float(np.percentile(lat, 50)), 3),
-                             "p99": round(float(np.percentile(lat, 99)), 3),
-                             "mean": round(float(lat.mean()), 3), "max": round(float(lat.max()), 3)},
-                 offered_keys_per_s=round(total / float(arrival[-1]), 1),
-                 saturated={"keys_per_s": round(total / span_sat, 1),
-                            "latency_p50_ms": round(float(np.percentile(lat_sat, 50)), 3),
-                            "latency_p99_ms": round(float(np.percentile(lat_sat, 99)), 3)},
-                 plain_one_at_a_time_keys_per_s=round(total / plain_s, 1),
-                 saturated_vs_plain=round(plain_s / span_sat, 2),
-                 server={"batches_run": st["batches_run"], "singles_run": st["singles_run"],
-                         "max_queue_depth": st["max_queue_depth"], "rejected_reserves": st["rejected"],
-                         "peak_bytes_in_use": st["peak_bytes_in_use"]},
-                 outputs_sorted=bool(ok1 and ok2))
+                 **{k: v for k, v in res.items() if k not in ("requests", "keys", "span_s", "achieved_keys_per_s")},
+                 outputs_sorted=bool(res["outputs_ok"]))
     print(json.dumps(line), flush=True)
 
 
@@ -450,6 +521,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=100_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="sort: skip the figures beside the headline (defaults, learned model, served)")
     ap.add_argument("--dists", default=",".join(DISTS))
     ap.add_argument("--sample-max", type=int, default=4096)
     ap.add_argument("--tile-keys", type=int, default=0, help="keys per distribution tile (0 = library default)")
@@ -606,7 +679,18 @@ def main():
         parity = bool(np.array_equal(g.cpu().numpy().view(np.uint64), want.view(np.uint64)))
         cpu_baseline = {"value": round(n / dt, 1), "unit": "keys/s", "cores": 1, "kind": "oracle",
                         "sample": f"one full step: {n} {d0} fp64 keys sorted by the sequential C oracle "
-                                  f"({dt:.1f} s on 1 thread of {cpu_model()}); GPU output bit-identical: {parity}"}
+                                  f"({dt:.1f} s on 1 thread of {cpu_model()}); GPU output bit-identical: {parity}",
+                        "host_cpus": os.cpu_count(), "host_cpus_usable": len(os.sched_getaffinity(0))}
+        # context: the C++ standard library's sorts on one thread, on the first 1e7 keys of that input
+        m = min(n, 10_000_000)
+        ctx = oracle.std_sorts_seconds(host_inputs[d0][:m])
+        cpu_baseline["context"] = {"sample": f"first {m} keys of the {d0} input, 1 thread, g++ -O2",
+                                   **{f"{k}_keys_per_s": round(m / v, 1) for k, v in ctx.items()}}
+
+    extras = {}
+    if not args.no_extras:
+        extras = sort_extras(args, dists, pristine, n)
+    del pristine
 
     line = {
         "metric": METRIC,
@@ -640,7 +724,65 @@ def main():
         "wall_s_timed": round(wall, 3),
         "outputs_sorted": all(checked.values()) and timed_ok,
     }
+    line.update(extras)
     print(json.dumps(line), flush=True)
+
+
+def sort_extras(args, dists, pristine, n):
+    """Figures beside the headline, all outside its timed region: the library's default parameters
+    on the same inputs, the learned model against FMCD on its two inputs, and the served form."""
+    import torch
+
+    import gen.device as gdev
+    import paper_2208_06902_amd as ipls
+
+    stream = torch.cuda.current_stream()
+
+    def timed(x, params, reps):
+        ms, st, out = [], None, None
+        for k in range(reps + 1):
+            out = x.clone()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            st = ipls.sort_(out, None, params, stats=True)
+            b.record(stream)
+            torch.cuda.synchronize()
+            if k:
+                ms.append(a.elapsed_time(b))
+        return sum(ms) / len(ms), st, out
+
+    print("# extras: default parameters", file=sys.stderr, flush=True)
+    dflt = ipls.default_params()
+    by = {d: timed(pristine[d], dflt, 2)[0] for d in dists}
+    out = {"default_params": {"sample": "1% jittered stratified, uncapped (the library's defaults)",
+                              "keys_per_s": round(n * len(dists) / (sum(by.values()) / 1e3), 1),
+                              "ms_by_dist": {d: round(v, 4) for d, v in by.items()}}}
+
+    print("# extras: learned model", file=sys.stderr, flush=True)
+    learned = {}
+    for dname, seed in (("lognormal2", 40), ("mixgauss20", 41)):
+        x = gdev.fp64(dname, n, seed)
+        r = {}
+        for tag, model in (("fmcd", 0), ("auto", 1)):
+            ms, st, o = timed(x, ipls.default_params(sample_max=args.sample_max, model=model), 3)
+            r[tag] = {"ms": round(ms, 4), "keys_per_s": round(n / (ms / 1e3), 1), "levels": st["levels"],
+                      "passes": st["passes"], "level1_max_load": st["level1_max_load"],
+                      "l2pl_used": st["l2pl_used"], "output_exact": _sorted_equal(o, x, 0, torch)}
+            del o
+        r["speedup"] = round(r["fmcd"]["ms"] / r["auto"]["ms"], 3)
+        learned[dname] = r
+        del x
+    out["learned"] = {"workload": f"{n} fp64 keys drawn on the device, sample capped at {args.sample_max} keys; "
+                                  "auto = two-level model when its max sample load is lower", **learned}
+    torch.cuda.empty_cache()
+
+    print("# extras: served", file=sys.stderr, flush=True)
+    res = run_served(args)
+    out["served"] = {"workload": f"{res['requests']} requests, Poisson {args.rate:g}/s, sizes log-uniform [1e3, 1e8], "
+                                 f"dtypes 50/30/20 f64/u64/f32, {args.budget_gb} GB budget, {args.lanes} lanes, "
+                                 f"learned model when lower max load", **res}
+    return out
 
 
 if __name__ == "__main__":

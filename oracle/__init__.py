@@ -56,12 +56,36 @@ def params(K=256, T=4096, divisor=100, sample_min=0, sample_max=0, seed=DEFAULT_
                   inherit)
 
 
+CTX_SRC = os.path.join(HERE, "cpu_context.cpp")
+CTX_LIB = os.path.join(HERE, "libcpu_context.so")
+
+
 def build(force: bool = False) -> str:
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", *CFLAGS, SRC, "-o", tmp, "-lm"])
         os.replace(tmp, LIB)
+    if force or not os.path.exists(CTX_LIB) or os.path.getmtime(CTX_LIB) < os.path.getmtime(CTX_SRC):
+        tmp = CTX_LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall", CTX_SRC, "-o", tmp])
+        os.replace(tmp, CTX_LIB)
     return LIB
+
+
+def std_sorts_seconds(x: np.ndarray) -> dict:
+    """Context baselines: seconds of std::sort and std::stable_sort of copies of the fp64 array x,
+    each on one thread."""
+    build()
+    L = C.CDLL(CTX_LIB)
+    out = {}
+    for name in ("ctx_std_sort_f64", "ctx_std_stable_sort_f64"):
+        f = getattr(L, name)
+        f.restype = C.c_double
+        f.argtypes = [C.c_void_p, C.c_size_t]
+        a = np.array(x, dtype=np.float64, copy=True)
+        out[name[4:-4]] = float(f(a.ctypes.data, a.size))
+        assert np.all(a[1:] >= a[:-1])
+    return out
 
 
 _lib = None
