@@ -133,6 +133,23 @@ ipls_status ipls_sort(void* keys, uint32_t* payload, size_t n, ipls_dtype dtype,
 ipls_status ipls_sort_ex(void* keys, uint32_t* payload, size_t n, ipls_dtype dtype, const ipls_params* p,
                          void* workspace, size_t workspace_bytes, ipls_stats* stats, void* stream);
 
+/* Allocation-free variant of ipls_sort_ex, for callers that cannot allocate device memory (code
+ * that must not call hipMalloc, serving loops that forbid allocation).  Same arguments, result and
+ * statistics as ipls_sort_ex with no workspace; the ping-pong copy of keys and payload and every
+ * per-level table are carved from a static device array of IPLS_NOALLOC_SCRATCH_BYTES that each
+ * GPU the library runs on holds until the process ends.  The call allocates nothing: no device
+ * or pinned memory, no stream or event; it runs entirely on `stream` and returns after the sort
+ * has completed.  n above IPLS_NOALLOC_MAX_KEYS returns IPLS_ERR_UNSUPPORTED before any work;
+ * IPLS_ERR_OOM means the parameters' tables did not fit the array.  Every call on one GPU uses
+ * the same array and leaves its last contents there (each call clears what must start at zero).
+ * Two calls on one GPU would race on it if they overlapped; the library prevents that: calls
+ * from several host threads are serialised, and every call, also a failing one, returns only
+ * after its stream has drained. */
+#define IPLS_NOALLOC_MAX_KEYS (1ull << 22)
+#define IPLS_NOALLOC_SCRATCH_BYTES (128ull << 20)
+ipls_status ipls_sort_noalloc(void* keys, uint32_t* payload, size_t n, ipls_dtype dtype, const ipls_params* p,
+                              ipls_stats* stats, void* stream);
+
 /* Sort nseg independent segments [seg_offsets[s], seg_offsets[s+1]) of one array, each exactly as
  * ipls_sort would sort it alone (sample offsets are relative to the segment's start).
  * seg_offsets: device array of nseg+1 non-decreasing uint64; keys span seg_offsets[nseg] elements.

@@ -20,7 +20,7 @@ KERNEL_SCATTER, KERNEL_CLASSIFY, KERNEL_BASE = 0, 1, 2
 STATUS = {0: "IPLS_OK", 1: "IPLS_ERR_INVALID", 2: "IPLS_ERR_DTYPE", 3: "IPLS_ERR_OOM", 4: "IPLS_ERR_HIP",
           5: "IPLS_ERR_DEVICE", 6: "IPLS_ERR_UNSUPPORTED"}
 
-EXPORTS = ["ipls_default_params", "ipls_sort", "ipls_sort_ex", "ipls_sort_segmented", "ipls_fit_model",
+EXPORTS = ["ipls_default_params", "ipls_sort", "ipls_sort_ex", "ipls_sort_noalloc", "ipls_sort_segmented", "ipls_fit_model",
            "ipls_partition", "ipls_l2pl_train", "ipls_l2pl_grad", "ipls_workspace_bytes", "ipls_stream_status",
            "ipls_status_string", "ipls_profile_enable", "ipls_profile_read", "ipls_autotune_segmented",
            "ipls_server_default_config", "ipls_server_create", "ipls_server_reserve", "ipls_server_submit",
@@ -107,6 +107,7 @@ def load(path: str = LIB_PATH):
         "ipls_default_params": (None, [C.POINTER(Params)]),
         "ipls_sort": (i32, [P, P, sz, i32, P]),
         "ipls_sort_ex": (i32, [P, P, sz, i32, C.POINTER(Params), P, sz, C.POINTER(Stats), P]),
+        "ipls_sort_noalloc": (i32, [P, P, sz, i32, C.POINTER(Params), C.POINTER(Stats), P]),
         "ipls_sort_segmented": (i32, [P, P, P, sz, i32, C.POINTER(Params), C.POINTER(Stats), P]),
         "ipls_fit_model": (i32, [P, sz, i32, i32, u32, P, P]),
         "ipls_partition": (i32, [P, P, sz, i32, C.POINTER(Params), P, P, P]),
@@ -201,6 +202,21 @@ def sort_(keys, payload=None, params: Params | None = None, workspace=None, stre
     rc = load().ipls_sort_ex(_ptr(keys), _ptr(payload), keys.numel(), _dtype_code(keys),
                              C.byref(params) if params is not None else None, ws, wsb, C.byref(st), _stream(stream))
     _check(rc, "ipls_sort_ex")
+    return st.as_dict() if stats else None
+
+
+NOALLOC_MAX_KEYS = 1 << 22  # IPLS_NOALLOC_MAX_KEYS
+
+
+def sort_noalloc_(keys, payload=None, params: Params | None = None, stream=None, stats: bool = False):
+    """ipls_sort_noalloc: as sort_ without a workspace, with every buffer carved from the library's
+    static device scratch array (no allocation); at most NOALLOC_MAX_KEYS keys."""
+    _check_tensor(keys, "keys")
+    _check_payload(payload, keys)
+    st = Stats()
+    rc = load().ipls_sort_noalloc(_ptr(keys), _ptr(payload), keys.numel(), _dtype_code(keys),
+                                  C.byref(params) if params is not None else None, C.byref(st), _stream(stream))
+    _check(rc, "ipls_sort_noalloc")
     return st.as_dict() if stats else None
 
 

@@ -40,9 +40,25 @@ struct Buf {
     size_t cap = 0;
 };
 
+// A call of the allocation-free entry point carves every buffer from its GPU's static scratch
+// array instead of allocating: t_arena is set for the duration of that call on its thread.
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, off = 0;
+};
+thread_local Arena* t_arena = nullptr;
+
 ipls_status ensure(Buf& b, size_t bytes) {
     if (b.p && bytes <= b.cap) return IPLS_OK;
     size_t want = std::max<size_t>(bytes + bytes / 4, 4096);
+    if (t_arena) {
+        want = (want + 255) & ~(size_t)255;
+        if (want > t_arena->cap - t_arena->off) return IPLS_ERR_OOM;  // the scratch array is full
+        b.p = t_arena->base + t_arena->off;
+        b.cap = want;
+        t_arena->off += want;
+        return IPLS_OK;
+    }
     if (b.p) {
         (void)hipDeviceSynchronize();
         (void)hipFree(b.p);
@@ -64,9 +80,21 @@ struct Depth {
         fit_map, chunk_map, models, masks, hist, bstart, tile_pref, chunk_sum, chunk_pref, sample, leaves, seg, roots,
         leaf_first, leaf_last, eqinfo, rsample, copy, copy_off, copy_map, treeflag, sample2, children[2], spans, cls, wide;
     Plan* plan_h = nullptr;     // pinned, coherent: k_plan writes it directly
-    Plan* plan_hd = nullptr;    // its device address
+    Plan* plan_hd = nullptr;    // its device address (null: the plan is copied into plan_copy)
     uint64_t plan_seq = 0;      // k_plan launches so far
+    Plan plan_copy;             // host copy of the plan for contexts that allocate nothing
 };
+
+template <class F>
+void for_each_buf(Depth& D, F&& f) {
+    for (Buf* b : {&D.scratch, &D.spay, &D.items[0], &D.items[1], &D.base[0], &D.base[1], &D.sample_base, &D.counters,
+                   &D.plan, &D.tile_off, &D.sample_off, &D.fit_off, &D.chunk_off, &D.tile_map, &D.fit_map,
+                   &D.chunk_map, &D.models, &D.masks, &D.hist, &D.bstart, &D.tile_pref, &D.chunk_sum, &D.chunk_pref,
+                   &D.sample, &D.leaves, &D.seg, &D.roots, &D.leaf_first, &D.leaf_last, &D.eqinfo, &D.rsample,
+                   &D.copy, &D.copy_off, &D.copy_map, &D.treeflag, &D.sample2, &D.children[0], &D.children[1],
+                   &D.spans, &D.cls, &D.wide})
+        f(*b);
+}
 
 // One engine context: the cached buffers of every nesting depth.  Calls on one context are
 // serialised by its mutex; separate contexts (the server's lanes) run concurrently.
@@ -79,6 +107,9 @@ struct Device {
     hipStream_t side = nullptr;
     hipEvent_t ev_base[2] = {nullptr, nullptr};
     hipEvent_t ev_defer = nullptr;  // a level's worklist, which a deferred base launch waits for
+    // The allocation-free entry point's context: buffers come from the scratch array, the plan is
+    // copied back, and everything runs on the caller's stream (no side stream, no events).
+    bool noalloc = false;
 };
 
 void release(Buf& b) {
@@ -89,14 +120,8 @@ void release(Buf& b) {
 
 void release_device(Device& dv) {
     for (Depth& D : dv.depth) {
-        for (Buf* b : {&D.scratch, &D.spay, &D.items[0], &D.items[1], &D.base[0], &D.base[1], &D.sample_base, &D.counters, &D.plan,
-                       &D.tile_off, &D.sample_off, &D.fit_off, &D.chunk_off, &D.tile_map, &D.fit_map, &D.chunk_map,
-                       &D.models, &D.masks, &D.hist, &D.bstart, &D.tile_pref, &D.chunk_sum, &D.chunk_pref, &D.sample,
-                       &D.leaves, &D.seg, &D.roots, &D.leaf_first, &D.leaf_last, &D.eqinfo, &D.rsample, &D.copy,
-                       &D.copy_off, &D.copy_map, &D.treeflag, &D.sample2, &D.children[0], &D.children[1],
-                       &D.spans, &D.cls, &D.wide})
-            release(*b);
-        if (D.plan_h) (void)hipHostFree(D.plan_h);
+        for_each_buf(D, [](Buf& b) { release(b); });
+        if (D.plan_h && D.plan_h != &D.plan_copy) (void)hipHostFree(D.plan_h);
         D.plan_h = nullptr;
         D.plan_hd = nullptr;
     }
@@ -159,7 +184,7 @@ struct ProfScope {
     double bytes;
     hipStream_t s;
     ProfScope(int k, double by, hipStream_t st) : kernel(k), bytes(by), s(st) {
-        if (g_prof.mask & (1 << k)) {
+        if ((g_prof.mask & (1 << k)) && !t_arena) {
             {
                 std::lock_guard<std::mutex> g(g_prof_mu);
                 a = prof_event();
@@ -428,7 +453,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     // base launch of level L + 1 reads (the seeds count as level -1).  The top-level sort runs those
     // launches on the side stream; the main stream waits for them only before the list is written
     // again, two levels later, and at the end of the sort.
-    const bool overlap = top;
+    const bool overlap = top && !dv.noalloc;
     if (overlap && !dv.side) {
         HIP_TRY(hipStreamCreateWithFlags(&dv.side, hipStreamNonBlocking));
         for (hipEvent_t* e : {&dv.ev_base[0], &dv.ev_base[1], &dv.ev_defer})
@@ -452,7 +477,10 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     ST_TRY(ensure(D.chunk_off, (item_cap + 1) * 8));
     ST_TRY(ensure(D.sample_base, item_cap * sizeof(BaseItem)));
     ST_TRY(ensure(D.wide, item_cap * 4));
-    if (!D.plan_h) {
+    if (!D.plan_h && dv.noalloc) {
+        D.plan_h = &D.plan_copy;
+        D.plan_hd = nullptr;
+    } else if (!D.plan_h) {
         HIP_TRY(hipHostMalloc((void**)&D.plan_h, sizeof(Plan), hipHostMallocMapped | hipHostMallocCoherent));
         std::memset(D.plan_h, 0, sizeof(Plan));
         HIP_TRY(hipHostGetDevicePointer((void**)&D.plan_hd, D.plan_h, 0));
@@ -499,7 +527,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                                   (const CopyItem*)D.copy.p, (uint64_t*)D.copy_off.p, copy_cap, prev_children,
                                   D.plan_hd, ++D.plan_seq, (BaseItem*)D.sample_base.p, (uint32_t*)D.wide.p);
         LAUNCH_CHECK();
-        HIP_TRY(wait_plan(s, (const volatile Plan*)D.plan_h, D.plan_seq));
+        if (D.plan_hd) HIP_TRY(wait_plan(s, (const volatile Plan*)D.plan_h, D.plan_seq));
         if (((volatile Plan*)D.plan_h)->seq != D.plan_seq) {
             // not visible yet through the mapped buffer: copy the device's plan instead
             HIP_TRY(hipMemcpyAsync(D.plan_h, D.plan.p, sizeof(Plan), hipMemcpyDeviceToHost, s));
@@ -852,6 +880,11 @@ extern "C" size_t ipls_workspace_bytes(size_t n, ipls_dtype dtype, int has_paylo
 
 namespace ipls {
 
+__global__ void k_single_segment(uint64_t* off, uint64_t n) {
+    off[0] = 0;
+    off[1] = n;
+}
+
 ipls_status sort_single(Device& dv, void* keys, uint32_t* payload, size_t n, ipls_dtype dtype, const ipls_params* p,
                         void* workspace, size_t workspace_bytes, ipls_stats* stats, hipStream_t s) {
     if (dtype != IPLS_F64 && dtype != IPLS_F32 && dtype != IPLS_U64) return IPLS_ERR_DTYPE;
@@ -867,7 +900,9 @@ ipls_status sort_single(Device& dv, void* keys, uint32_t* payload, size_t n, ipl
         return IPLS_ERR_INVALID;
     if (stats) std::memset(stats, 0, sizeof(*stats));
     if (n < 2) return IPLS_OK;
-    std::lock_guard<std::mutex> g(dv.mu);
+    // the allocation-free context is locked by its entry point, which also sets up its buffers
+    std::unique_lock<std::mutex> g(dv.mu, std::defer_lock);
+    if (!dv.noalloc) g.lock();
     Run run;
     run.p = prm;
     run.s = s;
@@ -876,14 +911,20 @@ ipls_status sort_single(Device& dv, void* keys, uint32_t* payload, size_t n, ipl
     Depth& D0 = dv.depth[0];
     st = ensure(D0.seg, 2 * sizeof(uint64_t));
     if (st != IPLS_OK) return st;
-    // single segment [0, n): offsets staged through the context's pinned host buffer
-    if (!dv.seg_h && hipHostMalloc((void**)&dv.seg_h, 2 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
-        return IPLS_ERR_HIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return IPLS_ERR_HIP;
-    dv.seg_h[0] = 0;
-    dv.seg_h[1] = n;
-    if (hipMemcpyAsync(D0.seg.p, dv.seg_h, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, s) != hipSuccess)
-        return IPLS_ERR_HIP;
+    if (dv.noalloc) {
+        // single segment [0, n): offsets written by a one-thread kernel (no host staging buffer)
+        k_single_segment<<<1, 1, 0, s>>>((uint64_t*)D0.seg.p, n);
+        if (hipGetLastError() != hipSuccess) return IPLS_ERR_HIP;
+    } else {
+        // single segment [0, n): offsets staged through the context's pinned host buffer
+        if (!dv.seg_h && hipHostMalloc((void**)&dv.seg_h, 2 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
+            return IPLS_ERR_HIP;
+        if (hipStreamSynchronize(s) != hipSuccess) return IPLS_ERR_HIP;
+        dv.seg_h[0] = 0;
+        dv.seg_h[1] = n;
+        if (hipMemcpyAsync(D0.seg.p, dv.seg_h, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, s) != hipSuccess)
+            return IPLS_ERR_HIP;
+    }
     st = dispatch(dv, run, keys, payload, n, (const uint64_t*)D0.seg.p, 1, workspace);
     if (st != IPLS_OK && dv.side) (void)hipStreamSynchronize(dv.side);
     st = finish(st, s);
@@ -928,6 +969,40 @@ ipls_status sort_multi(Device& dv, void* keys, uint32_t* payload, const uint64_t
 struct Engine {
     Device dev;
 };
+
+// The allocation-free entry point's scratch array and its per-GPU context.  In host code `scratch`
+// names a host-side stand-in: its device address on the current GPU comes from
+// hipGetSymbolAddress, once per GPU, and only that address is used.
+constexpr size_t kNoAllocBytes = IPLS_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+struct NoAllocCtx {
+    Device dv;
+    char* ptr = nullptr;  // scratch's address on this GPU
+};
+std::unordered_map<int, NoAllocCtx*> g_noalloc;  // by device, guarded by g_mu
+
+ipls_status noalloc_ctx(NoAllocCtx** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return IPLS_ERR_HIP;
+    std::lock_guard<std::mutex> g(g_mu);
+    auto it = g_noalloc.find(dev);
+    if (it != g_noalloc.end()) {
+        *out = it->second;
+        return IPLS_OK;
+    }
+    char* ptr = nullptr;
+    if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return IPLS_ERR_HIP;
+    }
+    NoAllocCtx* c = new NoAllocCtx();
+    c->dv.noalloc = true;
+    c->ptr = ptr;
+    g_noalloc[dev] = c;
+    *out = c;
+    return IPLS_OK;
+}
 
 Engine* engine_new() { return new Engine(); }
 
@@ -1096,6 +1171,32 @@ ipls_status ipls_l2pl_grad(const double* x, size_t S, uint32_t K, uint32_t M, co
     std::lock_guard<std::mutex> g(dv.mu);
     ipls_status st = l2pl_entry(dv, s, x, S, K, M, 0, nullptr, nullptr, nullptr, ab, grad, loss);
     return finish(st, s);
+}
+
+// ------------------------------------------------------------------ allocation-free entry point
+// ipls_sort_noalloc: the buffers of a sort (the ping-pong copy of the keys and payload and every
+// per-level table) are carved from `scratch`, a static device array that each GPU holds until the
+// process ends; the call allocates nothing.
+ipls_status ipls_sort_noalloc(void* keys, uint32_t* payload, size_t n, ipls_dtype dtype, const ipls_params* p,
+                              ipls_stats* stats, void* stream) {
+    if (dtype != IPLS_F64 && dtype != IPLS_F32 && dtype != IPLS_U64) return IPLS_ERR_DTYPE;
+    if (n > IPLS_NOALLOC_MAX_KEYS) return IPLS_ERR_UNSUPPORTED;  // larger than the scratch array serves
+    ipls::NoAllocCtx* c = nullptr;
+    const ipls_status st0 = ipls::noalloc_ctx(&c);
+    if (st0 != IPLS_OK) return st0;
+    std::lock_guard<std::mutex> g(c->dv.mu);  // held for the whole sort (sort_single does not take it)
+    // every call starts carving from the array's beginning: the previous call's buffers are
+    // forgotten (never freed: they are the array's own memory)
+    for (ipls::Depth& D : c->dv.depth) ipls::for_each_buf(D, [](ipls::Buf& b) { b = ipls::Buf{}; });
+    ipls::Arena arena;
+    arena.base = c->ptr;
+    arena.cap = ipls::kNoAllocBytes;
+    ipls::t_arena = &arena;
+    const ipls_status st = ipls::sort_single(c->dv, keys, payload, n, dtype, p, nullptr, 0, stats, (hipStream_t)stream);
+    ipls::t_arena = nullptr;
+    // a failed call may have left work on the stream: it must not outlive the call on the array
+    if (st != IPLS_OK) (void)hipStreamSynchronize((hipStream_t)stream);
+    return st;
 }
 
 void ipls_profile_enable(int mask) {

@@ -123,3 +123,14 @@ def test_wrapper_refuses_a_bad_payload_before_any_launch(monkeypatch, entry, bad
         else:
             getattr(ipls, entry)(keys, pay)
 
+
+def test_noalloc_entry_point_refuses_sizes_beyond_its_array_without_a_gpu():
+    # the dtype and size checks come before any HIP call, so they answer on a host without a GPU
+    if not os.path.exists(ipls.LIB_PATH):
+        pytest.skip("libipls.so not built")
+    lib = ipls.load()
+    assert lib.ipls_sort_noalloc(ctypes.c_void_p(4096), None, ipls.NOALLOC_MAX_KEYS + 1, ipls.F64, None, None,
+                                 None) == 6  # IPLS_ERR_UNSUPPORTED
+    assert lib.ipls_sort_noalloc(ctypes.c_void_p(4096), None, 100, 7, None, None, None) == 2  # IPLS_ERR_DTYPE
+    with open(os.path.join(ROOT, "include", "ipls.h")) as f:
+        assert f"#define IPLS_NOALLOC_MAX_KEYS (1ull << {ipls.NOALLOC_MAX_KEYS.bit_length() - 1})" in f.read()
