@@ -544,26 +544,26 @@ __device__ inline void base_large_keys(const BaseItem& bi, typename Key<DT>::T* 
     const uint32_t n = bi.n;
     const typename KT::T* src = bi.from_scratch ? skeys : keys;
     const uint32_t wbase = wave * kWave * IPT;
+    // lanes past the bucket's end load its first key (n >= 1): min, max and the shared low bits
+    // need no masking; the merge sort below pads them with kPad
     O o[IPT];
     {
         typename KT::T v[IPT];
 #pragma unroll
         for (int r = 0; r < IPT; ++r) {
             const uint32_t j = wbase + r * kWave + lane;
-            if (j < n) v[r] = __builtin_nontemporal_load(&src[bi.lo + j]);
+            v[r] = __builtin_nontemporal_load(&src[bi.lo + (j < n ? j : 0u)]);
         }
 #pragma unroll
-        for (int r = 0; r < IPT; ++r) o[r] = wbase + r * kWave + lane < n ? (O)KT::ord(v[r]) : kPad;
+        for (int r = 0; r < IPT; ++r) o[r] = (O)KT::ord(v[r]);
     }
-    const O oref = (O)KT::ord(src[bi.lo]);  // n >= 1
-    O mn = kPad, mx = 0, ov = 0;
+    const O oref = (O)KT::ord(src[bi.lo]);
+    O mn = o[0], mx = o[0], ov = 0;
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
-        if (wbase + r * kWave + lane < n) {
-            mn = o[r] < mn ? o[r] : mn;
-            mx = o[r] > mx ? o[r] : mx;
-            ov |= (O)(o[r] - oref);
-        }
+        mn = o[r] < mn ? o[r] : mn;
+        mx = o[r] > mx ? o[r] : mx;
+        ov |= (O)(o[r] - oref);
     }
     mn = (O)~wave_max((O)~mn);
     mx = wave_max(mx);
@@ -632,7 +632,10 @@ __device__ inline void base_large_keys(const BaseItem& bi, typename Key<DT>::T* 
     if (!exact && most > kSubMax) {
         // merge sort: keys to LDS at their input positions (padding keys at the end), then sort
 #pragma unroll
-        for (int r = 0; r < IPT; ++r) s_k[pad16(wbase + r * kWave + lane)] = o[r];
+        for (int r = 0; r < IPT; ++r) {
+            const uint32_t j = wbase + r * kWave + lane;
+            s_k[pad16(j)] = j < n ? o[r] : kPad;
+        }
         __syncthreads();
         merge_sort_lds<O, false, MT>(s_k, nullptr, (int)tid, tid < (uint32_t)MT);
 #pragma unroll

@@ -1511,8 +1511,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(CLS && 
             cnt += cw;
         }
     }
-    uint64_t tot;
-    const uint32_t loc = (uint32_t)block_exclusive_sum<uint64_t>(cnt, s_scan, &tot);
+    uint32_t tot;  // a tile's counts fit 32 bits
+    const uint32_t loc = block_exclusive_sum<uint32_t>(cnt, (uint32_t*)s_scan, &tot);
     if (b < K) {
         // each wave's first slot of bucket b in the staging buffer: one LDS read per key below
 #pragma unroll
@@ -1586,9 +1586,23 @@ __global__ __launch_bounds__(256) void k_worklist(const Item* items, uint64_t nu
     if (b <= (uint32_t)kBaseClasses) s_lc[b] = 0;
     if (b == 0) s_lkeys = 0;
     const uint64_t i0 = (uint64_t)blockIdx.x * IPW;
+    // the next item's model kind, bucket size and start are loaded while this one is processed
+    uint32_t kind_n = 0;
+    uint64_t c_n = 0, lo_n = 0;
+    auto prefetch = [&](uint64_t i) {
+        if (i < num_items && b < K) {
+            kind_n = models[i].kind;
+            c_n = hist[i * K + b];
+            lo_n = items[i].lo + bstart[i * K + b];
+        }
+    };
+    prefetch(i0);
     for (int j = 0; j < IPW; ++j) {
         const uint64_t i = i0 + j;
         if (i >= num_items) break;  // the same for the whole workgroup
+        const uint32_t kind = kind_n;
+        const uint64_t c_i = c_n, lo_i = lo_n;
+        if (j + 1 < IPW) prefetch(i + 1);
         const ChildSpan sp = spans ? spans[i] : ChildSpan{0u, 0u};
         if (b < kMaxBuckets) s_ent[b] = -1;
         __syncthreads();
@@ -1599,11 +1613,9 @@ __global__ __launch_bounds__(256) void k_worklist(const Item* items, uint64_t nu
         uint64_t c = 0, lo = 0;
         bool breaker = false;
         if (b < K) {
-            const uint64_t g = i * K + b;
-            const uint32_t kind = models[i].kind;
             if (kind != kKindClosedKeep && kind != kKindClosedMove) {
-                c = hist[g];
-                lo = items[i].lo + bstart[g];
+                c = c_i;
+                lo = lo_i;
                 // an equality bucket holds one value: closed here; moved back if it sits in the scratch buffer
                 const uint32_t neq = kind == kKindLinear ? models[i].neq : 0u;
                 bool is_eq = false;

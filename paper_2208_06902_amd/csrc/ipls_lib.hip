@@ -13,6 +13,7 @@
 #include <cstring>
 #include <mutex>
 #include <unordered_map>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/ipls.h"
@@ -23,7 +24,8 @@ namespace ipls {
 namespace {
 
 constexpr uint32_t kSmallS = kFitLds;  // samples up to this size are fitted in one workgroup's LDS
-constexpr int kWorklistItems = 8;      // items per k_worklist workgroup
+constexpr int kWorklistItems = 8;      // items per k_worklist workgroup at levels of many items
+constexpr uint64_t kWorklistOneItem = 2048;  // up to this many items: one item per workgroup
 constexpr uint64_t kDeferBaseItems = 2048;  // levels of at least this many items run before the previous level's base case
 constexpr uint32_t kFitChunk = 2048;   // windows per workgroup in the multi-round fit
 constexpr uint32_t kCand = 15;         // candidate widths per fit round
@@ -749,11 +751,21 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             HIP_TRY(hipStreamWaitEvent(s, dv.ev_base[par], 0));
             base_pending[par] = false;
         }
-        k_worklist<kWorklistItems><<<(unsigned)((ni + kWorklistItems - 1) / kWorklistItems), 256, 0, s>>>(
-            items, ni, models, (const uint64_t*)D.hist.p, (const uint64_t*)D.bstart.p, K, T_, src_scratch ? 0 : 1,
-            (Item*)D.items[cur ^ 1].p, (BaseItem*)D.base[par].p, bl, cnt, C_ITEMS0 + (cur ^ 1), item_cap,
-            (CopyItem*)D.copy.p, copy_cap, spans, children, (top && level == 0 && ni == 1) ? cnt + C_L1MAX : nullptr);
-        LAUNCH_CHECK();
+        {
+            // a workgroup per item while they all fit the GPU at once; beyond that several items a
+            // workgroup, so that thousands of workgroups do not queue on the same device counters
+            auto wl = [&](auto ipw) {
+                constexpr int W = decltype(ipw)::value;
+                k_worklist<W><<<(unsigned)((ni + W - 1) / W), 256, 0, s>>>(
+                    items, ni, models, (const uint64_t*)D.hist.p, (const uint64_t*)D.bstart.p, K, T_,
+                    src_scratch ? 0 : 1, (Item*)D.items[cur ^ 1].p, (BaseItem*)D.base[par].p, bl, cnt,
+                    C_ITEMS0 + (cur ^ 1), item_cap, (CopyItem*)D.copy.p, copy_cap, spans, children,
+                    (top && level == 0 && ni == 1) ? cnt + C_L1MAX : nullptr);
+            };
+            if (ni <= kWorklistOneItem) wl(std::integral_constant<int, 1>{});
+            else wl(std::integral_constant<int, kWorklistItems>{});
+            LAUNCH_CHECK();
+        }
         if (defer_base) {
             HIP_TRY(hipEventRecord(dv.ev_defer, s));
             HIP_TRY(hipStreamWaitEvent(sb, dv.ev_defer, 0));
