@@ -33,6 +33,7 @@ SEEDS = {"normal": 2, "lognormal": 3, "exponential": 4, "mixgauss": 5, "uniform_
 # the scatter and the helpers it uses (the base case lives in ipls_base.h and does not count)
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2208_06902_amd", "csrc", f) for f in ("ipls_kernels.h", "ipls_device.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scatter_traffic.json")
+PROFILE_LEVELS = 16  # IPLS_PROFILE_LEVELS
 
 
 def kernel_hash() -> str:
@@ -614,6 +615,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     sc_n, sc_ms, sc_bytes = ipls.profile_read(ipls.KERNEL_SCATTER)
+    sc_lv = [ipls.profile_read_level(ipls.KERNEL_SCATTER, lv) for lv in range(PROFILE_LEVELS)]
     ipls.profile_enable(False)
     gpu_ms = ev0.elapsed_time(ev1)
     # counting and base case: the same steps again (outside the timed region), profiled
@@ -625,6 +627,7 @@ def main():
     torch.cuda.synchronize()
     cl_n, cl_ms, cl_bytes = ipls.profile_read(ipls.KERNEL_CLASSIFY)
     bc_n, bc_ms, bc_bytes = ipls.profile_read(ipls.KERNEL_BASE)
+    cl_lv = [ipls.profile_read_level(ipls.KERNEL_CLASSIFY, lv) for lv in range(PROFILE_LEVELS)]
     ipls.profile_enable(False)
     steps_ms = [a.elapsed_time(b) for a, b in per_step_ms]
     ms_per_step = gpu_ms / args.steps
@@ -662,6 +665,19 @@ def main():
         "algorithmic_bytes_per_launch": round(sc_bytes / sc_n) if sc_n else None,
     }
     pass_gbs = (sc_bytes + cl_bytes) / ((sc_ms + cl_ms) / 1e3) / 1e9 if (sc_ms + cl_ms) > 0 else None
+    # each level's distribution pass (counting + scatter), per step: the keys it moves, its time and
+    # its rate against peak (the timed steps give the scatter, the profiled repeat the counting)
+    pass_by_level = []
+    for lv in range(PROFILE_LEVELS):
+        (sn, sms, sby), (cn, cms, cby) = sc_lv[lv], cl_lv[lv]
+        if sn == 0 or cn == 0:
+            continue
+        ms_lv = (sms + cms) / args.steps
+        gb_lv = (sby + cby) / args.steps / 1e9
+        pass_by_level.append({"level": lv, "scatter_launches_per_step": round(sn / args.steps, 2),
+                              "algorithmic_gb": round(gb_lv, 3), "ms": round(ms_lv, 4),
+                              "gbs": round(gb_lv / (ms_lv / 1e3), 1),
+                              "frac_of_peak": round(gb_lv / (ms_lv / 1e3) / HBM_PEAK_GBS, 4)})
 
     cpu_baseline = None
     if not args.no_cpu_baseline:
@@ -715,6 +731,7 @@ def main():
         "cpu_baseline": cpu_baseline,
         "pass_gbs": round(pass_gbs, 1) if pass_gbs else None,
         "pass_frac_of_peak": round(pass_gbs / HBM_PEAK_GBS, 4) if pass_gbs else None,
+        "pass_by_level": pass_by_level,
         "classify_gbs": round(cl_bytes / (cl_ms / 1e3) / 1e9, 1) if cl_ms > 0 else None,
         "base_case_ms_per_step": round(bc_ms / args.steps, 4),
         "scatter_ms_per_step": round(sc_ms / args.steps, 4),

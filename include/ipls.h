@@ -205,6 +205,13 @@ const char* ipls_status_string(ipls_status st);
  * and write).  Enabling resets the counters. */
 void ipls_profile_enable(int mask);
 void ipls_profile_read(int kernel, uint64_t* launches, double* ms, double* bytes);
+/* The same figures for the launches of one recursion level (0 .. IPLS_PROFILE_LEVELS - 1; deeper
+ * levels count in the last).  The counting and scatter launches of level L partition the buckets
+ * that level L - 1 made (level 0: the input); a base-case launch counts in the level whose pass
+ * made its buckets (level 0 for arrays or segments that needed no pass).  Levels out of range
+ * leave the outputs unchanged. */
+#define IPLS_PROFILE_LEVELS 16
+void ipls_profile_read_level(int kernel, int level, uint64_t* launches, double* ms, double* bytes);
 
 /* ---------------------------------------------------------------- batched form: autotuner
  * Picks num_buckets (K), base_case_max (T) and tile_keys for the segmented sort of a batch shaped

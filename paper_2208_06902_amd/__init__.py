@@ -22,7 +22,7 @@ STATUS = {0: "IPLS_OK", 1: "IPLS_ERR_INVALID", 2: "IPLS_ERR_DTYPE", 3: "IPLS_ERR
 
 EXPORTS = ["ipls_default_params", "ipls_sort", "ipls_sort_ex", "ipls_sort_noalloc", "ipls_sort_segmented", "ipls_fit_model",
            "ipls_partition", "ipls_l2pl_train", "ipls_l2pl_grad", "ipls_workspace_bytes", "ipls_stream_status",
-           "ipls_status_string", "ipls_profile_enable", "ipls_profile_read", "ipls_autotune_segmented",
+           "ipls_status_string", "ipls_profile_enable", "ipls_profile_read", "ipls_profile_read_level", "ipls_autotune_segmented",
            "ipls_server_default_config", "ipls_server_create", "ipls_server_reserve", "ipls_server_submit",
            "ipls_server_wait", "ipls_server_poll", "ipls_server_release", "ipls_server_stats_get",
            "ipls_server_destroy"]
@@ -118,6 +118,7 @@ def load(path: str = LIB_PATH):
         "ipls_status_string": (C.c_char_p, [i32]),
         "ipls_profile_enable": (None, [i32]),
         "ipls_profile_read": (None, [i32, C.POINTER(u64), C.POINTER(dbl), C.POINTER(dbl)]),
+        "ipls_profile_read_level": (None, [i32, i32, C.POINTER(u64), C.POINTER(dbl), C.POINTER(dbl)]),
         "ipls_autotune_segmented": (i32, [P, P, sz, i32, i32, C.POINTER(Params), C.POINTER(Params),
                                           C.POINTER(TuneReport), P]),
         "ipls_server_default_config": (None, [C.POINTER(ServerConfig)]),
@@ -309,6 +310,13 @@ def profile_enable(on=True):
 def profile_read(kernel: int):
     n, ms, by = C.c_uint64(), C.c_double(), C.c_double()
     load().ipls_profile_read(kernel, C.byref(n), C.byref(ms), C.byref(by))
+    return int(n.value), float(ms.value), float(by.value)
+
+
+def profile_read_level(kernel: int, level: int):
+    """(launches, ms, bytes) of one kernel id's launches at one recursion level."""
+    n, ms, by = C.c_uint64(), C.c_double(), C.c_double()
+    load().ipls_profile_read_level(kernel, level, C.byref(n), C.byref(ms), C.byref(by))
     return int(n.value), float(ms.value), float(by.value)
 
 

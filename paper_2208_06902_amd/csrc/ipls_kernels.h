@@ -398,6 +398,81 @@ __global__ __launch_bounds__(256) void k_fmcd_small(const typename Key<DT>::T* s
     if (threadIdx.x == 0) models[i] = m;
 }
 
+// ------------------------------------------------------------------ sample, sort and fit in one launch
+// For a level whose samples all hold at most CAP keys and whose items take the plain FMCD line (no
+// equality buckets, no inherited samples), one workgroup per item does what k_sample, the sample
+// sort and k_fmcd_small do in three launches: it gathers the item's sample (the same strata and
+// offsets as k_sample), sorts it in LDS by the keys' order-preserving integers (a bitonic network,
+// padded to a power of two with the largest integer, which sorts after every key or ties with one
+// of the same bits) and fits the line on the sorted values.  Nothing else reads the sorted sample
+// on this path, so it is not written back.  The first expand_blocks workgroups build the tile and
+// chunk maps, as in k_sample.
+template <int DT, int CAP>
+__global__ __launch_bounds__(256) void k_sample_fit(const Item* items, uint64_t num_items, const uint64_t* sample_off,
+                                                    const typename Key<DT>::T* src, uint64_t seed, Model* models,
+                                                    uint32_t K, uint64_t expand_blocks, const uint64_t* tile_off,
+                                                    uint64_t total_tiles, uint32_t* tile_map,
+                                                    const uint64_t* chunk_off, uint64_t total_chunks,
+                                                    uint32_t* chunk_map) {
+    using KT = Key<DT>;
+    static_assert((CAP & (CAP - 1)) == 0, "power of two");
+    __shared__ uint64_t s_o[CAP];
+    if (blockIdx.x < expand_blocks) {
+        expand2(blockIdx.x, tile_off, total_tiles, tile_map, chunk_off, total_chunks, chunk_map, num_items);
+        return;
+    }
+    const uint64_t i = blockIdx.x - expand_blocks;
+    if (i >= num_items) return;
+    const Item it = items[i];
+    const uint64_t off = sample_off[i];
+    const uint32_t S = (uint32_t)(sample_off[i + 1] - off);  // 1 <= S <= CAP (the host checks the level's maximum)
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
+    uint32_t P = 1;
+    while (P < S) P <<= 1;
+    // gather: stratum j = [floor(j n / S), floor((j+1) n / S)), offset mix64(stream + (j+1) gamma)
+    const uint64_t q = it.n / S, r = it.n % S;
+    const uint64_t stream = mix64(seed ^ mix64(it.lo_rel * kGamma + it.n));
+    for (uint32_t j = tid; j < P; j += nt) {
+        uint64_t o = ~0ull;
+        if (j < S) {
+            const uint64_t a = j * q + ((uint64_t)j * r) / S;
+            const uint64_t b = (uint64_t)(j + 1) * q + ((uint64_t)(j + 1) * r) / S;
+            const uint64_t h = mix64(stream + (uint64_t)(j + 1) * kGamma);
+            o = (uint64_t)KT::ord(src[it.lo + a + h % (b - a)]);
+        }
+        s_o[j] = o;
+    }
+    __syncthreads();
+    // bitonic sort of s_o[0, P): stage (k, h) compares elements h apart inside blocks of k
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t h = k >> 1; h > 0; h >>= 1) {
+            const uint32_t hs = (uint32_t)__builtin_ctz(h);
+            for (uint32_t t = tid; t < P / 2; t += nt) {
+                const uint32_t lo = ((t >> hs) << (hs + 1)) | (t & (h - 1));
+                const uint64_t x = s_o[lo], y = s_o[lo + h];
+                if ((x > y) == ((lo & k) == 0)) {
+                    s_o[lo] = y;
+                    s_o[lo + h] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // the fit reads the sorted values as fp64, in place of their integers
+    double* sx = (double*)s_o;
+    for (uint32_t j = tid; j < S; j += nt) sx[j] = KT::val(KT::from_ord(s_o[j]));
+    __syncthreads();
+    Model m = {};
+    m.S = S;
+    bool usable = S >= 3 && isfinite(sx[0]) && isfinite(sx[S - 1]);
+    if (usable) {
+        fmcd_search([&](uint64_t j) { return sx[j]; }, S, K, &m.a, &m.b, &m.D);
+        usable = fit_usable(m.a, m.b);
+    }
+    if (!usable) model_degenerate(m);
+    if (tid == 0) models[i] = m;
+}
+
 // ------------------------------------------------------------------ sample inheritance
 // Children of every item partitioned by the FMCD line (one workgroup per item, thread c: bucket
 // c): the sorted sample's keys the line sends to bucket c form the range [lb(c), lb(c+1)), lb(c)

@@ -139,15 +139,18 @@ void release_device(Device& dv) {
 
 struct Prof {
     std::atomic<int> mask{0};  // bit k: record kernel id k
+    static constexpr int kLevels = 16;  // per-level figures for levels 0..15 (deeper ones count in 15)
     struct Rec {
         hipEvent_t a, b;
-        int kernel;
+        int kernel, level;
         double bytes;
     };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
     uint64_t launches[3] = {0, 0, 0};
     double ms[3] = {0, 0, 0}, bytes[3] = {0, 0, 0};
+    uint64_t lv_launches[3][kLevels] = {};
+    double lv_ms[3][kLevels] = {}, lv_bytes[3][kLevels] = {};
 };
 
 std::mutex g_mu;         // the map of default contexts
@@ -182,10 +185,12 @@ hipEvent_t prof_event() {
 
 struct ProfScope {
     hipEvent_t a = nullptr;
-    int kernel;
+    int kernel, level;
     double bytes;
     hipStream_t s;
-    ProfScope(int k, double by, hipStream_t st) : kernel(k), bytes(by), s(st) {
+    // level: the recursion level of the launch (for the base case, the level whose pass made its
+    // buckets)
+    ProfScope(int k, int lv, double by, hipStream_t st) : kernel(k), level(lv), bytes(by), s(st) {
         if ((g_prof.mask & (1 << k)) && !t_arena) {
             {
                 std::lock_guard<std::mutex> g(g_prof_mu);
@@ -203,16 +208,19 @@ struct ProfScope {
             }
             (void)hipEventRecord(b, s);
             std::lock_guard<std::mutex> g(g_prof_mu);
-            g_prof.pending.push_back({a, b, kernel, bytes});
+            g_prof.pending.push_back({a, b, kernel, level, bytes});
         }
     }
 };
 
+static int prof_level(int level) { return level < 0 ? 0 : level < Prof::kLevels ? level : Prof::kLevels - 1; }
+
 // Bytes of a kernel known only after its launch was recorded (the class bytes a scatter wrote).
-void prof_add_bytes(int kernel, double bytes) {
+void prof_add_bytes(int kernel, int level, double bytes) {
     if (!(g_prof.mask & (1 << kernel))) return;
     std::lock_guard<std::mutex> g(g_prof_mu);
     g_prof.bytes[kernel] += bytes;
+    g_prof.lv_bytes[kernel][prof_level(level)] += bytes;
 }
 
 // Accumulates the finished records (the caller has synchronised the streams they were on).
@@ -230,6 +238,10 @@ void prof_collect() {
             g_prof.launches[r.kernel] += 1;
             g_prof.ms[r.kernel] += ms;
             g_prof.bytes[r.kernel] += r.bytes;
+            const int lv = prof_level(r.level);
+            g_prof.lv_launches[r.kernel][lv] += 1;
+            g_prof.lv_ms[r.kernel][lv] += ms;
+            g_prof.lv_bytes[r.kernel][lv] += r.bytes;
         }
         g_prof.pool.push_back(r.a);
         g_prof.pool.push_back(r.b);
@@ -544,7 +556,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             ST_TRY(join());
             return IPLS_ERR_DEVICE;
         }
-        if (top && inherit) prof_add_bytes(0, (double)pl.inh_n);  // class bytes the last scatter wrote
+        if (top && inherit) prof_add_bytes(0, level - 1, (double)pl.inh_n);  // class bytes the last scatter wrote
         if (top && level > 0) {
             // the previous level's buckets that were not closed were partitioned
             const uint64_t closed_now = pl.closed - prev_closed;
@@ -578,7 +590,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         // just seen the plan, so the main stream's earlier work is done)
         const int bp = (level + 1) & 1;
         auto launch_level_base = [&](hipStream_t sl) -> ipls_status {
-            ProfScope ps(2, (double)pl.base_keys * 2.0 * (kb + (PAY ? 4 : 0)), sl);
+            ProfScope ps(2, level - 1, (double)pl.base_keys * 2.0 * (kb + (PAY ? 4 : 0)), sl);
             for (int c = 0; c < kBaseClasses; ++c)
                 ST_TRY((launch_base<DT, PAY>(sl, c, (const BaseItem*)D.base[bp].p + bl.off[c], pl.cls_count[c], keys,
                                              pay, scratch, spay)));
@@ -629,41 +641,51 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         const Item* items = (const Item*)D.items[cur].p;
         Model* models = (Model*)D.models.p;
 
-        // the sample gather and the tile and chunk maps, in one launch
         const uint64_t eb = (std::max(nt, nc) + 255) / 256;
-        k_sample<DT><<<(unsigned)(eb + (pl.total_samples + 255) / 256), 256, 0, s>>>(
-            items, ni, (const uint64_t*)D.sample_off.p, pl.total_samples, src, sample, P.seed, prev_children,
-            prev_sample, eb, (const uint64_t*)D.tile_off.p, nt, (uint32_t*)D.tile_map.p,
-            (const uint64_t*)D.chunk_off.p, nc, (uint32_t*)D.chunk_map.p);
-        LAUNCH_CHECK();
-        ST_TRY(sort_samples<DT>(dv, run, d, pl, sample));
-
-        // FMCD fit (with equality buckets: on the sample without the heavy values' runs)
         const EqInfo* eq = nullptr;
-        if (P.equality) {
-            ST_TRY(ensure(D.eqinfo, ni * sizeof(EqInfo)));
-            ST_TRY(ensure(D.rsample, pl.total_samples * kb));
-            k_heavy<DT><<<(unsigned)ni, 256, 0, s>>>((const T*)sample, (const uint64_t*)D.sample_off.p, ni, K,
-                                                     (EqInfo*)D.eqinfo.p, (T*)D.rsample.p);
-            LAUNCH_CHECK();
-            eq = (const EqInfo*)D.eqinfo.p;
-        }
-        ST_TRY((fit_level<DT>(D, s, ni, pl.max_S, pl.total_fit_chunks,
-                              eq ? (const T*)D.rsample.p : (const T*)sample, (const uint64_t*)D.sample_off.p,
-                              (const uint64_t*)D.fit_off.p, models, K, eq)));
         const uint32_t* tree = nullptr;
-        if (P.model == 3) {
-            ST_TRY(ensure(D.leaves, ni * 4 * kMaxLeaves * 8));
-            ST_TRY(ensure(D.treeflag, ni * 4));
-            k_tree<DT><<<(unsigned)ni, 256, 0, s>>>((const T*)sample, (const uint64_t*)D.sample_off.p, ni, K,
-                                                    (double*)D.leaves.p, (uint32_t*)D.treeflag.p);
+        if (P.model == 0 && !P.equality && !inherit && pl.max_S <= (uint64_t)kFitLdsTiny) {
+            // the plain FMCD line on samples of at most 1024 keys (the deeper levels' items): gather,
+            // sort and fit in one launch, with the tile and chunk maps (a workgroup's bitonic sort of
+            // a larger sample takes longer than the three launches)
+            k_sample_fit<DT, kFitLdsTiny><<<(unsigned)(eb + ni), 256, 0, s>>>(
+                items, ni, (const uint64_t*)D.sample_off.p, src, P.seed, models, K, eb, (const uint64_t*)D.tile_off.p,
+                nt, (uint32_t*)D.tile_map.p, (const uint64_t*)D.chunk_off.p, nc, (uint32_t*)D.chunk_map.p);
             LAUNCH_CHECK();
-            tree = (const uint32_t*)D.treeflag.p;
+        } else {
+            // the sample gather and the tile and chunk maps, in one launch
+            k_sample<DT><<<(unsigned)(eb + (pl.total_samples + 255) / 256), 256, 0, s>>>(
+                items, ni, (const uint64_t*)D.sample_off.p, pl.total_samples, src, sample, P.seed, prev_children,
+                prev_sample, eb, (const uint64_t*)D.tile_off.p, nt, (uint32_t*)D.tile_map.p,
+                (const uint64_t*)D.chunk_off.p, nc, (uint32_t*)D.chunk_map.p);
+            LAUNCH_CHECK();
+            ST_TRY(sort_samples<DT>(dv, run, d, pl, sample));
+
+            // FMCD fit (with equality buckets: on the sample without the heavy values' runs)
+            if (P.equality) {
+                ST_TRY(ensure(D.eqinfo, ni * sizeof(EqInfo)));
+                ST_TRY(ensure(D.rsample, pl.total_samples * kb));
+                k_heavy<DT><<<(unsigned)ni, 256, 0, s>>>((const T*)sample, (const uint64_t*)D.sample_off.p, ni, K,
+                                                         (EqInfo*)D.eqinfo.p, (T*)D.rsample.p);
+                LAUNCH_CHECK();
+                eq = (const EqInfo*)D.eqinfo.p;
+            }
+            ST_TRY((fit_level<DT>(D, s, ni, pl.max_S, pl.total_fit_chunks,
+                                  eq ? (const T*)D.rsample.p : (const T*)sample, (const uint64_t*)D.sample_off.p,
+                                  (const uint64_t*)D.fit_off.p, models, K, eq)));
+            if (P.model == 3) {
+                ST_TRY(ensure(D.leaves, ni * 4 * kMaxLeaves * 8));
+                ST_TRY(ensure(D.treeflag, ni * 4));
+                k_tree<DT><<<(unsigned)ni, 256, 0, s>>>((const T*)sample, (const uint64_t*)D.sample_off.p, ni, K,
+                                                        (double*)D.leaves.p, (uint32_t*)D.treeflag.p);
+                LAUNCH_CHECK();
+                tree = (const uint32_t*)D.treeflag.p;
+            }
+            if (P.model == 1 || P.model == 2)
+                ST_TRY((train_l2pl<DT>(D, s, ni, pl.max_S, pl.total_fit_chunks, (const T*)sample,
+                                       (const uint64_t*)D.sample_off.p, (const uint64_t*)D.fit_off.p, models, K, P.leaves,
+                                       P.train_iters)));
         }
-        if (P.model == 1 || P.model == 2)
-            ST_TRY((train_l2pl<DT>(D, s, ni, pl.max_S, pl.total_fit_chunks, (const T*)sample,
-                                   (const uint64_t*)D.sample_off.p, (const uint64_t*)D.fit_off.p, models, K, P.leaves,
-                                   P.train_iters)));
 
         // degenerate buckets and final model
         k_minmax<DT><<<(unsigned)nc, 256, 0, s>>>(items, (const uint64_t*)D.chunk_off.p, (const uint32_t*)D.chunk_map.p,
@@ -676,7 +698,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
 
         // classify + per-tile counts, scan of the counts, bucket starts
         {
-            ProfScope ps(1, (double)(pl.sum_n - pl.inh_n) * kb + (double)pl.inh_n, s);
+            ProfScope ps(1, level, (double)(pl.sum_n - pl.inh_n) * kb + (double)pl.inh_n, s);
             auto kc = tile == kTile ? k_classify_hist<DT, 8, kPassIPT> : k_classify_hist<DT, 4, kPassIPT>;
             kc<<<(unsigned)nc, tile / kPassIPT, 0, s>>>(
                 items, (const uint64_t*)D.tile_off.p, (const uint64_t*)D.chunk_off.p, (const uint32_t*)D.chunk_map.p,
@@ -721,7 +743,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
 
         // scatter
         {
-            ProfScope ps(0, (double)pl.sum_n * 2.0 * (kb + (PAY ? 4 : 0)), s);
+            ProfScope ps(0, level, (double)pl.sum_n * 2.0 * (kb + (PAY ? 4 : 0)), s);
             auto ks = inherit ? (tile == kTile ? k_scatter<DT, PAY, 8, kPassIPT, true> : k_scatter<DT, PAY, 4, kPassIPT, true>)
                               : (tile == kTile ? k_scatter<DT, PAY, 8, kPassIPT, false>
                                                : k_scatter<DT, PAY, 4, kPassIPT, false>);
@@ -1218,6 +1240,11 @@ void ipls_profile_enable(int mask) {
         g_prof.launches[k] = 0;
         g_prof.ms[k] = 0;
         g_prof.bytes[k] = 0;
+        for (int l = 0; l < Prof::kLevels; ++l) {
+            g_prof.lv_launches[k][l] = 0;
+            g_prof.lv_ms[k][l] = 0;
+            g_prof.lv_bytes[k][l] = 0;
+        }
     }
 }
 
@@ -1227,6 +1254,14 @@ void ipls_profile_read(int kernel, uint64_t* launches, double* ms, double* bytes
     if (launches) *launches = g_prof.launches[kernel];
     if (ms) *ms = g_prof.ms[kernel];
     if (bytes) *bytes = g_prof.bytes[kernel];
+}
+
+void ipls_profile_read_level(int kernel, int level, uint64_t* launches, double* ms, double* bytes) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (kernel < 0 || kernel > 2 || level < 0 || level >= Prof::kLevels) return;
+    if (launches) *launches = g_prof.lv_launches[kernel][level];
+    if (ms) *ms = g_prof.lv_ms[kernel][level];
+    if (bytes) *bytes = g_prof.lv_bytes[kernel][level];
 }
 
 }  // extern "C"

@@ -192,6 +192,26 @@ def test_first_level_partition_parity(dist, dtype):
     assert np.array_equal(host(pd, np.uint32), wpay)
 
 
+@pytest.mark.parametrize("dist,n,smax", [("normal", 700_003, 4096), ("lognormal2", 300_001, 1000),
+                                         ("uniform_int", 250_000, 4096), ("two_dups", 90_001, 700),
+                                         ("mixgauss", 6_000, 0)])
+def test_first_level_partition_capped_samples(dist, n, smax):
+    # samples of at most 4096 keys are gathered, sorted and fitted by one launch: the same line
+    # and the same partition as the oracle's
+    k = gen.make(dist, n, 29)
+    pay = gen.index_payload(k.size)
+    print(f"partition {dist} n={n} sample_max={smax}", flush=True)
+    kd, pd = dev(k), dev(pay)
+    counts, (a, b, D, degen) = ipls.partition_(kd, pd, ipls.default_params(sample_max=smax))
+    torch.cuda.synchronize()
+    want, wpay, wcounts, m = oracle.partition(k, pay, oracle.params(sample_max=smax))
+    assert degen == 0 and m.degenerate == 0
+    assert (a, b, D) == (m.a, m.b, m.D)
+    assert np.array_equal(host(counts, np.uint64), wcounts)
+    assert same_bits(host(kd, k.dtype), want)
+    assert np.array_equal(host(pd, np.uint32), wpay)
+
+
 @pytest.mark.parametrize("S", [3, 5, 100, 511, 8192, 16384, 16385, 20_000, 100_003, 1_000_000])
 @pytest.mark.parametrize("K", [4, 37, 256])
 def test_fmcd_fit_parity(S, K):
