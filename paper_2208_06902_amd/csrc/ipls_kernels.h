@@ -1627,161 +1627,249 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(CLS && 
 }
 
 // ------------------------------------------------------------------ worklist
-// Children of every item, one workgroup per item (thread b: bucket b): > T keys -> next level's
-// items; equality buckets are closed (moved back if they sit in the scratch buffer).  Buckets of
-// T/2 < n <= T keys go to the base case alone.  Runs of adjacent smaller buckets (1 <= n <= T/2,
-// not separated by a bucket with keys of another kind) are sorted together: buckets are in key
-// order and a key's bucket is a function of the key, so sorting the run as one range gives the
-// same result.  Inside a run, bucket b joins group floor(p_b / (T/2)) (p_b: the keys of the run
-// before it), so a group holds fewer than T keys; the group's first bucket emits it.  A group of
-// a single key already in the caller's buffer needs no work.
-template <int IPW>
-__global__ __launch_bounds__(256) void k_worklist(const Item* items, uint64_t num_items, const Model* models,
-                                                  const uint64_t* hist, const uint64_t* bstart, uint32_t K, uint32_t T,
-                                                  int dst_is_scratch, Item* next, BaseItem* base, BaseLayout bl,
-                                                  uint64_t* cnt, int next_slot, uint64_t next_cap, CopyItem* copy,
-                                                  uint64_t copy_cap, const ChildSpan* spans, const Child* children,
-                                                  uint64_t* l1max) {
-    // IPW items per workgroup: each item's entries are ranked among the workgroup's entries of
-    // their class in LDS, then the workgroup reserves its ranges with one device atomic per class
-    // (one per item made a level of thousands of items wait on the same few counters) and writes.
-    __shared__ AppendScratch sc;
-    __shared__ int s_ent[kMaxBuckets];  // bucket -> its entry in the child list with a usable line, or -1
-    __shared__ uint64_t s_e[kMaxBuckets], s_p[kMaxBuckets], s_sum[kMaxBuckets];
-    __shared__ uint64_t s_scan[16];
-    __shared__ int s_iscan[16];
-    __shared__ int s_prev[kMaxBuckets + 1];
-    __shared__ uint32_t s_lc[kBaseClasses + 1];
-    __shared__ unsigned long long s_lkeys;
-    __shared__ uint64_t s_gb[kBaseClasses + 1];
-    __shared__ uint64_t s_n[IPW][kMaxBuckets];     // an entry's keys
-    __shared__ uint32_t s_rank[IPW][kMaxBuckets];  // its rank in its class, 4 bits of class + 1 above
-    __shared__ int s_inh[IPW][kMaxBuckets];        // its child-list entry + 1 (0: none)
-    const uint32_t b = threadIdx.x;
-    if (b <= (uint32_t)kBaseClasses) s_lc[b] = 0;
-    if (b == 0) s_lkeys = 0;
-    const uint64_t i0 = (uint64_t)blockIdx.x * IPW;
-    // the next item's model kind, bucket size and start are loaded while this one is processed
-    uint32_t kind_n = 0;
-    uint64_t c_n = 0, lo_n = 0;
-    auto prefetch = [&](uint64_t i) {
-        if (i < num_items && b < K) {
-            kind_n = models[i].kind;
-            c_n = hist[i * K + b];
-            lo_n = items[i].lo + bstart[i * K + b];
-        }
-    };
-    prefetch(i0);
-    for (int j = 0; j < IPW; ++j) {
-        const uint64_t i = i0 + j;
-        if (i >= num_items) break;  // the same for the whole workgroup
-        const uint32_t kind = kind_n;
-        const uint64_t c_i = c_n, lo_i = lo_n;
-        if (j + 1 < IPW) prefetch(i + 1);
+// Children of every item: > T keys -> next level's items; equality buckets are closed (moved back
+// if they sit in the scratch buffer).  Buckets of T/2 < n <= T keys go to the base case alone.
+// Runs of adjacent smaller buckets (1 <= n <= T/2, not separated by a bucket with keys of another
+// kind) are sorted together: buckets are in key order and a key's bucket is a function of the key,
+// so sorting the run as one range gives the same result.  Inside a run, bucket b joins group
+// floor(p_b / (T/2)) (p_b: the keys of the run before it), so a group holds fewer than T keys; the
+// group's first bucket emits it.  A group of a single key already in the caller's buffer needs no
+// work.
+//
+// One wave per item (lane l: buckets 4l .. 4l+3), W items a workgroup.  Every step over the
+// item's buckets is a scan inside the wave (no workgroup barrier); the workgroup only gathers its
+// entries' counts per class, reserves its ranges with one device atomic per class and writes.
+// Entries are ranked item by item, bucket by bucket, so the lists are the same on every run.
+
+// Inclusive max-scan over the wave (identity lo).
+template <typename V>
+__device__ inline V wave_inclusive_max(V v) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int s = 1; s < kWave; s <<= 1) {
+        const V o = __shfl_up(v, s, kWave);
+        if (lane >= (uint32_t)s) v = o > v ? o : v;
+    }
+    return v;
+}
+
+template <int W>
+__global__ __launch_bounds__(kWave * W) void k_worklist(const Item* items, uint64_t num_items, const Model* models,
+                                                        const uint64_t* hist, const uint64_t* bstart, uint32_t K,
+                                                        uint32_t T, int dst_is_scratch, Item* next, BaseItem* base,
+                                                        BaseLayout bl, uint64_t* cnt, int next_slot, uint64_t next_cap,
+                                                        CopyItem* copy, uint64_t copy_cap, const ChildSpan* spans,
+                                                        const Child* children, uint64_t* l1max) {
+    constexpr int NC = kBaseClasses + 1;  // class 0: next-level items; 1 + c: base-case class c
+    static_assert(kMaxBuckets == 4 * kWave, "four buckets a lane");
+    __shared__ uint64_t s_sum[W][kMaxBuckets];  // a group's keys, at its first bucket
+    __shared__ int s_ent[W][kMaxBuckets];       // bucket -> its child-list entry with a usable line, or -1
+    __shared__ uint32_t s_wc[W][NC];            // the wave's entries per class
+    __shared__ uint64_t s_gb[NC];
+    __shared__ unsigned long long s_keys;
+    const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+    const uint64_t i = (uint64_t)blockIdx.x * W + w;
+    const bool live = i < num_items;  // the same for the whole wave
+    const uint64_t half = T / 2 > 0 ? T / 2 : 1;
+    if (threadIdx.x == 0) s_keys = 0;
+
+    int ch[4] = {-1, -1, -1, -1};
+    uint64_t nn[4] = {0, 0, 0, 0}, lo[4] = {0, 0, 0, 0};
+    uint64_t rel0 = 0, it_lo = 0;
+    int ent[4] = {-1, -1, -1, -1};
+    if (live) {
+        const Model& m = models[i];
+        const uint32_t kind = m.kind;
+        const Item it = items[i];
+        rel0 = it.lo_rel;
+        it_lo = it.lo;
         const ChildSpan sp = spans ? spans[i] : ChildSpan{0u, 0u};
-        if (b < kMaxBuckets) s_ent[b] = -1;
-        __syncthreads();
-        if (b < sp.count) {
-            const Child ch = children[sp.base + b];
-            if (ch.a != 0.0) s_ent[ch.c] = (int)(sp.base + b);
+        if (sp.count) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s_ent[w][4 * lane + q] = -1;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            for (uint32_t u = lane; u < sp.count; u += kWave) {
+                const Child chd = children[sp.base + u];
+                if (chd.a != 0.0) s_ent[w][chd.c] = (int)(sp.base + u);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ent[q] = s_ent[w][4 * lane + q];
         }
-        uint64_t c = 0, lo = 0;
-        bool breaker = false;
-        if (b < K) {
-            if (kind != kKindClosedKeep && kind != kKindClosedMove) {
-                c = c_i;
-                lo = lo_i;
-                // an equality bucket holds one value: closed here; moved back if it sits in the scratch buffer
-                const uint32_t neq = kind == kKindLinear ? models[i].neq : 0u;
-                bool is_eq = false;
-                for (uint32_t e = 0; e < neq; ++e) is_eq |= models[i].eqb[e] == b;
-                if (is_eq && c > 0) {
-                    atomicAdd((unsigned long long*)&cnt[C_EQCLOSED], 1ull);
-                    if (dst_is_scratch) {
-                        const uint64_t q = atomicAdd((unsigned long long*)&cnt[C_COPY], 1ull);
-                        if (q < copy_cap) copy[q] = CopyItem{lo, c};
-                        atomicAdd((unsigned long long*)&cnt[C_COPYKEYS], (unsigned long long)c);
+        const bool open = kind != kKindClosedKeep && kind != kKindClosedMove;
+        const uint32_t neq = kind == kKindLinear ? m.neq : 0u;
+        uint64_t c[4];
+        bool brk[4];
+        uint64_t mx = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t b = 4 * lane + q;
+            c[q] = 0;
+            brk[q] = false;
+            if (b < K) {
+                const uint64_t h = hist[i * K + b];
+                mx = h > mx ? h : mx;
+                if (open) {
+                    c[q] = h;
+                    lo[q] = it.lo + bstart[i * K + b];
+                    // an equality bucket holds one value: closed here; moved back if it sits in the
+                    // scratch buffer
+                    bool is_eq = false;
+                    for (uint32_t e = 0; e < neq; ++e) is_eq |= m.eqb[e] == b;
+                    if (is_eq && c[q] > 0) {
+                        atomicAdd((unsigned long long*)&cnt[C_EQCLOSED], 1ull);
+                        if (dst_is_scratch) {
+                            const uint64_t qq = atomicAdd((unsigned long long*)&cnt[C_COPY], 1ull);
+                            if (qq < copy_cap) copy[qq] = CopyItem{lo[q], c[q]};
+                            atomicAdd((unsigned long long*)&cnt[C_COPYKEYS], (unsigned long long)c[q]);
+                        }
+                        c[q] = 0;  // neither an item nor a base-case bucket
+                        brk[q] = true;
                     }
-                    c = 0;  // neither an item nor a base-case bucket
-                    breaker = true;
                 }
             }
         }
         if (l1max) {  // the first level of a single array: its largest bucket, for the statistics
-            __shared__ uint64_t s_mx[kBlock / kWave];
-            const uint64_t h = wave_max<uint64_t>(b < K ? hist[i * K + b] : 0);
-            if (lane_id() == 0) s_mx[b / kWave] = h;
-            __syncthreads();
-            if (b == 0) {
-                uint64_t mx = 0;
-                for (uint32_t w = 0; w < blockDim.x / kWave; ++w) mx = s_mx[w] > mx ? s_mx[w] : mx;
-                *l1max = mx;
+            mx = wave_max<uint64_t>(mx);
+            if (lane == 0) *l1max = mx;
+        }
+        // e: keys of the small buckets before b; eb: e at the last breaker up to b; rs: one past
+        // the last breaker before b (the start of b's run)
+        bool small[4];
+        uint64_t e[4], run_e = 0, lane_brk_e = 0;
+        int lane_brk = -1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            small[q] = c[q] >= 1 && c[q] <= half;
+            brk[q] = brk[q] || c[q] > half;
+            e[q] = run_e;
+            if (brk[q]) {
+                lane_brk = (int)(4 * lane + q);
+                lane_brk_e = run_e;
+            }
+            run_e += small[q] ? c[q] : 0;
+        }
+        const uint64_t e_in = wave_inclusive_sum<uint64_t>(run_e) - run_e;
+        // the last breaker before this lane, and its e (e is nondecreasing: a max-scan finds it)
+        int brk_in = wave_inclusive_max<int>(lane_brk);
+        uint64_t eb_in = wave_inclusive_max<uint64_t>(lane_brk >= 0 ? e_in + lane_brk_e : 0);
+        brk_in = __shfl_up(brk_in, 1, kWave);
+        eb_in = __shfl_up(eb_in, 1, kWave);
+        if (lane == 0) {
+            brk_in = -1;
+            eb_in = 0;
+        }
+        uint64_t eb[4];
+        int rs[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            e[q] += e_in;
+            if (brk[q]) {
+                eb_in = e[q];
+                brk_in = (int)(4 * lane + q);
+            }
+            eb[q] = eb_in;
+            rs[q] = brk_in + 1;
+        }
+        // group key of a small bucket, (run start + 1) << 32 | floor(p / half), p = e - eb (p < K
+        // half): nondecreasing over the small buckets, so the previous small bucket's key comes
+        // from a max-scan; a small bucket whose key is larger starts a group
+        uint64_t key[4], run_key = 0;
+        uint64_t prevk[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint64_t p = small[q] ? e[q] - eb[q] : 0;
+            key[q] = small[q] ? (((uint64_t)(rs[q] + 1) << 32) | (p / half)) : 0;
+            prevk[q] = run_key;
+            run_key = key[q] > run_key ? key[q] : run_key;
+        }
+        uint64_t key_in = wave_inclusive_max<uint64_t>(run_key);
+        key_in = __shfl_up(key_in, 1, kWave);
+        if (lane == 0) key_in = 0;
+        bool leader[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint64_t pk = prevk[q] > key_in ? prevk[q] : key_in;
+            leader[q] = small[q] && pk < key[q];
+        }
+        // each small bucket adds its keys to its group's first bucket (the last leader up to it)
+        int run_lead = -1, lead[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (leader[q]) run_lead = (int)(4 * lane + q);
+            lead[q] = run_lead;
+        }
+        int lead_in = wave_inclusive_max<int>(run_lead);
+        lead_in = __shfl_up(lead_in, 1, kWave);
+        if (lane == 0) lead_in = -1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (lead[q] < 0) lead[q] = lead_in;
+            s_sum[w][4 * lane + q] = 0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (small[q]) atomicAdd((unsigned long long*)&s_sum[w][lead[q]], (unsigned long long)c[q]);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (c[q] > T) {
+                ch[q] = 0;
+                nn[q] = c[q];
+            } else if (c[q] > half) {
+                nn[q] = c[q];
+                ch[q] = 1 + base_class((uint32_t)c[q]);
+            } else if (leader[q]) {
+                nn[q] = s_sum[w][4 * lane + q];
+                if (nn[q] >= 2 || dst_is_scratch) ch[q] = 1 + base_class((uint32_t)nn[q]);
             }
         }
-        const uint64_t half = T / 2 > 0 ? T / 2 : 1;
-        const bool small = c >= 1 && c <= half;
-        breaker = breaker || c > half;
-        // runs of small buckets: run start = one past the last breaker before b
-        const int last_break = block_inclusive_max(breaker ? (int)b : -1, s_iscan);
-        const uint32_t run_start = (uint32_t)(last_break + 1);  // for a breaker itself: b + 1 (unused)
-        uint64_t tot;
-        const uint64_t e = block_exclusive_sum<uint64_t>(small ? c : 0, s_scan, &tot);
-        s_e[b] = e;
-        __syncthreads();
-        const uint64_t p = small ? e - s_e[run_start < blockDim.x ? run_start : b] : 0;
-        s_p[b] = p;
-        s_sum[b] = 0;
-        // the small bucket before b: the inclusive max of thread b - 1, passed through LDS
-        const int prev_small = block_inclusive_max(small ? (int)b : -1, s_iscan);
-        s_prev[b + 1] = prev_small;
-        if (b == 0) s_prev[0] = -1;
-        __syncthreads();
-        const int ps = s_prev[b];
-        const bool leader = small && (ps < (int)run_start || s_p[ps] / half != p / half);
-        const int lead = block_inclusive_max(leader ? (int)b : -1, s_iscan);
-        if (small) atomicAdd((unsigned long long*)&s_sum[lead], (unsigned long long)c);
-        __syncthreads();
-        int ch = -1;
-        uint64_t n = 0;
-        if (c > T) {
-            ch = 0;
-            n = c;
-        } else if (c > half) {
-            n = c;
-            ch = 1 + base_class((uint32_t)c);
-        } else if (leader) {
-            n = s_sum[b];
-            if (n >= 2 || dst_is_scratch) ch = 1 + base_class((uint32_t)n);
+    }
+    // ranks inside the wave, class by class (bucket order), and the wave's counts
+    uint32_t rk[4] = {0, 0, 0, 0};
+    uint64_t bkeys = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bkeys += ch[q] > 0 ? nn[q] : 0;
+    for (int cl = 0; cl < NC; ++cl) {
+        uint32_t mine = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) mine += ch[q] == cl ? 1u : 0u;
+        const uint32_t inc = wave_inclusive_sum<uint32_t>(mine);
+        uint32_t at = inc - mine;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (ch[q] == cl) rk[q] = at++;
         }
-        const uint32_t r = block_append_local(ch, n, sc, s_lc, &s_lkeys);
-        s_n[j][b] = n;
-        s_rank[j][b] = ch < 0 ? 0u : ((r << 4) | (uint32_t)(ch + 1));
-        s_inh[j][b] = s_ent[b] + 1;
-        (void)lo;
-        __syncthreads();
+        if (lane == kWave - 1) s_wc[w][cl] = inc;
     }
-    // the workgroup's ranges: one device atomic per class, one for the base-case keys
-    if (b <= (uint32_t)kBaseClasses) {
-        uint64_t* ctr = b == 0 ? &cnt[next_slot] : &cnt[C_CLS + b - 1];
-        s_gb[b] = s_lc[b] ? atomicAdd((unsigned long long*)ctr, (unsigned long long)s_lc[b]) : 0;
-    }
-    if (b == 0 && s_lkeys) atomicAdd((unsigned long long*)&cnt[C_BASEKEYS], s_lkeys);
+    bkeys = wave_inclusive_sum<uint64_t>(bkeys);
+    if (lane == kWave - 1 && bkeys) atomicAdd(&s_keys, (unsigned long long)bkeys);
     __syncthreads();
-    if (b >= K) return;
-    for (int j = 0; j < IPW; ++j) {
-        const uint64_t i = i0 + j;
-        if (i >= num_items) break;
-        const uint32_t rk = s_rank[j][b];
-        if (rk == 0) continue;
-        const int ch = (int)(rk & 15u) - 1;
-        const uint64_t q = s_gb[ch] + (rk >> 4);
-        const uint64_t g = i * K + b;
-        const Item it = items[i];
-        const uint64_t lo = it.lo + bstart[g];
-        const uint64_t n = s_n[j][b];
-        const int cls = ch > 0 ? ch - 1 : 0;
-        if (ch == 0 && q < next_cap) next[q] = Item{lo, n, it.lo_rel + bstart[g], (uint64_t)s_inh[j][b]};
-        if (ch > 0 && q < bl.cap[cls]) base[bl.off[cls] + q] = BaseItem{lo, (uint32_t)n, (uint32_t)dst_is_scratch};
+    // the workgroup's ranges: one device atomic per class, one for the base-case keys
+    if (threadIdx.x < (uint32_t)NC) {
+        const int cl = threadIdx.x;
+        uint32_t tot = 0;
+        for (int v = 0; v < W; ++v) tot += s_wc[v][cl];
+        uint64_t* ctr = cl == 0 ? &cnt[next_slot] : &cnt[C_CLS + cl - 1];
+        s_gb[cl] = tot ? atomicAdd((unsigned long long*)ctr, (unsigned long long)tot) : 0;
+    }
+    if (threadIdx.x == 0 && s_keys) atomicAdd((unsigned long long*)&cnt[C_BASEKEYS], s_keys);
+    __syncthreads();
+    if (!live) return;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int cl = ch[q];
+        if (cl < 0) continue;
+        uint64_t at = s_gb[cl] + rk[q];
+        for (uint32_t v = 0; v < w; ++v) at += s_wc[v][cl];
+        const int bc = cl > 0 ? cl - 1 : 0;
+        if (cl == 0 && at < next_cap) next[at] = Item{lo[q], nn[q], rel0 + (lo[q] - it_lo), (uint64_t)(ent[q] + 1)};
+        if (cl > 0 && at < bl.cap[bc]) base[bl.off[bc] + at] = BaseItem{lo[q], (uint32_t)nn[q], (uint32_t)dst_is_scratch};
     }
 }
 

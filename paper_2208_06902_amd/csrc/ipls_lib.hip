@@ -13,7 +13,6 @@
 #include <cstring>
 #include <mutex>
 #include <unordered_map>
-#include <type_traits>
 #include <vector>
 
 #include "../../include/ipls.h"
@@ -23,9 +22,8 @@
 namespace ipls {
 namespace {
 
+constexpr uint64_t kWorklistFewItems = 1024;  // up to this many items: four a k_worklist workgroup
 constexpr uint32_t kSmallS = kFitLds;  // samples up to this size are fitted in one workgroup's LDS
-constexpr int kWorklistItems = 8;      // items per k_worklist workgroup at levels of many items
-constexpr uint64_t kWorklistOneItem = 2048;  // up to this many items: one item per workgroup
 constexpr uint64_t kDeferBaseItems = 2048;  // levels of at least this many items run before the previous level's base case
 constexpr uint32_t kFitChunk = 2048;   // windows per workgroup in the multi-round fit
 constexpr uint32_t kCand = 15;         // candidate widths per fit round
@@ -103,7 +101,6 @@ void for_each_buf(Depth& D, F&& f) {
 struct Device {
     Depth depth[kMaxDepth];
     std::mutex mu;
-    uint64_t* seg_h = nullptr;  // pinned staging of a single segment's offsets
     // The top-level sort's base case runs on a stream of its own (non-blocking, default priority),
     // beside the next level's partition; ev_base[parity] marks the end of a level's base launch.
     hipStream_t side = nullptr;
@@ -127,8 +124,6 @@ void release_device(Device& dv) {
         D.plan_h = nullptr;
         D.plan_hd = nullptr;
     }
-    if (dv.seg_h) (void)hipHostFree(dv.seg_h);
-    dv.seg_h = nullptr;
     for (hipEvent_t* e : {&dv.ev_base[0], &dv.ev_base[1], &dv.ev_defer}) {
         if (*e) (void)hipEventDestroy(*e);
         *e = nullptr;
@@ -773,19 +768,15 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             HIP_TRY(hipStreamWaitEvent(s, dv.ev_base[par], 0));
             base_pending[par] = false;
         }
+        // a wave per item; levels of many items take 16 a workgroup, so that fewer workgroups queue
+        // on the same few device counters
         {
-            // a workgroup per item while they all fit the GPU at once; beyond that several items a
-            // workgroup, so that thousands of workgroups do not queue on the same device counters
-            auto wl = [&](auto ipw) {
-                constexpr int W = decltype(ipw)::value;
-                k_worklist<W><<<(unsigned)((ni + W - 1) / W), 256, 0, s>>>(
-                    items, ni, models, (const uint64_t*)D.hist.p, (const uint64_t*)D.bstart.p, K, T_,
-                    src_scratch ? 0 : 1, (Item*)D.items[cur ^ 1].p, (BaseItem*)D.base[par].p, bl, cnt,
-                    C_ITEMS0 + (cur ^ 1), item_cap, (CopyItem*)D.copy.p, copy_cap, spans, children,
-                    (top && level == 0 && ni == 1) ? cnt + C_L1MAX : nullptr);
-            };
-            if (ni <= kWorklistOneItem) wl(std::integral_constant<int, 1>{});
-            else wl(std::integral_constant<int, kWorklistItems>{});
+            auto kw = ni <= kWorklistFewItems ? k_worklist<4> : k_worklist<16>;
+            const uint32_t W = ni <= kWorklistFewItems ? 4 : 16;
+            kw<<<(unsigned)((ni + W - 1) / W), kWave * W, 0, s>>>(
+                items, ni, models, (const uint64_t*)D.hist.p, (const uint64_t*)D.bstart.p, K, T_, src_scratch ? 0 : 1,
+                (Item*)D.items[cur ^ 1].p, (BaseItem*)D.base[par].p, bl, cnt, C_ITEMS0 + (cur ^ 1), item_cap,
+                (CopyItem*)D.copy.p, copy_cap, spans, children, (top && level == 0 && ni == 1) ? cnt + C_L1MAX : nullptr);
             LAUNCH_CHECK();
         }
         if (defer_base) {
@@ -945,20 +936,11 @@ ipls_status sort_single(Device& dv, void* keys, uint32_t* payload, size_t n, ipl
     Depth& D0 = dv.depth[0];
     st = ensure(D0.seg, 2 * sizeof(uint64_t));
     if (st != IPLS_OK) return st;
-    if (dv.noalloc) {
-        // single segment [0, n): offsets written by a one-thread kernel (no host staging buffer)
-        k_single_segment<<<1, 1, 0, s>>>((uint64_t*)D0.seg.p, n);
-        if (hipGetLastError() != hipSuccess) return IPLS_ERR_HIP;
-    } else {
-        // single segment [0, n): offsets staged through the context's pinned host buffer
-        if (!dv.seg_h && hipHostMalloc((void**)&dv.seg_h, 2 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
-            return IPLS_ERR_HIP;
-        if (hipStreamSynchronize(s) != hipSuccess) return IPLS_ERR_HIP;
-        dv.seg_h[0] = 0;
-        dv.seg_h[1] = n;
-        if (hipMemcpyAsync(D0.seg.p, dv.seg_h, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, s) != hipSuccess)
-            return IPLS_ERR_HIP;
-    }
+    // single segment [0, n): the offsets are written on the stream by a one-thread kernel.  (A copy
+    // from a pinned host buffer of default flags, which is not coherent, could read values the CPU
+    // had not yet written back to memory, and the buffer's reuse needed a stream synchronisation.)
+    k_single_segment<<<1, 1, 0, s>>>((uint64_t*)D0.seg.p, n);
+    if (hipGetLastError() != hipSuccess) return IPLS_ERR_HIP;
     st = dispatch(dv, run, keys, payload, n, (const uint64_t*)D0.seg.p, 1, workspace);
     if (st != IPLS_OK && dv.side) (void)hipStreamSynchronize(dv.side);
     st = finish(st, s);
@@ -1174,12 +1156,8 @@ ipls_status ipls_partition(void* keys, uint32_t* payload, size_t n, ipls_dtype d
     st = ensure(D0.seg, 2 * sizeof(uint64_t) + sizeof(ipls_linear_model));
     if (st != IPLS_OK) return st;
     run.part_model = model ? model : (ipls_linear_model*)((uint64_t*)D0.seg.p + 2);
-    HIP_TRY(hipStreamSynchronize(s));
-    if (!dv.seg_h && hipHostMalloc((void**)&dv.seg_h, 2 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
-        return IPLS_ERR_HIP;
-    dv.seg_h[0] = 0;
-    dv.seg_h[1] = n;
-    HIP_TRY(hipMemcpyAsync(D0.seg.p, dv.seg_h, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    k_single_segment<<<1, 1, 0, s>>>((uint64_t*)D0.seg.p, n);
+    LAUNCH_CHECK();
     HIP_TRY(hipMemsetAsync(counts, 0, prm.num_buckets * 8, s));
     st = dispatch(dv, run, keys, payload, n, (const uint64_t*)D0.seg.p, 1, nullptr);
     return finish(st, s);

@@ -257,6 +257,7 @@ void ipls_server::run_batch(ipls::Engine& e, hipStream_t s, int64_t bid, uint64_
         }
         const uint64_t nseg = rs.size(), k0 = rs[0].keys_off;
         if (status == IPLS_OK) {
+            // offs_h is coherent pinned memory: the copy engine reads what the CPU has just written
             for (uint64_t i = 0; i < nseg; ++i) offs_h[i] = (rs[i].keys_off - k0) / w;
             offs_h[nseg] = offs_h[nseg - 1] + rs[nseg - 1].n;
             if (hipMemcpyAsync(offs_d, offs_h, (nseg + 1) * 8, hipMemcpyHostToDevice, s) != hipSuccess)
@@ -292,7 +293,7 @@ void ipls_server::lane_main(int lane) {
     ipls::Engine* e = ipls::engine_new();
     uint64_t* offs_h = nullptr;
     bool ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess &&
-              hipHostMalloc((void**)&offs_h, (cfg.batch_max_requests + 1) * 8, hipHostMallocDefault) == hipSuccess;
+              hipHostMalloc((void**)&offs_h, (cfg.batch_max_requests + 1) * 8, hipHostMallocCoherent) == hipSuccess;
     for (;;) {
         WorkItem w;
         {
