@@ -137,6 +137,38 @@ def test_sizes_around_tiles_and_base_case(n):
     assert same_bits(got, oracle.sort(k)[0]) if n else got.size == 0
 
 
+def test_back_to_back_sorts_of_changing_sizes():
+    # each call's segment offsets [0, n] must be its own: sorts of changing sizes issued back to
+    # back (some with payloads, some on a second stream), every result checked
+    r = np.random.default_rng(77)
+    side = torch.cuda.Stream()
+    cases = []
+    for c in range(40):
+        n = int(r.integers(2, 300_000)) if c % 4 else int(r.integers(4097, 20_000))
+        k = gen.make(["normal", "exponential", "uniform_int", "lognormal2"][c % 4], n, 500 + c)
+        pay = gen.index_payload(n) if c % 3 == 0 else None
+        cases.append((k, pay))
+    print(f"back to back: {len(cases)} sorts", flush=True)
+    outs = []
+    for c, (k, pay) in enumerate(cases):
+        kd = dev(k)
+        pd = None if pay is None else dev(pay)
+        if c % 5 == 4:
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                ipls.sort_(kd, pd)
+            torch.cuda.current_stream().wait_stream(side)
+        else:
+            ipls.sort_(kd, pd)
+        outs.append((kd, pd))
+    torch.cuda.synchronize()
+    for (k, pay), (kd, pd) in zip(cases, outs):
+        order = np.argsort(k, kind="stable")
+        assert same_bits(host(kd, k.dtype), k[order])
+        if pay is not None:
+            assert np.array_equal(host(pd, np.uint32), pay[order])
+
+
 def test_all_equal_and_two_valued():
     k = np.full(100_000, 2.5)
     st = check_sort(k, gen.index_payload(k.size))
