@@ -599,8 +599,9 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                                                                     keys, pay, scratch, spay);
             LAUNCH_CHECK();
         }
-        // the previous level's buckets of <= T keys: base[(level - 1) & 1], complete (the host has
-        // just seen the plan, so the main stream's earlier work is done)
+        // the previous level's buckets of <= T keys: base[(level - 1) & 1], whose list is complete
+        // (its worklist ran before this plan); their keys come from the previous level's scatter,
+        // which a side-stream launch waits for (ev_scat)
         const int bp = (level + 1) & 1;
         auto launch_level_base = [&](hipStream_t sl) -> ipls_status {
             ProfScope ps(2, level - 1, (double)pl.base_keys * 2.0 * (kb + (PAY ? 4 : 0)), sl);
