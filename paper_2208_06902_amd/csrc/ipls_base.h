@@ -672,14 +672,16 @@ __device__ inline void base_large_keys(const BaseItem& bi, typename Key<DT>::T* 
                     const uint32_t st = ds[r] & 0xfffu, cn = ds[r] >> 18;
                     const O x = (O)((((uint64_t)(o[r] - mn) >> z) << DB) | (st + ((ds[r] >> 12) & 0x3fu)));
                     uint32_t before = 0;
+                    if (cn > 1) {  // a key alone in its digit is in place: its lane reads nothing
 #pragma unroll
-                    for (uint32_t q = 0; q < 4; ++q) {
-                        // read unconditionally (the slots past the digit, at most three past the
-                        // last key, lie in the counter area) and counted only inside the digit
-                        const O y = s_k[st + q];
-                        before += ((q < cn) & (y < x)) ? 1u : 0u;
+                        for (uint32_t q = 0; q < 4; ++q) {
+                            // read unconditionally (the slots past the digit, at most three past
+                            // the last key, lie in the counter area), counted only inside the digit
+                            const O y = s_k[st + q];
+                            before += ((q < cn) & (y < x)) ? 1u : 0u;
+                        }
+                        for (uint32_t q = 4; q < cn; ++q) before += s_k[st + q] < x ? 1u : 0u;
                     }
-                    for (uint32_t q = 4; q < cn; ++q) before += s_k[st + q] < x ? 1u : 0u;
                     ds[r] = st + before;
                 }
             }
