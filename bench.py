@@ -427,7 +427,11 @@ def run_served(args, validate=True):
                                     "batch_size": d["batch_size"], "mismatches": int(diff.numel()),
                                     "first": int(diff[0]) if diff.numel() else None,
                                     "last": int(diff[-1]) if diff.numel() else None,
-                                    "sorted": bool((got[1:] >= got[:-1]).all())})
+                                    "sorted": bool((got[1:] >= got[:-1]).all()),
+                                    # the input left as it was / the input's keys in another order
+                                    "unchanged": bool(torch.equal(got, _ord_i64(ref, dt, torch))),
+                                    "permutation": bool(torch.equal(torch.sort(got).values, want)),
+                                    "arena_offset": int(kv.data_ptr() - arena.data_ptr())})
                 srv.release(d["req_id"])
 
         t0 = time.monotonic() + 0.02

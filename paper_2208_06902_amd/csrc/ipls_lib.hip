@@ -76,9 +76,7 @@ ipls_status ensure(Buf& b, size_t bytes) {
 
 
 struct Depth {
-    // tile_off and chunk_off alternate by level parity: the next level's plan is written while this
-    // level's scatter, which reads them, may still run
-    Buf scratch, spay, items[2], base[2], sample_base, counters, plan, tile_off[2], sample_off, fit_off, chunk_off[2], tile_map,
+    Buf scratch, spay, items[2], base[2], sample_base, counters, plan, tile_off, sample_off, fit_off, chunk_off, tile_map,
         fit_map, chunk_map, models, masks, hist, bstart, tile_pref, chunk_sum, chunk_pref, sample, leaves, seg, roots,
         leaf_first, leaf_last, eqinfo, rsample, copy, copy_off, copy_map, treeflag, sample2, children[2], spans, cls, wide;
     Plan* plan_h = nullptr;     // pinned, coherent: k_plan writes it directly
@@ -90,8 +88,7 @@ struct Depth {
 template <class F>
 void for_each_buf(Depth& D, F&& f) {
     for (Buf* b : {&D.scratch, &D.spay, &D.items[0], &D.items[1], &D.base[0], &D.base[1], &D.sample_base, &D.counters,
-                   &D.plan, &D.tile_off[0], &D.tile_off[1], &D.sample_off, &D.fit_off, &D.chunk_off[0],
-                   &D.chunk_off[1], &D.tile_map, &D.fit_map,
+                   &D.plan, &D.tile_off, &D.sample_off, &D.fit_off, &D.chunk_off, &D.tile_map, &D.fit_map,
                    &D.chunk_map, &D.models, &D.masks, &D.hist, &D.bstart, &D.tile_pref, &D.chunk_sum, &D.chunk_pref,
                    &D.sample, &D.leaves, &D.seg, &D.roots, &D.leaf_first, &D.leaf_last, &D.eqinfo, &D.rsample,
                    &D.copy, &D.copy_off, &D.copy_map, &D.treeflag, &D.sample2, &D.children[0], &D.children[1],
@@ -108,8 +105,7 @@ struct Device {
     // beside the next level's partition; ev_base[parity] marks the end of a level's base launch.
     hipStream_t side = nullptr;
     hipEvent_t ev_base[2] = {nullptr, nullptr};
-    hipEvent_t ev_defer = nullptr;  // a level's scatter, which a deferred base launch waits for
-    hipEvent_t ev_scat = nullptr;   // a level's scatter, which the next level's base launch waits for
+    hipEvent_t ev_defer = nullptr;  // a level's worklist, which a deferred base launch waits for
     // The allocation-free entry point's context: buffers come from the scratch array, the plan is
     // copied back, and everything runs on the caller's stream (no side stream, no events).
     bool noalloc = false;
@@ -128,7 +124,7 @@ void release_device(Device& dv) {
         D.plan_h = nullptr;
         D.plan_hd = nullptr;
     }
-    for (hipEvent_t* e : {&dv.ev_base[0], &dv.ev_base[1], &dv.ev_defer, &dv.ev_scat}) {
+    for (hipEvent_t* e : {&dv.ev_base[0], &dv.ev_base[1], &dv.ev_defer}) {
         if (*e) (void)hipEventDestroy(*e);
         *e = nullptr;
     }
@@ -469,7 +465,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     const bool overlap = top && !dv.noalloc;
     if (overlap && !dv.side) {
         HIP_TRY(hipStreamCreateWithFlags(&dv.side, hipStreamNonBlocking));
-        for (hipEvent_t* e : {&dv.ev_base[0], &dv.ev_base[1], &dv.ev_defer, &dv.ev_scat})
+        for (hipEvent_t* e : {&dv.ev_base[0], &dv.ev_base[1], &dv.ev_defer})
             HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
     }
     hipStream_t sb = overlap ? dv.side : s;  // stream of the base-case launches
@@ -484,12 +480,10 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     };
     ST_TRY(ensure(D.counters, C_N * sizeof(uint64_t)));
     ST_TRY(ensure(D.plan, sizeof(Plan)));
-    ST_TRY(ensure(D.tile_off[0], (item_cap + 1) * 8));
-    ST_TRY(ensure(D.tile_off[1], (item_cap + 1) * 8));
+    ST_TRY(ensure(D.tile_off, (item_cap + 1) * 8));
     ST_TRY(ensure(D.sample_off, (item_cap + 1) * 8));
     ST_TRY(ensure(D.fit_off, (item_cap + 1) * 8));
-    ST_TRY(ensure(D.chunk_off[0], (item_cap + 1) * 8));
-    ST_TRY(ensure(D.chunk_off[1], (item_cap + 1) * 8));
+    ST_TRY(ensure(D.chunk_off, (item_cap + 1) * 8));
     ST_TRY(ensure(D.sample_base, item_cap * sizeof(BaseItem)));
     ST_TRY(ensure(D.wide, item_cap * 4));
     if (!D.plan_h && dv.noalloc) {
@@ -534,26 +528,14 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
 
     int cur = 0;
     uint64_t prev_items = 0, prev_sum_n = 0, prev_closed = 0, prev_closed_keys = 0;
-    // The plan of level lv over the item list items[c].  Level 0's is launched here; every later
-    // level's is launched by the level before it, after its worklist and ahead of its scatter, so
-    // that the host reads the plan while that scatter runs.
-    auto launch_plan = [&](int lv, int c) -> ipls_status {
-        const int pp = lv & 1;
-        const Child* pc = (inherit && lv > 0) ? (const Child*)D.children[pp ^ 1].p : nullptr;
-        k_plan<<<1, 256, 0, s>>>((const Item*)D.items[c].p, cnt, c, (Plan*)D.plan.p, (uint64_t*)D.tile_off[pp].p,
-                                  (uint64_t*)D.sample_off.p, (uint64_t*)D.fit_off.p, (uint64_t*)D.chunk_off[pp].p, A,
-                                  item_cap, bl, (const CopyItem*)D.copy.p, (uint64_t*)D.copy_off.p, copy_cap, pc,
-                                  D.plan_hd, ++D.plan_seq, (BaseItem*)D.sample_base.p, (uint32_t*)D.wide.p);
-        LAUNCH_CHECK();
-        return IPLS_OK;
-    };
-    ST_TRY(launch_plan(0, cur));
-    bool scat_recorded = false;  // ev_scat marks the last scatter (the side stream's base launches wait for it)
     for (int level = 0;; ++level) {
         const int par = level & 1;
         const Child* prev_children = (inherit && level > 0) ? (const Child*)D.children[par ^ 1].p : nullptr;
-        const uint64_t* tile_off = (const uint64_t*)D.tile_off[par].p;
-        const uint64_t* chunk_off = (const uint64_t*)D.chunk_off[par].p;
+        k_plan<<<1, 256, 0, s>>>((const Item*)D.items[cur].p, cnt, cur, (Plan*)D.plan.p, (uint64_t*)D.tile_off.p, (uint64_t*)D.sample_off.p,
+                                  (uint64_t*)D.fit_off.p, (uint64_t*)D.chunk_off.p, A, item_cap, bl,
+                                  (const CopyItem*)D.copy.p, (uint64_t*)D.copy_off.p, copy_cap, prev_children,
+                                  D.plan_hd, ++D.plan_seq, (BaseItem*)D.sample_base.p, (uint32_t*)D.wide.p);
+        LAUNCH_CHECK();
         if (D.plan_hd) HIP_TRY(wait_plan(s, (const volatile Plan*)D.plan_h, D.plan_seq));
         if (((volatile Plan*)D.plan_h)->seq != D.plan_seq) {
             // not visible yet through the mapped buffer: copy the device's plan instead
@@ -599,9 +581,8 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                                                                     keys, pay, scratch, spay);
             LAUNCH_CHECK();
         }
-        // the previous level's buckets of <= T keys: base[(level - 1) & 1], whose list is complete
-        // (its worklist ran before this plan); their keys come from the previous level's scatter,
-        // which a side-stream launch waits for (ev_scat)
+        // the previous level's buckets of <= T keys: base[(level - 1) & 1], complete (the host has
+        // just seen the plan, so the main stream's earlier work is done)
         const int bp = (level + 1) & 1;
         auto launch_level_base = [&](hipStream_t sl) -> ipls_status {
             ProfScope ps(2, level - 1, (double)pl.base_keys * 2.0 * (kb + (PAY ? 4 : 0)), sl);
@@ -618,8 +599,6 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         const bool side = overlap && pl.num_items > 0;
         const bool defer_base = side && pl.num_base && pl.num_items >= kDeferBaseItems;
         if (pl.num_base && !defer_base) {
-            // the buckets were written by the last scatter, which may still run
-            if (side && scat_recorded) HIP_TRY(hipStreamWaitEvent(sb, dv.ev_scat, 0));
             ST_TRY(launch_level_base(side ? sb : s));
             if (side) {
                 HIP_TRY(hipEventRecord(dv.ev_base[bp], sb));
@@ -665,15 +644,15 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             // sort and fit in one launch, with the tile and chunk maps (a workgroup's bitonic sort of
             // a larger sample takes longer than the three launches)
             k_sample_fit<DT, kFitLdsTiny><<<(unsigned)(eb + ni), 256, 0, s>>>(
-                items, ni, (const uint64_t*)D.sample_off.p, src, P.seed, models, K, eb, tile_off,
-                nt, (uint32_t*)D.tile_map.p, chunk_off, nc, (uint32_t*)D.chunk_map.p);
+                items, ni, (const uint64_t*)D.sample_off.p, src, P.seed, models, K, eb, (const uint64_t*)D.tile_off.p,
+                nt, (uint32_t*)D.tile_map.p, (const uint64_t*)D.chunk_off.p, nc, (uint32_t*)D.chunk_map.p);
             LAUNCH_CHECK();
         } else {
             // the sample gather and the tile and chunk maps, in one launch
             k_sample<DT><<<(unsigned)(eb + (pl.total_samples + 255) / 256), 256, 0, s>>>(
                 items, ni, (const uint64_t*)D.sample_off.p, pl.total_samples, src, sample, P.seed, prev_children,
-                prev_sample, eb, tile_off, nt, (uint32_t*)D.tile_map.p,
-                chunk_off, nc, (uint32_t*)D.chunk_map.p);
+                prev_sample, eb, (const uint64_t*)D.tile_off.p, nt, (uint32_t*)D.tile_map.p,
+                (const uint64_t*)D.chunk_off.p, nc, (uint32_t*)D.chunk_map.p);
             LAUNCH_CHECK();
             ST_TRY(sort_samples<DT>(dv, run, d, pl, sample));
 
@@ -704,7 +683,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         }
 
         // degenerate buckets and final model
-        k_minmax<DT><<<(unsigned)nc, 256, 0, s>>>(items, chunk_off, (const uint32_t*)D.chunk_map.p,
+        k_minmax<DT><<<(unsigned)nc, 256, 0, s>>>(items, (const uint64_t*)D.chunk_off.p, (const uint32_t*)D.chunk_map.p,
                                                   models, src, tile, kChunk);
         LAUNCH_CHECK();
         k_finalize<DT><<<(unsigned)((ni + 255) / 256), 256, 0, s>>>(items, models, (const Model*)D.roots.p, ni, K,
@@ -717,20 +696,20 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             ProfScope ps(1, level, (double)(pl.sum_n - pl.inh_n) * kb + (double)pl.inh_n, s);
             auto kc = tile == kTile ? k_classify_hist<DT, 8, kPassIPT> : k_classify_hist<DT, 4, kPassIPT>;
             kc<<<(unsigned)nc, tile / kPassIPT, 0, s>>>(
-                items, tile_off, chunk_off, (const uint32_t*)D.chunk_map.p,
+                items, (const uint64_t*)D.tile_off.p, (const uint64_t*)D.chunk_off.p, (const uint32_t*)D.chunk_map.p,
                 nc, models, (const double*)D.leaves.p, src, (uint32_t*)D.tile_pref.p, (uint32_t*)D.chunk_sum.p, K,
                 P.leaves, cls);
             LAUNCH_CHECK();
         }
         // chunk prefixes, bucket sizes and bucket starts: a workgroup per item; wide items by a
         // workgroup per (item, bucket), then their starts
-        k_scan_chunks<<<(unsigned)ni, 256, 0, s>>>(chunk_off, K, (const uint32_t*)D.chunk_sum.p,
+        k_scan_chunks<<<(unsigned)ni, 256, 0, s>>>((const uint64_t*)D.chunk_off.p, K, (const uint32_t*)D.chunk_sum.p,
                                                    (uint64_t*)D.chunk_pref.p, (uint64_t*)D.hist.p,
                                                    (uint64_t*)D.bstart.p);
         LAUNCH_CHECK();
         if (pl.n_wide) {
             k_scan_chunks_wide<<<(unsigned)(pl.n_wide * K), 256, 0, s>>>(
-                chunk_off, (const uint32_t*)D.wide.p, K, (const uint32_t*)D.chunk_sum.p,
+                (const uint64_t*)D.chunk_off.p, (const uint32_t*)D.wide.p, K, (const uint32_t*)D.chunk_sum.p,
                 (uint64_t*)D.chunk_pref.p, (uint64_t*)D.hist.p);
             LAUNCH_CHECK();
             k_bucket_starts<<<(unsigned)pl.n_wide, 256, 0, s>>>((const uint64_t*)D.hist.p, (uint64_t*)D.bstart.p, K,
@@ -757,29 +736,6 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             LAUNCH_CHECK();
         }
 
-        // the next level's items and base-case lists, and its plan, ahead of this level's scatter:
-        // they need only the bucket sizes, and the host then reads the plan while the scatter runs
-        const bool last_pass = top && level == 0 && run.single_pass;
-        if (!last_pass) {
-            // next level; this level's base-case list is base[level & 1], whose last reader may still run
-            if (base_pending[par]) {
-                HIP_TRY(hipStreamWaitEvent(s, dv.ev_base[par], 0));
-                base_pending[par] = false;
-            }
-            // a wave per item; levels of many items take 16 a workgroup, so that fewer workgroups queue
-            // on the same few device counters
-            {
-                auto kw = ni <= kWorklistFewItems ? k_worklist<4> : k_worklist<16>;
-                const uint32_t W = ni <= kWorklistFewItems ? 4 : 16;
-                kw<<<(unsigned)((ni + W - 1) / W), kWave * W, 0, s>>>(
-                    items, ni, models, (const uint64_t*)D.hist.p, (const uint64_t*)D.bstart.p, K, T_, src_scratch ? 0 : 1,
-                    (Item*)D.items[cur ^ 1].p, (BaseItem*)D.base[par].p, bl, cnt, C_ITEMS0 + (cur ^ 1), item_cap,
-                    (CopyItem*)D.copy.p, copy_cap, spans, children, (top && level == 0 && ni == 1) ? cnt + C_L1MAX : nullptr);
-                LAUNCH_CHECK();
-            }
-            ST_TRY(launch_plan(level + 1, cur ^ 1));
-        }
-
         // scatter
         {
             ProfScope ps(0, level, (double)pl.sum_n * 2.0 * (kb + (PAY ? 4 : 0)), s);
@@ -787,7 +743,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                               : (tile == kTile ? k_scatter<DT, PAY, 8, kPassIPT, false>
                                                : k_scatter<DT, PAY, 4, kPassIPT, false>);
             ks<<<(unsigned)nt, tile / kPassIPT, 0, s>>>(
-                items, tile_off, (const uint32_t*)D.tile_map.p, nt, chunk_off,
+                items, (const uint64_t*)D.tile_off.p, (const uint32_t*)D.tile_map.p, nt, (const uint64_t*)D.chunk_off.p,
                 nc, models, (const double*)D.leaves.p, (const uint64_t*)D.bstart.p, (const uint64_t*)D.chunk_pref.p,
                 (const uint32_t*)D.tile_pref.p, src, psrc, dst, pdst, K, P.leaves, spans, children, cls);
             LAUNCH_CHECK();
@@ -807,9 +763,21 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             return IPLS_OK;
         }
 
-        if (overlap) {
-            HIP_TRY(hipEventRecord(dv.ev_scat, s));
-            scat_recorded = true;
+        // next level; this level's base-case list is base[level & 1], whose last reader may still run
+        if (base_pending[par]) {
+            HIP_TRY(hipStreamWaitEvent(s, dv.ev_base[par], 0));
+            base_pending[par] = false;
+        }
+        // a wave per item; levels of many items take 16 a workgroup, so that fewer workgroups queue
+        // on the same few device counters
+        {
+            auto kw = ni <= kWorklistFewItems ? k_worklist<4> : k_worklist<16>;
+            const uint32_t W = ni <= kWorklistFewItems ? 4 : 16;
+            kw<<<(unsigned)((ni + W - 1) / W), kWave * W, 0, s>>>(
+                items, ni, models, (const uint64_t*)D.hist.p, (const uint64_t*)D.bstart.p, K, T_, src_scratch ? 0 : 1,
+                (Item*)D.items[cur ^ 1].p, (BaseItem*)D.base[par].p, bl, cnt, C_ITEMS0 + (cur ^ 1), item_cap,
+                (CopyItem*)D.copy.p, copy_cap, spans, children, (top && level == 0 && ni == 1) ? cnt + C_L1MAX : nullptr);
+            LAUNCH_CHECK();
         }
         if (defer_base) {
             HIP_TRY(hipEventRecord(dv.ev_defer, s));
