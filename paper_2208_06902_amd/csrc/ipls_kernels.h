@@ -1666,12 +1666,11 @@ __global__ __launch_bounds__(kWave * W) void k_worklist(const Item* items, uint6
     __shared__ int s_ent[W][kMaxBuckets];       // bucket -> its child-list entry with a usable line, or -1
     __shared__ uint32_t s_wc[W][NC];            // the wave's entries per class
     __shared__ uint64_t s_gb[NC];
-    __shared__ unsigned long long s_keys;
+    __shared__ uint64_t s_wkeys[W];             // the wave's base-case keys
     const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
     const uint64_t i = (uint64_t)blockIdx.x * W + w;
     const bool live = i < num_items;  // the same for the whole wave
     const uint64_t half = T / 2 > 0 ? T / 2 : 1;
-    if (threadIdx.x == 0) s_keys = 0;
 
     int ch[4] = {-1, -1, -1, -1};
     uint64_t nn[4] = {0, 0, 0, 0}, lo[4] = {0, 0, 0, 0};
@@ -1848,7 +1847,7 @@ __global__ __launch_bounds__(kWave * W) void k_worklist(const Item* items, uint6
         if (lane == kWave - 1) s_wc[w][cl] = inc;
     }
     bkeys = wave_inclusive_sum<uint64_t>(bkeys);
-    if (lane == kWave - 1 && bkeys) atomicAdd(&s_keys, (unsigned long long)bkeys);
+    if (lane == kWave - 1) s_wkeys[w] = bkeys;
     __syncthreads();
     // the workgroup's ranges: one device atomic per class, one for the base-case keys
     if (threadIdx.x < (uint32_t)NC) {
@@ -1858,7 +1857,11 @@ __global__ __launch_bounds__(kWave * W) void k_worklist(const Item* items, uint6
         uint64_t* ctr = cl == 0 ? &cnt[next_slot] : &cnt[C_CLS + cl - 1];
         s_gb[cl] = tot ? atomicAdd((unsigned long long*)ctr, (unsigned long long)tot) : 0;
     }
-    if (threadIdx.x == 0 && s_keys) atomicAdd((unsigned long long*)&cnt[C_BASEKEYS], s_keys);
+    if (threadIdx.x == 0) {
+        uint64_t keys = 0;
+        for (int v = 0; v < W; ++v) keys += s_wkeys[v];
+        if (keys) atomicAdd((unsigned long long*)&cnt[C_BASEKEYS], (unsigned long long)keys);
+    }
     __syncthreads();
     if (!live) return;
 #pragma unroll
