@@ -10,6 +10,8 @@
 // when every sample has at most T keys.
 #include <algorithm>
 #include <atomic>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <unordered_map>
@@ -244,12 +246,25 @@ void prof_collect() {
     g_prof.pending.swap(keep);
 }
 
-#define HIP_TRY(x)                               \
-    do {                                         \
-        if ((x) != hipSuccess) {                 \
-            (void)hipGetLastError();             \
-            return IPLS_ERR_HIP;                 \
-        }                                        \
+// With IPLS_VERBOSE set in the environment, a failed HIP call is reported on stderr (source line
+// and HIP's error name) before the entry point returns IPLS_ERR_HIP.
+void report_hip_failure(int line, hipError_t e) {
+    static const bool verbose = std::getenv("IPLS_VERBOSE") != nullptr;
+    if (verbose) std::fprintf(stderr, "ipls: HIP call at ipls_lib.hip:%d failed: %s\n", line, hipGetErrorName(e));
+}
+
+// The runtime keeps a thread's last error until it is read, including a "not ready" from the
+// caller's own queries; each entry point reads it off before its first launch check.
+inline void clear_stale_error() { (void)hipGetLastError(); }
+
+#define HIP_TRY(x)                                 \
+    do {                                           \
+        const hipError_t e_ = (x);                 \
+        if (e_ != hipSuccess) {                    \
+            report_hip_failure(__LINE__, e_);      \
+            (void)hipGetLastError();               \
+            return IPLS_ERR_HIP;                   \
+        }                                          \
     } while (0)
 #define ST_TRY(x)                     \
     do {                              \
@@ -272,6 +287,7 @@ static hipError_t wait_plan(hipStream_t s, const volatile Plan* ph, uint64_t seq
         if ((i & 255) == 0) {
             const hipError_t q = hipStreamQuery(s);
             if (q != hipErrorNotReady) return q;
+            (void)hipGetLastError();  // the runtime keeps "not ready" as the thread's last error
         }
     }
 }
@@ -795,6 +811,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
 template <int DT>
 ipls_status fit_entry(Device& dv, Run& run, const void* sample, uint64_t S, bool sorted, uint32_t K,
                       ipls_linear_model* out) {
+    clear_stale_error();
     using T = typename Key<DT>::T;
     hipStream_t s = run.s;
     Depth& D = dv.depth[0];
@@ -826,6 +843,7 @@ ipls_status fit_entry(Device& dv, Run& run, const void* sample, uint64_t S, bool
 ipls_status l2pl_entry(Device& dv, hipStream_t s, const double* x, uint64_t S, uint32_t K, uint32_t M, uint32_t iters,
                        double* root_out, double* leaf_out, double* ab_out, const double* ab_in, double* grad_out,
                        double* loss_out) {
+    clear_stale_error();
     Depth& D = dv.depth[0];
     ST_TRY(ensure(D.sample, S * 8));
     ST_TRY(ensure(D.models, sizeof(Model)));
@@ -912,6 +930,7 @@ __global__ void k_single_segment(uint64_t* off, uint64_t n) {
 
 ipls_status sort_single(Device& dv, void* keys, uint32_t* payload, size_t n, ipls_dtype dtype, const ipls_params* p,
                         void* workspace, size_t workspace_bytes, ipls_stats* stats, hipStream_t s) {
+    clear_stale_error();
     if (dtype != IPLS_F64 && dtype != IPLS_F32 && dtype != IPLS_U64) return IPLS_ERR_DTYPE;
     if (n > 0 && !keys) return IPLS_ERR_INVALID;
     ipls_params prm;
@@ -951,6 +970,7 @@ ipls_status sort_single(Device& dv, void* keys, uint32_t* payload, size_t n, ipl
 ipls_status sort_multi(Device& dv, void* keys, uint32_t* payload, const uint64_t* seg_offsets, size_t nseg,
                                   ipls_dtype dtype, const ipls_params* p, void* workspace, size_t workspace_bytes,
                                   ipls_stats* stats, hipStream_t s) {
+    clear_stale_error();
     if (dtype != IPLS_F64 && dtype != IPLS_F32 && dtype != IPLS_U64) return IPLS_ERR_DTYPE;
     if (stats) std::memset(stats, 0, sizeof(*stats));
     if (nseg == 0) return IPLS_OK;
@@ -1135,6 +1155,7 @@ ipls_status ipls_fit_model(const void* sample, size_t S, ipls_dtype dtype, int s
 
 ipls_status ipls_partition(void* keys, uint32_t* payload, size_t n, ipls_dtype dtype, const ipls_params* p,
                            uint64_t* counts, ipls_linear_model* model, void* stream) {
+    clear_stale_error();
     if (dtype != IPLS_F64 && dtype != IPLS_F32 && dtype != IPLS_U64) return IPLS_ERR_DTYPE;
     ipls_params prm;
     if (p) prm = *p;
@@ -1176,6 +1197,7 @@ ipls_status ipls_l2pl_train(const double* x, size_t S, uint32_t K, uint32_t M, u
 
 ipls_status ipls_l2pl_grad(const double* x, size_t S, uint32_t K, uint32_t M, const double* ab, double* grad,
                            double* loss, void* stream) {
+    clear_stale_error();
     if (!x || !ab || !grad || S < 3 || K < 4 || M < 4) return IPLS_ERR_INVALID;
     if (K > (uint32_t)kMaxBuckets || M > (uint32_t)kMaxLeaves || S > 0xffffffffull) return IPLS_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
