@@ -29,7 +29,8 @@
  *   - Results are deterministic and bit-identical for identical inputs and parameters; with a
  *     payload the sort is stable, so the output is unique.
  *   - Argument errors are reported synchronously and nothing is enqueued.  No C++ exception
- *     crosses this interface.
+ *     crosses this interface.  With IPLS_VERBOSE set in the environment, a HIP call that fails
+ *     inside the library (the cause of IPLS_ERR_HIP) is reported on stderr with its error name.
  *   - The plain entry points share one engine context per device: their calls are serialised
  *     (one runs at a time), and the buffers the library allocates for its own use are cached in
  *     that context and reused across calls.  The request server's lanes own contexts of their
