@@ -1,4 +1,4 @@
-"""Stream ordering of the sort on a caller's stream.
+"""Stream ordering of the sort on a caller's stream, and the per-level profile records.
 
 The top-level sort runs its base case on a second stream of the engine context.  The caller's
 stream must still see the finished result: work queued on it after the call, with no host
@@ -13,6 +13,7 @@ import gen
 import paper_2208_06902_amd as ipls
 
 torch = pytest.importorskip("torch")
+from gpu_util import dev  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -55,3 +56,25 @@ def test_segmented_many_small_and_large_on_a_stream():
     s1.synchronize()
     want = np.concatenate([np.sort(keys[off[i]:off[i + 1]]) for i in range(sizes.size)])
     assert np.array_equal(got.numpy().view(np.uint64), want.view(np.uint64))
+
+
+def test_profile_records_per_level_add_up_to_the_totals():
+    # the per-level figures of each profiled kernel sum to its totals; the counting and scatter
+    # bytes of a level are w and 2w per key of the level's items
+    k = gen.make("normal", 2_000_000, 41)
+    print("profile per level: 2e6 normal", flush=True)
+    kd = dev(k)
+    ipls.profile_enable(True)
+    st = ipls.sort_(kd, None, ipls.default_params(sample_max=4096), stats=True)
+    torch.cuda.synchronize()
+    for kern in (ipls.KERNEL_SCATTER, ipls.KERNEL_CLASSIFY, ipls.KERNEL_BASE):
+        n, ms, by = ipls.profile_read(kern)
+        per = [ipls.profile_read_level(kern, lv) for lv in range(16)]
+        assert n == sum(p[0] for p in per) and n > 0
+        assert abs(by - sum(p[2] for p in per)) <= 1e-6 * by
+        assert abs(ms - sum(p[1] for p in per)) <= 1e-6 * max(ms, 1e-9)
+    n0, _, b0 = ipls.profile_read_level(ipls.KERNEL_SCATTER, 0)
+    c0 = ipls.profile_read_level(ipls.KERNEL_CLASSIFY, 0)[2]
+    assert n0 == 1 and b0 == 2 * 8 * k.size and c0 == 8 * k.size
+    assert ipls.profile_read_level(ipls.KERNEL_SCATTER, st["levels"])[0] == 0
+    ipls.profile_enable(False)
