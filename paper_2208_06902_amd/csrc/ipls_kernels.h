@@ -1409,6 +1409,74 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(6))) vo
     }
 }
 
+// The same counts with one workgroup per tile (levels without inherited class bytes): every
+// workgroup loads its whole tile at once and exits, which streams the keys faster than a
+// workgroup walking the 8 tiles of a chunk (6.9 against 7.3 TB/s for a plain read with these
+// layouts), and writes the tile's counts to tile_pref[t][b]; k_chunk_prefix then turns them into
+// the prefixes inside each chunk and the chunk totals, as k_classify_hist leaves them.
+template <int DT, int NW, int IPT>
+__global__ __launch_bounds__(64 * NW) void k_count_tile(const Item* items, const uint64_t* tile_off,
+                                                        const uint32_t* tile_map, uint64_t total_tiles,
+                                                        const Model* models, const double* leaves,
+                                                        const typename Key<DT>::T* src, uint32_t* tile_cnt,
+                                                        uint32_t K, uint32_t M) {
+    using T = typename Key<DT>::T;
+    constexpr int NT = kWave * NW, TILE = NT * IPT;
+    __shared__ uint32_t h[kMaxBuckets];
+    __shared__ double s_leaf[4 * kMaxLeaves];
+    const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
+    const uint64_t t = blockIdx.x;
+    if (t >= total_tiles) return;
+    const uint32_t i = tile_map[t];
+    const Item it = items[i];
+    const Model m = models[i];
+    const uint64_t tau = t - tile_off[i];
+    const uint64_t rem = it.n - tau * TILE;
+    const uint32_t tn = rem < (uint64_t)TILE ? (uint32_t)rem : (uint32_t)TILE;
+    const uint32_t wbase = wave * kWave * IPT;
+    const bool counting = m.kind != kKindClosedKeep && m.kind != kKindClosedMove;
+    T k[IPT];
+    uint32_t nop[1];
+    if (counting) load_tile<DT, false, IPT>(src, nullptr, it.lo + tau * TILE, tn, wbase, k, nop);
+    for (uint32_t q = tid, nq = model_table_size(m.kind, K, M); q < nq; q += NT)
+        s_leaf[q] = leaves[(uint64_t)i * 4 * kMaxLeaves + q];
+    for (uint32_t b = tid; b < kMaxBuckets; b += NT) h[b] = 0;
+    __syncthreads();
+    if (counting) {
+        classify_rows<DT, IPT>(m, s_leaf, K, M, k, [&](int r, uint32_t b) {
+            if (wbase + r * kWave + lane < tn) atomicAdd(&h[b], 1u);
+        });
+    } else if (m.kind == kKindClosedMove && tid == 0) {
+        h[0] = tn;
+    }
+    __syncthreads();
+    for (uint32_t b = tid; b < K; b += NT) tile_cnt[t * K + b] = h[b];
+}
+
+// Per chunk (a workgroup, thread b: bucket b): the tile counts of bucket b become exclusive prefixes
+// inside the chunk, in place, and their total the chunk's.
+__global__ __launch_bounds__(256) void k_chunk_prefix(const uint64_t* tile_off, const uint64_t* chunk_off,
+                                                      const uint32_t* chunk_map, uint64_t total_chunks,
+                                                      uint32_t* tile_pref, uint32_t* chunk_sum, uint32_t K) {
+    const uint64_t c = blockIdx.x;
+    if (c >= total_chunks) return;
+    const uint32_t i = chunk_map[c];
+    const uint64_t t_first = tile_off[i] + (c - chunk_off[i]) * kChunk;
+    const uint64_t t_end = (t_first + kChunk < tile_off[i + 1]) ? t_first + kChunk : tile_off[i + 1];
+    for (uint32_t b = threadIdx.x; b < K; b += blockDim.x) {
+        uint32_t v[kChunk];
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) v[q] = t_first + q < t_end ? tile_pref[(t_first + q) * K + b] : 0u;
+        uint32_t run = 0;
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) {
+            if (t_first + q < t_end) tile_pref[(t_first + q) * K + b] = run;
+            run += v[q];
+        }
+        chunk_sum[c * K + b] = run;
+    }
+}
+
 // Exclusive prefix of every item's chunk totals, per bucket (chunk_pref[c][b]); the total is the
 // item's bucket size hist[i][b].  Items of at most kScanSerial chunks: one thread per (item, bucket)
 // walks the chunks (neighbouring threads read neighbouring buckets).  Larger items (only at the

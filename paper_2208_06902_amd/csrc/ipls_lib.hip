@@ -710,12 +710,24 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         // classify + per-tile counts, scan of the counts, bucket starts
         {
             ProfScope ps(1, level, (double)(pl.sum_n - pl.inh_n) * kb + (double)pl.inh_n, s);
-            auto kc = tile == kTile ? k_classify_hist<DT, 8, kPassIPT> : k_classify_hist<DT, 4, kPassIPT>;
-            kc<<<(unsigned)nc, tile / kPassIPT, 0, s>>>(
-                items, (const uint64_t*)D.tile_off.p, (const uint64_t*)D.chunk_off.p, (const uint32_t*)D.chunk_map.p,
-                nc, models, (const double*)D.leaves.p, src, (uint32_t*)D.tile_pref.p, (uint32_t*)D.chunk_sum.p, K,
-                P.leaves, cls);
-            LAUNCH_CHECK();
+            if (!cls) {
+                // a workgroup per tile, then the prefixes inside each chunk
+                auto kt = tile == kTile ? k_count_tile<DT, 8, kPassIPT> : k_count_tile<DT, 4, kPassIPT>;
+                kt<<<(unsigned)nt, tile / kPassIPT, 0, s>>>(items, (const uint64_t*)D.tile_off.p, (const uint32_t*)D.tile_map.p, nt,
+                                                            models, (const double*)D.leaves.p, src,
+                                                            (uint32_t*)D.tile_pref.p, K, P.leaves);
+                LAUNCH_CHECK();
+                k_chunk_prefix<<<(unsigned)nc, 256, 0, s>>>((const uint64_t*)D.tile_off.p, (const uint64_t*)D.chunk_off.p, (const uint32_t*)D.chunk_map.p, nc,
+                                                            (uint32_t*)D.tile_pref.p, (uint32_t*)D.chunk_sum.p, K);
+                LAUNCH_CHECK();
+            } else {
+                auto kc = tile == kTile ? k_classify_hist<DT, 8, kPassIPT> : k_classify_hist<DT, 4, kPassIPT>;
+                kc<<<(unsigned)nc, tile / kPassIPT, 0, s>>>(
+                    items, (const uint64_t*)D.tile_off.p, (const uint64_t*)D.chunk_off.p, (const uint32_t*)D.chunk_map.p,
+                    nc, models, (const double*)D.leaves.p, src, (uint32_t*)D.tile_pref.p, (uint32_t*)D.chunk_sum.p, K,
+                    P.leaves, cls);
+                LAUNCH_CHECK();
+            }
         }
         // chunk prefixes, bucket sizes and bucket starts: a workgroup per item; wide items by a
         // workgroup per (item, bucket), then their starts
