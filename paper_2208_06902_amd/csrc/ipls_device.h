@@ -57,6 +57,13 @@ struct ChildSpan {
     uint32_t base, count;
 };
 
+// A pass tile: its first key's position in the level's source buffer, its item and its key count,
+// so that a pass's workgroup can issue its key loads after one dependent read.
+struct TileInfo {
+    uint64_t base;
+    uint32_t item, n;
+};
+
 // A bucket of <= T keys for the base case, at [lo, lo+n) of the caller's buffer (from_scratch = 0)
 // or of the scratch buffer (1).  The result always lands in the caller's buffer.
 struct BaseItem {

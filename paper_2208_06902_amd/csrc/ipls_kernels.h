@@ -221,10 +221,12 @@ __global__ void k_expand(const uint64_t* off, uint64_t num_items, uint64_t total
     map[t] = (uint32_t)lo;
 }
 
-// Two maps from one workgroup index: map1 over [0, total1) from off1, map2 over [0, total2) from
-// off2 (both with num_items ranges).
-__device__ inline void expand2(uint64_t block, const uint64_t* off1, uint64_t total1, uint32_t* map1,
-                               const uint64_t* off2, uint64_t total2, uint32_t* map2, uint64_t num_items) {
+// Two maps from one workgroup index: the tiles over [0, total1) from off1 (each item's tiles of
+// `tile` keys, the last one ragged), and map2 over [0, total2) from off2 (both with num_items
+// ranges).
+__device__ inline void expand2(uint64_t block, const uint64_t* off1, uint64_t total1, TileInfo* map1,
+                               const Item* items, uint32_t tile, const uint64_t* off2, uint64_t total2,
+                               uint32_t* map2, uint64_t num_items) {
     const uint64_t t = block * blockDim.x + threadIdx.x;
     auto find = [&](const uint64_t* off) {
         uint64_t lo = 0, hi = num_items;  // largest i with off[i] <= t
@@ -235,7 +237,12 @@ __device__ inline void expand2(uint64_t block, const uint64_t* off1, uint64_t to
         }
         return (uint32_t)lo;
     };
-    if (t < total1) map1[t] = find(off1);
+    if (t < total1) {
+        const uint32_t i = find(off1);
+        const Item it = items[i];
+        const uint64_t first = (t - off1[i]) * tile, rem = it.n - first;
+        map1[t] = TileInfo{it.lo + first, i, rem < (uint64_t)tile ? (uint32_t)rem : tile};
+    }
     if (t < total2) map2[t] = find(off2);
 }
 
@@ -272,10 +279,11 @@ template <int DT>
 __global__ void k_sample(const Item* items, uint64_t num_items, const uint64_t* sample_off, uint64_t total,
                          const typename Key<DT>::T* src, typename Key<DT>::T* sample, uint64_t seed,
                          const Child* prev_children, const typename Key<DT>::T* prev_sample, uint64_t expand_blocks,
-                         const uint64_t* tile_off, uint64_t total_tiles, uint32_t* tile_map, const uint64_t* chunk_off,
-                         uint64_t total_chunks, uint32_t* chunk_map) {
+                         const uint64_t* tile_off, uint64_t total_tiles, TileInfo* tile_map, uint32_t tile,
+                         const uint64_t* chunk_off, uint64_t total_chunks, uint32_t* chunk_map) {
     if (blockIdx.x < expand_blocks) {
-        expand2(blockIdx.x, tile_off, total_tiles, tile_map, chunk_off, total_chunks, chunk_map, num_items);
+        expand2(blockIdx.x, tile_off, total_tiles, tile_map, items, tile, chunk_off, total_chunks, chunk_map,
+                num_items);
         return;
     }
     uint64_t s = (uint64_t)(blockIdx.x - expand_blocks) * blockDim.x + threadIdx.x;
@@ -411,14 +419,15 @@ template <int DT, int CAP>
 __global__ __launch_bounds__(256) void k_sample_fit(const Item* items, uint64_t num_items, const uint64_t* sample_off,
                                                     const typename Key<DT>::T* src, uint64_t seed, Model* models,
                                                     uint32_t K, uint64_t expand_blocks, const uint64_t* tile_off,
-                                                    uint64_t total_tiles, uint32_t* tile_map,
+                                                    uint64_t total_tiles, TileInfo* tile_map, uint32_t tile,
                                                     const uint64_t* chunk_off, uint64_t total_chunks,
                                                     uint32_t* chunk_map) {
     using KT = Key<DT>;
     static_assert((CAP & (CAP - 1)) == 0, "power of two");
     __shared__ uint64_t s_o[CAP];
     if (blockIdx.x < expand_blocks) {
-        expand2(blockIdx.x, tile_off, total_tiles, tile_map, chunk_off, total_chunks, chunk_map, num_items);
+        expand2(blockIdx.x, tile_off, total_tiles, tile_map, items, tile, chunk_off, total_chunks, chunk_map,
+                num_items);
         return;
     }
     const uint64_t i = blockIdx.x - expand_blocks;
@@ -1414,30 +1423,28 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(6))) vo
 // workgroup walking the 8 tiles of a chunk (6.9 against 7.3 TB/s for a plain read with these
 // layouts), and writes the tile's counts to tile_pref[t][b]; k_chunk_prefix then turns them into
 // the prefixes inside each chunk and the chunk totals, as k_classify_hist leaves them.
+// The tile's keys are loaded before its model is read (a homogeneous item's tiles are read and
+// not counted).
 template <int DT, int NW, int IPT>
-__global__ __launch_bounds__(64 * NW) void k_count_tile(const Item* items, const uint64_t* tile_off,
-                                                        const uint32_t* tile_map, uint64_t total_tiles,
+__global__ __launch_bounds__(64 * NW) void k_count_tile(const TileInfo* tile_map, uint64_t total_tiles,
                                                         const Model* models, const double* leaves,
                                                         const typename Key<DT>::T* src, uint32_t* tile_cnt,
                                                         uint32_t K, uint32_t M) {
     using T = typename Key<DT>::T;
-    constexpr int NT = kWave * NW, TILE = NT * IPT;
+    constexpr int NT = kWave * NW;
     __shared__ uint32_t h[kMaxBuckets];
     __shared__ double s_leaf[4 * kMaxLeaves];
     const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
     const uint64_t t = blockIdx.x;
     if (t >= total_tiles) return;
-    const uint32_t i = tile_map[t];
-    const Item it = items[i];
-    const Model m = models[i];
-    const uint64_t tau = t - tile_off[i];
-    const uint64_t rem = it.n - tau * TILE;
-    const uint32_t tn = rem < (uint64_t)TILE ? (uint32_t)rem : (uint32_t)TILE;
+    const TileInfo ti = tile_map[t];
+    const uint32_t i = ti.item, tn = ti.n;
     const uint32_t wbase = wave * kWave * IPT;
-    const bool counting = m.kind != kKindClosedKeep && m.kind != kKindClosedMove;
     T k[IPT];
     uint32_t nop[1];
-    if (counting) load_tile<DT, false, IPT>(src, nullptr, it.lo + tau * TILE, tn, wbase, k, nop);
+    load_tile<DT, false, IPT>(src, nullptr, ti.base, tn, wbase, k, nop);
+    const Model m = models[i];
+    const bool counting = m.kind != kKindClosedKeep && m.kind != kKindClosedMove;
     for (uint32_t q = tid, nq = model_table_size(m.kind, K, M); q < nq; q += NT)
         s_leaf[q] = leaves[(uint64_t)i * 4 * kMaxLeaves + q];
     for (uint32_t b = tid; b < kMaxBuckets; b += NT) h[b] = 0;
@@ -1566,7 +1573,7 @@ __device__ inline uint64_t xcd_tile(uint64_t g, uint64_t nt) {
 // such a child gets its class under the child's line in registers, the class is staged beside the
 // key and written to dst_cls at the key's destination.  No barrier is added.
 template <int DT, bool PAY, int NW, int IPT, bool CLS>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(CLS && !PAY && NW == 8 ? 6 : 1))) void k_scatter(const Item* items, const uint64_t* tile_off, const uint32_t* tile_map,
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(CLS && !PAY && NW == 8 ? 6 : 1))) void k_scatter(const Item* items, const TileInfo* tile_map,
                                                  uint64_t total_tiles, const uint64_t* chunk_off,
                                                  uint64_t total_chunks, const Model* models, const double* leaves,
                                                  const uint64_t* bstart, const uint64_t* chunk_pref,
@@ -1595,21 +1602,19 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(CLS && 
 
     const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
     const uint64_t t = xcd_tile(blockIdx.x, total_tiles);
-    const uint32_t i = tile_map[t];
-    const Model m = models[i];
-    if (m.kind == kKindClosedKeep) return;
-    const Item it = items[i];
-    const uint64_t tau = t - tile_off[i];
-    const uint64_t c = chunk_off[i] + tau / kChunk;
-    const uint64_t base = it.lo + tau * TILE;
-    const uint64_t rem = it.n - tau * TILE;
-    const uint32_t tn = rem < (uint64_t)TILE ? (uint32_t)rem : (uint32_t)TILE;
-    // issue the tile's loads and the destination bases together, then one barrier
+    const TileInfo ti = tile_map[t];
+    const uint32_t i = ti.item, tn = ti.n;
+    // issue the tile's loads, then read the model and the destination bases, then one barrier (a
+    // homogeneous item already in place has its tiles read and left)
     T k[IPT];
     uint32_t p[PAY ? IPT : 1];
     uint32_t bk[IPT], rk[IPT];
     const uint32_t wbase = wave * kWave * IPT;
-    load_tile<DT, PAY, IPT>(src, src_pay, base, tn, wbase, k, p);
+    load_tile<DT, PAY, IPT>(src, src_pay, ti.base, tn, wbase, k, p);
+    const Model m = models[i];
+    if (m.kind == kKindClosedKeep) return;
+    const Item it = items[i];
+    const uint64_t c = chunk_off[i] + (ti.base - it.lo) / TILE / kChunk;
     const ChildSpan sp = CLS ? spans[i] : ChildSpan{0u, 0u};
     Child ch = {};
     if (CLS && tid < sp.count) ch = children[sp.base + tid];

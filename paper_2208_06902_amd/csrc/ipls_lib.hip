@@ -636,7 +636,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         prev_sum_n = pl.sum_n;
 
         const uint64_t ni = pl.num_items, nt = pl.total_tiles;
-        ST_TRY(ensure(D.tile_map, nt * 4));
+        ST_TRY(ensure(D.tile_map, nt * sizeof(TileInfo)));
         Buf& sbuf = (inherit && par) ? D.sample2 : D.sample;
         ST_TRY(ensure(sbuf, pl.total_samples * kb));
         T* sample = (T*)sbuf.p;
@@ -661,13 +661,13 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             // a larger sample takes longer than the three launches)
             k_sample_fit<DT, kFitLdsTiny><<<(unsigned)(eb + ni), 256, 0, s>>>(
                 items, ni, (const uint64_t*)D.sample_off.p, src, P.seed, models, K, eb, (const uint64_t*)D.tile_off.p,
-                nt, (uint32_t*)D.tile_map.p, (const uint64_t*)D.chunk_off.p, nc, (uint32_t*)D.chunk_map.p);
+                nt, (TileInfo*)D.tile_map.p, tile, (const uint64_t*)D.chunk_off.p, nc, (uint32_t*)D.chunk_map.p);
             LAUNCH_CHECK();
         } else {
             // the sample gather and the tile and chunk maps, in one launch
             k_sample<DT><<<(unsigned)(eb + (pl.total_samples + 255) / 256), 256, 0, s>>>(
                 items, ni, (const uint64_t*)D.sample_off.p, pl.total_samples, src, sample, P.seed, prev_children,
-                prev_sample, eb, (const uint64_t*)D.tile_off.p, nt, (uint32_t*)D.tile_map.p,
+                prev_sample, eb, (const uint64_t*)D.tile_off.p, nt, (TileInfo*)D.tile_map.p, tile,
                 (const uint64_t*)D.chunk_off.p, nc, (uint32_t*)D.chunk_map.p);
             LAUNCH_CHECK();
             ST_TRY(sort_samples<DT>(dv, run, d, pl, sample));
@@ -713,7 +713,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             if (!cls) {
                 // a workgroup per tile, then the prefixes inside each chunk
                 auto kt = tile == kTile ? k_count_tile<DT, 8, kPassIPT> : k_count_tile<DT, 4, kPassIPT>;
-                kt<<<(unsigned)nt, tile / kPassIPT, 0, s>>>(items, (const uint64_t*)D.tile_off.p, (const uint32_t*)D.tile_map.p, nt,
+                kt<<<(unsigned)nt, tile / kPassIPT, 0, s>>>((const TileInfo*)D.tile_map.p, nt,
                                                             models, (const double*)D.leaves.p, src,
                                                             (uint32_t*)D.tile_pref.p, K, P.leaves);
                 LAUNCH_CHECK();
@@ -771,7 +771,7 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                               : (tile == kTile ? k_scatter<DT, PAY, 8, kPassIPT, false>
                                                : k_scatter<DT, PAY, 4, kPassIPT, false>);
             ks<<<(unsigned)nt, tile / kPassIPT, 0, s>>>(
-                items, (const uint64_t*)D.tile_off.p, (const uint32_t*)D.tile_map.p, nt, (const uint64_t*)D.chunk_off.p,
+                items, (const TileInfo*)D.tile_map.p, nt, (const uint64_t*)D.chunk_off.p,
                 nc, models, (const double*)D.leaves.p, (const uint64_t*)D.bstart.p, (const uint64_t*)D.chunk_pref.p,
                 (const uint32_t*)D.tile_pref.p, src, psrc, dst, pdst, K, P.leaves, spans, children, cls);
             LAUNCH_CHECK();
