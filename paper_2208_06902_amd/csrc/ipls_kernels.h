@@ -381,6 +381,7 @@ __device__ inline void fmcd_search(const X& x, uint64_t S, uint32_t K, double* a
 constexpr int kFitLds = 16384;
 constexpr int kFitLdsSmall = 4096;
 constexpr int kFitLdsTiny = 1024;
+constexpr int kFitLdsFused = 2048;  // the largest sample k_sample_fit takes
 
 template <int DT, int LDS_KEYS>
 __global__ __launch_bounds__(256) void k_fmcd_small(const typename Key<DT>::T* sample, const uint64_t* sample_off,

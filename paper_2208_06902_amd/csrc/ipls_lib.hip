@@ -655,11 +655,12 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         const uint64_t eb = (std::max(nt, nc) + 255) / 256;
         const EqInfo* eq = nullptr;
         const uint32_t* tree = nullptr;
-        if (P.model == 0 && !P.equality && !inherit && pl.max_S <= (uint64_t)kFitLdsTiny) {
-            // the plain FMCD line on samples of at most 1024 keys (the deeper levels' items): gather,
+        if (P.model == 0 && !P.equality && !inherit && pl.max_S <= (uint64_t)kFitLdsFused) {
+            // the plain FMCD line on samples of at most 2048 keys (the deeper levels' items): gather,
             // sort and fit in one launch, with the tile and chunk maps (a workgroup's bitonic sort of
             // a larger sample takes longer than the three launches)
-            k_sample_fit<DT, kFitLdsTiny><<<(unsigned)(eb + ni), 256, 0, s>>>(
+            auto ksf = pl.max_S <= (uint64_t)kFitLdsTiny ? k_sample_fit<DT, kFitLdsTiny> : k_sample_fit<DT, kFitLdsFused>;
+            ksf<<<(unsigned)(eb + ni), 256, 0, s>>>(
                 items, ni, (const uint64_t*)D.sample_off.p, src, P.seed, models, K, eb, (const uint64_t*)D.tile_off.p,
                 nt, (TileInfo*)D.tile_map.p, tile, (const uint64_t*)D.chunk_off.p, nc, (uint32_t*)D.chunk_map.p);
             LAUNCH_CHECK();
