@@ -130,18 +130,23 @@ __device__ inline void merge_sort_lds(O* sk, uint32_t* sp, int t_in, bool active
     __syncthreads();
 }
 
+// The merge-sort classes' LDS: 256 / NT groups of 16 NT keys and their pad slots, the same size for
+// every NT.
+constexpr int kBaseSortLds = kBlock * 17;
+
+// One workgroup (block blk of its class) of the merge-sort classes: 256 / NT buckets of at most 16 NT
+// keys each, s_k and s_p holding kBaseSortLds slots.
 template <int DT, bool PAY, int NT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PAY ? 3 : 1))) void k_base_sort(const BaseItem* list, uint64_t count, typename Key<DT>::T* keys,
-                                                   uint32_t* pay, const typename Key<DT>::T* skeys,
-                                                   const uint32_t* spay) {
+__device__ inline void base_sort_block(const BaseItem* list, uint64_t count, uint64_t blk, typename Key<DT>::T* keys,
+                                       uint32_t* pay, const typename Key<DT>::T* skeys, const uint32_t* spay,
+                                       typename Key<DT>::O* s_k, uint32_t* s_p) {
     using KT = Key<DT>;
     using O = typename KT::O;
     constexpr int IPT = 16, G = kBlock / NT, CAP = NT * IPT, PCAP = CAP + CAP / 16;
+    static_assert(G * PCAP == kBaseSortLds, "every class fills the same LDS");
     constexpr O kPad = (O)~(O)0;
-    __shared__ O s_k[G * PCAP];
-    __shared__ uint32_t s_p[PAY ? G * PCAP : 1];
     const int g = threadIdx.x / NT, t = threadIdx.x % NT;
-    const uint64_t bidx = (uint64_t)blockIdx.x * G + g;
+    const uint64_t bidx = blk * G + g;
     BaseItem bi = {0, 0, 0};
     if (bidx < count) bi = list[bidx];
     const uint32_t n = bi.n;
@@ -183,6 +188,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PAY ? 3 : 1
             if (PAY) pay[bi.lo + j] = pv[r];
         }
     }
+}
+
+template <int DT, bool PAY, int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PAY ? 3 : 1))) void k_base_sort(const BaseItem* list, uint64_t count, typename Key<DT>::T* keys,
+                                                   uint32_t* pay, const typename Key<DT>::T* skeys,
+                                                   const uint32_t* spay) {
+    using O = typename Key<DT>::O;
+    __shared__ O s_k[kBaseSortLds];
+    __shared__ uint32_t s_p[PAY ? kBaseSortLds : 1];
+    base_sort_block<DT, PAY, NT>(list, count, blockIdx.x, keys, pay, skeys, spay, s_k, s_p);
+}
+
+// The four merge-sort classes (buckets of at most 64, 128, 256 and 512 keys) in one launch: the
+// workgroups [first[c], first[c + 1]) are class c's.  A level's smallest classes hold few buckets
+// each, and four launches of a few workgroups run one after another.
+struct BaseSmall {
+    const BaseItem* list[4];
+    uint64_t count[4];
+    uint64_t first[5];
+};
+
+template <int DT, bool PAY>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PAY ? 3 : 1))) void k_base_sort_small(
+    BaseSmall a, typename Key<DT>::T* keys, uint32_t* pay, const typename Key<DT>::T* skeys, const uint32_t* spay) {
+    using O = typename Key<DT>::O;
+    __shared__ O s_k[kBaseSortLds];
+    __shared__ uint32_t s_p[PAY ? kBaseSortLds : 1];
+    const uint64_t b = blockIdx.x;
+    if (b < a.first[1])
+        base_sort_block<DT, PAY, 4>(a.list[0], a.count[0], b, keys, pay, skeys, spay, s_k, s_p);
+    else if (b < a.first[2])
+        base_sort_block<DT, PAY, 8>(a.list[1], a.count[1], b - a.first[1], keys, pay, skeys, spay, s_k, s_p);
+    else if (b < a.first[3])
+        base_sort_block<DT, PAY, 16>(a.list[2], a.count[2], b - a.first[2], keys, pay, skeys, spay, s_k, s_p);
+    else if (b < a.first[4])
+        base_sort_block<DT, PAY, 32>(a.list[3], a.count[3], b - a.first[3], keys, pay, skeys, spay, s_k, s_p);
 }
 
 // Stable counting of one digit (0..255) per key over a workgroup of NW waves, with the same

@@ -420,6 +420,29 @@ ipls_status launch_base(hipStream_t s, int cls, const BaseItem* list, uint64_t c
     }
 }
 
+// The merge-sort classes 0..3 of a level's base-case lists (at list + off[c], count[c] buckets each)
+// in one launch.
+template <int DT, bool PAY>
+ipls_status launch_base_small(hipStream_t s, const BaseItem* list, const BaseLayout& bl, const uint64_t* count,
+                              typename Key<DT>::T* keys, uint32_t* pay, const typename Key<DT>::T* sk,
+                              const uint32_t* sp) {
+    static_assert(kBaseClasses > 4, "classes 0..3 are the merge sorts");
+    BaseSmall a;
+    uint64_t g = 0;
+    for (int c = 0; c < 4; ++c) {
+        const uint64_t G = (uint64_t)kBlock / (4u << c);  // buckets per workgroup
+        a.list[c] = list + bl.off[c];
+        a.count[c] = count[c];
+        a.first[c] = g;
+        g += (count[c] + G - 1) / G;
+    }
+    a.first[4] = g;
+    if (g == 0) return IPLS_OK;
+    k_base_sort_small<DT, PAY><<<(unsigned)g, kBlock, 0, s>>>(a, keys, pay, sk, sp);
+    LAUNCH_CHECK();
+    return IPLS_OK;
+}
+
 // Sort the samples of a level: base case when every sample fits, else the engine one level deeper.
 template <int DT>
 ipls_status sort_samples(Device& dv, Run& run, int d, const Plan& pl, typename Key<DT>::T* sample) {
@@ -602,7 +625,9 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         const int bp = (level + 1) & 1;
         auto launch_level_base = [&](hipStream_t sl) -> ipls_status {
             ProfScope ps(2, level - 1, (double)pl.base_keys * 2.0 * (kb + (PAY ? 4 : 0)), sl);
-            for (int c = 0; c < kBaseClasses; ++c)
+            ST_TRY((launch_base_small<DT, PAY>(sl, (const BaseItem*)D.base[bp].p, bl, pl.cls_count, keys, pay, scratch,
+                                               spay)));
+            for (int c = 4; c < kBaseClasses; ++c)
                 ST_TRY((launch_base<DT, PAY>(sl, c, (const BaseItem*)D.base[bp].p + bl.off[c], pl.cls_count[c], keys,
                                              pay, scratch, spay)));
             return IPLS_OK;
