@@ -687,7 +687,12 @@ static void fit_bucket(const void* keys, uint64_t n, int dtype, const oracle_par
         return;
     }
     m->kind = MODEL_LINEAR;
-    if (p->model != 0 && l2 && l2_leaf) {
+    /* Every D + 1 consecutive sample keys span at least a bucket's width, so a bucket of the line
+     * holds at most about D of the S sample keys, D n / S of the bucket's n.  The auto policy tries
+     * the two-level model only where that can exceed the base-case threshold T (D n > T S, in
+     * integers as D > floor(T S / n)): elsewhere FMCD already leaves no bucket for another level. */
+    const int try_l2pl = p->model == 2 || (p->model == 1 && m->D > (uint64_t)p->base_case_max * S / n);
+    if (p->model != 0 && try_l2pl && l2 && l2_leaf) {
         double root[2];
         l2->M = p->leaves ? p->leaves : 256;
         l2->leaf = l2_leaf;

@@ -711,14 +711,22 @@ __device__ inline double l2pl_target(uint64_t j, uint64_t S, uint32_t K) {
 
 // first[i][l] = first sample of leaf l of item i (M + 1 entries; empty leaves get zero-length ranges)
 template <int DT>
+// gate_T (the auto policy): an item whose FMCD conflict degree D gives D n <= T S (the line
+// leaves no bucket of more than about T keys) keeps its line: its root is marked unusable, which
+// every later kernel of the two-level model skips.
 __global__ __launch_bounds__(256) void k_l2pl_bounds(const typename Key<DT>::T* sample, const uint64_t* sample_off,
-                                                     uint64_t num_items, const Model* models, const Model* roots,
-                                                     uint32_t M, uint32_t* first) {
+                                                     uint64_t num_items, const Model* models, Model* roots,
+                                                     uint32_t M, uint32_t* first, const Item* items,
+                                                     uint32_t gate_T) {
     using KT = Key<DT>;
     const uint64_t i = blockIdx.x;
     if (i >= num_items || models[i].kind != kKindLinear || roots[i].kind != kKindLinear) return;
-    const double ra = roots[i].a, rb = roots[i].b;
     const uint64_t off = sample_off[i], S = sample_off[i + 1] - off;
+    if (gate_T && !(models[i].D > (uint64_t)gate_T * S / items[i].n)) {
+        if (threadIdx.x == 0) roots[i].kind = kKindPending;
+        return;
+    }
+    const double ra = roots[i].a, rb = roots[i].b;
     uint32_t* f = first + i * (M + 1);
     for (uint64_t j = threadIdx.x; j <= S; j += blockDim.x) {
         const int lp = j == 0 ? -1 : (int)classify_linear(ra, rb, M, KT::val(sample[off + j - 1]), false);

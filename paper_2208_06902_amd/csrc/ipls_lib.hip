@@ -356,7 +356,8 @@ template <int DT>
 ipls_status train_l2pl(Depth& D, hipStream_t s, uint64_t ni, uint64_t max_S, uint64_t total_fit_chunks,
                        const typename Key<DT>::T* sample, const uint64_t* sample_off, const uint64_t* fit_off,
                        Model* models, uint32_t K, uint32_t M, uint32_t iters, const double* ab_in = nullptr,
-                       double* grad_out = nullptr, double* loss_out = nullptr, double* ab_out = nullptr) {
+                       double* grad_out = nullptr, double* loss_out = nullptr, double* ab_out = nullptr,
+                       const Item* items = nullptr, uint32_t gate_T = 0) {
     ST_TRY(ensure(D.roots, ni * sizeof(Model)));
     ST_TRY(ensure(D.leaf_first, ni * (M + 1) * 4));
     ST_TRY(ensure(D.leaves, ni * 4 * kMaxLeaves * 8));
@@ -364,7 +365,7 @@ ipls_status train_l2pl(Depth& D, hipStream_t s, uint64_t ni, uint64_t max_S, uin
     Model* roots = (Model*)D.roots.p;
     ST_TRY((fit_level<DT>(D, s, ni, max_S, total_fit_chunks, sample, sample_off, fit_off, roots, M)));
     k_l2pl_bounds<DT><<<(unsigned)ni, 256, 0, s>>>(sample, sample_off, ni, models, roots, M,
-                                                   (uint32_t*)D.leaf_first.p);
+                                                   (uint32_t*)D.leaf_first.p, items, items ? gate_T : 0u);
     LAUNCH_CHECK();
     k_l2pl_train<DT><<<(unsigned)((ni * M + 3) / 4), 256, 0, s>>>(
         sample, sample_off, ni, models, roots, (const uint32_t*)D.leaf_first.p, K, M, iters, (double*)D.leaves.p,
@@ -721,7 +722,8 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             if (P.model == 1 || P.model == 2)
                 ST_TRY((train_l2pl<DT>(D, s, ni, pl.max_S, pl.total_fit_chunks, (const T*)sample,
                                        (const uint64_t*)D.sample_off.p, (const uint64_t*)D.fit_off.p, models, K, P.leaves,
-                                       P.train_iters)));
+                                       P.train_iters, nullptr, nullptr, nullptr, nullptr, items,
+                                       P.model == 1 ? T_ : 0u)));
         }
 
         // degenerate buckets and final model

@@ -175,3 +175,28 @@ def test_exported_leaf_line_is_the_trained_line(dist):
             assert abs(got - exact) <= bound, (l, j, float(got), float(exact))
             checked += 1
     assert checked > 200
+
+
+@pytest.mark.parametrize("dist", ["lognormal2", "mixgauss20", "exponential"])
+def test_auto_policy_tries_the_learned_model_only_where_fmcd_can_overflow(dist):
+    # FMCD's conflict degree D bounds a bucket's sample keys, so its buckets hold about D n / S of
+    # the n keys at most.  The auto policy trains the two-level model only when that exceeds the
+    # base-case threshold T (D n > T S); elsewhere the item keeps its line untrained.  D comes from
+    # the exhaustive search of the FMCD definition on the item's sample, not from the oracle's fit.
+    import test_oracle_pins as pins
+    K, n = 64, 20000
+    keys = gen.make(dist, n, 12)
+    p0 = oracle.params(K=K, model=1)
+    S = oracle.sample_size(n, p0)
+    x = np.sort(keys[oracle.sample_positions(n, 0, S, p0.seed).astype(np.int64)])
+    D, _, _ = pins.fmcd_brute(list(x), K)
+    t_try, t_keep = max(1, D * n // S - 1), D * n // S + 1
+    assert D * n > t_try * S and D * n <= t_keep * S
+    m, _, _ = oracle.fit_bucket(keys, oracle.params(K=K, T=t_keep, model=1))
+    assert m.D == D and m.kind == oracle.MODEL_LINEAR and m.max_load_l2pl == 0 and m.max_load_linear == 0
+    m, _, _ = oracle.fit_bucket(keys, oracle.params(K=K, T=t_try, model=1))
+    assert m.D == D and m.max_load_l2pl > 0
+    assert (m.kind == oracle.MODEL_L2PL) == (m.max_load_l2pl < m.max_load_linear)
+    # the forced two-level policy ignores the gate
+    m, _, _ = oracle.fit_bucket(keys, oracle.params(K=K, T=t_keep, model=2))
+    assert m.max_load_l2pl > 0
