@@ -27,6 +27,7 @@ namespace {
 constexpr uint64_t kWorklistFewItems = 1024;  // up to this many items: four a k_worklist workgroup
 constexpr uint32_t kSmallS = kFitLds;  // samples up to this size are fitted in one workgroup's LDS
 constexpr uint64_t kDeferBaseItems = 2048;  // levels of at least this many items run before the previous level's base case
+constexpr uint64_t kDeferBaseShare = 64;    // ... and levels of at least 1/64 of its keys
 constexpr uint32_t kFitChunk = 2048;   // windows per workgroup in the multi-round fit
 constexpr uint32_t kCand = 15;         // candidate widths per fit round
 constexpr uint32_t kSmallTile = 4 * kWave * kPassIPT;  // 2048 keys: 4 waves
@@ -635,11 +636,14 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         };
         // They go to the side stream while another level follows on the main stream; the last
         // level's go to the main stream, beside the side stream's earlier (larger) base-case
-        // launch, whose tail leaves most of the device idle.  Before a level of many items the
-        // launch waits for that level's worklist: its latency-bound per-item kernels would
-        // otherwise wait for CUs held by the base case's large-LDS workgroups.
+        // launch, whose tail leaves most of the device idle.  The launch waits for the coming
+        // level's worklist when that level has many items (its latency-bound per-item kernels
+        // would otherwise wait for CUs held by the base case's large-LDS workgroups) or holds at
+        // least 1/64 as many keys as the base case (its counting and scatter then stream at the
+        // device's full bandwidth instead of sharing it); a level of a few keys runs beside it.
         const bool side = overlap && pl.num_items > 0;
-        const bool defer_base = side && pl.num_base && pl.num_items >= kDeferBaseItems;
+        const bool defer_base = side && pl.num_base &&
+                                (pl.num_items >= kDeferBaseItems || pl.sum_n * kDeferBaseShare >= pl.base_keys);
         if (pl.num_base && !defer_base) {
             ST_TRY(launch_level_base(side ? sb : s));
             if (side) {
