@@ -383,10 +383,18 @@ constexpr int kFitLdsSmall = 4096;
 constexpr int kFitLdsTiny = 1024;
 constexpr int kFitLdsFused = 2048;  // the largest sample k_sample_fit takes
 
+// The auto policy's gate for the learned model's root fit: an item whose FMCD line (lines[i]) gives
+// D n <= T S is not trained, and its root is left unusable (k_l2pl_bounds applies the same rule).
+struct FitGate {
+    const Model* lines;
+    const Item* items;
+    uint32_t T;  // 0: no gate
+};
+
 template <int DT, int LDS_KEYS>
 __global__ __launch_bounds__(256) void k_fmcd_small(const typename Key<DT>::T* sample, const uint64_t* sample_off,
                                                     uint64_t num_items, Model* models, uint32_t K_all, uint32_t small_S,
-                                                    const EqInfo* eq) {
+                                                    const EqInfo* eq, FitGate gate) {
     __shared__ double sx[LDS_KEYS];
     const uint64_t i = blockIdx.x;
     if (i >= num_items) return;
@@ -394,6 +402,14 @@ __global__ __launch_bounds__(256) void k_fmcd_small(const typename Key<DT>::T* s
     const uint64_t off = sample_off[i], S = eq ? eq[i].sr : sample_off[i + 1] - off;
     const uint32_t K = eq ? eq[i].km : K_all;
     if (S > small_S) return;
+    if (gate.T && !(gate.lines[i].kind == kKindLinear && gate.lines[i].D > (uint64_t)gate.T * S / gate.items[i].n)) {
+        if (threadIdx.x == 0) {
+            Model m = {};
+            model_degenerate(m);
+            models[i] = m;
+        }
+        return;
+    }
     fill_sample_lds<DT>(sx, sample + off, S);
     __syncthreads();
     Model m = {};

@@ -321,13 +321,14 @@ struct Run {
 template <int DT>
 ipls_status fit_level(Depth& D, hipStream_t s, uint64_t ni, uint64_t max_S, uint64_t total_fit_chunks,
                       const typename Key<DT>::T* sample, const uint64_t* sample_off, const uint64_t* fit_off,
-                      Model* models, uint32_t K, const EqInfo* eq = nullptr) {
+                      Model* models, uint32_t K, const EqInfo* eq = nullptr, FitGate gate = {nullptr, nullptr, 0}) {
     if (max_S <= (uint64_t)kFitLdsTiny)
-        k_fmcd_small<DT, kFitLdsTiny><<<(unsigned)ni, 256, 0, s>>>(sample, sample_off, ni, models, K, kSmallS, eq);
+        k_fmcd_small<DT, kFitLdsTiny><<<(unsigned)ni, 256, 0, s>>>(sample, sample_off, ni, models, K, kSmallS, eq, gate);
     else if (max_S <= (uint64_t)kFitLdsSmall)
-        k_fmcd_small<DT, kFitLdsSmall><<<(unsigned)ni, 256, 0, s>>>(sample, sample_off, ni, models, K, kSmallS, eq);
+        k_fmcd_small<DT, kFitLdsSmall><<<(unsigned)ni, 256, 0, s>>>(sample, sample_off, ni, models, K, kSmallS, eq,
+                                                                   gate);
     else
-        k_fmcd_small<DT, kFitLds><<<(unsigned)ni, 256, 0, s>>>(sample, sample_off, ni, models, K, kSmallS, eq);
+        k_fmcd_small<DT, kFitLds><<<(unsigned)ni, 256, 0, s>>>(sample, sample_off, ni, models, K, kSmallS, eq, gate);
     LAUNCH_CHECK();
     if (max_S <= kSmallS) return IPLS_OK;
     const int R = fit_rounds(max_S);
@@ -364,7 +365,8 @@ ipls_status train_l2pl(Depth& D, hipStream_t s, uint64_t ni, uint64_t max_S, uin
     ST_TRY(ensure(D.leaves, ni * 4 * kMaxLeaves * 8));
     ST_TRY(ensure(D.leaf_last, ni * kMaxLeaves * 8));
     Model* roots = (Model*)D.roots.p;
-    ST_TRY((fit_level<DT>(D, s, ni, max_S, total_fit_chunks, sample, sample_off, fit_off, roots, M)));
+    ST_TRY((fit_level<DT>(D, s, ni, max_S, total_fit_chunks, sample, sample_off, fit_off, roots, M, nullptr,
+                          FitGate{models, items, items ? gate_T : 0u})));
     k_l2pl_bounds<DT><<<(unsigned)ni, 256, 0, s>>>(sample, sample_off, ni, models, roots, M,
                                                    (uint32_t*)D.leaf_first.p, items, items ? gate_T : 0u);
     LAUNCH_CHECK();
