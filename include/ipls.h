@@ -31,6 +31,13 @@
  *   - Argument errors are reported synchronously and nothing is enqueued.  No C++ exception
  *     crosses this interface.  With IPLS_VERBOSE set in the environment, a HIP call that fails
  *     inside the library (the cause of IPLS_ERR_HIP) is reported on stderr with its error name.
+ *   - With IPLS_DEBUG_CHECKS=1 in the environment (read on every call), the sort entry points
+ *     that may allocate check the sort's invariants on the device: after every distribution pass
+ *     each bucketed array's histogram sums to its key count, the pass moved the same multiset of
+ *     keys (and payloads), and every key lies in the bucket its model gives it; at the end every
+ *     segment is sorted and holds its input's multiset.  A failed check returns IPLS_ERR_DEVICE.
+ *     The checks cost several extra passes over the data.  IPLS_DEBUG_CHECKS=2 also plants a
+ *     mismatch in the final multiset comparison, to exercise that error path.
  *   - The plain entry points share one engine context per device: their calls are serialised
  *     (one runs at a time), and the buffers the library allocates for its own use are cached in
  *     that context and reused across calls.  The request server's lanes own contexts of their

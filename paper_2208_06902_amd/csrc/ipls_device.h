@@ -159,7 +159,7 @@ __device__ __host__ inline int base_class(uint32_t n) {
 }
 
 // Error bits of the device error word.
-enum : uint64_t { kErrOffsets = 1, kErrCapacity = 2, kErrProgress = 4 };
+enum : uint64_t { kErrOffsets = 1, kErrCapacity = 2, kErrProgress = 4, kErrInvariant = 8 };
 
 // ------------------------------------------------------------------ key map
 // ord(): IEEE 754 totalOrder as an unsigned integer (flip a negative number's bits, set a positive

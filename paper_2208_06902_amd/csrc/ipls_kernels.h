@@ -2000,3 +2000,5 @@ __global__ __launch_bounds__(256) void k_copy(const CopyItem* copy, const uint64
 
 // The base case (buckets of at most T keys) lives in its own header.
 #include "ipls_base.h"
+// Invariant checks (IPLS_DEBUG_CHECKS).
+#include "ipls_debug.h"

@@ -28,6 +28,15 @@ constexpr uint64_t kWorklistFewItems = 1024;  // up to this many items: four a k
 constexpr uint32_t kSmallS = kFitLds;  // samples up to this size are fitted in one workgroup's LDS
 constexpr uint64_t kDeferBaseItems = 2048;  // levels of at least this many items run before the previous level's base case
 constexpr uint64_t kDeferBaseShare = 64;    // ... and levels of at least 1/64 of its keys
+
+// IPLS_DEBUG_CHECKS in the environment: 1 checks the sort's invariants after every pass and at
+// the end (ipls_debug.h); 2 does the same and plants a mismatch in the final multiset comparison,
+// so that a test sees the error reported.  Read on every top-level sort.
+int debug_checks() {
+    const char* v = std::getenv("IPLS_DEBUG_CHECKS");
+    if (!v || !*v || *v == '0') return 0;
+    return *v == '2' ? 2 : 1;
+}
 constexpr uint32_t kFitChunk = 2048;   // windows per workgroup in the multi-round fit
 constexpr uint32_t kCand = 15;         // candidate widths per fit round
 constexpr uint32_t kSmallTile = 4 * kWave * kPassIPT;  // 2048 keys: 4 waves
@@ -81,7 +90,8 @@ ipls_status ensure(Buf& b, size_t bytes) {
 struct Depth {
     Buf scratch, spay, items[2], base[2], sample_base, counters, plan, tile_off, sample_off, fit_off, chunk_off, tile_map,
         fit_map, chunk_map, models, masks, hist, bstart, tile_pref, chunk_sum, chunk_pref, sample, leaves, seg, roots,
-        leaf_first, leaf_last, eqinfo, rsample, copy, copy_off, copy_map, treeflag, sample2, children[2], spans, cls, wide;
+        leaf_first, leaf_last, eqinfo, rsample, copy, copy_off, copy_map, treeflag, sample2, children[2], spans, cls, wide,
+        dbg_all, dbg_acc;
     Plan* plan_h = nullptr;     // pinned, coherent: k_plan writes it directly
     Plan* plan_hd = nullptr;    // its device address (null: the plan is copied into plan_copy)
     uint64_t plan_seq = 0;      // k_plan launches so far
@@ -95,7 +105,7 @@ void for_each_buf(Depth& D, F&& f) {
                    &D.chunk_map, &D.models, &D.masks, &D.hist, &D.bstart, &D.tile_pref, &D.chunk_sum, &D.chunk_pref,
                    &D.sample, &D.leaves, &D.seg, &D.roots, &D.leaf_first, &D.leaf_last, &D.eqinfo, &D.rsample,
                    &D.copy, &D.copy_off, &D.copy_map, &D.treeflag, &D.sample2, &D.children[0], &D.children[1],
-                   &D.spans, &D.cls, &D.wide})
+                   &D.spans, &D.cls, &D.wide, &D.dbg_all, &D.dbg_acc})
         f(*b);
 }
 
@@ -546,6 +556,16 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     uint8_t* cls = inherit ? (uint8_t*)D.cls.p : nullptr;
 
     HIP_TRY(hipMemsetAsync(cnt, 0, C_N * sizeof(uint64_t), s));
+    // IPLS_DEBUG_CHECKS: the input's multiset hash before anything moves (top-level sorts that may
+    // allocate; the checks' buffers come from the cache)
+    const int dbg = (top && !dv.noalloc) ? debug_checks() : 0;
+    const unsigned dbg_grid = (unsigned)std::min<uint64_t>((len + 255) / 256, 4096);
+    if (dbg) {
+        ST_TRY(ensure(D.dbg_all, 4 * sizeof(uint64_t)));
+        k_dbg_zero<<<1, 64, 0, s>>>((uint64_t*)D.dbg_all.p, 4);
+        k_dbg_hash_all<DT, PAY><<<dbg_grid, 256, 0, s>>>(keys, pay, len, (uint64_t*)D.dbg_all.p);
+        LAUNCH_CHECK();
+    }
     k_seed<<<(unsigned)((nseg + 255) / 256), 256, 0, s>>>(seg_off, nseg, T_, (Item*)D.items[0].p,
                                                           (BaseItem*)D.base[1].p, bl, cnt, item_cap);
     LAUNCH_CHECK();
@@ -810,6 +830,22 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                 (const uint32_t*)D.tile_pref.p, src, psrc, dst, pdst, K, P.leaves, spans, children, cls);
             LAUNCH_CHECK();
         }
+        if (dbg) {
+            // the pass's invariants; a failure shows in the next level's plan
+            ST_TRY(ensure(D.dbg_acc, ni * 4 * sizeof(uint64_t)));
+            uint64_t* acc = (uint64_t*)D.dbg_acc.p;
+            k_dbg_zero<<<(unsigned)((4 * ni + 255) / 256), 256, 0, s>>>(acc, 4 * ni);
+            k_dbg_hash_tiles<DT, PAY><<<(unsigned)nt, 256, 0, s>>>((const TileInfo*)D.tile_map.p, nt, models, src, psrc,
+                                                                   acc);
+            k_dbg_hash_tiles<DT, PAY><<<(unsigned)nt, 256, 0, s>>>((const TileInfo*)D.tile_map.p, nt, models, dst, pdst,
+                                                                   acc + 2 * ni);
+            k_dbg_place<DT><<<(unsigned)nt, 256, 0, s>>>((const TileInfo*)D.tile_map.p, nt, items, models,
+                                                        (const double*)D.leaves.p, dst, (const uint64_t*)D.bstart.p,
+                                                        K, P.leaves, cnt + C_ERR);
+            k_dbg_level<<<(unsigned)((ni + 255) / 256), 256, 0, s>>>(items, ni, models, (const uint64_t*)D.hist.p, K,
+                                                                     acc, acc + 2 * ni, cnt + C_ERR);
+            LAUNCH_CHECK();
+        }
         if (top && level == 0 && run.single_pass) {
             k_export_model<<<1, 1, 0, s>>>(models, run.part_model, K);
             LAUNCH_CHECK();
@@ -851,7 +887,20 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
         cur ^= 1;
     }
     // the caller's stream completes only after the base case
-    return join();
+    ST_TRY(join());
+    if (dbg) {
+        // the output: sorted segments holding the input's multiset
+        uint64_t* all = (uint64_t*)D.dbg_all.p;
+        k_dbg_hash_all<DT, PAY><<<dbg_grid, 256, 0, s>>>(keys, pay, len, all + 2);
+        k_dbg_sorted<DT><<<dbg_grid, 256, 0, s>>>(keys, len, seg_off, nseg, cnt + C_ERR);
+        k_dbg_compare<<<1, 1, 0, s>>>(all, dbg == 2 ? 1 : 0, cnt + C_ERR);
+        LAUNCH_CHECK();
+        uint64_t e = 0;
+        HIP_TRY(hipMemcpyAsync(&e, cnt + C_ERR, sizeof(e), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (e) return IPLS_ERR_DEVICE;
+    }
+    return IPLS_OK;
 }
 
 template <int DT>
