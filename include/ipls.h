@@ -103,6 +103,12 @@ typedef struct {
                               * counting pass reads one byte a key instead of the key.  Within the paper's
                               * sample -> sort -> train -> predict pipeline (Machine Learning Models
                               * chapter); the paper itself samples every bucket afresh.  0 (default) */
+    uint32_t bucket_policy;  /* 1 (default): with the plain FMCD line (model 0, equality 0, inherit 0) a
+                              * bucket of n keys is partitioned into the smallest power of two k >= 8n/T
+                              * buckets, kept within [min(K, 64), K], and its sample's 2K minimum uses
+                              * that k: IPS4o, whose bucket count IPLS keeps (Proposed Algorithm), gives
+                              * subproblems near the base case fewer buckets.  0: K buckets everywhere.
+                              * ipls_partition always uses K. */
 } ipls_params;
 
 /* FMCD linear model of a sample: bucket(x) = clamp(floor(fma(a, x, b)), 0, K-1). */

@@ -26,7 +26,7 @@ class Params(C.Structure):
     _fields_ = [("num_buckets", C.c_uint32), ("base_case_max", C.c_uint32), ("sample_divisor", C.c_uint32),
                 ("sample_min", C.c_uint32), ("sample_max", C.c_uint64), ("seed", C.c_uint64),
                 ("model", C.c_uint32), ("leaves", C.c_uint32), ("train_iters", C.c_uint32), ("sample_policy", C.c_uint32),
-                ("equality", C.c_uint32), ("inherit", C.c_uint32)]
+                ("equality", C.c_uint32), ("inherit", C.c_uint32), ("bucket_policy", C.c_uint32)]
 
 
 class Model(C.Structure):
@@ -51,9 +51,13 @@ DEFAULT_SEED = 0x1F5A_2208_0690_2000
 
 
 def params(K=256, T=4096, divisor=100, sample_min=0, sample_max=0, seed=DEFAULT_SEED, model=0, leaves=256,
-           train_iters=4, sample_policy=0, equality=0, inherit=0) -> Params:
+           train_iters=4, sample_policy=0, equality=0, inherit=0, bucket_policy=1) -> Params:
     return Params(K, T, divisor, sample_min, sample_max, seed, model, leaves, train_iters, sample_policy, equality,
-                  inherit)
+                  inherit, bucket_policy)
+
+
+def bucket_count(n: int, p: Params) -> int:
+    return int(lib().oracle_bucket_count(n, C.byref(p)))
 
 
 CTX_SRC = os.path.join(HERE, "cpu_context.cpp")
@@ -101,6 +105,7 @@ def lib():
         sig = {
             "oracle_mix64": (u64, [u64]),
             "oracle_sample_size": (u64, [u64, C.POINTER(Params)]),
+            "oracle_bucket_count": (u32, [u64, C.POINTER(Params)]),
             "oracle_log2": (C.c_double, [u64]),
             "oracle_sample_positions": (None, [u64, u64, u64, u64, P]),
             "oracle_sorted_sample": (None, [P, u64, i32, u64, u64, u64, P]),

@@ -63,6 +63,7 @@ typedef struct {
     uint32_t sample_policy;  /* 0: S = ceil(n / divisor); 1: the paper's alpha*K - 1 */
     uint32_t equality;       /* 1: equality buckets for heavy sample values (IPS4o) */
     uint32_t inherit;        /* 1: a child bucket reuses its part of the parent's sorted sample */
+    uint32_t bucket_policy;  /* 1: fewer buckets for small buckets (bucket_count) */
 } oracle_params;
 
 typedef struct {
@@ -621,11 +622,34 @@ static int fit_equality(const double* x, const uint64_t* o, uint64_t S, uint32_t
     return 1;
 }
 
+/* Buckets of the partition of a bucket of n keys.  IPLS keeps IPS4o's bucket count (Proposed
+ * Algorithm), and IPS4o gives a subproblem close to the base case fewer buckets.  With
+ * bucket_policy 1 and the plain FMCD line (model 0, no equality buckets, no inheritance) this
+ * reading takes the smallest power of two k with k >= 8n/T (a bucket then expects at most T/8
+ * keys), kept within [min(K, 64), K]; otherwise K. */
+uint32_t oracle_bucket_count(uint64_t n, const oracle_params* p) {
+    const uint32_t K = p->num_buckets;
+    if (!p->bucket_policy || p->model != 0 || p->equality || p->inherit) return K;
+    const uint64_t need = (8 * n + p->base_case_max - 1) / p->base_case_max;
+    uint32_t k = 1;
+    while (k < need && k < K) k <<= 1;
+    const uint32_t lo = K < 64 ? K : 64;
+    if (k < lo) k = lo;
+    if (k > K) k = K;
+    return k;
+}
+
 /* inh/inh_len: a sorted sample handed down by the parent (sample inheritance), used instead of a
- * fresh one.  sample_out (nullable): receives the sorted sample's ords (caller frees). */
-static void fit_bucket(const void* keys, uint64_t n, int dtype, const oracle_params* p, uint64_t lo_rel,
+ * fresh one.  sample_out (nullable): receives the sorted sample's ords (caller frees).  adapt: the
+ * bucket count follows oracle_bucket_count (a bucket of the recursion); else K (one pass of the
+ * whole array, as asked). */
+static void fit_bucket(const void* keys, uint64_t n, int dtype, const oracle_params* p_in, uint64_t lo_rel,
                        oracle_model* m, l2pl_model* l2, double* l2_leaf, const uint64_t* inh, uint64_t inh_len,
-                       uint64_t** sample_out, uint64_t* sample_len) {
+                       uint64_t** sample_out, uint64_t* sample_len, int adapt) {
+    /* the sample size's 2K minimum (and the paper's alpha K - 1) follow the bucket's K */
+    oracle_params q = *p_in;
+    if (adapt) q.num_buckets = oracle_bucket_count(n, p_in);
+    const oracle_params* p = &q;
     uint32_t K = p->num_buckets;
     memset(m, 0, sizeof(*m));
     m->K = K;
@@ -909,7 +933,7 @@ static void ipls(ctx_t* cx, char* keys, uint32_t* pay, uint64_t n, uint64_t lo_r
     double* leaf = p->model ? (double*)malloc(4 * (size_t)M * sizeof(double)) : NULL;
     uint64_t* smp = NULL;
     uint64_t slen = 0;
-    fit_bucket(keys, n, cx->dtype, p, lo_rel, &m, &l2, leaf, inh, inh_len, p->inherit ? &smp : NULL, &slen);
+    fit_bucket(keys, n, cx->dtype, p, lo_rel, &m, &l2, leaf, inh, inh_len, p->inherit ? &smp : NULL, &slen, 1);
     if (m.kind == MODEL_CLOSED) {
         cx->st->closed += 1;
         free(leaf);
@@ -922,7 +946,7 @@ static void ipls(ctx_t* cx, char* keys, uint32_t* pay, uint64_t n, uint64_t lo_r
     cx->st->passes += 1;
     cx->st->keys_partitioned += n;
     if (level > cx->st->max_level) cx->st->max_level = level;
-    uint32_t K = p->num_buckets;
+    uint32_t K = m.K;
     uint64_t* counts = (uint64_t*)malloc(K * sizeof(uint64_t));
     distribute(cx, keys, pay, n, &m, &l2, counts);
     free(leaf);
@@ -1044,7 +1068,7 @@ int oracle_fit_bucket(const void* keys, uint64_t n, int dtype, const oracle_para
     uint32_t M = p->leaves ? p->leaves : 256;
     l2pl_model l2 = {0, 0.0, 0.0, NULL};
     double* leaf = p->model ? (double*)malloc(4 * (size_t)M * sizeof(double)) : NULL;
-    fit_bucket(keys, n, dtype, p, lo_rel, m, &l2, leaf, NULL, 0, NULL, NULL);
+    fit_bucket(keys, n, dtype, p, lo_rel, m, &l2, leaf, NULL, 0, NULL, NULL, 1);
     if (m->kind == MODEL_L2PL && leaf_out && root_out) {
         memcpy(leaf_out, leaf, 4 * (size_t)M * sizeof(double));
         root_out[0] = l2.ra;
@@ -1063,7 +1087,7 @@ int oracle_child_sample(const void* keys, uint64_t n, int dtype, const oracle_pa
     oracle_model m;
     uint64_t* smp = NULL;
     uint64_t slen = 0;
-    fit_bucket(keys, n, dtype, p, 0, &m, NULL, NULL, NULL, 0, &smp, &slen);
+    fit_bucket(keys, n, dtype, p, 0, &m, NULL, NULL, NULL, 0, &smp, &slen, 1);
     if (m.kind == MODEL_LINEAR && m.neq == 0 && n > p->base_case_max) {
         uint64_t* sub = NULL;
         uint64_t* sub_off = NULL;
@@ -1098,7 +1122,7 @@ int oracle_partition(void* keys, uint32_t* payload, uint64_t n, int dtype, const
     l2pl_model l2 = {0, 0.0, 0.0, NULL};
     double* leaf = p->model ? (double*)malloc(4 * (size_t)M * sizeof(double)) : NULL;
     oracle_model m;
-    fit_bucket(keys, n, dtype, p, 0, &m, &l2, leaf, NULL, 0, NULL, NULL);
+    fit_bucket(keys, n, dtype, p, 0, &m, &l2, leaf, NULL, 0, NULL, NULL, 0);
     for (uint32_t c = 0; c < p->num_buckets; ++c) counts[c] = 0;
     if (m.kind != MODEL_CLOSED) distribute(&cx, (char*)keys, payload, n, &m, &l2, counts);
     if (m_out) *m_out = m;

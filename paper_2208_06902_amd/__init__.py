@@ -39,7 +39,7 @@ class Params(C.Structure):
                 ("sample_min", C.c_uint32), ("sample_max", C.c_uint64), ("seed", C.c_uint64),
                 ("model", C.c_uint32), ("leaves", C.c_uint32), ("train_iters", C.c_uint32),
                 ("tile_keys", C.c_uint32), ("sample_policy", C.c_uint32),
-                ("equality", C.c_uint32), ("inherit", C.c_uint32)]
+                ("equality", C.c_uint32), ("inherit", C.c_uint32), ("bucket_policy", C.c_uint32)]
 
 
 class LinearModel(C.Structure):

@@ -85,7 +85,8 @@ struct Model {
     uint32_t inh;                // 1: inherited line; the level's counts come from the class bytes
     // equality buckets: neq heavy values (ords, ascending); the linear part has km buckets, or
     // sends every other key to bucket 0 (const0)
-    uint32_t neq, km, const0, pad2;
+    uint32_t neq, km, const0;
+    uint32_t kb;  // buckets of this item's line when they differ from the level's K (0: K)
     uint64_t heavy[kMaxHeavy];
     uint8_t eqb[kMaxHeavy];  // the bucket of each heavy value
 };
@@ -156,6 +157,18 @@ __device__ __host__ inline int base_class(uint32_t n) {
         ++c;
     }
     return c;
+}
+
+// Buckets of the partition of an item of n keys under the bucket policy (adapt != 0): the smallest
+// power of two k >= 8n/T within [min(K, 64), K] (a bucket then expects at most T/8 keys);
+// otherwise K.
+__device__ __host__ inline uint32_t bucket_count(uint64_t n, uint32_t K, uint32_t T, uint32_t adapt) {
+    if (!adapt) return K;
+    const uint64_t need = (8 * n + T - 1) / T;
+    uint32_t k = 1;
+    while (k < need && k < K) k <<= 1;
+    const uint32_t lo = K < 64 ? K : 64;
+    return k < lo ? lo : (k > K ? K : k);
 }
 
 // Error bits of the device error word.
@@ -320,7 +333,7 @@ __device__ inline uint32_t classify_key(const Model& m, const double* leaf, uint
         case kKindL2pl: return classify_l2pl(m.a, m.b, M, leaf, K, KT::val(u), KT::neg(u));
         default:
             if (m.neq) return classify_equality<DT>(m, u);
-            return classify_linear(m.a, m.b, K, KT::val(u), KT::neg(u));
+            return classify_linear(m.a, m.b, m.kb ? m.kb : K, KT::val(u), KT::neg(u));
     }
 }
 

@@ -26,6 +26,8 @@ struct LevelArgs {
     uint64_t div, smin, smax, seed;
     uint32_t policy;
     uint32_t tile_keys, small_S, fit_chunk, cand, chunk;
+    uint32_t adapt;       // bucket policy: an item's K is bucket_count(n) (and its sample's 2K minimum)
+    uint64_t smin_param;  // the caller's sample minimum (0: 2K, none under policy 1)
 };
 
 // ------------------------------------------------------------------ plan
@@ -40,8 +42,10 @@ __device__ inline void plan_item(const Item& it, const Child* prev_children, con
     const uint32_t ts = __builtin_ctz(A.tile_keys), cs = __builtin_ctz(A.chunk), fs = __builtin_ctz(A.fit_chunk);
     const uint64_t nt = (n + A.tile_keys - 1) >> ts;
     const uint64_t nc = (nt + A.chunk - 1) >> cs;
+    const uint32_t Ki = bucket_count(n, A.K, A.T, A.adapt);
+    const uint64_t smin = A.adapt ? (A.smin_param ? A.smin_param : (A.policy == 1 ? 0 : 2ull * Ki)) : A.smin;
     const uint64_t ns = (it.inh && prev_children) ? prev_children[it.inh - 1].s_len
-                                                  : sample_size(n, A.div, A.smin, A.smax, A.policy, A.K);
+                                                  : sample_size(n, A.div, smin, A.smax, A.policy, Ki);
     w[0] = nc;
     w[1] = nt;
     w[2] = ns;
@@ -388,7 +392,8 @@ constexpr int kFitLdsFused = 2048;  // the largest sample k_sample_fit takes
 struct FitGate {
     const Model* lines;
     const Item* items;
-    uint32_t T;  // 0: no gate
+    uint32_t T;        // 0: no gate
+    uint32_t adapt_T;  // bucket policy: an item's K is bucket_count(n, K, adapt_T) (0: K for every item)
 };
 
 template <int DT, int LDS_KEYS>
@@ -400,7 +405,7 @@ __global__ __launch_bounds__(256) void k_fmcd_small(const typename Key<DT>::T* s
     if (i >= num_items) return;
     // with equality buckets: the sample without heavy runs, and K - 2E buckets
     const uint64_t off = sample_off[i], S = eq ? eq[i].sr : sample_off[i + 1] - off;
-    const uint32_t K = eq ? eq[i].km : K_all;
+    const uint32_t K = eq ? eq[i].km : (gate.adapt_T ? bucket_count(gate.items[i].n, K_all, gate.adapt_T, 1) : K_all);
     if (S > small_S) return;
     if (gate.T && !(gate.lines[i].kind == kKindLinear && gate.lines[i].D > (uint64_t)gate.T * S / gate.items[i].n)) {
         if (threadIdx.x == 0) {
@@ -414,6 +419,7 @@ __global__ __launch_bounds__(256) void k_fmcd_small(const typename Key<DT>::T* s
     __syncthreads();
     Model m = {};
     m.S = S;
+    m.kb = K != K_all && !eq ? K : 0u;
     bool usable = S >= 3 && isfinite(sx[0]) && isfinite(sx[S - 1]);
     if (usable) {
         fmcd_search([&](uint64_t j) { return sx[j]; }, S, K, &m.a, &m.b, &m.D);
@@ -438,7 +444,7 @@ __global__ __launch_bounds__(256) void k_sample_fit(const Item* items, uint64_t 
                                                     uint32_t K, uint64_t expand_blocks, const uint64_t* tile_off,
                                                     uint64_t total_tiles, TileInfo* tile_map, uint32_t tile,
                                                     const uint64_t* chunk_off, uint64_t total_chunks,
-                                                    uint32_t* chunk_map) {
+                                                    uint32_t* chunk_map, uint32_t adapt_T) {
     using KT = Key<DT>;
     static_assert((CAP & (CAP - 1)) == 0, "power of two");
     __shared__ uint64_t s_o[CAP];
@@ -488,11 +494,13 @@ __global__ __launch_bounds__(256) void k_sample_fit(const Item* items, uint64_t 
     double* sx = (double*)s_o;
     for (uint32_t j = tid; j < S; j += nt) sx[j] = KT::val(KT::from_ord(s_o[j]));
     __syncthreads();
+    const uint32_t Ki = adapt_T ? bucket_count(it.n, K, adapt_T, 1) : K;
     Model m = {};
     m.S = S;
+    m.kb = Ki != K ? Ki : 0u;
     bool usable = S >= 3 && isfinite(sx[0]) && isfinite(sx[S - 1]);
     if (usable) {
-        fmcd_search([&](uint64_t j) { return sx[j]; }, S, K, &m.a, &m.b, &m.D);
+        fmcd_search([&](uint64_t j) { return sx[j]; }, S, Ki, &m.a, &m.b, &m.D);
         usable = fit_usable(m.a, m.b);
     }
     if (!usable) model_degenerate(m);
@@ -1194,7 +1202,8 @@ __global__ void k_finalize(const Item* items, Model* models, const Model* roots,
             atomicAdd((unsigned long long*)&stat_counts[0], 1ull);
             atomicAdd((unsigned long long*)&stat_counts[3], (unsigned long long)items[i].n);
         } else {
-            const int sh = (int)bit_length(m.umax - m.umin) - (int)(31 - __clz((int)K));
+            const uint32_t Kb = m.kb ? m.kb : K;
+            const int sh = (int)bit_length(m.umax - m.umin) - (int)(31 - __clz((int)Kb));
             m.kind = kKindDigit;
             m.shift = sh > 0 ? (uint32_t)sh : 0u;
             atomicAdd((unsigned long long*)&stat_counts[1], 1ull);
@@ -1333,7 +1342,7 @@ __device__ inline void classify_rows(const Model& m, const double* leaf, uint32_
                 for (int r = 0; r < IPT; ++r) f(r, classify_equality<DT>(m, k[r]));
             } else {
 #pragma unroll
-                for (int r = 0; r < IPT; ++r) f(r, classify_linear(m.a, m.b, K, KT::val(k[r]), KT::neg(k[r])));
+                for (int r = 0; r < IPT; ++r) f(r, classify_linear(m.a, m.b, m.kb ? m.kb : K, KT::val(k[r]), KT::neg(k[r])));
             }
             break;
     }

@@ -577,6 +577,10 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
     A.div = P.sample_divisor;
     A.smin = P.sample_min ? P.sample_min : (P.sample_policy == 1 ? 0 : 2ull * K);
     A.smax = P.sample_max;
+    // the bucket policy: the plain FMCD line of a sort (a single pass keeps K)
+    const bool adapt = P.bucket_policy && P.model == 0 && !P.equality && !inherit && !run.single_pass;
+    A.adapt = adapt ? 1u : 0u;
+    A.smin_param = P.sample_min;
     A.policy = P.sample_policy;
     A.seed = P.seed;
     const uint32_t tile = tile_keys_of(P);
@@ -714,7 +718,8 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             auto ksf = pl.max_S <= (uint64_t)kFitLdsTiny ? k_sample_fit<DT, kFitLdsTiny> : k_sample_fit<DT, kFitLdsFused>;
             ksf<<<(unsigned)(eb + ni), 256, 0, s>>>(
                 items, ni, (const uint64_t*)D.sample_off.p, src, P.seed, models, K, eb, (const uint64_t*)D.tile_off.p,
-                nt, (TileInfo*)D.tile_map.p, tile, (const uint64_t*)D.chunk_off.p, nc, (uint32_t*)D.chunk_map.p);
+                nt, (TileInfo*)D.tile_map.p, tile, (const uint64_t*)D.chunk_off.p, nc, (uint32_t*)D.chunk_map.p,
+                adapt ? T_ : 0u);
             LAUNCH_CHECK();
         } else {
             // the sample gather and the tile and chunk maps, in one launch
@@ -736,7 +741,8 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
             }
             ST_TRY((fit_level<DT>(D, s, ni, pl.max_S, pl.total_fit_chunks,
                                   eq ? (const T*)D.rsample.p : (const T*)sample, (const uint64_t*)D.sample_off.p,
-                                  (const uint64_t*)D.fit_off.p, models, K, eq)));
+                                  (const uint64_t*)D.fit_off.p, models, K, eq,
+                                  FitGate{nullptr, items, 0u, adapt ? T_ : 0u})));
             if (P.model == 3) {
                 ST_TRY(ensure(D.leaves, ni * 4 * kMaxLeaves * 8));
                 ST_TRY(ensure(D.treeflag, ni * 4));
@@ -969,7 +975,7 @@ ipls_status l2pl_entry(Device& dv, hipStream_t s, const double* x, uint64_t S, u
 
 ipls_status check_params(const ipls_params& p) {
     if (p.num_buckets < 4 || p.base_case_max < 1 || p.sample_divisor < 2) return IPLS_ERR_INVALID;
-    if (p.sample_policy > 1 || p.equality > 1 || p.inherit > 1) return IPLS_ERR_INVALID;
+    if (p.sample_policy > 1 || p.equality > 1 || p.inherit > 1 || p.bucket_policy > 1) return IPLS_ERR_INVALID;
     if (p.inherit && (p.model != 0 || p.equality)) return IPLS_ERR_INVALID;  // defined for the FMCD line alone
     if (p.tile_keys != 0 && p.tile_keys != kTile && p.tile_keys != kSmallTile) return IPLS_ERR_INVALID;
     const uint64_t smin = p.sample_min ? p.sample_min : (p.sample_policy == 1 ? 0 : 2ull * p.num_buckets);
@@ -1180,6 +1186,7 @@ void ipls_default_params(ipls_params* p) {
     p->sample_policy = 0;
     p->equality = 0;
     p->inherit = 0;
+    p->bucket_policy = 1;
 }
 
 const char* ipls_status_string(ipls_status st) {

@@ -502,3 +502,38 @@ def test_segmented_equals_per_segment():
     for s in range(len(sizes)):
         a, b = int(off[s]), int(off[s + 1])
         assert np.array_equal(out[a:b], np.sort(keys[a:b]))
+
+
+def _bucket_rule(n, K, T):
+    # the smallest power of two k >= 8n/T, kept within [min(K, 64), K]
+    need = -(-8 * n // T)
+    k = 1
+    while k < need and k < K:
+        k *= 2
+    return min(max(k, min(K, 64)), K)
+
+
+@pytest.mark.parametrize("K,T", [(256, 4096), (256, 256), (128, 4096), (48, 1024), (200, 4096)])
+def test_bucket_policy_count(K, T):
+    # a bucket of n keys is partitioned into the rule's number of buckets with the plain FMCD line;
+    # every other configuration, and bucket_policy 0, keeps K
+    for n in (T + 1, 2 * T, 8 * T - 1, 8 * T, 8 * T + 1, 32 * T, 32 * T + 1, 10**8):
+        p = oracle.params(K=K, T=T)
+        assert oracle.bucket_count(n, p) == _bucket_rule(n, K, T), (n, K, T)
+        for other in (dict(bucket_policy=0), dict(model=1), dict(model=3), dict(equality=1), dict(inherit=1)):
+            assert oracle.bucket_count(n, oracle.params(K=K, T=T, **other)) == K, (n, other)
+
+
+@pytest.mark.parametrize("n", [5000, 20000, 150000])
+def test_bucket_policy_fit_uses_the_bucket_count(n):
+    # the fitted line maps onto the bucket's own count, and its sample's 2K minimum follows it
+    keys = gen.make("exponential", n, 3)
+    p = oracle.params()
+    m, _, _ = oracle.fit_bucket(keys, p)
+    Ki = _bucket_rule(n, 256, 4096)
+    assert m.K == Ki
+    assert m.S == min(n, max(2 * Ki, -(-n // 100)))
+    out, _, _ = oracle.sort(keys, None, p)
+    assert np.array_equal(out, np.sort(keys))
+    m0, _, _ = oracle.fit_bucket(keys, oracle.params(bucket_policy=0))
+    assert m0.K == 256
