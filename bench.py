@@ -34,6 +34,7 @@ SEEDS = {"normal": 2, "lognormal": 3, "exponential": 4, "mixgauss": 5, "uniform_
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2208_06902_amd", "csrc", f) for f in ("ipls_kernels.h", "ipls_device.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scatter_traffic.json")
 PROFILE_LEVELS = 16  # IPLS_PROFILE_LEVELS
+BUCKET_POLICY_LABEL = "256, fewer for a bucket below 32T keys: the smallest power of two >= 8n/T, at least 64"
 
 
 def kernel_hash() -> str:
@@ -260,6 +261,7 @@ def bench_large_u64(args):
             if zipf else "plain single-array sort, 1000000000 uniform uint64 keys, keys only")
     line = _line(n / (mean_ms / 1e3), mean_ms, args.steps, args.warmup, "u64",
                  {"workload": desc, "n": n, "num_buckets": 256, "base_case_max": 4096,
+                  "bucket_policy": BUCKET_POLICY_LABEL if not args.equality else "256 everywhere",
                   "sample": sample_label(args), "model": "FMCD",
                   "equality_buckets": bool(args.equality), "parallelism": "single GPU"},
                  roofline={"kernel": "k_scatter", "bound": "hbm",
@@ -727,6 +729,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"plain single-array sort, {n} fp64 keys per step, keys only, cycling "
                                + "/".join(dists), "n": n, "num_buckets": 256, "base_case_max": 4096,
+                   "bucket_policy": BUCKET_POLICY_LABEL if args.sort_model == 0 else "256 everywhere",
                    "sample": sample_label(args),
                    "model": ("FMCD", "auto (learned model when lower max load)", "learned",
                              "splitter tree")[args.sort_model],
