@@ -387,8 +387,9 @@ constexpr int kFitLdsSmall = 4096;
 constexpr int kFitLdsTiny = 1024;
 constexpr int kFitLdsFused = 2048;  // the largest sample k_sample_fit takes
 
-// The auto policy's gate for the learned model's root fit: an item whose FMCD line (lines[i]) gives
-// D n <= T S is not trained, and its root is left unusable (k_l2pl_bounds applies the same rule).
+// Per-item options of k_fmcd_small: the auto policy's gate for the learned model's root fit (an
+// item whose FMCD line lines[i] gives D n <= T S is not trained, and its root is left unusable;
+// k_l2pl_bounds applies the same rule), and the bucket policy's K of each item.
 struct FitGate {
     const Model* lines;
     const Item* items;
