@@ -29,7 +29,8 @@ def oracle_params(**kw):
     m = dict(K=kw.get("num_buckets", 256), T=kw.get("base_case_max", 4096), divisor=kw.get("sample_divisor", 100),
              sample_min=kw.get("sample_min", 0), sample_max=kw.get("sample_max", 0),
              model=kw.get("model", 0), leaves=kw.get("leaves", 256), train_iters=kw.get("train_iters", 4),
-             sample_policy=kw.get("sample_policy", 0), equality=kw.get("equality", 0))
+             sample_policy=kw.get("sample_policy", 0), equality=kw.get("equality", 0),
+             bucket_policy=kw.get("bucket_policy", 1))
     return oracle.params(**m)
 
 
@@ -59,7 +60,9 @@ def test_sort_f64_default_params(dist):
 @pytest.mark.parametrize("kw", [dict(num_buckets=16, base_case_max=64), dict(num_buckets=64, base_case_max=200),
                                 dict(num_buckets=4, base_case_max=8, sample_min=8),
                                 dict(num_buckets=256, base_case_max=1000, sample_divisor=7),
-                                dict(tile_keys=2048), dict(tile_keys=2048, num_buckets=64, base_case_max=1024)])
+                                dict(tile_keys=2048), dict(tile_keys=2048, num_buckets=64, base_case_max=1024),
+                                dict(bucket_policy=0), dict(bucket_policy=0, num_buckets=64, base_case_max=200),
+                                dict(num_buckets=200, base_case_max=300)])
 def test_sort_f64_params(dist, kw):
     check_sort(gen.make(dist, 50_000, 5), **kw)
 
