@@ -62,7 +62,7 @@ def test_sort_f64_default_params(dist):
                                 dict(num_buckets=256, base_case_max=1000, sample_divisor=7),
                                 dict(tile_keys=2048), dict(tile_keys=2048, num_buckets=64, base_case_max=1024),
                                 dict(bucket_policy=0), dict(bucket_policy=0, num_buckets=64, base_case_max=200),
-                                dict(num_buckets=200, base_case_max=300)])
+                                dict(num_buckets=200, base_case_max=1000)])
 def test_sort_f64_params(dist, kw):
     check_sort(gen.make(dist, 50_000, 5), **kw)
 
