@@ -751,7 +751,15 @@ ipls_status sort_segments(Device& dv, Run& run, int d, typename Key<DT>::T* keys
                 LAUNCH_CHECK();
                 tree = (const uint32_t*)D.treeflag.p;
             }
-            if (P.model == 1 || P.model == 2)
+            // the auto policy trains an item only if D n > T S.  D <= S/3 + 1 and every sample holds
+            // at least s0 keys (the sample minimum, or the cap below it; items have more than
+            // T >= s0 keys), so a level whose largest item has n (s0 + 3) <= 3 T s0 trains none and
+            // skips the launches
+            uint64_t s0 = P.sample_min ? P.sample_min : 2ull * K;
+            if (P.sample_max && P.sample_max < s0) s0 = P.sample_max;
+            const bool none_trained = P.model == 1 && P.sample_policy == 0 && s0 > 0 &&
+                                      pl.max_n * (s0 + 3) <= 3ull * T_ * s0;
+            if ((P.model == 1 && !none_trained) || P.model == 2)
                 ST_TRY((train_l2pl<DT>(D, s, ni, pl.max_S, pl.total_fit_chunks, (const T*)sample,
                                        (const uint64_t*)D.sample_off.p, (const uint64_t*)D.fit_off.p, models, K, P.leaves,
                                        P.train_iters, nullptr, nullptr, nullptr, nullptr, items,
