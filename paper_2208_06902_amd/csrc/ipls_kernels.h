@@ -68,8 +68,8 @@ __global__ __launch_bounds__(256) void k_plan(const Item* items, uint64_t* cnt, 
     constexpr int kPlanWords = (int)(sizeof(Plan) / 8);
     static_assert(sizeof(Plan) % 8 == 0 && offsetof(Plan, seq) == sizeof(Plan) - 8, "seq is the plan's last word");
     __shared__ uint64_t s_plan[kPlanWords];
-    constexpr int kPlanIPT = 8;  // consecutive items per thread and round
-    __shared__ uint4 s_w[kPlanIPT][256];  // an item's chunks, tiles, samples, fit chunks (first pass)
+    constexpr int kPlanIPT = 8;  // items per thread and round
+    __shared__ uint4 s_w[kPlanIPT * 256];  // an item's chunks, tiles, samples, fit chunks
     if (threadIdx.x < (uint32_t)C_N) s_cnt[threadIdx.x] = cnt[threadIdx.x];
     if (threadIdx.x == 0) { s_max[0] = s_max[1] = s_max[2] = s_max[3] = 0; }
     __syncthreads();
@@ -82,24 +82,39 @@ __global__ __launch_bounds__(256) void k_plan(const Item* items, uint64_t* cnt, 
     }
     uint64_t run_t = 0, run_s = 0, run_f = 0, run_c = 0, run_w = 0, sum_n = 0, sum_inh = 0;
     const uint64_t use = num < item_cap ? num : item_cap;
-    // kPlanIPT consecutive items per thread: a pass for the thread's sums (which keeps each item's
-    // figures in LDS), one block scan, then a pass that writes the item's offsets (levels of many
-    // items take few block scans)
-    for (uint64_t base = 0; base < use; base += (uint64_t)blockDim.x * kPlanIPT) {
-        const uint64_t i0 = base + (uint64_t)threadIdx.x * kPlanIPT;
-        uint64_t v[7] = {0, 0, 0, 0, 0, 0, 0}, mS = 0, mN = 0;
+    const uint32_t t = threadIdx.x, per = kPlanIPT * blockDim.x;
+    // a round of kPlanIPT * 256 items: every thread reads kPlanIPT of them, 256 apart (coalesced,
+    // all in flight) and keeps their figures in LDS; then thread t sums the kPlanIPT consecutive
+    // items from kPlanIPT t, one block scan gives their offsets, and it writes them
+    for (uint64_t base = 0; base < use; base += per) {
+        uint64_t mS = 0, mN = 0, pn = 0, pinh = 0;
+        uint64_t its_n[kPlanIPT], its_inh[kPlanIPT];  // the fields plan_item reads
 #pragma unroll
         for (int k = 0; k < kPlanIPT; ++k) {
-            if (i0 + k < use) {
-                uint64_t w[7];
-                plan_item(items[i0 + k], prev_children, A, w);
+            const uint64_t i = base + (uint64_t)k * blockDim.x + t;
+            its_n[k] = i < use ? items[i].n : 0;
+            its_inh[k] = i < use ? items[i].inh : 0;
+        }
+#pragma unroll 1
+        for (int k = 0; k < kPlanIPT; ++k) {
+            const uint32_t j = (uint32_t)k * blockDim.x + t;
+            if (base + j >= use) break;
+            uint64_t w[7];
+            Item it = {0, 0, 0, 0};
+            // a register array is indexed by constants only
 #pragma unroll
-                for (int j = 0; j < 7; ++j) v[j] += w[j];
-                mS = w[2] > mS ? w[2] : mS;
-                mN = w[4] > mN ? w[4] : mN;
-                // each fits 32 bits: an item has fewer than 2^44 keys, its sample fewer than 2^32
-                s_w[k][threadIdx.x] = make_uint4((uint32_t)w[0], (uint32_t)w[1], (uint32_t)w[2], (uint32_t)w[3]);
-            }
+            for (int q = 0; q < kPlanIPT; ++q)
+                if (q == k) {
+                    it.n = its_n[q];
+                    it.inh = its_inh[q];
+                }
+            plan_item(it, prev_children, A, w);
+            mS = w[2] > mS ? w[2] : mS;
+            mN = w[4] > mN ? w[4] : mN;
+            pn += w[4];
+            pinh += w[5];
+            // each fits 32 bits: an item has fewer than 2^44 keys, its sample fewer than 2^32
+            s_w[j] = make_uint4((uint32_t)w[0], (uint32_t)w[1], (uint32_t)w[2], (uint32_t)w[3]);
         }
         // maxima: one LDS atomic per wave
         mS = wave_max<uint64_t>(mS);
@@ -108,28 +123,65 @@ __global__ __launch_bounds__(256) void k_plan(const Item* items, uint64_t* cnt, 
             atomicMax((unsigned long long*)&s_max[0], (unsigned long long)mS);
             atomicMax((unsigned long long*)&s_max[1], (unsigned long long)mN);
         }
+        __syncthreads();
+        const uint64_t i0 = base + (uint64_t)t * kPlanIPT;
+        uint64_t v[7] = {0, 0, 0, 0, pn, pinh, 0};
+#pragma unroll 1
+        for (int k = 0; k < kPlanIPT; ++k) {
+            if (i0 + k >= use) break;
+            const uint4 q = s_w[t * kPlanIPT + k];
+            v[0] += q.x;
+            v[1] += q.y;
+            v[2] += q.z;
+            v[3] += q.w;
+            v[6] += q.x > kScanSerial ? 1u : 0u;
+        }
         uint64_t ex[7], tot[7];
         block_exclusive_sums<7>(v, ex, tot, sc6);
         uint64_t at_c = run_c + ex[0], at_t = run_t + ex[1], at_s = run_s + ex[2], at_f = run_f + ex[3],
                  at_w = run_w + ex[6];
+        // the thread's kPlanIPT offsets of each array are one aligned 64-byte run (the arrays are
+        // 256-byte aligned): written with 16-byte stores when the run is whole
+        uint64_t oc[kPlanIPT], ot[kPlanIPT], os[kPlanIPT], of[kPlanIPT];
+        uint32_t nsam[kPlanIPT];
+#pragma unroll
         for (int k = 0; k < kPlanIPT; ++k) {
-            const uint64_t i = i0 + k;
-            if (i >= use) break;
-            const uint4 q = s_w[k][threadIdx.x];
-            const uint64_t w[7] = {q.x, q.y, q.z, q.w, 0, 0, q.x > kScanSerial ? 1u : 0u};
-            chunk_off[i] = at_c;
-            tile_off[i] = at_t;
-            sample_off[i] = at_s;
-            fit_off[i] = at_f;
-            // the samples as base-case buckets of the sample buffer (used when every sample has <= T keys)
-            if (sample_base) sample_base[i] = BaseItem{at_s, (uint32_t)w[2], 0};
-            if (w[6]) wide_items[at_w] = (uint32_t)i;  // items whose chunks a workgroup per bucket scans
-            at_c += w[0];
-            at_t += w[1];
-            at_s += w[2];
-            at_f += w[3];
-            at_w += w[6];
+            const bool in = i0 + k < use;
+            const uint4 q = in ? s_w[t * kPlanIPT + k] : make_uint4(0u, 0u, 0u, 0u);
+            oc[k] = at_c;
+            ot[k] = at_t;
+            os[k] = at_s;
+            of[k] = at_f;
+            nsam[k] = q.z;
+            if (q.x > kScanSerial) wide_items[at_w++] = (uint32_t)(i0 + k);  // items whose chunks a workgroup per bucket scans
+            at_c += q.x;
+            at_t += q.y;
+            at_s += q.z;
+            at_f += q.w;
         }
+        if (i0 + kPlanIPT <= use) {
+#pragma unroll
+            for (int k = 0; k < kPlanIPT; k += 2) {
+                *(ulonglong2*)&chunk_off[i0 + k] = make_ulonglong2(oc[k], oc[k + 1]);
+                *(ulonglong2*)&tile_off[i0 + k] = make_ulonglong2(ot[k], ot[k + 1]);
+                *(ulonglong2*)&sample_off[i0 + k] = make_ulonglong2(os[k], os[k + 1]);
+                *(ulonglong2*)&fit_off[i0 + k] = make_ulonglong2(of[k], of[k + 1]);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kPlanIPT; ++k)
+                if (i0 + k < use) {
+                    chunk_off[i0 + k] = oc[k];
+                    tile_off[i0 + k] = ot[k];
+                    sample_off[i0 + k] = os[k];
+                    fit_off[i0 + k] = of[k];
+                }
+        }
+        // the samples as base-case buckets of the sample buffer (used when every sample has <= T keys)
+        if (sample_base)
+#pragma unroll
+            for (int k = 0; k < kPlanIPT; ++k)
+                if (i0 + k < use) sample_base[i0 + k] = BaseItem{os[k], nsam[k], 0};
         run_c += tot[0];
         run_t += tot[1];
         run_s += tot[2];
@@ -137,6 +189,7 @@ __global__ __launch_bounds__(256) void k_plan(const Item* items, uint64_t* cnt, 
         sum_n += tot[4];
         sum_inh += tot[5];
         run_w += tot[6];
+        __syncthreads();  // s_w is refilled by the next round
     }
     if (threadIdx.x == 0) {
         s_max[2] = sum_n;
@@ -193,7 +246,6 @@ __global__ __launch_bounds__(256) void k_plan(const Item* items, uint64_t* cnt, 
         P.seq = seq;
     }
     // counters the coming level appends to start from zero; this level's list is consumed
-    const uint32_t t = threadIdx.x;
     if (t == C_CHILD || t == C_COPY || t == C_COPYKEYS || t == C_BASEKEYS || t == C_BASE ||
         t == (uint32_t)(C_ITEMS0 + cur) || t == (uint32_t)(C_ITEMS0 + (cur ^ 1)) ||
         (t >= (uint32_t)C_CLS && t < (uint32_t)(C_CLS + kBaseClasses)))
@@ -358,16 +410,26 @@ __device__ inline void fill_sample_lds(double* x, const typename Key<DT>::T* xs,
 }
 
 // Binary search for FMCD's D over [1, S/3 + 1] by the whole block, x(j) the j-th value of a sorted
-// sample of S >= 3 keys with finite ends; then the line.  Every thread gets the same result.
+// sample of S >= 3 keys (fewer than 2^32, in LDS) with finite ends; then the line.  Every thread
+// gets the same result.  A probe tests its windows four at a time (the test is an OR, so the order
+// does not matter), which keeps several LDS loads in flight.
 template <typename X>
 __device__ inline void fmcd_search(const X& x, uint64_t S, uint32_t K, double* a, double* b, uint64_t* Dout) {
     const uint64_t Dmax = S / 3;
     uint64_t lo = 1, hi = Dmax + 1;
+    const uint32_t nt = blockDim.x;
     while (lo < hi) {
         const uint64_t D = lo + ((hi - lo) >> 1);
         const double u = fmcd_spread(x(S - 1 - D), x(D), K);
-        int fail = 0;
-        for (uint64_t w = threadIdx.x; w + D < S; w += blockDim.x) fail |= !(x(w + D) - x(w) >= u);
+        const uint32_t d = (uint32_t)D, nw = (uint32_t)(S - D);  // windows [w, w + D], w < S - D
+        bool fail = false;
+        uint32_t w = threadIdx.x;
+        for (; w + 3 * nt < nw; w += 4 * nt) {
+            const double g0 = x(w + d) - x(w), g1 = x(w + nt + d) - x(w + nt);
+            const double g2 = x(w + 2 * nt + d) - x(w + 2 * nt), g3 = x(w + 3 * nt + d) - x(w + 3 * nt);
+            fail |= !(g0 >= u) | !(g1 >= u) | !(g2 >= u) | !(g3 >= u);
+        }
+        for (; w < nw; w += nt) fail |= !(x(w + d) - x(w) >= u);
         if (__syncthreads_or(fail)) lo = D + 1;
         else hi = D;
     }
