@@ -164,9 +164,9 @@ __device__ __host__ inline int base_class(uint32_t n) {
 // otherwise K.
 __device__ __host__ inline uint32_t bucket_count(uint64_t n, uint32_t K, uint32_t T, uint32_t adapt) {
     if (!adapt) return K;
-    const uint64_t need = (8 * n + T - 1) / T;
+    // k < ceil(8n/T) exactly when k T < 8n (k an integer): no 64-bit division
     uint32_t k = 1;
-    while (k < need && k < K) k <<= 1;
+    while (k < K && (uint64_t)k * T < 8 * n) k <<= 1;
     const uint32_t lo = K < 64 ? K : 64;
     return k < lo ? lo : (k > K ? K : k);
 }

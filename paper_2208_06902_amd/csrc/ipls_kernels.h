@@ -69,7 +69,9 @@ __global__ __launch_bounds__(256) void k_plan(const Item* items, uint64_t* cnt, 
     static_assert(sizeof(Plan) % 8 == 0 && offsetof(Plan, seq) == sizeof(Plan) - 8, "seq is the plan's last word");
     __shared__ uint64_t s_plan[kPlanWords];
     constexpr int kPlanIPT = 8;  // items per thread and round
-    __shared__ uint4 s_w[kPlanIPT * 256];  // an item's chunks, tiles, samples, fit chunks
+    // an item's chunks, tiles, samples, fit chunks; entry j at j + j/8, so that the 16-byte reads
+    // of kPlanIPT consecutive items per thread (144 bytes apart) hit distinct LDS banks
+    __shared__ uint4 s_w[kPlanIPT * 256 + kPlanIPT * 256 / 8];
     if (threadIdx.x < (uint32_t)C_N) s_cnt[threadIdx.x] = cnt[threadIdx.x];
     if (threadIdx.x == 0) { s_max[0] = s_max[1] = s_max[2] = s_max[3] = 0; }
     __syncthreads();
@@ -114,7 +116,7 @@ __global__ __launch_bounds__(256) void k_plan(const Item* items, uint64_t* cnt, 
             pn += w[4];
             pinh += w[5];
             // each fits 32 bits: an item has fewer than 2^44 keys, its sample fewer than 2^32
-            s_w[j] = make_uint4((uint32_t)w[0], (uint32_t)w[1], (uint32_t)w[2], (uint32_t)w[3]);
+            s_w[j + (j >> 3)] = make_uint4((uint32_t)w[0], (uint32_t)w[1], (uint32_t)w[2], (uint32_t)w[3]);
         }
         // maxima: one LDS atomic per wave
         mS = wave_max<uint64_t>(mS);
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(256) void k_plan(const Item* items, uint64_t* cnt, 
 #pragma unroll 1
         for (int k = 0; k < kPlanIPT; ++k) {
             if (i0 + k >= use) break;
-            const uint4 q = s_w[t * kPlanIPT + k];
+            const uint4 q = s_w[t * (kPlanIPT + 1) + k];
             v[0] += q.x;
             v[1] += q.y;
             v[2] += q.z;
@@ -147,7 +149,7 @@ __global__ __launch_bounds__(256) void k_plan(const Item* items, uint64_t* cnt, 
 #pragma unroll
         for (int k = 0; k < kPlanIPT; ++k) {
             const bool in = i0 + k < use;
-            const uint4 q = in ? s_w[t * kPlanIPT + k] : make_uint4(0u, 0u, 0u, 0u);
+            const uint4 q = in ? s_w[t * (kPlanIPT + 1) + k] : make_uint4(0u, 0u, 0u, 0u);
             oc[k] = at_c;
             ot[k] = at_t;
             os[k] = at_s;
